@@ -1,0 +1,174 @@
+/*
+ * accord.h -- C ABI of the MI355X (gfx950) ACCORD-FBS library.
+ *
+ * The library computes the ACCORD estimator (arXiv 2412.11554, eq. 3.2)
+ *
+ *     Omega_hat = argmin  -sum_j log Omega_jj  +  ||X Omega||_F^2 / (2n)  +  lambda ||Omega||_1
+ *
+ * with the forward-backward splitting iteration of Alg. 1 (ACCORD-FBS with
+ * backtracking).  The penalty covers all p^2 entries, the diagonal included
+ * (eq. 3.2; the diagonal update of eq. 3.5 carries the -tau*lambda term).
+ *
+ * Matrix convention.  The paper writes the smooth part as tr(Omega^T Omega S)/2
+ * with gradient Omega S, so row i of the paper's Omega is node-wise problem i
+ * (supplement, proof of Theorem 3.2).  This library works on the transpose
+ * ("column form"): column j of Omega is node-wise problem j, the smooth part is
+ * g(Omega) = ||X Omega||_F^2 / (2n) and its gradient is G = X^T (X Omega) / n.
+ * Column-form matrices are stored COLUMN-MAJOR: entry (i, j) at [j*p + i].
+ * That buffer is byte-identical to the paper's Omega stored row-major, i.e. a
+ * C-contiguous torch [p, p] tensor holding the paper's Omega.
+ *
+ * Layouts.  X is n x p, row-major (entry (k, i) at [k*p + i]), float32, with
+ * centred columns (Sec. 2).  W = X Omega is n x p row-major.  Omega, G and
+ * Omega_out are p x p column-major as above.  All pointers marked "device"
+ * must be device memory on the current HIP device, 16-byte aligned.
+ *
+ * Ownership.  The caller owns every buffer, including the workspace `ws`
+ * (device, 256-byte aligned, at least accord_workspace_bytes() bytes).  The
+ * library allocates no device memory and frees nothing; its only global state
+ * is a thread-local last-error string.  Calls with distinct workspaces are
+ * independent; calls sharing a workspace must be stream-ordered.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = default stream).
+ * accord_grad, accord_prox and accord_objective are asynchronous and
+ * stream-ordered; problems found on the device (non-finite values, a
+ * non-positive diagonal) show up as NaN / inf in their outputs.  accord_fit is
+ * synchronous: it returns after its work on `stream` has completed.
+ *
+ * Errors.  Every entry point returns an accord_status.  Argument, alignment and
+ * workspace-size problems are detected on the host and returned before any
+ * work is enqueued.  HIP runtime failures return ACCORD_ERR_HIP; the text is in
+ * accord_last_error().
+ */
+#ifndef ACCORD_H
+#define ACCORD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ACCORD_OK = 0,
+    ACCORD_ERR_INVALID_ARG = 1,  /* null pointer, size < 1, bad parameter, misalignment */
+    ACCORD_ERR_DOMAIN = 2,       /* some Omega_jj <= 0 where a positive diagonal is required */
+    ACCORD_ERR_NONFINITE = 3,    /* NaN/inf in X or in an iterate */
+    ACCORD_ERR_WORKSPACE = 4,    /* workspace null, misaligned or smaller than required */
+    ACCORD_ERR_UNSUPPORTED = 5,  /* precision form not available on this device/build */
+    ACCORD_ERR_HIP = 6           /* HIP runtime error (see accord_last_error) */
+} accord_status;
+
+typedef enum {
+    ACCORD_FP32 = 0     /* FP32 MFMA contractions, FP64 reductions and diagonal root */
+} accord_precision;
+
+/* Columns of the optional per-iteration trace (device double[(max_iter+1) * 8]).
+ * Row 0 describes the starting point, row t+1 the iterate after iteration t. */
+enum {
+    ACCORD_TRACE_F = 0,         /* f = g + h                                       */
+    ACCORD_TRACE_G = 1,         /* g = ||X Omega||_F^2 / (2n)                      */
+    ACCORD_TRACE_H = 2,         /* h = -sum log Omega_jj + lambda ||Omega||_1      */
+    ACCORD_TRACE_TAU = 3,       /* accepted step tau_t                             */
+    ACCORD_TRACE_TRIALS = 4,    /* backtracking trials used                        */
+    ACCORD_TRACE_DELTA = 5,     /* ||Omega_{t+1} - Omega_t||_F                     */
+    ACCORD_TRACE_FLOOR = 6,     /* 1 if accepted only because tau <= 1/L           */
+    ACCORD_TRACE_NNZ = 7,       /* nonzero off-diagonal entries of the iterate     */
+    ACCORD_TRACE_COLS = 8
+};
+
+/* Parameters of accord_fit (Alg. 1 inputs plus run control). */
+typedef struct {
+    double lambda;      /* penalty, >= 0 */
+    double tau0;        /* initial step of EVERY iteration (Alg. 1), > 0; typical 1 */
+    double beta;        /* backtracking factor in (0, 1]; 1 = fixed step tau0, no test */
+    double lipschitz;   /* L = sigma_max(X^T X / n) (Sec. 3.2); 0 = estimate on the device
+                           by power iteration.  The step floor of Alg. 1 is tau <= 1/L. */
+    double tol;         /* 0 = run exactly max_iter iterations; > 0 = also stop once
+                           ||Delta||_F <= tol * max(1, ||Omega_{t+1}||_F) */
+    int32_t max_iter;   /* iterations, >= 0 */
+    int32_t precision;  /* accord_precision */
+    int32_t check_every;/* with tol > 0: poll the stop flag every this many iterations (>= 1) */
+    int32_t power_iters;/* power-iteration steps when lipschitz == 0 (0 = 200) */
+    int32_t timing;     /* 1 = time every kernel launch with HIP events (fills the *_ms fields) */
+    int32_t reserved[3];
+} accord_params;
+
+/* Results of accord_fit (host memory, filled on return). */
+typedef struct {
+    int32_t iters;          /* iterations completed */
+    int32_t trials;         /* backtracking trials over all iterations */
+    int32_t floor_accepts;  /* trials accepted only by the tau <= 1/L rule */
+    int32_t converged;      /* tol-based stop reached */
+    int64_t nnz_offdiag;    /* nonzero off-diagonal entries of the result */
+    double f, g, h;         /* objective pieces at the result */
+    double tau_last;        /* accepted step of the last iteration */
+    double delta_fro;       /* ||Delta||_F of the last iteration */
+    double lipschitz;       /* L used for the step floor */
+    /* per-kernel device time (params.timing == 1; executed launches only) */
+    double grad_gemm_ms;    int32_t grad_gemm_launches;   /* G = X^T W / n          */
+    double trial_gemm_ms;   int32_t trial_gemm_launches;  /* W+ = W + X Delta       */
+    double prox_ms;         int32_t prox_launches;        /* fused prox + reductions */
+    double total_ms;        /* event time of the whole fit on the stream */
+} accord_stats;
+
+/* Fills `prm` with defaults: lambda 0.1, tau0 1, beta 0.5, lipschitz 0 (estimate),
+ * tol 0, max_iter 100, FP32, check_every 10, power_iters 200, timing 0. */
+void accord_default_params(accord_params* prm);
+
+/* Workspace bytes needed by accord_fit for an n x p problem with `prm` (NULL =
+ * defaults).  The same size (or accord_workspace_bytes(n, p, NULL)) is enough for
+ * accord_grad and accord_objective on that problem, and accord_workspace_bytes(1, p,
+ * NULL) for accord_prox.  Returns 0 for n < 1 or p < 1. */
+size_t accord_workspace_bytes(int64_t n, int64_t p, const accord_params* prm);
+
+/* Gradient of the smooth part (eq. 3.4; Remark 3.1's two-step product):
+ *     W = X Omega  (n x p, row-major, optional: W may be NULL)
+ *     G = X^T W / n  (p x p, column form, column-major)
+ * X: device n x p.  Omega: device p x p column form.  Asynchronous. */
+int accord_grad(const float* X, int64_t n, int64_t p, const float* Omega,
+                float* W, float* G, void* ws, size_t ws_bytes, void* stream);
+
+/* One proximal (backward) step at a given tau (eq. 3.5), for the whole matrix:
+ *     A = Omega - tau*G;  off-diagonal: soft-threshold at tau*lambda;
+ *     diagonal: (b + sqrt(b^2 + 4 tau)) / 2 with b = A_jj - tau*lambda (FP64).
+ * Omega, G, Omega_out: device p x p column form (Omega_out must not alias).
+ * red (device double[6], written): { ||Delta||_F^2, <Delta, G>, ||Omega_out||_1,
+ *   sum_j log Omega_out_jj, nnz off-diagonal of Omega_out, ||Omega_out||_F^2 },
+ * Delta = Omega_out - Omega, sums in FP64 in a fixed order.  tau > 0, lambda >= 0.
+ * Asynchronous. */
+int accord_prox(const float* Omega, const float* G, int64_t p, double tau, double lambda,
+                float* Omega_out, double* red, void* ws, size_t ws_bytes, void* stream);
+
+/* Objective of eq. 3.2 at Omega (column form):
+ * out (device double[3], written) = { g, h, f } with g = ||X Omega||_F^2/(2n),
+ * h = -sum_j log Omega_jj + lambda ||Omega||_1 (+inf if some Omega_jj <= 0), f = g + h.
+ * Asynchronous. */
+int accord_objective(const float* X, int64_t n, int64_t p, const float* Omega, double lambda,
+                     double* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ACCORD-FBS (Alg. 1).  Omega: device p x p column form; on input the starting
+ * point Omega^(0) (diagonal > 0, else ACCORD_ERR_DOMAIN), on output the last iterate.
+ * Every iteration computes G = X^T (X Omega_t) / n once, then tries
+ * tau = tau0, beta*tau0, ... : Omega+ = prox(Omega_t - tau G) (eq. 3.5),
+ * Delta = Omega+ - Omega_t, and accepts the first tau with
+ *     ||X Delta||_F^2 / n <= ||Delta||_F^2 / tau      or      tau <= 1/L
+ * (the acceptance inequality of Alg. 1, written without subtracting values of g,
+ * which is exact because g is quadratic).  stats: host, filled on return (may be
+ * NULL).  trace: device double[(max_iter+1) * ACCORD_TRACE_COLS] or NULL.
+ * Synchronous. */
+int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_params* prm,
+               accord_stats* stats, double* trace, void* ws, size_t ws_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* accord_status_str(int status);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char* accord_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACCORD_H */

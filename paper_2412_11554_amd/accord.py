@@ -1,0 +1,221 @@
+"""Python binding of libaccord (ctypes), with the entry-point names of include/accord.h.
+
+Argument marshalling only: every step runs in the library's HIP kernels.  torch
+supplies device memory and the stream; tensors must be float32/float64 CUDA
+(HIP) tensors, C-contiguous.  There is no CPU path: a missing library or a
+non-device tensor raises.
+
+Matrix convention: Omega / G are torch [p, p] tensors holding the paper's Omega
+(row j = node-wise problem j).  Their memory is the column form used by the
+library (column j of the column-form matrix = node-wise problem j), so
+``tensor.T`` is the column-form matrix g(Omega) = ||X Omega||^2/(2n) refers to.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch  # noqa: F401  -- load torch's HIP runtime first; libaccord binds to it
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaccord.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "accord.h")
+
+ACCORD_OK = 0
+STATUS_NAMES = {0: "ACCORD_OK", 1: "ACCORD_ERR_INVALID_ARG", 2: "ACCORD_ERR_DOMAIN",
+                3: "ACCORD_ERR_NONFINITE", 4: "ACCORD_ERR_WORKSPACE",
+                5: "ACCORD_ERR_UNSUPPORTED", 6: "ACCORD_ERR_HIP"}
+PRECISIONS = {"fp32": 0}
+TRACE_COLS = 8
+TRACE_FIELDS = ("f", "g", "h", "tau", "trials", "delta_fro", "floor", "nnz")
+
+
+class accord_params(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("tau0", ctypes.c_double),
+                ("beta", ctypes.c_double), ("lipschitz", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("power_iters", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+class accord_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("trials", ctypes.c_int32),
+                ("floor_accepts", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("nnz_offdiag", ctypes.c_int64), ("f", ctypes.c_double),
+                ("g", ctypes.c_double), ("h", ctypes.c_double), ("tau_last", ctypes.c_double),
+                ("delta_fro", ctypes.c_double), ("lipschitz", ctypes.c_double),
+                ("grad_gemm_ms", ctypes.c_double), ("grad_gemm_launches", ctypes.c_int32),
+                ("trial_gemm_ms", ctypes.c_double), ("trial_gemm_launches", ctypes.c_int32),
+                ("prox_ms", ctypes.c_double), ("prox_launches", ctypes.c_int32),
+                ("total_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class AccordError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_d = ctypes.c_double
+_sz = ctypes.c_size_t
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libaccord.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.accord_default_params.argtypes = [ctypes.POINTER(accord_params)]
+        L.accord_default_params.restype = None
+        L.accord_workspace_bytes.argtypes = [_i64, _i64, ctypes.POINTER(accord_params)]
+        L.accord_workspace_bytes.restype = _sz
+        L.accord_grad.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.accord_prox.argtypes = [_vp, _vp, _i64, _d, _d, _vp, _vp, _vp, _sz, _vp]
+        L.accord_objective.argtypes = [_vp, _i64, _i64, _vp, _d, _vp, _vp, _sz, _vp]
+        L.accord_fit.argtypes = [_vp, _i64, _i64, _vp, ctypes.POINTER(accord_params),
+                                 ctypes.POINTER(accord_stats), _vp, _vp, _sz, _vp]
+        for f in ("accord_grad", "accord_prox", "accord_objective", "accord_fit"):
+            getattr(L, f).restype = ctypes.c_int
+        L.accord_status_str.argtypes = [ctypes.c_int]
+        L.accord_status_str.restype = ctypes.c_char_p
+        L.accord_last_error.argtypes = []
+        L.accord_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/accord.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w ]+?\*?\s*)\b(accord_\w+)\s*\(", text, re.M)))
+
+
+def _check(status: int) -> None:
+    if status != ACCORD_OK:
+        msg = lib().accord_last_error().decode()
+        raise AccordError(status, msg)
+
+
+def _dev(t: torch.Tensor, name: str, dtype=torch.float32) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def default_params(**kw) -> accord_params:
+    prm = accord_params()
+    lib().accord_default_params(ctypes.byref(prm))
+    for k, v in kw.items():
+        if k == "lam":
+            k = "lambda_"
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
+        if not hasattr(prm, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(prm, k, v)
+    return prm
+
+
+def accord_workspace_bytes(n: int, p: int, params: accord_params | None = None) -> int:
+    return int(lib().accord_workspace_bytes(n, p, ctypes.byref(params) if params else None))
+
+
+def _workspace(n: int, p: int, params, device, ws):
+    need = accord_workspace_bytes(n, p, params)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=device)
+    return ws
+
+
+def accord_grad(X: torch.Tensor, Omega: torch.Tensor, *, want_W: bool = False,
+                G: torch.Tensor | None = None, W: torch.Tensor | None = None, ws=None):
+    """G = X^T (X Omega_col) / n (returned as the paper-form [p, p] tensor) and
+    optionally W = X Omega_col ([n, p])."""
+    n, p = X.shape
+    dev = X.device
+    if G is None:
+        G = torch.empty((p, p), dtype=torch.float32, device=dev)
+    if want_W and W is None:
+        W = torch.empty((n, p), dtype=torch.float32, device=dev)
+    ws = _workspace(n, p, None, dev, ws)
+    _check(lib().accord_grad(_dev(X, "X"), n, p, _dev(Omega, "Omega"),
+                             _dev(W, "W") if W is not None else None, _dev(G, "G"),
+                             ws.data_ptr(), ws.numel(), _stream(dev)))
+    return G, W
+
+
+def accord_prox(Omega: torch.Tensor, G: torch.Tensor, tau: float, lam: float, *,
+                out: torch.Tensor | None = None, red: torch.Tensor | None = None, ws=None):
+    """One eq.-3.5 step; returns (Omega_out, red[6] float64 device tensor)."""
+    p = Omega.shape[0]
+    dev = Omega.device
+    if out is None:
+        out = torch.empty_like(Omega)
+    if red is None:
+        red = torch.empty(6, dtype=torch.float64, device=dev)
+    ws = _workspace(1, p, None, dev, ws)
+    _check(lib().accord_prox(_dev(Omega, "Omega"), _dev(G, "G"), p, float(tau), float(lam),
+                             _dev(out, "Omega_out"), _dev(red, "red", torch.float64),
+                             ws.data_ptr(), ws.numel(), _stream(dev)))
+    return out, red
+
+
+def accord_objective(X: torch.Tensor, Omega: torch.Tensor, lam: float, *, out=None, ws=None):
+    """(g, h, f) at Omega as a float64 device tensor of length 3."""
+    n, p = X.shape
+    dev = X.device
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=dev)
+    ws = _workspace(n, p, None, dev, ws)
+    _check(lib().accord_objective(_dev(X, "X"), n, p, _dev(Omega, "Omega"), float(lam),
+                                  _dev(out, "out", torch.float64), ws.data_ptr(), ws.numel(),
+                                  _stream(dev)))
+    return out
+
+
+def accord_fit(X: torch.Tensor, lam: float, max_iter: int, *, omega0: torch.Tensor | None = None,
+               tau0: float = 1.0, beta: float = 0.5, lipschitz: float = 0.0, tol: float = 0.0,
+               check_every: int = 10, power_iters: int = 0, precision: str = "fp32",
+               trace: bool = False, timing: bool = False, ws=None, omega_out=None):
+    """ACCORD-FBS (Alg. 1).  Returns (Omega [p, p] paper form, stats dict, trace or None).
+    omega0 defaults to the identity."""
+    n, p = X.shape
+    dev = X.device
+    prm = default_params(lam=lam, max_iter=max_iter, tau0=tau0, beta=beta, lipschitz=lipschitz,
+                         tol=tol, check_every=check_every, power_iters=power_iters,
+                         precision=precision, timing=1 if timing else 0)
+    if omega_out is None:
+        omega_out = torch.empty((p, p), dtype=torch.float32, device=dev)
+    if omega0 is None:
+        omega_out.zero_()
+        omega_out.diagonal().fill_(1.0)
+    else:
+        omega_out.copy_(omega0)
+    tr = torch.zeros(((max_iter + 1) * TRACE_COLS,), dtype=torch.float64, device=dev) if trace else None
+    ws = _workspace(n, p, prm, dev, ws)
+    st = accord_stats()
+    _check(lib().accord_fit(_dev(X, "X"), n, p, _dev(omega_out, "Omega"), ctypes.byref(prm),
+                            ctypes.byref(st), _dev(tr, "trace", torch.float64) if tr is not None else None,
+                            ws.data_ptr(), ws.numel(), _stream(dev)))
+    stats = st.as_dict()
+    if tr is not None:
+        tr = tr.view(max_iter + 1, TRACE_COLS)[: stats["iters"] + 1]
+    return omega_out, stats, tr

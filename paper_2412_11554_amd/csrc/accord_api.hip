@@ -1,0 +1,581 @@
+// Host side of the libaccord C ABI (declared in include/accord.h).
+//
+// Every entry point validates its arguments on the host before enqueuing work,
+// carves the caller's workspace into the padded operand buffers, and enqueues
+// the kernels of accord_kernels.hip on the caller's stream.
+//
+// accord_fit runs Alg. 1 with the backtracking loop predicated on the device:
+// per iteration the host enqueues the gradient GEMM and then, for each step in
+// tau0, beta tau0, ... down to the first one at or below 1/L (the floor at which
+// Alg. 1 always accepts), a prox / trial-GEMM / acceptance triple.  Once a trial
+// is accepted, the remaining triples of that iteration return immediately, so
+// the host never waits for the device inside the loop.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/accord.h"
+#include "accord_internal.h"
+
+using namespace accord;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int status, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(ACCORD_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                        __FILE__, __LINE__);                                               \
+    } while (0)
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// ---------------------------------------------------------------------------
+// workspace layout (byte offsets, each region 256-byte aligned).  Regions are
+// ordered so each entry point needs a prefix: prox < grad/objective < fit.
+// ---------------------------------------------------------------------------
+struct Plan {
+    int64_t n, p, n_pad, p_pad;
+    // trial GEMM  (C = W^T:  M = n_pad, N = p, K = p_pad)
+    int t_tilesM, t_tilesN, t_splits, t_ksteps;
+    // gradient GEMM  (C = G:  M = p_pad, N = p, K = n_pad)
+    int g_tilesM, g_tilesN, g_ksteps;
+    int nprox;
+    size_t off_ls, off_prox_part, off_norm_part, off_pow_u, off_pow_w, off_pow_pu, off_pow_pw,
+        off_trials, off_xp, off_xt, off_wt0, off_wt1, off_split, off_om0, end_grad, off_g,
+        off_d, off_om1, end_fit;
+    size_t end_prox;
+};
+
+size_t bump(size_t& cur, size_t bytes) {
+    size_t at = cur;
+    cur = (size_t)round_up((int64_t)(cur + bytes), 256);
+    return at;
+}
+
+int choose_splits(int tiles, int ksteps) {
+    // pick S minimising (rounds of kSlots resident workgroups) / S; keep >= 4 K steps
+    int best = 1;
+    double best_cost = (double)cdiv(tiles, kSlots);
+    for (int s = 2; s <= 8; ++s) {
+        if (ksteps / s < 4) break;
+        const double cost = (double)cdiv((int64_t)tiles * s, kSlots) / s;
+        if (cost < best_cost * 0.9) {
+            best = s;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
+Plan make_plan(int64_t n, int64_t p, int32_t max_iter) {
+    Plan P = {};
+    P.n = n;
+    P.p = p;
+    P.n_pad = round_up(n, kPad);
+    P.p_pad = round_up(p, kPad);
+    P.t_tilesM = (int)cdiv(P.n_pad, kBM);
+    P.t_tilesN = (int)cdiv(p, kBN);
+    P.t_ksteps = (int)(P.p_pad / kBK);
+    P.t_splits = choose_splits(P.t_tilesM * P.t_tilesN, P.t_ksteps);
+    P.g_tilesM = (int)cdiv(P.p_pad, kBM);
+    P.g_tilesN = (int)cdiv(p, kBN);
+    P.g_ksteps = (int)(P.n_pad / kBK);
+    P.nprox = prox_blocks(p * P.p_pad);
+    const int ttiles = P.t_tilesM * P.t_tilesN;
+    size_t cur = 0;
+    P.off_ls = bump(cur, sizeof(LsState));
+    P.off_prox_part = bump(cur, (size_t)kMaxProxBlocks * kPartCols * sizeof(double));
+    P.end_prox = cur;
+    P.off_norm_part = bump(cur, (size_t)ttiles * kNormCols * sizeof(double));
+    P.off_pow_u = bump(cur, (size_t)P.n_pad * sizeof(double));
+    P.off_pow_w = bump(cur, (size_t)P.p_pad * sizeof(double));
+    P.off_pow_pu = bump(cur, (size_t)cdiv(n, kThreads / 64) * sizeof(double));
+    P.off_pow_pw = bump(cur, (size_t)cdiv(p, kThreads / 64) * sizeof(double));
+    P.off_trials = bump(cur, (size_t)(max_iter > 0 ? max_iter : 1) * sizeof(int32_t));
+    P.off_xp = bump(cur, (size_t)(P.n_pad * P.p_pad) * sizeof(float));
+    P.off_xt = bump(cur, (size_t)(P.p_pad * P.n_pad) * sizeof(float));
+    P.off_wt0 = bump(cur, (size_t)(p * P.n_pad) * sizeof(float));
+    P.off_wt1 = bump(cur, (size_t)(p * P.n_pad) * sizeof(float));
+    P.off_split = bump(cur, P.t_splits > 1 ? (size_t)P.t_splits * ttiles * kBM * kBN * sizeof(float)
+                                           : 0);
+    P.off_om0 = bump(cur, (size_t)(p * P.p_pad) * sizeof(float));
+    P.end_grad = cur;
+    P.off_g = bump(cur, (size_t)(p * P.p_pad) * sizeof(float));
+    P.off_d = bump(cur, (size_t)(p * P.p_pad) * sizeof(float));
+    P.off_om1 = bump(cur, (size_t)(p * P.p_pad) * sizeof(float));
+    P.end_fit = cur;
+    return P;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+    return (T*)((char*)ws + off);
+}
+
+// trial GEMM: Wt_out = Wt_prev + (X B)^T  with B = p columns (ld p_pad), W^T layout p x n_pad
+GemmArgs trial_args(const Plan& P, void* ws, const float* B, const float* Wprev, float* Wout,
+                    LsState* ls, int pred) {
+    GemmArgs a = {};
+    a.A = at<float>(ws, P.off_xp);
+    a.B = B;
+    a.lda = P.p_pad;
+    a.ldb = P.p_pad;
+    a.M = (int)P.n_pad;
+    a.N = (int)P.p;
+    a.ksteps = P.t_ksteps;
+    a.tilesM = P.t_tilesM;
+    a.tilesN = P.t_tilesN;
+    a.splits = P.t_splits;
+    a.C = Wout;
+    a.ldc = P.n_pad;
+    a.vec_store = 1;
+    a.alpha = 1.f;
+    a.Wprev = Wprev;
+    a.P = P.t_splits > 1 ? at<float>(ws, P.off_split) : nullptr;
+    a.norm_part = at<double>(ws, P.off_norm_part);
+    a.ls = ls;
+    a.pred = pred;
+    a.Mvalid = (int)P.n;
+    a.Nvalid = (int)P.p;
+    return a;
+}
+
+void enqueue_trial(const GemmArgs& a, hipStream_t st) {
+    if (a.splits > 1) {
+        launch_gemm(a, EPI_PARTIAL, st);
+        launch_splitk_reduce(a, st);
+    } else {
+        launch_gemm(a, EPI_TRIAL, st);
+    }
+}
+
+// gradient GEMM: C = Xt * Wt^T / n  (M = p_pad or p rows of C, N = p)
+GemmArgs grad_args(const Plan& P, void* ws, const float* Wt, float* C, int64_t ldc, int M,
+                   LsState* ls) {
+    GemmArgs a = {};
+    a.A = at<float>(ws, P.off_xt);
+    a.B = Wt;
+    a.lda = P.n_pad;
+    a.ldb = P.n_pad;
+    a.M = M;
+    a.N = (int)P.p;
+    a.ksteps = P.g_ksteps;
+    a.tilesM = (int)cdiv(M, kBM);
+    a.tilesN = P.g_tilesN;
+    a.splits = 1;
+    a.C = C;
+    a.ldc = ldc;
+    a.vec_store = (ldc % 4 == 0) && aligned(C, 16);
+    a.alpha = (float)(1.0 / (double)P.n);
+    a.ls = ls;
+    a.pred = ls ? 1 : 0;
+    a.begin_iter = ls ? 1 : 0;
+    return a;
+}
+
+int check_dims(int64_t n, int64_t p) {
+    if (n < 1 || p < 1) return fail(ACCORD_ERR_INVALID_ARG, "n and p must be >= 1 (n=%lld p=%lld)",
+                                    (long long)n, (long long)p);
+    // GEMM tile indices and row counts are 32-bit
+    if (n > (1LL << 24) || p > (1LL << 24))
+        return fail(ACCORD_ERR_INVALID_ARG, "n or p too large (n=%lld p=%lld)", (long long)n,
+                    (long long)p);
+    return ACCORD_OK;
+}
+
+int check_ws(void* ws, size_t ws_bytes, size_t need) {
+    if (!ws) return fail(ACCORD_ERR_WORKSPACE, "workspace pointer is null");
+    if (!aligned(ws, 256)) return fail(ACCORD_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(ACCORD_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return ACCORD_OK;
+}
+
+int check_ptr(const void* p, const char* name) {
+    if (!p) return fail(ACCORD_ERR_INVALID_ARG, "%s is null", name);
+    if (!aligned(p, 16)) return fail(ACCORD_ERR_INVALID_ARG, "%s must be 16-byte aligned", name);
+    return ACCORD_OK;
+}
+
+#define TRY(expr)                    \
+    do {                             \
+        int s_ = (expr);             \
+        if (s_ != ACCORD_OK) return s_; \
+    } while (0)
+
+int check_params(const accord_params* prm) {
+    if (!prm) return fail(ACCORD_ERR_INVALID_ARG, "params is null");
+    if (!(prm->lambda >= 0.0) || !isfinite(prm->lambda))
+        return fail(ACCORD_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+    if (!(prm->tau0 > 0.0) || !isfinite(prm->tau0))
+        return fail(ACCORD_ERR_INVALID_ARG, "tau0 must be finite and > 0");
+    if (!(prm->beta > 0.0 && prm->beta <= 1.0))
+        return fail(ACCORD_ERR_INVALID_ARG, "beta must lie in (0, 1]");
+    if (!(prm->lipschitz >= 0.0) || !isfinite(prm->lipschitz))
+        return fail(ACCORD_ERR_INVALID_ARG, "lipschitz must be finite and >= 0");
+    if (!(prm->tol >= 0.0) || !isfinite(prm->tol))
+        return fail(ACCORD_ERR_INVALID_ARG, "tol must be finite and >= 0");
+    if (prm->max_iter < 0) return fail(ACCORD_ERR_INVALID_ARG, "max_iter must be >= 0");
+    if (prm->precision != ACCORD_FP32)
+        return fail(ACCORD_ERR_UNSUPPORTED, "precision form %d is not available", prm->precision);
+    if (prm->tol > 0.0 && prm->check_every < 1)
+        return fail(ACCORD_ERR_INVALID_ARG, "check_every must be >= 1 when tol > 0");
+    if (prm->power_iters < 0) return fail(ACCORD_ERR_INVALID_ARG, "power_iters must be >= 0");
+    return ACCORD_OK;
+}
+
+// number of trials Alg. 1 can need: tau0, beta*tau0, ... up to the first tau <= 1/L,
+// evaluated with the same double arithmetic as the device (tau *= beta).
+int max_trials(double tau0, double beta, double inv_L) {
+    if (beta >= 1.0) return 1;
+    int k = 1;
+    double tau = tau0;
+    while (!(tau <= inv_L) && k < 200) {
+        tau *= beta;
+        ++k;
+    }
+    return k;
+}
+
+// HIP event pool for per-kernel timing
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    hipEvent_t get() {
+        if (used == ev.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ev.push_back(e);
+        }
+        return ev[used++];
+    }
+    ~EventPool() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+void accord_default_params(accord_params* prm) {
+    if (!prm) return;
+    memset(prm, 0, sizeof *prm);
+    prm->lambda = 0.1;
+    prm->tau0 = 1.0;
+    prm->beta = 0.5;
+    prm->lipschitz = 0.0;
+    prm->tol = 0.0;
+    prm->max_iter = 100;
+    prm->precision = ACCORD_FP32;
+    prm->check_every = 10;
+    prm->power_iters = 200;
+    prm->timing = 0;
+}
+
+size_t accord_workspace_bytes(int64_t n, int64_t p, const accord_params* prm) {
+    if (n < 1 || p < 1 || n > (1LL << 24) || p > (1LL << 24)) return 0;
+    accord_params d;
+    if (!prm) {
+        accord_default_params(&d);
+        prm = &d;
+    }
+    return make_plan(n, p, prm->max_iter).end_fit;
+}
+
+const char* accord_status_str(int s) {
+    switch (s) {
+        case ACCORD_OK: return "ok";
+        case ACCORD_ERR_INVALID_ARG: return "invalid argument";
+        case ACCORD_ERR_DOMAIN: return "diagonal of Omega must be positive";
+        case ACCORD_ERR_NONFINITE: return "non-finite value";
+        case ACCORD_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+        case ACCORD_ERR_UNSUPPORTED: return "unsupported";
+        case ACCORD_ERR_HIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+const char* accord_last_error(void) { return g_last_error.c_str(); }
+
+int accord_prox(const float* Omega, const float* G, int64_t p, double tau, double lambda,
+                float* Omega_out, double* red, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    TRY(check_dims(1, p));
+    TRY(check_ptr(Omega, "Omega"));
+    TRY(check_ptr(G, "G"));
+    TRY(check_ptr(Omega_out, "Omega_out"));
+    if (!red || !aligned(red, 8)) return fail(ACCORD_ERR_INVALID_ARG, "red must be non-null, 8-byte aligned");
+    if (Omega_out == Omega || Omega_out == G)
+        return fail(ACCORD_ERR_INVALID_ARG, "Omega_out must not alias Omega or G");
+    if (!(tau > 0.0) || !isfinite(tau)) return fail(ACCORD_ERR_INVALID_ARG, "tau must be finite and > 0");
+    if (!(lambda >= 0.0) || !isfinite(lambda))
+        return fail(ACCORD_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+    const Plan P = make_plan(1, p, 1);
+    TRY(check_ws(ws, ws_bytes, P.end_prox));
+    hipStream_t st = (hipStream_t)stream;
+    ProxArgs a = {};
+    a.om = Omega;
+    a.g = G;
+    a.om_new = Omega_out;
+    a.d = nullptr;
+    a.total = p * p;
+    a.ld = p;
+    a.p = p;
+    a.tau = tau;
+    a.lambda = lambda;
+    a.part = at<double>(ws, P.off_prox_part);
+    const int nb = prox_blocks(a.total);
+    launch_prox(a, nb, st);
+    launch_combine_prox(a.part, nb, red, st);
+    HIP_TRY(hipGetLastError());
+    return ACCORD_OK;
+}
+
+// shared by accord_grad and accord_objective: X -> padded copies, Omega -> Om0,
+// Wt0 = (X Omega)^T with norm partials
+static int enqueue_w(const Plan& P, const float* X, const float* Omega, void* ws, hipStream_t st) {
+    LsState* ls = at<LsState>(ws, P.off_ls);
+    launch_init_state(ls, 1.0, 0.5, 0.0, 0.0, 1.0 / (double)P.n, 0.0, 0, st);
+    launch_pad_x(X, P.n, P.p, at<float>(ws, P.off_xp), P.p_pad, at<float>(ws, P.off_xt), P.n_pad,
+                 ls, st);
+    float* om0 = at<float>(ws, P.off_om0);
+    launch_copy_cols(Omega, P.p, om0, P.p_pad, P.p, P.p_pad, nullptr, st);
+    GemmArgs t = trial_args(P, ws, om0, nullptr, at<float>(ws, P.off_wt0), nullptr, 0);
+    enqueue_trial(t, st);
+    return ACCORD_OK;
+}
+
+int accord_grad(const float* X, int64_t n, int64_t p, const float* Omega, float* W, float* G,
+                void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    TRY(check_dims(n, p));
+    TRY(check_ptr(X, "X"));
+    TRY(check_ptr(Omega, "Omega"));
+    TRY(check_ptr(G, "G"));
+    if (W) TRY(check_ptr(W, "W"));
+    const Plan P = make_plan(n, p, 1);
+    TRY(check_ws(ws, ws_bytes, P.end_grad));
+    hipStream_t st = (hipStream_t)stream;
+    TRY(enqueue_w(P, X, Omega, ws, st));
+    const float* wt = at<float>(ws, P.off_wt0);
+    if (W) launch_transpose_w(wt, P.n_pad, n, p, W, st);
+    GemmArgs g = grad_args(P, ws, wt, G, p, (int)p, nullptr);
+    launch_gemm(g, EPI_GRAD, st);
+    HIP_TRY(hipGetLastError());
+    return ACCORD_OK;
+}
+
+int accord_objective(const float* X, int64_t n, int64_t p, const float* Omega, double lambda,
+                     double* out, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    TRY(check_dims(n, p));
+    TRY(check_ptr(X, "X"));
+    TRY(check_ptr(Omega, "Omega"));
+    if (!out || !aligned(out, 8)) return fail(ACCORD_ERR_INVALID_ARG, "out must be non-null, 8-byte aligned");
+    if (!(lambda >= 0.0) || !isfinite(lambda))
+        return fail(ACCORD_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+    const Plan P = make_plan(n, p, 1);
+    TRY(check_ws(ws, ws_bytes, P.end_grad));
+    hipStream_t st = (hipStream_t)stream;
+    TRY(enqueue_w(P, X, Omega, ws, st));
+    ProxArgs a = {};
+    a.om = at<float>(ws, P.off_om0);
+    a.total = p * P.p_pad;
+    a.ld = P.p_pad;
+    a.p = p;
+    a.part = at<double>(ws, P.off_prox_part);
+    a.reduce_only = 1;
+    const int nb = prox_blocks(a.total);
+    launch_prox(a, nb, st);
+    launch_combine_objective(a.part, nb, at<double>(ws, P.off_norm_part),
+                             P.t_tilesM * P.t_tilesN, lambda, 1.0 / (double)n, out, st);
+    HIP_TRY(hipGetLastError());
+    return ACCORD_OK;
+}
+
+int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_params* prm,
+               accord_stats* stats, double* trace, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    TRY(check_dims(n, p));
+    TRY(check_ptr(X, "X"));
+    TRY(check_ptr(Omega, "Omega"));
+    TRY(check_params(prm));
+    if (trace && !aligned(trace, 8)) return fail(ACCORD_ERR_INVALID_ARG, "trace must be 8-byte aligned");
+    const Plan P = make_plan(n, p, prm->max_iter);
+    TRY(check_ws(ws, ws_bytes, P.end_fit));
+    if (stats) memset(stats, 0, sizeof *stats);
+    hipStream_t st = (hipStream_t)stream;
+    const bool timing = prm->timing != 0;
+    EventPool pool;
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+    if (timing) {
+        ev_begin = pool.get();
+        ev_end = pool.get();
+        HIP_TRY(hipEventRecord(ev_begin, st));
+    }
+
+    LsState* ls = at<LsState>(ws, P.off_ls);
+    float* xp = at<float>(ws, P.off_xp);
+    float* xt = at<float>(ws, P.off_xt);
+    float* om[2] = {at<float>(ws, P.off_om0), at<float>(ws, P.off_om1)};
+    float* wt[2] = {at<float>(ws, P.off_wt0), at<float>(ws, P.off_wt1)};
+    float* G = at<float>(ws, P.off_g);
+    float* D = at<float>(ws, P.off_d);
+    double* prox_part = at<double>(ws, P.off_prox_part);
+    double* norm_part = at<double>(ws, P.off_norm_part);
+    int32_t* trials_log = at<int32_t>(ws, P.off_trials);
+    const int ttiles = P.t_tilesM * P.t_tilesN;
+    const int64_t total = p * P.p_pad;
+
+    // ---- setup: operands, L, W0 = X Omega0, f(Omega0)
+    launch_init_state(ls, prm->tau0, prm->beta, prm->lambda, prm->tol, 1.0 / (double)n,
+                      prm->lipschitz, prm->max_iter, st);
+    launch_pad_x(X, n, p, xp, P.p_pad, xt, P.n_pad, ls, st);
+    launch_copy_cols(Omega, p, om[0], P.p_pad, p, P.p_pad, ls, st);
+    if (prm->lipschitz <= 0.0) {
+        launch_power_iteration(xp, P.p_pad, xt, P.n_pad, n, p, at<double>(ws, P.off_pow_w),
+                               at<double>(ws, P.off_pow_u), at<double>(ws, P.off_pow_pu),
+                               at<double>(ws, P.off_pow_pw),
+                               prm->power_iters > 0 ? prm->power_iters : 200, ls, st);
+    }
+    enqueue_trial(trial_args(P, ws, om[0], nullptr, wt[0], nullptr, 0), st);
+    {
+        ProxArgs a = {};
+        a.om = om[0];
+        a.total = total;
+        a.ld = P.p_pad;
+        a.p = p;
+        a.part = prox_part;
+        a.reduce_only = 1;
+        launch_prox(a, P.nprox, st);
+    }
+    launch_fit_init(ls, prox_part, P.nprox, norm_part, ttiles, trace, st);
+    HIP_TRY(hipGetLastError());
+    LsState host = {};
+    HIP_TRY(hipMemcpyAsync(&host, ls, sizeof host, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (host.bad & 2) return fail(ACCORD_ERR_NONFINITE, "non-finite value in X or Omega0");
+    if (host.bad & 1) return fail(ACCORD_ERR_DOMAIN, "Omega0 has a non-positive diagonal entry");
+    if (!(host.L > 0.0) || !isfinite(host.L))
+        return fail(ACCORD_ERR_NONFINITE, "Lipschitz estimate is not positive (L=%g)", host.L);
+    const int ntr = max_trials(prm->tau0, prm->beta, host.inv_L);
+
+    // ---- Alg. 1
+    struct Launch { hipEvent_t a, b; int iter, trial; };
+    std::vector<Launch> ev_grad, ev_trial, ev_prox;
+    int cur = 0;
+    for (int t = 0; t < prm->max_iter; ++t) {
+        if (prm->tol > 0.0 && t > 0 && t % prm->check_every == 0) {
+            int32_t conv = 0;
+            HIP_TRY(hipMemcpyAsync(&conv, &ls->converged, sizeof conv, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (conv) break;
+        }
+        const int nxt = cur ^ 1;
+        GemmArgs ga = grad_args(P, ws, wt[cur], G, P.p_pad, (int)P.p_pad, ls);
+        Launch lg = {nullptr, nullptr, t, 0};
+        if (timing) { lg.a = pool.get(); lg.b = pool.get(); HIP_TRY(hipEventRecord(lg.a, st)); }
+        launch_gemm(ga, EPI_GRAD, st);
+        if (timing) { HIP_TRY(hipEventRecord(lg.b, st)); ev_grad.push_back(lg); }
+        for (int k = 0; k < ntr; ++k) {
+            ProxArgs a = {};
+            a.om = om[cur];
+            a.g = G;
+            a.om_new = om[nxt];
+            a.d = D;
+            a.total = total;
+            a.ld = P.p_pad;
+            a.p = p;
+            a.ls = ls;
+            a.part = prox_part;
+            Launch lp = {nullptr, nullptr, t, k};
+            if (timing) { lp.a = pool.get(); lp.b = pool.get(); HIP_TRY(hipEventRecord(lp.a, st)); }
+            launch_prox(a, P.nprox, st);
+            if (timing) { HIP_TRY(hipEventRecord(lp.b, st)); ev_prox.push_back(lp); }
+            Launch lt = {nullptr, nullptr, t, k};
+            if (timing) { lt.a = pool.get(); lt.b = pool.get(); HIP_TRY(hipEventRecord(lt.a, st)); }
+            enqueue_trial(trial_args(P, ws, D, wt[cur], wt[nxt], ls, 2), st);
+            if (timing) { HIP_TRY(hipEventRecord(lt.b, st)); ev_trial.push_back(lt); }
+            launch_finalize(ls, prox_part, P.nprox, norm_part, ttiles, trace, trials_log, st);
+        }
+        HIP_TRY(hipGetLastError());
+        cur = nxt;
+    }
+    if (timing) HIP_TRY(hipEventRecord(ev_end, st));
+    HIP_TRY(hipMemcpyAsync(&host, ls, sizeof host, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+
+    // the current iterate sits in om[iter % 2]: buffers alternate once per accepted
+    // iteration, and iterations after a stop did no work
+    const int res = host.iter & 1;
+    launch_copy_cols(om[res], P.p_pad, Omega, p, p, p, nullptr, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+
+    if (stats) {
+        stats->iters = host.iter;
+        stats->trials = host.total_trials;
+        stats->floor_accepts = host.floor_accepts;
+        stats->converged = (prm->tol > 0.0 && host.iter < prm->max_iter && host.converged &&
+                            !host.bad) ? 1 : 0;
+        stats->nnz_offdiag = host.nnz_off;
+        stats->f = host.f_cur;
+        stats->g = host.g_cur;
+        stats->h = host.h_cur;
+        stats->tau_last = host.tau_acc;
+        stats->delta_fro = host.delta_fro;
+        stats->lipschitz = host.L;
+        if (timing) {
+            std::vector<int32_t> tl((size_t)(host.iter > 0 ? host.iter : 1), 0);
+            if (host.iter > 0)
+                HIP_TRY(hipMemcpy(tl.data(), trials_log, sizeof(int32_t) * host.iter,
+                                  hipMemcpyDeviceToHost));
+            float ms = 0.f;
+            for (const Launch& l : ev_grad) {
+                if (l.iter >= host.iter) continue;
+                HIP_TRY(hipEventElapsedTime(&ms, l.a, l.b));
+                stats->grad_gemm_ms += ms;
+                stats->grad_gemm_launches += 1;
+            }
+            for (const Launch& l : ev_trial) {
+                if (l.iter >= host.iter || l.trial >= tl[l.iter]) continue;
+                HIP_TRY(hipEventElapsedTime(&ms, l.a, l.b));
+                stats->trial_gemm_ms += ms;
+                stats->trial_gemm_launches += 1;
+            }
+            for (const Launch& l : ev_prox) {
+                if (l.iter >= host.iter || l.trial >= tl[l.iter]) continue;
+                HIP_TRY(hipEventElapsedTime(&ms, l.a, l.b));
+                stats->prox_ms += ms;
+                stats->prox_launches += 1;
+            }
+            HIP_TRY(hipEventElapsedTime(&ms, ev_begin, ev_end));
+            stats->total_ms = ms;
+        }
+    }
+    if (host.bad & 2) return fail(ACCORD_ERR_NONFINITE, "non-finite value in an iterate");
+    if (host.bad & 1) return fail(ACCORD_ERR_DOMAIN, "non-positive diagonal in an iterate");
+    return ACCORD_OK;
+}
+
+}  // extern "C"

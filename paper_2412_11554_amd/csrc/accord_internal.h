@@ -1,0 +1,122 @@
+// Internal declarations shared by the kernel and host translation units of
+// libaccord (gfx950).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace accord {
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+constexpr int kPad = 32;            // K-dimension padding of every MFMA operand
+constexpr int kBM = 128;            // GEMM workgroup tile (rows of C)
+constexpr int kBN = 128;            // GEMM workgroup tile (columns of C)
+constexpr int kBK = 32;             // GEMM K step staged through LDS
+constexpr int kThreads = 256;       // threads per workgroup for every kernel
+constexpr int kMaxProxBlocks = 4096;
+constexpr int kPartCols = 8;        // FP64 partial sums per prox workgroup
+constexpr int kNormCols = 2;        // FP64 partial sums per trial-GEMM tile
+constexpr int kPowBlocksMax = 4096; // power-iteration partial sums
+constexpr int kSlots = 512;         // resident GEMM workgroups assumed by the split-K choice
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// prox partial columns
+enum { P_D2 = 0, P_DG = 1, P_L1 = 2, P_LOGD = 3, P_NNZ = 4, P_FRO = 5 };
+
+// ---------------------------------------------------------------------------
+// device-resident iteration state of accord_fit (one per workspace)
+// ---------------------------------------------------------------------------
+struct LsState {
+    double tau;        // step of the trial in flight
+    double inv_L;      // step floor 1/L
+    double L;
+    double tau0, beta, lambda, tol, inv_n;
+    double g_cur, h_cur, f_cur;  // objective pieces at the current iterate
+    double delta_fro;            // ||Delta||_F of the last accepted step
+    double tau_acc;              // accepted step of the last iteration
+    double pow_scale;            // power iteration: 1 / ||w||
+    double pow_rayleigh;         // power iteration: Rayleigh quotient of the last vector
+    int64_t nnz_off;
+    int32_t done;       // current iteration accepted a trial: later trials are skipped
+    int32_t converged;  // stop: every later launch is skipped
+    int32_t trials;     // trials of the current iteration
+    int32_t iter;       // accepted iterations
+    int32_t total_trials;
+    int32_t floor_accepts;
+    int32_t bad;        // bit 0: diagonal <= 0, bit 1: non-finite value
+    int32_t max_iter;
+    int32_t fixed_step; // beta == 1: the single trial is accepted
+    int32_t pad_;
+};
+
+// ---------------------------------------------------------------------------
+// kernel argument blocks
+// ---------------------------------------------------------------------------
+enum GemmEpi { EPI_GRAD = 0, EPI_TRIAL = 1, EPI_PARTIAL = 2 };
+
+struct GemmArgs {
+    const float* A;     // M x K row-major (lda), K = ksteps * kBK, zero-padded
+    const float* B;     // N x K row-major (ldb)
+    int64_t lda, ldb;
+    int M, N;           // rows of A / rows of B; C is M x N column-major
+    int ksteps;
+    int tilesM, tilesN, splits;
+    float* C;           // C[m + n*ldc]
+    int64_t ldc;
+    int vec_store;      // ldc % 4 == 0 and C 16-byte aligned
+    float alpha;        // EPI_GRAD scale
+    const float* Wprev; // EPI_TRIAL: C += Wprev (same layout), may be null
+    float* P;           // EPI_PARTIAL: split partial tiles
+    double* norm_part;  // EPI_TRIAL: per tile {||V||^2, ||C||^2}
+    LsState* ls;        // predication state (null = always run)
+    int pred;           // 1: skip if converged; 2: skip if done or converged
+    int begin_iter;     // reset the line-search state of a new iteration
+    int Mvalid, Nvalid; // extent counted in the norms
+};
+
+struct ProxArgs {
+    const float* om;
+    const float* g;
+    float* om_new;      // may be null in reduce-only mode
+    float* d;           // Delta output (same layout), may be null
+    int64_t total;      // elements = p * ld
+    int64_t ld;         // rows stored per column (>= p)
+    int64_t p;
+    int64_t step_col, step_row;  // advance of (col,row) per 4*kThreads elements
+    double tau, lambda; // used when ls == null
+    const LsState* ls;  // if set: tau/lambda from here; skip if done or converged
+    double* part;       // [gridDim.x][kPartCols]
+    int reduce_only;    // 1: no writes, statistics of om itself
+};
+
+// ---------------------------------------------------------------------------
+// launchers (accord_kernels.hip)
+// ---------------------------------------------------------------------------
+void launch_init_state(LsState* ls, double tau0, double beta, double lambda, double tol,
+                       double inv_n, double L, int max_iter, hipStream_t st);
+void launch_pad_x(const float* X, int64_t n, int64_t p, float* Xp, int64_t p_pad, float* Xt,
+                  int64_t n_pad, LsState* ls, hipStream_t st);
+void launch_copy_cols(const float* src, int64_t ld_src, float* dst, int64_t ld_dst, int64_t p,
+                      int64_t rows, LsState* check_ls, hipStream_t st);
+void launch_gemm(const GemmArgs& a, int epi, hipStream_t st);
+void launch_splitk_reduce(const GemmArgs& a, hipStream_t st);
+int prox_blocks(int64_t total);
+void launch_prox(ProxArgs a, int nblocks, hipStream_t st);
+void launch_finalize(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
+                     int ntiles, double* trace, int32_t* trials_log, hipStream_t st);
+void launch_fit_init(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
+                     int ntiles, double* trace, hipStream_t st);
+void launch_combine_prox(const double* prox_part, int nprox, double* red, hipStream_t st);
+void launch_combine_objective(const double* prox_part, int nprox, const double* norm_part,
+                              int ntiles, double lambda, double inv_n, double* out, hipStream_t st);
+void launch_transpose_w(const float* Wt, int64_t ldt, int64_t n, int64_t p, float* W,
+                        hipStream_t st);
+void launch_power_iteration(const float* Xp, int64_t p_pad, const float* Xt, int64_t n_pad,
+                            int64_t n, int64_t p, double* w, double* u, double* part_u,
+                            double* part_w, int steps, LsState* ls, hipStream_t st);
+
+}  // namespace accord

@@ -1,0 +1,122 @@
+"""Host-side tests of the C ABI (no GPU needed): the library loads, exports every
+function include/accord.h declares, its structs match the ctypes mirrors, and
+argument validation returns the documented status before touching the device."""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+from paper_2412_11554_amd import accord
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(accord.LIB_PATH):
+        pytest.skip("libaccord.so not built")
+    return accord.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = accord.header_functions()
+    assert {"accord_fit", "accord_grad", "accord_prox", "accord_objective",
+            "accord_workspace_bytes", "accord_status_str", "accord_last_error"} <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", accord.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    for n in names:
+        assert n in exported, n
+        assert hasattr(L, n)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "accord.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(accord_params), sizeof(accord_stats),"
+        " offsetof(accord_stats, grad_gemm_ms), offsetof(accord_stats, total_ms),"
+        " offsetof(accord_params, timing)); return 0;}\n")
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(accord.accord_params)
+    assert vals[1] == ctypes.sizeof(accord.accord_stats)
+    assert vals[2] == accord.accord_stats.grad_gemm_ms.offset
+    assert vals[3] == accord.accord_stats.total_ms.offset
+    assert vals[4] == accord.accord_params.timing.offset
+
+
+def test_default_params(L):
+    prm = accord.default_params()
+    assert prm.lambda_ == 0.1 and prm.tau0 == 1.0 and prm.beta == 0.5
+    assert prm.lipschitz == 0.0 and prm.max_iter == 100 and prm.check_every == 10
+
+
+def test_status_strings(L):
+    for s in range(7):
+        assert L.accord_status_str(s)
+    assert L.accord_status_str(99) == b"unknown status"
+
+
+def test_workspace_bytes(L):
+    assert accord.accord_workspace_bytes(0, 10) == 0
+    assert accord.accord_workspace_bytes(10, 0) == 0
+    small = accord.accord_workspace_bytes(100, 200)
+    big = accord.accord_workspace_bytes(500, 5000)
+    assert 0 < small < big
+    # at least the four p x p_pad FP32 matrices of the iteration
+    p_pad = 5024
+    assert big >= 4 * 5000 * p_pad * 4
+    # fits one 288 GB device at the largest single-GPU problem (n=1000, p=100000)
+    assert accord.accord_workspace_bytes(1000, 100000) < 200e9
+
+
+FAKE = 1 << 20  # a 16-byte aligned non-null address; validation fails before any use
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(X=None), 1), (dict(n=0), 1), (dict(p=0), 1), (dict(Omega=None), 1),
+    (dict(X=FAKE + 4), 1), (dict(ws=None), 4), (dict(ws=FAKE + 16), 4), (dict(ws_bytes=10), 4),
+    (dict(lam=-1.0), 1), (dict(tau0=0.0), 1), (dict(beta=0.0), 1), (dict(beta=1.5), 1),
+    (dict(max_iter=-1), 1), (dict(precision=7), 5), (dict(tol=1e-6, check_every=0), 1),
+    (dict(lipschitz=-2.0), 1), (dict(lam=float("nan")), 1),
+])
+def test_fit_validation(L, kw, status):
+    args = dict(X=FAKE, n=10, p=12, Omega=FAKE, ws=FAKE, ws_bytes=1 << 40, lam=0.1, tau0=1.0,
+                beta=0.5, max_iter=3, precision=0, tol=0.0, check_every=10, lipschitz=0.0)
+    args.update(kw)
+    prm = accord.default_params(lam=args["lam"], tau0=args["tau0"], beta=args["beta"],
+                                max_iter=args["max_iter"], precision=args["precision"],
+                                tol=args["tol"], check_every=args["check_every"],
+                                lipschitz=args["lipschitz"])
+    st = accord.accord_stats()
+    r = L.accord_fit(args["X"], args["n"], args["p"], args["Omega"], ctypes.byref(prm),
+                     ctypes.byref(st), None, args["ws"], args["ws_bytes"], None)
+    assert r == status, L.accord_last_error()
+    assert L.accord_last_error()
+
+
+def test_prox_validation(L):
+    r = L.accord_prox(FAKE, FAKE, 10, 0.0, 0.1, FAKE + 256, FAKE + 512, FAKE, 1 << 30, None)
+    assert r == 1  # tau must be > 0
+    r = L.accord_prox(FAKE, FAKE, 10, 0.5, 0.1, FAKE, FAKE + 512, FAKE, 1 << 30, None)
+    assert r == 1  # output aliases input
+    r = L.accord_prox(FAKE, FAKE, 10, 0.5, 0.1, FAKE + 256, FAKE + 512, FAKE, 16, None)
+    assert r == 4  # workspace too small
+
+
+def test_grad_objective_validation(L):
+    assert L.accord_grad(FAKE, 0, 5, FAKE, None, FAKE, FAKE, 1 << 30, None) == 1
+    assert L.accord_grad(FAKE, 5, 5, FAKE, None, None, FAKE, 1 << 30, None) == 1
+    assert L.accord_objective(FAKE, 5, 5, FAKE, -0.1, FAKE, FAKE, 1 << 30, None) == 1
+    assert L.accord_objective(FAKE, 5, 5, FAKE, 0.1, None, FAKE, 1 << 30, None) == 1
+    assert L.accord_objective(FAKE, 5, 5, FAKE, 0.1, FAKE, FAKE, 8, None) == 4
+
+
+def test_binding_rejects_host_tensors(L):
+    import torch
+    with pytest.raises(TypeError):
+        accord.accord_fit(torch.zeros(4, 5), 0.1, 2)

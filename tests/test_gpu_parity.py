@@ -1,0 +1,331 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances follow from FP32 arithmetic (unit roundoff u = 2^-24):
+  prox off-diagonal: one fused multiply-add and one subtraction in FP32, plus the
+    FP32 rounding of tau and tau*lambda -> |err| <= 4u (|Omega| + tau|G| + tau*lambda);
+  prox diagonal: evaluated in FP64 from the same inputs, rounded once -> <= 1 ulp (FP32);
+  GEMMs: FP32 products accumulated over K terms -> |err| <= K u (|A||B|) elementwise;
+  fits: relative Frobenius error <= 1e-4 against the oracle replaying the GPU's
+    accepted step sizes (the tolerance the FP32 form is specified to meet).
+Where a float decides a discrete outcome (zero / nonzero, accept / reject), the
+outcome is compared only where the oracle's margin exceeds the float error.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+
+def _col(t):
+    """torch [p, p] paper-form tensor -> column-form float64 numpy matrix"""
+    return t.detach().cpu().numpy().astype(np.float64).T
+
+
+def _paper(om_col):
+    return np.ascontiguousarray(om_col.T, dtype=np.float32)
+
+
+def _sparse_omega(p, seed, density=0.05):
+    rng = np.random.default_rng(seed)
+    om = rng.normal(0, 0.1, size=(p, p)) * (rng.random((p, p)) < density)
+    om[np.diag_indices(p)] = rng.uniform(0.5, 1.5, size=p)
+    return om
+
+
+@pytest.fixture(scope="module")
+def dev(gpu_lib):
+    import torch
+    return torch.device("cuda:0")
+
+
+# ---------------------------------------------------------------------------- prox
+@pytest.mark.parametrize("p,tau,lam", [(333, 0.37, 0.2), (64, 1.0, 0.0), (1, 0.5, 0.3),
+                                       (1000, 0.03125, 0.05)])
+def test_prox_elementwise(gpu_lib, dev, p, tau, lam):
+    import torch
+    print(f"prox p={p} tau={tau} lam={lam}", flush=True)
+    acc = gpu_lib
+    rng = np.random.default_rng(p)
+    om_col = _sparse_omega(p, p, 0.3)
+    g_col = rng.normal(0, 0.5, size=(p, p))
+    # some exact ties |a| == tau*lam are not representable; include exact zeros instead
+    om32 = om_col.astype(np.float32).astype(np.float64)
+    g32 = g_col.astype(np.float32).astype(np.float64)
+    out, red = acc.accord_prox(_t(_paper(om32), dev), _t(_paper(g32), dev), tau, lam)
+    torch.cuda.synchronize()
+    got = _col(out)
+    ref = oracle.prox(om32, g32, tau, lam)
+    off = ~np.eye(p, dtype=bool)
+    bound = 4 * U32 * (np.abs(om32) + tau * np.abs(g32) + tau * lam) + 1e-30
+    assert np.all(np.abs(got - ref)[off] <= bound[off])
+    # zero pattern wherever the threshold margin exceeds the error
+    a = om32 - tau * g32
+    safe = off & (np.abs(np.abs(a) - tau * lam) > bound)
+    assert np.array_equal((got != 0)[safe], (ref != 0)[safe])
+    d = np.diag_indices(p)
+    assert np.all(np.abs(got[d] - ref[d]) <= np.spacing(np.abs(ref[d]).astype(np.float32)))
+    assert np.all(got[d] > 0)
+    # reductions: FP64 sums of the GPU's own FP32 outputs (Delta rounded in FP32)
+    r = red.cpu().numpy()
+    dl = (got.astype(np.float32) - om32.astype(np.float32)).astype(np.float64)
+    expect = [np.sum(dl * dl), np.sum(dl * g32), np.sum(np.abs(got)), np.sum(np.log(got[d])),
+              np.count_nonzero(got[off]), np.sum(got * got)]
+    for k in range(6):
+        assert np.isclose(r[k], expect[k], rtol=1e-12, atol=1e-300), (k, r[k], expect[k])
+
+
+def test_prox_matches_oracle_reductions(gpu_lib, dev):
+    import torch
+    p, tau, lam = 257, 0.25, 0.1
+    om = _sparse_omega(p, 3, 0.2).astype(np.float32).astype(np.float64)
+    g = np.random.default_rng(4).normal(0, 0.3, (p, p)).astype(np.float32).astype(np.float64)
+    _, red = gpu_lib.accord_prox(_t(_paper(om), dev), _t(_paper(g), dev), tau, lam)
+    torch.cuda.synchronize()
+    ref = oracle.prox(om, g, tau, lam)
+    dl = ref - om
+    r = red.cpu().numpy()
+    assert np.isclose(r[0], np.sum(dl * dl), rtol=1e-5)
+    assert np.isclose(r[2], np.sum(np.abs(ref)), rtol=1e-6)
+    assert np.isclose(r[3], np.sum(np.log(np.diag(ref))), rtol=1e-6, atol=1e-6)
+
+
+# ---------------------------------------------------------------------------- grad / objective
+@pytest.mark.parametrize("n,p", [(77, 333), (100, 200), (1, 5), (33, 1), (500, 640)])
+def test_grad_parity(gpu_lib, dev, n, p):
+    import torch
+    print(f"grad n={n} p={p}", flush=True)
+    w = datagen.small_random_problem(n, p, seed=n + p)
+    x = w.X.astype(np.float64)
+    om = _sparse_omega(p, 5).astype(np.float32).astype(np.float64)
+    G, W = gpu_lib.accord_grad(_t(w.X, dev), _t(_paper(om), dev), want_W=True)
+    torch.cuda.synchronize()
+    W_ref = x @ om
+    W_bound = p * U32 * (np.abs(x) @ np.abs(om)) + 1e-30
+    assert np.all(np.abs(W.cpu().numpy() - W_ref) <= W_bound)
+    G_ref = oracle.grad(x, om)
+    G_bound = (n + p) * U32 * (np.abs(x).T @ (np.abs(x) @ np.abs(om))) / n + 1e-30
+    got = _col(G)
+    assert np.all(np.abs(got - G_ref) <= G_bound)
+    assert np.linalg.norm(got - G_ref) <= 1e-5 * np.linalg.norm(G_ref)
+
+
+def test_grad_full_size_sampled_columns(gpu_lib, dev):
+    """n=500, p=5000 (the benchmarked shape), sampled columns against FP64."""
+    import torch
+    w = datagen.workload("ba5000")
+    x = w.X.astype(np.float64)
+    p = w.p
+    om = _sparse_omega(p, 11, 0.01).astype(np.float32)
+    G, _ = gpu_lib.accord_grad(_t(w.X, dev), _t(_paper(om), dev))
+    torch.cuda.synchronize()
+    cols = np.array([0, 1, 127, 128, 2500, 4991, 4998, 4999])
+    om64 = om.astype(np.float64)
+    ref = x.T @ (x @ om64[:, cols]) / w.n
+    got = G.cpu().numpy()[cols, :].astype(np.float64).T     # columns of the column form
+    bound = (w.n + p) * U32 * (np.abs(x).T @ (np.abs(x) @ np.abs(om64[:, cols]))) / w.n
+    assert np.all(np.abs(got - ref) <= bound)
+
+
+@pytest.mark.parametrize("n,p,lam", [(77, 333, 0.1), (20, 3, 0.0)])
+def test_objective_parity(gpu_lib, dev, n, p, lam):
+    import torch
+    w = datagen.small_random_problem(n, p, seed=7)
+    x = w.X.astype(np.float64)
+    om = _sparse_omega(p, 9).astype(np.float32).astype(np.float64)
+    out = gpu_lib.accord_objective(_t(w.X, dev), _t(_paper(om), dev), lam)
+    torch.cuda.synchronize()
+    g, h, f = oracle.objective(x, om, lam)
+    r = out.cpu().numpy()
+    assert np.isclose(r[0], g, rtol=2 * p * U32)
+    assert np.isclose(r[1], h, rtol=1e-12, atol=1e-12)
+    assert np.isclose(r[2], f, rtol=2 * p * U32)
+
+
+def test_objective_outside_domain_is_inf(gpu_lib, dev):
+    import torch
+    w = datagen.small_random_problem(10, 6, seed=1)
+    om = np.eye(6)
+    om[2, 2] = 0.0
+    out = gpu_lib.accord_objective(_t(w.X, dev), _t(_paper(om), dev), 0.1)
+    torch.cuda.synchronize()
+    assert np.isinf(out.cpu().numpy()[1]) and out.cpu().numpy()[1] > 0
+
+
+# ---------------------------------------------------------------------------- fits
+def _fit_and_replay(gpu_lib, dev, x32, lam, iters, L, **kw):
+    import torch
+    om, stats, tr = gpu_lib.accord_fit(_t(x32, dev), lam, iters, lipschitz=L, trace=True, **kw)
+    torch.cuda.synchronize()
+    tr = tr.cpu().numpy()
+    taus = tr[1:, 3]
+    omega0 = kw.get("omega0")
+    ref = oracle.fit_fbs(x32.astype(np.float64), lam, len(taus), L=L, tau_replay=taus,
+                         omega0=None if omega0 is None else _col(omega0))
+    return _col(om), stats, tr, ref
+
+
+@pytest.mark.parametrize("name", ["er200"])
+def test_fit_small_workload_parity(gpu_lib, dev, name):
+    """n=100, p=200 Erdos-Renyi workload, 200 iterations: step sequence and iterates."""
+    w = datagen.workload(name)
+    x = w.X.astype(np.float64)
+    L = oracle.lipschitz(x)
+    got, stats, tr, ref = _fit_and_replay(gpu_lib, dev, w.X, w.lam, w.iters, L)
+    assert stats["iters"] == w.iters
+    rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
+    assert rel <= 1e-4, rel
+    assert np.allclose(tr[:, 0], ref.f, rtol=1e-5)
+    # the oracle's own step decisions agree with the GPU's until a near-tie
+    own = oracle.fit_fbs(x, w.lam, w.iters, L=L)
+    taus = tr[1:, 3]
+    mism = np.nonzero(~np.isclose(taus, own.tau))[0]
+    if mism.size:
+        t0 = mism[0]
+        om_t = oracle.fit_fbs(x, w.lam, t0, L=L).omega
+        G = oracle.grad(x, om_t)
+        tau = max(taus[t0], own.tau[t0])
+        d = oracle.prox(om_t, G, tau, w.lam) - om_t
+        lhs = np.sum((x @ d) ** 2) / w.n
+        rhs = np.sum(d * d) / tau
+        assert abs(lhs - rhs) <= 1e-4 * rhs, (t0, lhs, rhs)
+    # trace invariants: monotone objective, tau = tau0 beta^(k-1), floor respected
+    assert np.all(np.diff(tr[:, 0]) <= 1e-6 * np.abs(tr[1:, 0]))
+    assert np.allclose(tr[1:, 3], 0.5 ** (tr[1:, 4] - 1))
+    assert np.all(tr[1:, 3] >= 0.5 / L * (1 - 1e-12))
+
+
+def test_fit_benchmark_shape_sampled_columns(gpu_lib, dev):
+    """n=500, p=5000 block power-law workload, 500 iterations, L by power iteration
+    (the benchmarked configuration); the oracle replays the GPU's steps on sampled
+    columns (columns evolve independently once the steps are fixed)."""
+    import torch
+    w = datagen.workload("ba5000")
+    x = w.X.astype(np.float64)
+    om, stats, tr = gpu_lib.accord_fit(_t(w.X, dev), w.lam, w.iters, trace=True)
+    torch.cuda.synchronize()
+    tr = tr.cpu().numpy()
+    assert stats["iters"] == w.iters
+    L = oracle.lipschitz(x)
+    assert abs(stats["lipschitz"] - L) <= 1e-6 * L
+    cols = np.array([0, 1, 499, 500, 2047, 2048, 3333, 4990, 4998, 4999])
+    ref = oracle.fit_fbs(x, w.lam, w.iters, L=stats["lipschitz"], tau_replay=tr[1:, 3],
+                         columns=cols)
+    got = om.cpu().numpy()[cols, :].astype(np.float64).T
+    rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
+    assert rel <= 1e-4, rel
+    assert np.all(np.diff(tr[:, 0]) <= 1e-6 * np.abs(tr[1:, 0]))
+    assert np.all(tr[1:, 4] >= 1)
+
+
+@pytest.mark.parametrize("n,p,lam,iters", [(33, 97, 0.1, 40), (3, 1, 0.2, 10), (1, 2, 0.1, 5),
+                                           (130, 129, 0.05, 25)])
+def test_fit_ragged_shapes(gpu_lib, dev, n, p, lam, iters):
+    print(f"fit n={n} p={p}", flush=True)
+    rng = np.random.default_rng(n * 1000 + p)
+    x32 = rng.normal(size=(n, p)).astype(np.float32)
+    x = x32.astype(np.float64)
+    L = max(oracle.lipschitz(x), 1e-3)
+    got, stats, tr, ref = _fit_and_replay(gpu_lib, dev, x32, lam, iters, L)
+    assert stats["iters"] == iters
+    rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
+    assert rel <= 1e-4, rel
+
+
+def test_fit_fixed_step_and_start_point(gpu_lib, dev):
+    import torch
+    w = datagen.small_random_problem(60, 90, seed=3)
+    x = w.X.astype(np.float64)
+    L = oracle.lipschitz(x)
+    om0 = _sparse_omega(90, 21, 0.05).astype(np.float32)
+    got, stats, tr, ref = _fit_and_replay(gpu_lib, dev, w.X, 0.1, 30, L, tau0=1.0 / L, beta=1.0,
+                                          omega0=_t(_paper(om0.astype(np.float64)), dev))
+    assert stats["trials"] == 30 and stats["floor_accepts"] == 0
+    own = oracle.fit_fbs(x, 0.1, 30, L=L, tau0=1.0 / L, beta=1.0, omega0=om0.astype(np.float64))
+    assert np.allclose(tr[1:, 3], own.tau)
+    rel = np.linalg.norm(got - own.omega) / np.linalg.norm(own.omega)
+    assert rel <= 1e-4
+    del torch
+
+
+def test_fit_converges_to_kkt_point(gpu_lib, dev):
+    """tol-based stop: the result satisfies eq. 3.3 to FP32 accuracy and matches the
+    oracle's converged estimate and support."""
+    import torch
+    w = datagen.small_random_problem(40, 60, seed=8)
+    x = w.X.astype(np.float64)
+    lam = 0.15
+    om, stats, _ = gpu_lib.accord_fit(_t(w.X, dev), lam, 5000, tol=1e-7, check_every=20,
+                                      lipschitz=oracle.lipschitz(x))
+    torch.cuda.synchronize()
+    assert stats["converged"] == 1 and stats["iters"] < 5000
+    got = _col(om)
+    ref = oracle.fit_fbs(x, lam, 50000, tol=1e-15).omega
+    assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+    G = oracle.grad(x, ref)
+    margin = lam - np.abs(G)
+    off = ~np.eye(60, dtype=bool)
+    safe = off & ((ref != 0) | (margin > 1e-4))
+    assert np.array_equal((got != 0)[safe], (ref != 0)[safe])
+
+
+def test_fit_large_lambda_diagonal(gpu_lib, dev):
+    import torch
+    w = datagen.small_random_problem(30, 50, seed=2)
+    x = w.X.astype(np.float64)
+    S = x.T @ x / 30
+    lam = 2.0
+    om, stats, _ = gpu_lib.accord_fit(_t(w.X, dev), lam, 2000, tol=1e-8, check_every=10)
+    torch.cuda.synchronize()
+    got = _col(om)
+    assert stats["nnz_offdiag"] == 0
+    assert np.count_nonzero(got - np.diag(np.diag(got))) == 0
+    d = (-lam + np.sqrt(lam ** 2 + 4 * np.diag(S))) / (2 * np.diag(S))
+    assert np.allclose(np.diag(got), d, rtol=1e-5)
+
+
+def test_fit_deterministic(gpu_lib, dev):
+    import torch
+    w = datagen.workload("er200")
+    X = _t(w.X, dev)
+    a, sa, ta = gpu_lib.accord_fit(X, w.lam, 50, trace=True)
+    b, sb, tb = gpu_lib.accord_fit(X, w.lam, 50, trace=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(ta, tb)
+    assert sa["f"] == sb["f"]
+
+
+def test_fit_errors(gpu_lib, dev):
+    import torch
+    w = datagen.small_random_problem(20, 30, seed=5)
+    X = _t(w.X, dev)
+    om0 = torch.eye(30, device=dev)
+    om0[4, 4] = 0.0
+    with pytest.raises(gpu_lib.AccordError) as e:
+        gpu_lib.accord_fit(X, 0.1, 5, omega0=om0)
+    assert e.value.status == 2
+    Xbad = X.clone()
+    Xbad[3, 7] = float("nan")
+    with pytest.raises(gpu_lib.AccordError) as e:
+        gpu_lib.accord_fit(Xbad, 0.1, 5)
+    assert e.value.status == 3
+
+
+def test_fit_zero_iterations_returns_start(gpu_lib, dev):
+    import torch
+    w = datagen.small_random_problem(20, 30, seed=6)
+    om, stats, tr = gpu_lib.accord_fit(_t(w.X, dev), 0.1, 0, trace=True)
+    torch.cuda.synchronize()
+    assert stats["iters"] == 0
+    assert torch.equal(om, torch.eye(30, device=dev))
+    assert np.isclose(tr.cpu().numpy()[0, 0],
+                      oracle.objective(w.X.astype(np.float64), np.eye(30), 0.1)[2], rtol=1e-6)
