@@ -60,8 +60,17 @@ typedef enum {
     ACCORD_ERR_HIP = 6           /* HIP runtime error (see accord_last_error) */
 } accord_status;
 
+/* Arithmetic of the two contractions X Delta and X^T W (a6 of the hot path).  The
+ * prox, the acceptance test, the objective sums and the diagonal root are the same in
+ * every form (FP32 iterate, FP64 sums and root); W = X Omega is carried in FP32. */
 typedef enum {
-    ACCORD_FP32 = 0     /* FP32 MFMA contractions, FP64 reductions and diagonal root */
+    ACCORD_FP32 = 0,    /* FP32 MFMA (v_mfma_f32_16x16x4f32) */
+    ACCORD_BF16X1 = 1,  /* bf16 MFMA on bf16(X), bf16(Delta), bf16(W); FP32 accumulation.
+                           About 3 significant digits: use for a first phase, then refine
+                           with ACCORD_BF16X3 from its result (Omega in/out). */
+    ACCORD_BF16X3 = 2   /* bf16 MFMA on the split x = hi + lo (hi = bf16(x), lo =
+                           bf16(x - hi)) of every operand: hi*hi + hi*lo + lo*hi, FP32
+                           accumulation; relative product error about 2^-16 */
 } accord_precision;
 
 /* Columns of the optional per-iteration trace (device double[(max_iter+1) * 8]).
@@ -90,7 +99,7 @@ typedef struct {
     int32_t max_iter;   /* iterations, >= 0 */
     int32_t precision;  /* accord_precision */
     int32_t check_every;/* with tol > 0: poll the stop flag every this many iterations (>= 1) */
-    int32_t power_iters;/* power-iteration steps when lipschitz == 0 (0 = 200) */
+    int32_t power_iters;/* power-iteration steps when lipschitz == 0 (0 = 400) */
     int32_t timing;     /* 1 = time every kernel launch with HIP events (fills the *_ms fields) */
     int32_t reserved[3];
 } accord_params;
@@ -114,7 +123,7 @@ typedef struct {
 } accord_stats;
 
 /* Fills `prm` with defaults: lambda 0.1, tau0 1, beta 0.5, lipschitz 0 (estimate),
- * tol 0, max_iter 100, FP32, check_every 10, power_iters 200, timing 0. */
+ * tol 0, max_iter 100, FP32, check_every 10, power_iters 400, timing 0. */
 void accord_default_params(accord_params* prm);
 
 /* Workspace bytes needed by accord_fit for an n x p problem with `prm` (NULL =

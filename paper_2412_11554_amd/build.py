@@ -22,6 +22,8 @@ HIPCC_FLAGS = [
     "-Wall",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep private arrays in registers: LDS is sized for the GEMM tiles
+    "-mllvm", "-disable-promote-alloca-to-lds",
 ]
 
 

@@ -54,14 +54,15 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // ---------------------------------------------------------------------------
 struct Plan {
     int64_t n, p, n_pad, p_pad;
+    int prec;
     // trial GEMM  (C = W^T:  M = n_pad, N = p, K = p_pad)
-    int t_tilesM, t_tilesN, t_splits, t_ksteps;
+    int t_tilesM, t_tilesN, t_splits;
     // gradient GEMM  (C = G:  M = p_pad, N = p, K = n_pad)
-    int g_tilesM, g_tilesN, g_ksteps;
+    int g_tilesM, g_tilesN;
     int nprox;
     size_t off_ls, off_prox_part, off_norm_part, off_pow_u, off_pow_w, off_pow_pu, off_pow_pw,
-        off_trials, off_xp, off_xt, off_wt0, off_wt1, off_split, off_om0, end_grad, off_g,
-        off_d, off_om1, end_fit;
+        off_trials, off_xp, off_xt, off_xsplit[4], off_wt0, off_wt1, off_wsplit[4], off_split,
+        off_om0, end_grad, off_g, off_d, off_dh, off_dl, off_om1, end_fit;
     size_t end_prox;
 };
 
@@ -71,12 +72,12 @@ size_t bump(size_t& cur, size_t bytes) {
     return at;
 }
 
-int choose_splits(int tiles, int ksteps) {
-    // pick S minimising (rounds of kSlots resident workgroups) / S; keep >= 4 K steps
+int choose_splits(int tiles, int ksteps64) {
+    // pick S minimising (rounds of kSlots resident workgroups) / S; keep >= 2 steps of 64
     int best = 1;
     double best_cost = (double)cdiv(tiles, kSlots);
     for (int s = 2; s <= 8; ++s) {
-        if (ksteps / s < 4) break;
+        if (ksteps64 / s < 2) break;
         const double cost = (double)cdiv((int64_t)tiles * s, kSlots) / s;
         if (cost < best_cost * 0.9) {
             best = s;
@@ -86,21 +87,24 @@ int choose_splits(int tiles, int ksteps) {
     return best;
 }
 
-Plan make_plan(int64_t n, int64_t p, int32_t max_iter) {
+Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     Plan P = {};
     P.n = n;
     P.p = p;
+    P.prec = prec;
     P.n_pad = round_up(n, kPad);
     P.p_pad = round_up(p, kPad);
     P.t_tilesM = (int)cdiv(P.n_pad, kBM);
     P.t_tilesN = (int)cdiv(p, kBN);
-    P.t_ksteps = (int)(P.p_pad / kBK);
-    P.t_splits = choose_splits(P.t_tilesM * P.t_tilesN, P.t_ksteps);
+    P.t_splits = choose_splits(P.t_tilesM * P.t_tilesN, (int)(P.p_pad / kPad));
     P.g_tilesM = (int)cdiv(P.p_pad, kBM);
     P.g_tilesN = (int)cdiv(p, kBN);
-    P.g_ksteps = (int)(P.n_pad / kBK);
     P.nprox = prox_blocks(p * P.p_pad);
+    const bool bf = prec != PREC_FP32;
     const int ttiles = P.t_tilesM * P.t_tilesN;
+    const size_t xn = (size_t)(P.n_pad * P.p_pad);   // padded X elements
+    const size_t wn = (size_t)(p * P.n_pad);         // W^T elements
+    const size_t on = (size_t)(p * P.p_pad);         // p x p_pad elements
     size_t cur = 0;
     P.off_ls = bump(cur, sizeof(LsState));
     P.off_prox_part = bump(cur, (size_t)kMaxProxBlocks * kPartCols * sizeof(double));
@@ -111,17 +115,21 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter) {
     P.off_pow_pu = bump(cur, (size_t)cdiv(n, kThreads / 64) * sizeof(double));
     P.off_pow_pw = bump(cur, (size_t)cdiv(p, kThreads / 64) * sizeof(double));
     P.off_trials = bump(cur, (size_t)(max_iter > 0 ? max_iter : 1) * sizeof(int32_t));
-    P.off_xp = bump(cur, (size_t)(P.n_pad * P.p_pad) * sizeof(float));
-    P.off_xt = bump(cur, (size_t)(P.p_pad * P.n_pad) * sizeof(float));
-    P.off_wt0 = bump(cur, (size_t)(p * P.n_pad) * sizeof(float));
-    P.off_wt1 = bump(cur, (size_t)(p * P.n_pad) * sizeof(float));
+    P.off_xp = bump(cur, xn * sizeof(float));
+    P.off_xt = bump(cur, xn * sizeof(float));
+    for (int k = 0; k < 4; ++k) P.off_xsplit[k] = bump(cur, bf ? xn * sizeof(uint16_t) : 0);
+    P.off_wt0 = bump(cur, wn * sizeof(float));
+    P.off_wt1 = bump(cur, wn * sizeof(float));
+    for (int k = 0; k < 4; ++k) P.off_wsplit[k] = bump(cur, bf ? wn * sizeof(uint16_t) : 0);
     P.off_split = bump(cur, P.t_splits > 1 ? (size_t)P.t_splits * ttiles * kBM * kBN * sizeof(float)
                                            : 0);
-    P.off_om0 = bump(cur, (size_t)(p * P.p_pad) * sizeof(float));
+    P.off_om0 = bump(cur, on * sizeof(float));
     P.end_grad = cur;
-    P.off_g = bump(cur, (size_t)(p * P.p_pad) * sizeof(float));
-    P.off_d = bump(cur, (size_t)(p * P.p_pad) * sizeof(float));
-    P.off_om1 = bump(cur, (size_t)(p * P.p_pad) * sizeof(float));
+    P.off_g = bump(cur, on * sizeof(float));
+    P.off_d = bump(cur, bf ? 0 : on * sizeof(float));
+    P.off_dh = bump(cur, bf ? on * sizeof(uint16_t) : 0);
+    P.off_dl = bump(cur, prec == PREC_BF16X3 ? on * sizeof(uint16_t) : 0);
+    P.off_om1 = bump(cur, on * sizeof(float));
     P.end_fit = cur;
     return P;
 }
@@ -131,21 +139,34 @@ T* at(void* ws, size_t off) {
     return (T*)((char*)ws + off);
 }
 
-// trial GEMM: Wt_out = Wt_prev + (X B)^T  with B = p columns (ld p_pad), W^T layout p x n_pad
-GemmArgs trial_args(const Plan& P, void* ws, const float* B, const float* Wprev, float* Wout,
-                    LsState* ls, int pred) {
+// trial GEMM: Wt_out = Wt_prev + (X B)^T, W^T layout p x n_pad.  prec selects the
+// operands: FP32 (Xp, B32) or bf16 splits (Xp hi/lo, Bh/Bl).  wslot >= 0 also writes
+// the bf16 split of the result into W split slot wslot.
+GemmArgs trial_args(const Plan& P, void* ws, int prec, const float* B32, const uint16_t* Bh,
+                    const uint16_t* Bl, const float* Wprev, float* Wout, int wslot, LsState* ls,
+                    int pred) {
     GemmArgs a = {};
     a.A = at<float>(ws, P.off_xp);
-    a.B = B;
+    a.B = B32;
+    if (prec != PREC_FP32) {
+        a.Ah = at<uint16_t>(ws, P.off_xsplit[0]);
+        a.Al = at<uint16_t>(ws, P.off_xsplit[1]);
+        a.Bh = Bh;
+        a.Bl = Bl;
+    }
     a.lda = P.p_pad;
     a.ldb = P.p_pad;
     a.M = (int)P.n_pad;
     a.N = (int)P.p;
-    a.ksteps = P.t_ksteps;
+    a.K = (int)P.p_pad;
     a.tilesM = P.t_tilesM;
     a.tilesN = P.t_tilesN;
     a.splits = P.t_splits;
     a.C = Wout;
+    if (wslot >= 0) {
+        a.Ch = at<uint16_t>(ws, P.off_wsplit[2 * wslot]);
+        a.Cl = at<uint16_t>(ws, P.off_wsplit[2 * wslot + 1]);
+    }
     a.ldc = P.n_pad;
     a.vec_store = 1;
     a.alpha = 1.f;
@@ -159,26 +180,33 @@ GemmArgs trial_args(const Plan& P, void* ws, const float* B, const float* Wprev,
     return a;
 }
 
-void enqueue_trial(const GemmArgs& a, hipStream_t st) {
+void enqueue_trial(const GemmArgs& a, int prec, hipStream_t st) {
     if (a.splits > 1) {
-        launch_gemm(a, EPI_PARTIAL, st);
+        launch_gemm(a, EPI_PARTIAL, prec, st);
         launch_splitk_reduce(a, st);
     } else {
-        launch_gemm(a, EPI_TRIAL, st);
+        launch_gemm(a, EPI_TRIAL, prec, st);
     }
 }
 
-// gradient GEMM: C = Xt * Wt^T / n  (M = p_pad or p rows of C, N = p)
-GemmArgs grad_args(const Plan& P, void* ws, const float* Wt, float* C, int64_t ldc, int M,
-                   LsState* ls) {
+// gradient GEMM: C = Xt * Wt^T / n  (M = p_pad or p rows of C, N = p); bf16 forms
+// read the split of W^T from slot wslot
+GemmArgs grad_args(const Plan& P, void* ws, int prec, const float* Wt, int wslot, float* C,
+                   int64_t ldc, int M, LsState* ls) {
     GemmArgs a = {};
     a.A = at<float>(ws, P.off_xt);
     a.B = Wt;
+    if (prec != PREC_FP32) {
+        a.Ah = at<uint16_t>(ws, P.off_xsplit[2]);
+        a.Al = at<uint16_t>(ws, P.off_xsplit[3]);
+        a.Bh = at<uint16_t>(ws, P.off_wsplit[2 * wslot]);
+        a.Bl = at<uint16_t>(ws, P.off_wsplit[2 * wslot + 1]);
+    }
     a.lda = P.n_pad;
     a.ldb = P.n_pad;
     a.M = M;
     a.N = (int)P.p;
-    a.ksteps = P.g_ksteps;
+    a.K = (int)P.n_pad;
     a.tilesM = (int)cdiv(M, kBM);
     a.tilesN = P.g_tilesN;
     a.splits = 1;
@@ -190,6 +218,17 @@ GemmArgs grad_args(const Plan& P, void* ws, const float* Wt, float* C, int64_t l
     a.pred = ls ? 1 : 0;
     a.begin_iter = ls ? 1 : 0;
     return a;
+}
+
+XSplit x_split(const Plan& P, void* ws) {
+    XSplit sp = {};
+    if (P.prec != PREC_FP32) {
+        sp.xp_h = at<uint16_t>(ws, P.off_xsplit[0]);
+        sp.xp_l = at<uint16_t>(ws, P.off_xsplit[1]);
+        sp.xt_h = at<uint16_t>(ws, P.off_xsplit[2]);
+        sp.xt_l = at<uint16_t>(ws, P.off_xsplit[3]);
+    }
+    return sp;
 }
 
 int check_dims(int64_t n, int64_t p) {
@@ -235,7 +274,8 @@ int check_params(const accord_params* prm) {
     if (!(prm->tol >= 0.0) || !isfinite(prm->tol))
         return fail(ACCORD_ERR_INVALID_ARG, "tol must be finite and >= 0");
     if (prm->max_iter < 0) return fail(ACCORD_ERR_INVALID_ARG, "max_iter must be >= 0");
-    if (prm->precision != ACCORD_FP32)
+    if (prm->precision != ACCORD_FP32 && prm->precision != ACCORD_BF16X1 &&
+        prm->precision != ACCORD_BF16X3)
         return fail(ACCORD_ERR_UNSUPPORTED, "precision form %d is not available", prm->precision);
     if (prm->tol > 0.0 && prm->check_every < 1)
         return fail(ACCORD_ERR_INVALID_ARG, "check_every must be >= 1 when tol > 0");
@@ -288,7 +328,7 @@ void accord_default_params(accord_params* prm) {
     prm->max_iter = 100;
     prm->precision = ACCORD_FP32;
     prm->check_every = 10;
-    prm->power_iters = 200;
+    prm->power_iters = 400;
     prm->timing = 0;
 }
 
@@ -299,7 +339,7 @@ size_t accord_workspace_bytes(int64_t n, int64_t p, const accord_params* prm) {
         accord_default_params(&d);
         prm = &d;
     }
-    return make_plan(n, p, prm->max_iter).end_fit;
+    return make_plan(n, p, prm->max_iter, prm->precision).end_fit;
 }
 
 const char* accord_status_str(int s) {
@@ -330,7 +370,7 @@ int accord_prox(const float* Omega, const float* G, int64_t p, double tau, doubl
     if (!(tau > 0.0) || !isfinite(tau)) return fail(ACCORD_ERR_INVALID_ARG, "tau must be finite and > 0");
     if (!(lambda >= 0.0) || !isfinite(lambda))
         return fail(ACCORD_ERR_INVALID_ARG, "lambda must be finite and >= 0");
-    const Plan P = make_plan(1, p, 1);
+    const Plan P = make_plan(1, p, 1, PREC_FP32);
     TRY(check_ws(ws, ws_bytes, P.end_prox));
     hipStream_t st = (hipStream_t)stream;
     ProxArgs a = {};
@@ -357,11 +397,12 @@ static int enqueue_w(const Plan& P, const float* X, const float* Omega, void* ws
     LsState* ls = at<LsState>(ws, P.off_ls);
     launch_init_state(ls, 1.0, 0.5, 0.0, 0.0, 1.0 / (double)P.n, 0.0, 0, st);
     launch_pad_x(X, P.n, P.p, at<float>(ws, P.off_xp), P.p_pad, at<float>(ws, P.off_xt), P.n_pad,
-                 ls, st);
+                 x_split(P, ws), ls, st);
     float* om0 = at<float>(ws, P.off_om0);
     launch_copy_cols(Omega, P.p, om0, P.p_pad, P.p, P.p_pad, nullptr, st);
-    GemmArgs t = trial_args(P, ws, om0, nullptr, at<float>(ws, P.off_wt0), nullptr, 0);
-    enqueue_trial(t, st);
+    GemmArgs t = trial_args(P, ws, PREC_FP32, om0, nullptr, nullptr, nullptr,
+                            at<float>(ws, P.off_wt0), -1, nullptr, 0);
+    enqueue_trial(t, PREC_FP32, st);
     return ACCORD_OK;
 }
 
@@ -373,14 +414,14 @@ int accord_grad(const float* X, int64_t n, int64_t p, const float* Omega, float*
     TRY(check_ptr(Omega, "Omega"));
     TRY(check_ptr(G, "G"));
     if (W) TRY(check_ptr(W, "W"));
-    const Plan P = make_plan(n, p, 1);
+    const Plan P = make_plan(n, p, 1, PREC_FP32);
     TRY(check_ws(ws, ws_bytes, P.end_grad));
     hipStream_t st = (hipStream_t)stream;
     TRY(enqueue_w(P, X, Omega, ws, st));
     const float* wt = at<float>(ws, P.off_wt0);
     if (W) launch_transpose_w(wt, P.n_pad, n, p, W, st);
-    GemmArgs g = grad_args(P, ws, wt, G, p, (int)p, nullptr);
-    launch_gemm(g, EPI_GRAD, st);
+    GemmArgs g = grad_args(P, ws, PREC_FP32, wt, 0, G, p, (int)p, nullptr);
+    launch_gemm(g, EPI_GRAD, PREC_FP32, st);
     HIP_TRY(hipGetLastError());
     return ACCORD_OK;
 }
@@ -394,7 +435,7 @@ int accord_objective(const float* X, int64_t n, int64_t p, const float* Omega, d
     if (!out || !aligned(out, 8)) return fail(ACCORD_ERR_INVALID_ARG, "out must be non-null, 8-byte aligned");
     if (!(lambda >= 0.0) || !isfinite(lambda))
         return fail(ACCORD_ERR_INVALID_ARG, "lambda must be finite and >= 0");
-    const Plan P = make_plan(n, p, 1);
+    const Plan P = make_plan(n, p, 1, PREC_FP32);
     TRY(check_ws(ws, ws_bytes, P.end_grad));
     hipStream_t st = (hipStream_t)stream;
     TRY(enqueue_w(P, X, Omega, ws, st));
@@ -421,7 +462,7 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
     TRY(check_ptr(Omega, "Omega"));
     TRY(check_params(prm));
     if (trace && !aligned(trace, 8)) return fail(ACCORD_ERR_INVALID_ARG, "trace must be 8-byte aligned");
-    const Plan P = make_plan(n, p, prm->max_iter);
+    const Plan P = make_plan(n, p, prm->max_iter, prm->precision);
     TRY(check_ws(ws, ws_bytes, P.end_fit));
     if (stats) memset(stats, 0, sizeof *stats);
     hipStream_t st = (hipStream_t)stream;
@@ -440,7 +481,11 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
     float* om[2] = {at<float>(ws, P.off_om0), at<float>(ws, P.off_om1)};
     float* wt[2] = {at<float>(ws, P.off_wt0), at<float>(ws, P.off_wt1)};
     float* G = at<float>(ws, P.off_g);
-    float* D = at<float>(ws, P.off_d);
+    const int prec = prm->precision;
+    const bool bf = prec != PREC_FP32;
+    float* D = bf ? nullptr : at<float>(ws, P.off_d);
+    uint16_t* Dh = bf ? at<uint16_t>(ws, P.off_dh) : nullptr;
+    uint16_t* Dl = prec == PREC_BF16X3 ? at<uint16_t>(ws, P.off_dl) : nullptr;
     double* prox_part = at<double>(ws, P.off_prox_part);
     double* norm_part = at<double>(ws, P.off_norm_part);
     int32_t* trials_log = at<int32_t>(ws, P.off_trials);
@@ -450,15 +495,18 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
     // ---- setup: operands, L, W0 = X Omega0, f(Omega0)
     launch_init_state(ls, prm->tau0, prm->beta, prm->lambda, prm->tol, 1.0 / (double)n,
                       prm->lipschitz, prm->max_iter, st);
-    launch_pad_x(X, n, p, xp, P.p_pad, xt, P.n_pad, ls, st);
+    launch_pad_x(X, n, p, xp, P.p_pad, xt, P.n_pad, x_split(P, ws), ls, st);
     launch_copy_cols(Omega, p, om[0], P.p_pad, p, P.p_pad, ls, st);
     if (prm->lipschitz <= 0.0) {
         launch_power_iteration(xp, P.p_pad, xt, P.n_pad, n, p, at<double>(ws, P.off_pow_w),
                                at<double>(ws, P.off_pow_u), at<double>(ws, P.off_pow_pu),
                                at<double>(ws, P.off_pow_pw),
-                               prm->power_iters > 0 ? prm->power_iters : 200, ls, st);
+                               prm->power_iters > 0 ? prm->power_iters : 400, ls, st);
     }
-    enqueue_trial(trial_args(P, ws, om[0], nullptr, wt[0], nullptr, 0), st);
+    // W0 = X Omega0 in FP32 (once), plus its bf16 split for the first gradient
+    enqueue_trial(trial_args(P, ws, PREC_FP32, om[0], nullptr, nullptr, nullptr, wt[0],
+                             bf ? 0 : -1, nullptr, 0),
+                  PREC_FP32, st);
     {
         ProxArgs a = {};
         a.om = om[0];
@@ -492,10 +540,10 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
             if (conv) break;
         }
         const int nxt = cur ^ 1;
-        GemmArgs ga = grad_args(P, ws, wt[cur], G, P.p_pad, (int)P.p_pad, ls);
+        GemmArgs ga = grad_args(P, ws, prec, wt[cur], cur, G, P.p_pad, (int)P.p_pad, ls);
         Launch lg = {nullptr, nullptr, t, 0};
         if (timing) { lg.a = pool.get(); lg.b = pool.get(); HIP_TRY(hipEventRecord(lg.a, st)); }
-        launch_gemm(ga, EPI_GRAD, st);
+        launch_gemm(ga, EPI_GRAD, prec, st);
         if (timing) { HIP_TRY(hipEventRecord(lg.b, st)); ev_grad.push_back(lg); }
         for (int k = 0; k < ntr; ++k) {
             ProxArgs a = {};
@@ -503,6 +551,8 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
             a.g = G;
             a.om_new = om[nxt];
             a.d = D;
+            a.dh = Dh;
+            a.dl = Dl;
             a.total = total;
             a.ld = P.p_pad;
             a.p = p;
@@ -514,7 +564,8 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
             if (timing) { HIP_TRY(hipEventRecord(lp.b, st)); ev_prox.push_back(lp); }
             Launch lt = {nullptr, nullptr, t, k};
             if (timing) { lt.a = pool.get(); lt.b = pool.get(); HIP_TRY(hipEventRecord(lt.a, st)); }
-            enqueue_trial(trial_args(P, ws, D, wt[cur], wt[nxt], ls, 2), st);
+            enqueue_trial(trial_args(P, ws, prec, D, Dh, Dl, wt[cur], wt[nxt], bf ? nxt : -1, ls, 2),
+                          prec, st);
             if (timing) { HIP_TRY(hipEventRecord(lt.b, st)); ev_trial.push_back(lt); }
             launch_finalize(ls, prox_part, P.nprox, norm_part, ttiles, trace, trials_log, st);
         }

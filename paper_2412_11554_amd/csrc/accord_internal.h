@@ -10,15 +10,14 @@ namespace accord {
 // ---------------------------------------------------------------------------
 // geometry
 // ---------------------------------------------------------------------------
-constexpr int kPad = 32;            // K-dimension padding of every MFMA operand
+constexpr int kPad = 64;            // K-dimension padding of every MFMA operand
 constexpr int kBM = 128;            // GEMM workgroup tile (rows of C)
 constexpr int kBN = 128;            // GEMM workgroup tile (columns of C)
-constexpr int kBK = 32;             // GEMM K step staged through LDS
+constexpr int kBK32 = 32;           // FP32 GEMM K step staged through LDS
 constexpr int kThreads = 256;       // threads per workgroup for every kernel
 constexpr int kMaxProxBlocks = 4096;
 constexpr int kPartCols = 8;        // FP64 partial sums per prox workgroup
 constexpr int kNormCols = 2;        // FP64 partial sums per trial-GEMM tile
-constexpr int kPowBlocksMax = 4096; // power-iteration partial sums
 constexpr int kSlots = 512;         // resident GEMM workgroups assumed by the split-K choice
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -38,8 +37,6 @@ struct LsState {
     double g_cur, h_cur, f_cur;  // objective pieces at the current iterate
     double delta_fro;            // ||Delta||_F of the last accepted step
     double tau_acc;              // accepted step of the last iteration
-    double pow_scale;            // power iteration: 1 / ||w||
-    double pow_rayleigh;         // power iteration: Rayleigh quotient of the last vector
     int64_t nnz_off;
     int32_t done;       // current iteration accepted a trial: later trials are skipped
     int32_t converged;  // stop: every later launch is skipped
@@ -57,15 +54,29 @@ struct LsState {
 // kernel argument blocks
 // ---------------------------------------------------------------------------
 enum GemmEpi { EPI_GRAD = 0, EPI_TRIAL = 1, EPI_PARTIAL = 2 };
+enum Prec { PREC_FP32 = 0, PREC_BF16X1 = 1, PREC_BF16X3 = 2 };
+
+// optional bf16 hi/lo copies of the padded X operands
+struct XSplit {
+    uint16_t* xp_h;
+    uint16_t* xp_l;
+    uint16_t* xt_h;
+    uint16_t* xt_l;
+};
 
 struct GemmArgs {
-    const float* A;     // M x K row-major (lda), K = ksteps * kBK, zero-padded
-    const float* B;     // N x K row-major (ldb)
-    int64_t lda, ldb;
-    int M, N;           // rows of A / rows of B; C is M x N column-major
-    int ksteps;
+    const float* A;     // FP32: M x K row-major (lda), K a multiple of kPad, zero-padded
+    const float* B;     // FP32: N x K row-major (ldb)
+    const uint16_t* Ah; // bf16 forms: hi / lo parts of A and B, same layouts
+    const uint16_t* Al;
+    const uint16_t* Bh;
+    const uint16_t* Bl;
+    int64_t lda, ldb;   // elements
+    int M, N, K;        // C is M x N column-major; K = padded contraction length
     int tilesM, tilesN, splits;
     float* C;           // C[m + n*ldc]
+    uint16_t* Ch;       // optional bf16 hi/lo split of C (same layout)
+    uint16_t* Cl;
     int64_t ldc;
     int vec_store;      // ldc % 4 == 0 and C 16-byte aligned
     float alpha;        // EPI_GRAD scale
@@ -82,7 +93,9 @@ struct ProxArgs {
     const float* om;
     const float* g;
     float* om_new;      // may be null in reduce-only mode
-    float* d;           // Delta output (same layout), may be null
+    float* d;           // Delta output, FP32 (same layout), may be null
+    uint16_t* dh;       // Delta output as bf16 hi (and lo), instead of d
+    uint16_t* dl;
     int64_t total;      // elements = p * ld
     int64_t ld;         // rows stored per column (>= p)
     int64_t p;
@@ -99,10 +112,10 @@ struct ProxArgs {
 void launch_init_state(LsState* ls, double tau0, double beta, double lambda, double tol,
                        double inv_n, double L, int max_iter, hipStream_t st);
 void launch_pad_x(const float* X, int64_t n, int64_t p, float* Xp, int64_t p_pad, float* Xt,
-                  int64_t n_pad, LsState* ls, hipStream_t st);
+                  int64_t n_pad, XSplit sp, LsState* ls, hipStream_t st);
 void launch_copy_cols(const float* src, int64_t ld_src, float* dst, int64_t ld_dst, int64_t p,
                       int64_t rows, LsState* check_ls, hipStream_t st);
-void launch_gemm(const GemmArgs& a, int epi, hipStream_t st);
+void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st);
 void launch_splitk_reduce(const GemmArgs& a, hipStream_t st);
 int prox_blocks(int64_t total);
 void launch_prox(ProxArgs a, int nblocks, hipStream_t st);

@@ -1,7 +1,9 @@
 // HIP kernels of the ACCORD-FBS hot path for gfx950 (MI355X).
 //
 //   k_gemm_f32     FP32 MFMA (v_mfma_f32_16x16x4f32) GEMM, LDS double-buffered
-//                  128x128x32 tiles, XCD-aware tile order.  Two uses:
+//                  128x128 tiles, XCD-aware tile order
+//   k_gemm_bf16    the same with v_mfma_f32_16x16x32_bf16 on bf16 (hi) or hi+lo
+//                  split operands (1 or 3 MFMA passes).  Two uses of both:
 //                    gradient  G  = X^T W / n              (Remark 3.1, two-step product)
 //                    trial     W+ = W + X Delta, ||X Delta||^2, ||W+||^2 (Alg. 1 test)
 //   k_splitk_reduce fixed-order sum of split-K partial tiles + trial epilogue
@@ -29,28 +31,34 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// Block-wide sum of NV doubles (blockDim.x == kThreads); result valid in thread 0.
+// Block-wide sum of NV doubles (blockDim.x == kThreads) through the LDS scratch `sh`
+// (kThreads / 64 * NV doubles); result valid in thread 0.
 template <int NV>
-__device__ inline void block_sum(double (&v)[NV]) {
-    __shared__ double sh[kThreads / 64][NV];
+__device__ inline void block_sum_in(double (&v)[NV], double* sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
     __syncthreads();
     if (lane == 0) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) sh[wave][q] = v[q];
+        for (int q = 0; q < NV; ++q) sh[wave * NV + q] = v[q];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
-            double s = sh[0][q];
-            for (int w = 1; w < kThreads / 64; ++w) s += sh[w][q];
+            double s = sh[q];
+            for (int w = 1; w < kThreads / 64; ++w) s += sh[w * NV + q];
             v[q] = s;
         }
     }
     __syncthreads();
+}
+
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV]) {
+    __shared__ double sh[kThreads / 64 * NV];
+    block_sum_in<NV>(v, sh);
 }
 
 // Sum of `count` rows of a [count][stride] partial array, columns 0..NV-1,
@@ -64,6 +72,14 @@ __device__ inline void sum_partials(const double* part, int count, int stride, d
         for (int q = 0; q < NV; ++q) v[q] += part[(int64_t)r * stride + q];
     }
     block_sum<NV>(v);
+}
+
+// FP32 value -> bf16 hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest even)
+__device__ inline void split_bf16(float x, uint16_t& h, uint16_t& l) {
+    const __bf16 bh = (__bf16)x;
+    const __bf16 bl = (__bf16)(x - (float)bh);
+    h = __builtin_bit_cast(uint16_t, bh);
+    l = __builtin_bit_cast(uint16_t, bl);
 }
 
 // ---------------------------------------------------------------------------
@@ -95,11 +111,12 @@ void launch_init_state(LsState* ls, double tau0, double beta, double lambda, dou
 // operand preparation
 // ---------------------------------------------------------------------------
 // X (n x p row-major) -> Xp (n_pad x p_pad row-major) and Xt (p_pad x n_pad row-major),
-// zero padding; flags non-finite input (bit 1 of ls->bad).
+// zero padding, plus (if requested) their bf16 hi/lo splits; flags non-finite input
+// (bit 1 of ls->bad).
 __global__ void __launch_bounds__(kThreads) k_pad_x(const float* __restrict__ X, int64_t n,
                                                     int64_t p, float* __restrict__ Xp,
                                                     int64_t p_pad, float* __restrict__ Xt,
-                                                    int64_t n_pad, LsState* ls) {
+                                                    int64_t n_pad, XSplit sp, LsState* ls) {
     __shared__ float tile[32][33];
     const int64_t c0 = (int64_t)blockIdx.x * 32;  // column block of X (variable index)
     const int64_t r0 = (int64_t)blockIdx.y * 32;  // row block of X (sample index)
@@ -114,19 +131,32 @@ __global__ void __launch_bounds__(kThreads) k_pad_x(const float* __restrict__ X,
         }
         tile[rr][tx] = v;
         Xp[r * p_pad + c] = v;
+        if (sp.xp_h) {
+            uint16_t h, l;
+            split_bf16(v, h, l);
+            sp.xp_h[r * p_pad + c] = h;
+            sp.xp_l[r * p_pad + c] = l;
+        }
     }
     __syncthreads();
     for (int cc = ty; cc < 32; cc += 8) {
         const int64_t c = c0 + cc, r = r0 + tx;
-        Xt[c * n_pad + r] = tile[tx][cc];
+        const float v = tile[tx][cc];
+        Xt[c * n_pad + r] = v;
+        if (sp.xt_h) {
+            uint16_t h, l;
+            split_bf16(v, h, l);
+            sp.xt_h[c * n_pad + r] = h;
+            sp.xt_l[c * n_pad + r] = l;
+        }
     }
     if (bad) atomicOr(&ls->bad, 2);
 }
 
 void launch_pad_x(const float* X, int64_t n, int64_t p, float* Xp, int64_t p_pad, float* Xt,
-                  int64_t n_pad, LsState* ls, hipStream_t st) {
+                  int64_t n_pad, XSplit sp, LsState* ls, hipStream_t st) {
     dim3 grid((unsigned)(p_pad / 32), (unsigned)(n_pad / 32));
-    k_pad_x<<<grid, kThreads, 0, st>>>(X, n, p, Xp, p_pad, Xt, n_pad, ls);
+    k_pad_x<<<grid, kThreads, 0, st>>>(X, n, p, Xp, p_pad, Xt, n_pad, sp, ls);
 }
 
 // Column-by-column copy of p columns: dst[j*ld_dst + i] = src[j*ld_src + i] for i < p,
@@ -184,22 +214,28 @@ void launch_transpose_w(const float* Wt, int64_t ldt, int64_t n, int64_t p, floa
 }
 
 // ---------------------------------------------------------------------------
-// FP32 MFMA GEMM:  C(m, n) = sum_k A[m, k] * B[n, k]   (both operands K-contiguous)
+// GEMMs:  C(m, n) = sum_k A[m, k] * B[n, k]   (both operands K-contiguous)
 //
 // Workgroup tile 128 x 128, 4 waves in a 2 x 2 arrangement, each wave 64 x 64 =
-// 4 x 4 blocks of v_mfma_f32_16x16x4f32.  A 32-wide K step is staged in LDS
-// (row stride 36 floats, so 16 lanes reading 16 rows at one K offset hit distinct
-// banks) and double-buffered: the next step's global loads are in flight while
-// the current step's MFMAs run.
+// 4 x 4 blocks of 16 x 16 MFMA outputs.  One K step is staged in LDS and
+// double-buffered: the next step's global loads are in flight while the current
+// step's MFMAs run.  LDS rows are padded by 16 bytes, so the 16 lanes that read
+// 16 rows at one K offset hit distinct banks.
 //
-// Lane l of a wave supplies, for one MFMA, A row (l % 16) and B column (l % 16)
-// at MFMA-internal k = l / 16.  Each lane reads 4 consecutive K values with one
-// 16-byte LDS read and feeds them to 4 successive MFMAs, i.e. MFMA-internal k = g
-// of step q maps to tile column 4g + q.  A and B use the same map, so every
-// product pairs matching K indices; only the summation order changes.
-// The 16x16 accumulator holds C(4*(l/16) + r, l % 16) in register r of lane l.
+//   FP32:    v_mfma_f32_16x16x4f32, 32-wide K steps.  Lane l supplies A row l % 16
+//            and B column l % 16 at MFMA-internal k = l / 16.  Each lane reads 4
+//            consecutive K values with one 16-byte LDS read and feeds them to 4
+//            successive MFMAs (MFMA-internal k = g of step q is tile column 4g + q;
+//            A and B use the same map, so only the summation order changes).
+//   BF16xP:  v_mfma_f32_16x16x32_bf16.  Lane l supplies 8 consecutive K values of
+//            A row l % 16 / B column l % 16 starting at 8 (l / 16).  Operands are
+//            pre-split FP32 values x = hi + lo (hi = bf16(x), lo = bf16(x - hi));
+//            P = 1 multiplies hi parts only, P = 3 adds hi*lo and lo*hi (the lo*lo
+//            term, relative size 2^-16, is dropped).  FP32 accumulation.
+//
+// The 16 x 16 accumulator holds C(4 (l / 16) + r, l % 16) in register r of lane l.
 // ---------------------------------------------------------------------------
-constexpr int kLDK = kBK + 4;
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 __device__ inline void decode_tile(const GemmArgs& g, int& tile_m, int& tile_n, int& split) {
     // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
@@ -228,11 +264,11 @@ __device__ inline void decode_tile(const GemmArgs& g, int& tile_m, int& tile_n, 
     }
 }
 
-template <int EPI>
-__global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
+// Predication and iteration start; returns true if the launch has nothing to do.
+__device__ inline bool gemm_skip(const GemmArgs& g) {
     if (g.ls) {
-        if (g.pred >= 1 && g.ls->converged) return;
-        if (g.pred >= 2 && g.ls->done) return;
+        if (g.pred >= 1 && g.ls->converged) return true;
+        if (g.pred >= 2 && g.ls->done) return true;
     }
     if (g.begin_iter && blockIdx.x == 0 && threadIdx.x == 0) {
         // a new iteration starts from tau0 (Alg. 1); nothing else reads these now
@@ -240,14 +276,111 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
         g.ls->trials = 0;
         g.ls->tau = g.ls->tau0;
     }
-    __shared__ __attribute__((aligned(16))) float sA[2][kBM * kLDK];
-    __shared__ __attribute__((aligned(16))) float sB[2][kBN * kLDK];
+    return false;
+}
+
+// Stores one 4-row accumulator fragment (rows m..m+3 of column n).
+//   EPI_GRAD:  C = alpha * acc
+//   EPI_TRIAL: C = Wprev + acc, with FP64 sums of acc^2 and C^2 over the valid extent
+// With Ch/Cl set, the bf16 hi/lo split of the stored value is written as well.
+template <int EPI>
+__device__ inline void store_frag(const GemmArgs& g, f4 v, int m, int n, double (&nv)[2]) {
+    if (n >= g.N || m >= g.M) return;
+    const int64_t off = (int64_t)n * g.ldc + m;
+    const bool vec = g.vec_store && m + 3 < g.M;
+    if (EPI == EPI_GRAD) {
+        v = v * g.alpha;
+    } else {
+        f4 w = f4{0.f, 0.f, 0.f, 0.f};
+        if (g.Wprev) {
+            if (vec) {
+                w = *(const f4*)(g.Wprev + off);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) w[r] = (m + r < g.M) ? g.Wprev[off + r] : 0.f;
+            }
+        }
+        const f4 out = w + v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (m + r < g.Mvalid && n < g.Nvalid) {
+                nv[0] += (double)v[r] * (double)v[r];
+                nv[1] += (double)out[r] * (double)out[r];
+            }
+        }
+        v = out;
+    }
+    uint16_t h[4], l[4];
+    if (g.Ch) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) split_bf16(v[r], h[r], l[r]);
+    }
+    if (vec) {
+        *(f4*)(g.C + off) = v;
+        if (g.Ch) {
+            *(uint2*)(g.Ch + off) = make_uint2(h[0] | ((uint32_t)h[1] << 16),
+                                               h[2] | ((uint32_t)h[3] << 16));
+            *(uint2*)(g.Cl + off) = make_uint2(l[0] | ((uint32_t)l[1] << 16),
+                                               l[2] | ((uint32_t)l[3] << 16));
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (m + r < g.M) {
+                g.C[off + r] = v[r];
+                if (g.Ch) {
+                    g.Ch[off + r] = h[r];
+                    g.Cl[off + r] = l[r];
+                }
+            }
+        }
+    }
+}
+
+// Epilogue shared by all GEMM kernels (thread t owns fragments (i, j) of its wave).
+template <int EPI>
+__device__ inline void gemm_epilogue(const GemmArgs& g, f4 (&acc)[4][4], int tile_m, int tile_n,
+                                     int split, double* red_lds) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = tile_m + tile_n * g.tilesM;
+    if (EPI == EPI_PARTIAL) {
+        f4* P = (f4*)(g.P + ((int64_t)split * g.tilesM * g.tilesN + tile) * (kBM * kBN));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) P[(i * 4 + j) * kThreads + tid] = acc[i][j];
+        return;
+    }
+    const int m0 = tile_m * kBM + (wave >> 1) * 64 + (lane >> 4) * 4;
+    const int n0 = tile_n * kBN + (wave & 1) * 64 + (lane & 15);
+    double nv[2] = {0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) store_frag<EPI>(g, acc[i][j], m0 + 16 * i, n0 + 16 * j, nv);
+    if (EPI == EPI_TRIAL) {
+        block_sum_in<2>(nv, red_lds);  // the tile LDS is free after the K loop
+        if (tid == 0) {
+            g.norm_part[(int64_t)tile * kNormCols + 0] = nv[0];
+            g.norm_part[(int64_t)tile * kNormCols + 1] = nv[1];
+        }
+    }
+}
+
+constexpr int kLDK32 = kBK32 + 4;  // FP32 LDS row stride (floats)
+
+template <int EPI>
+__global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
+    if (gemm_skip(g)) return;
+    __shared__ __attribute__((aligned(16))) float sA[2][kBM * kLDK32];
+    __shared__ __attribute__((aligned(16))) float sB[2][kBN * kLDK32];
 
     int tile_m, tile_n, split;
     decode_tile(g, tile_m, tile_n, split);
     const int m0 = tile_m * kBM, n0 = tile_n * kBN;
-    const int s_begin = (int)((int64_t)g.ksteps * split / g.splits);
-    const int s_end = (int)((int64_t)g.ksteps * (split + 1) / g.splits);
+    const int ksteps = g.K / kBK32;
+    const int s_begin = (int)((int64_t)ksteps * split / g.splits);
+    const int s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lrow = tid >> 3, lcol = (tid & 7) * 4;
@@ -274,7 +407,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
 
     if (s_begin < s_end) {
         {
-            const int64_t ko = (int64_t)s_begin * kBK;
+            const int64_t ko = (int64_t)s_begin * kBK32;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 va[i] = *(const f4*)(pa[i] + ko);
@@ -282,8 +415,8 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                *(f4*)&sA[0][(lrow + 32 * i) * kLDK + lcol] = va[i];
-                *(f4*)&sB[0][(lrow + 32 * i) * kLDK + lcol] = vb[i];
+                *(f4*)&sA[0][(lrow + 32 * i) * kLDK32 + lcol] = va[i];
+                *(f4*)&sB[0][(lrow + 32 * i) * kLDK32 + lcol] = vb[i];
             }
         }
         __syncthreads();
@@ -291,22 +424,22 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
         for (int s = s_begin; s < s_end; ++s) {
             const bool more = s + 1 < s_end;
             if (more) {
-                const int64_t ko = (int64_t)(s + 1) * kBK;
+                const int64_t ko = (int64_t)(s + 1) * kBK32;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     va[i] = *(const f4*)(pa[i] + ko);
                     vb[i] = *(const f4*)(pb[i] + ko);
                 }
             }
-            const float* a_base = &sA[cur][(wm + r16) * kLDK + g4];
-            const float* b_base = &sB[cur][(wn + r16) * kLDK + g4];
+            const float* a_base = &sA[cur][(wm + r16) * kLDK32 + g4];
+            const float* b_base = &sB[cur][(wn + r16) * kLDK32 + g4];
 #pragma unroll
-            for (int kk = 0; kk < kBK; kk += 16) {
+            for (int kk = 0; kk < kBK32; kk += 16) {
                 f4 af[4], bf[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) af[i] = *(const f4*)(a_base + i * 16 * kLDK + kk);
+                for (int i = 0; i < 4; ++i) af[i] = *(const f4*)(a_base + i * 16 * kLDK32 + kk);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) bf[j] = *(const f4*)(b_base + j * 16 * kLDK + kk);
+                for (int j = 0; j < 4; ++j) bf[j] = *(const f4*)(b_base + j * 16 * kLDK32 + kk);
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -319,79 +452,141 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
             if (more) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    *(f4*)&sA[cur ^ 1][(lrow + 32 * i) * kLDK + lcol] = va[i];
-                    *(f4*)&sB[cur ^ 1][(lrow + 32 * i) * kLDK + lcol] = vb[i];
+                    *(f4*)&sA[cur ^ 1][(lrow + 32 * i) * kLDK32 + lcol] = va[i];
+                    *(f4*)&sB[cur ^ 1][(lrow + 32 * i) * kLDK32 + lcol] = vb[i];
                 }
             }
             __syncthreads();
             cur ^= 1;
         }
     }
+    __syncthreads();
+    gemm_epilogue<EPI>(g, acc, tile_m, tile_n, split, (double*)&sA[0][0]);
+}
 
-    const int tile = tile_m + tile_n * g.tilesM;
-    if (EPI == EPI_PARTIAL) {
-        f4* P = (f4*)(g.P + ((int64_t)split * g.tilesM * g.tilesN + tile) * (kBM * kBN));
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) P[(i * 4 + j) * kThreads + tid] = acc[i][j];
-        return;
-    }
+template <int PASSES, int EPI>
+__global__ void __launch_bounds__(kThreads, 2) k_gemm_bf16(GemmArgs g) {
+    if (gemm_skip(g)) return;
+    constexpr int BK = PASSES == 1 ? 64 : 32;       // K per LDS stage
+    constexpr int LDK = BK + 8;                     // bf16 per LDS row (16-byte pad)
+    constexpr int H = PASSES == 1 ? 1 : 2;          // hi, or hi + lo
+    constexpr int CPR = BK / 8;                     // 16-byte chunks per row
+    constexpr int ROWS = kThreads / CPR;            // rows covered by one load pass
+    constexpr int RPT = kBM / ROWS;                 // load passes per operand half
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][H][kBM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][H][kBN * LDK];
 
-    double nv[2] = {0.0, 0.0};
+    int tile_m, tile_n, split;
+    decode_tile(g, tile_m, tile_n, split);
+    const int m0 = tile_m * kBM, n0 = tile_n * kBN;
+    const int ksteps = g.K / BK;
+    const int s_begin = (int)((int64_t)ksteps * split / g.splits);
+    const int s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lrow = tid / CPR, lcol = (tid % CPR) * 8;
+    const uint16_t* pa[H][RPT];
+    const uint16_t* pb[H][RPT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int m = m0 + wm + 16 * i + g4;
-            const int n = n0 + wn + 16 * j + r16;
-            if (n >= g.N || m >= g.M) continue;
-            f4 v = acc[i][j];
-            float* c = g.C + (int64_t)n * g.ldc + m;
-            if (EPI == EPI_GRAD) {
-                v = v * g.alpha;
-            } else {
-                f4 w = f4{0.f, 0.f, 0.f, 0.f};
-                if (g.Wprev) {
-                    const float* wp = g.Wprev + (int64_t)n * g.ldc + m;
-                    if (g.vec_store && m + 3 < g.M) {
-                        w = *(const f4*)wp;
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) w[r] = (m + r < g.M) ? wp[r] : 0.f;
-                    }
-                }
-                const f4 out = w + v;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (m + r < g.Mvalid && n < g.Nvalid) {
-                        nv[0] += (double)v[r] * (double)v[r];
-                        nv[1] += (double)out[r] * (double)out[r];
-                    }
-                }
-                v = out;
-            }
-            if (g.vec_store && m + 3 < g.M) {
-                *(f4*)c = v;
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (m + r < g.M) c[r] = v[r];
-            }
+    for (int i = 0; i < RPT; ++i) {
+        int ra = m0 + lrow + ROWS * i;
+        ra = ra < g.M ? ra : g.M - 1;
+        int rb = n0 + lrow + ROWS * i;
+        rb = rb < g.N ? rb : g.N - 1;
+        pa[0][i] = g.Ah + (int64_t)ra * g.lda + lcol;
+        pb[0][i] = g.Bh + (int64_t)rb * g.ldb + lcol;
+        if (H == 2) {
+            pa[H - 1][i] = g.Al + (int64_t)ra * g.lda + lcol;
+            pb[H - 1][i] = g.Bl + (int64_t)rb * g.ldb + lcol;
         }
     }
-    if (EPI == EPI_TRIAL) {
-        block_sum<2>(nv);
-        if (tid == 0) {
-            g.norm_part[(int64_t)tile * kNormCols + 0] = nv[0];
-            g.norm_part[(int64_t)tile * kNormCols + 1] = nv[1];
+    uint4 va[H][RPT], vb[H][RPT];
+    f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int r16 = lane & 15, k8 = (lane >> 4) * 8;
+
+    auto gload = [&](int s) {
+        const int64_t ko = (int64_t)s * BK;
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                va[h][i] = *(const uint4*)(pa[h][i] + ko);
+                vb[h][i] = *(const uint4*)(pb[h][i] + ko);
+            }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                *(uint4*)&sA[buf][h][(lrow + ROWS * i) * LDK + lcol] = va[h][i];
+                *(uint4*)&sB[buf][h][(lrow + ROWS * i) * LDK + lcol] = vb[h][i];
+            }
+    };
+
+    if (s_begin < s_end) {
+        gload(s_begin);
+        sstore(0);
+        __syncthreads();
+        int cur = 0;
+        for (int s = s_begin; s < s_end; ++s) {
+            const bool more = s + 1 < s_end;
+            if (more) gload(s + 1);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 32) {
+                bf8 ah[4], bh[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    ah[i] = *(const bf8*)&sA[cur][0][(wm + 16 * i + r16) * LDK + kk + k8];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    bh[j] = *(const bf8*)&sB[cur][0][(wn + 16 * j + r16) * LDK + kk + k8];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j],
+                                                                            acc[i][j], 0, 0, 0);
+                if (PASSES == 3) {
+                    bf8 al[4], bl[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        bl[j] = *(const bf8*)&sB[cur][H - 1][(wn + 16 * j + r16) * LDK + kk + k8];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        al[i] = *(const bf8*)&sA[cur][H - 1][(wm + 16 * i + r16) * LDK + kk + k8];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                al[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+            }
+            if (more) sstore(cur ^ 1);
+            __syncthreads();
+            cur ^= 1;
         }
     }
+    __syncthreads();
+    gemm_epilogue<EPI>(g, acc, tile_m, tile_n, split, (double*)&sA[0][0][0]);
 }
 
 // Fixed-order sum of the split-K partial tiles, then the trial epilogue.
-// One workgroup per tile; thread t owns the same accumulator slots it had in
-// k_gemm_f32, so (m, n) follow from (t, i, j) exactly as there.
+// One workgroup per tile; thread t owns the same accumulator slots it had in the
+// GEMM kernel, so (m, n) follow from (t, i, j) exactly as there.
 __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
     if (g.ls) {
         if (g.pred >= 1 && g.ls->converged) return;
@@ -399,46 +594,20 @@ __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
     }
     const int tile = blockIdx.x;
     const int tile_m = tile % g.tilesM, tile_n = tile / g.tilesM;
-    const int m0 = tile_m * kBM, n0 = tile_n * kBN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-    const int r16 = lane & 15, g4 = (lane >> 4) * 4;
+    const int m0 = tile_m * kBM + (wave >> 1) * 64 + (lane >> 4) * 4;
+    const int n0 = tile_n * kBN + (wave & 1) * 64 + (lane & 15);
     const int64_t tiles = (int64_t)g.tilesM * g.tilesN;
     double nv[2] = {0.0, 0.0};
 #pragma unroll 1
     for (int idx = 0; idx < 16; ++idx) {
         const int i = idx >> 2, j = idx & 3;
-        const int m = m0 + wm + 16 * i + g4;
-        const int n = n0 + wn + 16 * j + r16;
         f4 v = f4{0.f, 0.f, 0.f, 0.f};
         for (int s = 0; s < g.splits; ++s) {
             const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kBM * kBN));
             v += P[idx * kThreads + tid];
         }
-        if (n >= g.N || m >= g.M) continue;
-        float* c = g.C + (int64_t)n * g.ldc + m;
-        f4 w = f4{0.f, 0.f, 0.f, 0.f};
-        if (g.Wprev) {
-            const float* wp = g.Wprev + (int64_t)n * g.ldc + m;
-            if (g.vec_store && m + 3 < g.M) {
-                w = *(const f4*)wp;
-            } else {
-                for (int r = 0; r < 4; ++r) w[r] = (m + r < g.M) ? wp[r] : 0.f;
-            }
-        }
-        const f4 out = w + v;
-        for (int r = 0; r < 4; ++r) {
-            if (m + r < g.Mvalid && n < g.Nvalid) {
-                nv[0] += (double)v[r] * (double)v[r];
-                nv[1] += (double)out[r] * (double)out[r];
-            }
-        }
-        if (g.vec_store && m + 3 < g.M) {
-            *(f4*)c = out;
-        } else {
-            for (int r = 0; r < 4; ++r)
-                if (m + r < g.M) c[r] = out[r];
-        }
+        store_frag<EPI_TRIAL>(g, v, m0 + 16 * i, n0 + 16 * j, nv);
     }
     block_sum<2>(nv);
     if (tid == 0) {
@@ -447,14 +616,24 @@ __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
     }
 }
 
-void launch_gemm(const GemmArgs& a, int epi, hipStream_t st) {
+template <int EPI>
+static void launch_gemm_epi(const GemmArgs& a, int prec, unsigned blocks, hipStream_t st) {
+    if (prec == PREC_BF16X3)
+        k_gemm_bf16<3, EPI><<<blocks, kThreads, 0, st>>>(a);
+    else if (prec == PREC_BF16X1)
+        k_gemm_bf16<1, EPI><<<blocks, kThreads, 0, st>>>(a);
+    else
+        k_gemm_f32<EPI><<<blocks, kThreads, 0, st>>>(a);
+}
+
+void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st) {
     const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
     if (epi == EPI_GRAD)
-        k_gemm_f32<EPI_GRAD><<<blocks, kThreads, 0, st>>>(a);
+        launch_gemm_epi<EPI_GRAD>(a, prec, blocks, st);
     else if (epi == EPI_TRIAL)
-        k_gemm_f32<EPI_TRIAL><<<blocks, kThreads, 0, st>>>(a);
+        launch_gemm_epi<EPI_TRIAL>(a, prec, blocks, st);
     else
-        k_gemm_f32<EPI_PARTIAL><<<blocks, kThreads, 0, st>>>(a);
+        launch_gemm_epi<EPI_PARTIAL>(a, prec, blocks, st);
 }
 
 void launch_splitk_reduce(const GemmArgs& a, hipStream_t st) {
@@ -465,12 +644,14 @@ void launch_splitk_reduce(const GemmArgs& a, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Fused prox (eq. 3.5) + line-search partial sums.
 //
-// Streams Omega and G once (16-byte loads), writes Omega+ and Delta, and keeps
-// per-thread FP64 sums of ||Delta||^2, <Delta, G>, ||Omega+||_1, sum log Omega+_jj,
-// the off-diagonal nonzero count and ||Omega+||_F^2.  Off-diagonal entries are
+// Streams Omega and G once (16-byte loads), writes Omega+ and Delta (in the trial
+// GEMM's operand format: FP32, bf16 hi, or bf16 hi + lo), and keeps per-thread
+// FP64 sums of ||Delta||^2, <Delta, G>, ||Omega+||_1, sum log Omega+_jj, the
+// off-diagonal nonzero count and ||Omega+||_F^2.  Off-diagonal entries are
 // soft-thresholded in FP32; the diagonal root is evaluated in FP64 in the
 // cancellation-free form  b >= 0: (b + r)/2,  b < 0: 2 tau / (r - b),
 // r = sqrt(b^2 + 4 tau), which equals (b + r)/2 exactly in real arithmetic.
+// The sums use the Delta the GEMM will multiply (the split's hi + lo, or hi).
 // ---------------------------------------------------------------------------
 struct ProxAcc {
     double d2 = 0, dg = 0, l1 = 0, logd = 0, nnz = 0, fro = 0;
@@ -490,11 +671,10 @@ __device__ inline float prox_one(float o, float gv, bool diag, double tau, doubl
     return s > 0.f ? copysignf(s, a) : 0.f;
 }
 
-__device__ inline void prox_account(ProxAcc& acc, float o, float gv, float nw, bool diag,
+__device__ inline void prox_account(ProxAcc& acc, float dl, float gv, float nw, bool diag,
                                     bool valid, bool reduce_only) {
     if (!valid) return;
     if (!reduce_only) {
-        const float dl = nw - o;
         acc.d2 += (double)dl * (double)dl;
         acc.dg += (double)dl * (double)gv;
     }
@@ -507,6 +687,17 @@ __device__ inline void prox_account(ProxAcc& acc, float o, float gv, float nw, b
     }
 }
 
+// Delta as the GEMM sees it: DOUT 0 = FP32, 1 = bf16(Delta), 2 = hi + lo
+template <int DOUT>
+__device__ inline float delta_repr(float dl, uint16_t& h, uint16_t& l) {
+    if (DOUT == 0) return dl;
+    split_bf16(dl, h, l);
+    const float fh = (float)__builtin_bit_cast(__bf16, h);
+    if (DOUT == 1) return fh;
+    return fh + (float)__builtin_bit_cast(__bf16, l);
+}
+
+template <int DOUT>
 __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
     double tau = a.tau, lam = a.lambda;
     if (a.ls) {
@@ -524,6 +715,8 @@ __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
     const f4* g4 = (const f4*)a.g;
     f4* on4 = (f4*)a.om_new;
     f4* d4 = (f4*)a.d;
+    uint2* dh2 = (uint2*)a.dh;
+    uint2* dl2 = (uint2*)a.dl;
 
     int64_t q = q_begin + threadIdx.x;
     int64_t e = q << 2;
@@ -531,7 +724,8 @@ __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
     for (; q < q_end; q += kThreads) {
         const f4 o = om4[q];
         const f4 gv = a.reduce_only ? f4{0.f, 0.f, 0.f, 0.f} : g4[q];
-        f4 nw;
+        f4 nw, dv;
+        uint16_t h[4], l[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             int64_t r = row + u, c = col;
@@ -540,13 +734,19 @@ __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
                 c += 1;
             }
             const bool diag = (r == c);
-            const bool valid = r < a.p;
             nw[u] = a.reduce_only ? o[u] : prox_one(o[u], gv[u], diag, tau, lam, tau_f, thr_f);
-            prox_account(acc, o[u], gv[u], nw[u], diag, valid, a.reduce_only);
+            dv[u] = delta_repr<DOUT>(nw[u] - o[u], h[u], l[u]);
+            prox_account(acc, dv[u], gv[u], nw[u], diag, r < a.p, a.reduce_only);
         }
         if (!a.reduce_only) {
             on4[q] = nw;
-            if (d4) d4[q] = nw - o;
+            if (DOUT == 0) {
+                if (d4) d4[q] = dv;
+            } else {
+                dh2[q] = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
+                if (DOUT == 2)
+                    dl2[q] = make_uint2(l[0] | ((uint32_t)l[1] << 16), l[2] | ((uint32_t)l[3] << 16));
+            }
         }
         row += a.step_row;
         col += a.step_col;
@@ -563,10 +763,17 @@ __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
         const float gv = a.reduce_only ? 0.f : a.g[ee];
         const bool diag = (r == c);
         const float nw = a.reduce_only ? o : prox_one(o, gv, diag, tau, lam, tau_f, thr_f);
-        prox_account(acc, o, gv, nw, diag, r < a.p, a.reduce_only);
+        uint16_t h, l;
+        const float dv = delta_repr<DOUT>(nw - o, h, l);
+        prox_account(acc, dv, gv, nw, diag, r < a.p, a.reduce_only);
         if (!a.reduce_only) {
             a.om_new[ee] = nw;
-            if (a.d) a.d[ee] = nw - o;
+            if (DOUT == 0) {
+                if (a.d) a.d[ee] = dv;
+            } else {
+                a.dh[ee] = h;
+                if (DOUT == 2) a.dl[ee] = l;
+            }
         }
     }
     double v[6] = {acc.d2, acc.dg, acc.l1, acc.logd, acc.nnz, acc.fro};
@@ -592,7 +799,12 @@ void launch_prox(ProxArgs a, int nblocks, hipStream_t st) {
     const int64_t step = 4 * (int64_t)kThreads;
     a.step_col = step / a.ld;
     a.step_row = step - a.step_col * a.ld;
-    k_prox<<<nblocks, kThreads, 0, st>>>(a);
+    if (a.dh && a.dl)
+        k_prox<2><<<nblocks, kThreads, 0, st>>>(a);
+    else if (a.dh)
+        k_prox<1><<<nblocks, kThreads, 0, st>>>(a);
+    else
+        k_prox<0><<<nblocks, kThreads, 0, st>>>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -743,31 +955,41 @@ void launch_combine_objective(const double* prox_part, int nprox, const double* 
 // ---------------------------------------------------------------------------
 // Power iteration for L = sigma_max(X^T X / n):  v <- X^T (X v) / ||X^T (X v)||.
 // The Rayleigh quotient ||X v||^2 / n of the last unit vector is L's estimate
-// (it approaches sigma_max from below).  FP64 vectors, FP32 data.
+// (it approaches sigma_max from below; the error shrinks like (l2/l1)^(2k)).
+// FP64 vectors, FP32 data.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_pow_start(double* w, int64_t p, LsState* ls) {
+__global__ void __launch_bounds__(kThreads) k_pow_start(double* w, int64_t p) {
     for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < p;
          k += (int64_t)gridDim.x * kThreads) {
-        // fixed pseudo-random signs (integer hash), unit-norm after scaling
+        // fixed pseudo-random signs (integer hash); ||w|| = sqrt(p)
         uint32_t h = (uint32_t)k * 2654435761u;
         h ^= h >> 15;
         h *= 2246822519u;
         h ^= h >> 13;
         w[k] = (h & 1u) ? 1.0 : -1.0;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) ls->pow_scale = 1.0 / sqrt((double)p);
 }
 
-// u = X (scale * w): one wave per sample row
+// u = X (w / ||w||): one wave per sample row.  ||w||^2 is summed from the previous
+// step's partials by every workgroup in the same fixed order (or is p at step 0).
 __global__ void __launch_bounds__(kThreads) k_pow_xv(const float* __restrict__ Xp,
                                                      int64_t ldx, int64_t n, int64_t p,
                                                      const double* __restrict__ w,
+                                                     const double* __restrict__ part_w, int nbw,
                                                      double* __restrict__ u,
-                                                     double* __restrict__ part_u,
-                                                     const LsState* ls) {
+                                                     double* __restrict__ part_u) {
+    double ww[1];
+    if (part_w) {
+        sum_partials<1>(part_w, nbw, 1, ww);
+    } else if (threadIdx.x == 0) {
+        ww[0] = (double)p;
+    }
+    __shared__ double s_scale;
+    if (threadIdx.x == 0) s_scale = ww[0] > 0.0 ? 1.0 / sqrt(ww[0]) : 0.0;
+    __syncthreads();
+    const double scale = s_scale;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * (kThreads / 64) + wave;
-    const double scale = ls->pow_scale;
     double s = 0.0;
     if (i < n) {
         const float* row = Xp + i * ldx;
@@ -800,19 +1022,14 @@ __global__ void __launch_bounds__(kThreads) k_pow_xtu(const float* __restrict__ 
     if (threadIdx.x == 0) part_w[blockIdx.x] = v[0];
 }
 
-__global__ void __launch_bounds__(kThreads) k_pow_norm(const double* part_w, int nbw,
-                                                       const double* part_u, int nbu,
-                                                       LsState* ls, int last) {
-    double vw[1], vu[1];
-    sum_partials<1>(part_w, nbw, 1, vw);
+// L = ||X v||^2 / n for the last unit vector v (its Rayleigh quotient)
+__global__ void __launch_bounds__(kThreads) k_pow_finish(const double* part_u, int nbu,
+                                                         LsState* ls) {
+    double vu[1];
     sum_partials<1>(part_u, nbu, 1, vu);
     if (threadIdx.x != 0) return;
-    ls->pow_rayleigh = vu[0] * ls->inv_n;
-    ls->pow_scale = vw[0] > 0.0 ? 1.0 / sqrt(vw[0]) : 0.0;
-    if (last) {
-        ls->L = ls->pow_rayleigh;
-        ls->inv_L = ls->L > 0.0 ? 1.0 / ls->L : 0.0;
-    }
+    ls->L = vu[0] * ls->inv_n;
+    ls->inv_L = ls->L > 0.0 ? 1.0 / ls->L : 0.0;
 }
 
 void launch_power_iteration(const float* Xp, int64_t p_pad, const float* Xt, int64_t n_pad,
@@ -820,13 +1037,14 @@ void launch_power_iteration(const float* Xp, int64_t p_pad, const float* Xt, int
                             double* part_w, int steps, LsState* ls, hipStream_t st) {
     const int nbu = (int)cdiv(n, kThreads / 64);
     const int nbw = (int)cdiv(p, kThreads / 64);
-    k_pow_start<<<(unsigned)(cdiv(p, kThreads) < 1024 ? cdiv(p, kThreads) : 1024), kThreads, 0,
-                  st>>>(w, p, ls);
+    const int64_t sb = cdiv(p, kThreads);
+    k_pow_start<<<(unsigned)(sb < 1024 ? sb : 1024), kThreads, 0, st>>>(w, p);
     for (int s = 0; s < steps; ++s) {
-        k_pow_xv<<<nbu, kThreads, 0, st>>>(Xp, p_pad, n, p, w, u, part_u, ls);
-        k_pow_xtu<<<nbw, kThreads, 0, st>>>(Xt, n_pad, p, n, u, w, part_w);
-        k_pow_norm<<<1, kThreads, 0, st>>>(part_w, nbw, part_u, nbu, ls, s == steps - 1);
+        k_pow_xv<<<nbu, kThreads, 0, st>>>(Xp, p_pad, n, p, w, s == 0 ? nullptr : part_w, nbw,
+                                           u, part_u);
+        if (s + 1 < steps) k_pow_xtu<<<nbw, kThreads, 0, st>>>(Xt, n_pad, p, n, u, w, part_w);
     }
+    k_pow_finish<<<1, kThreads, 0, st>>>(part_u, nbu, ls);
 }
 
 }  // namespace accord

@@ -185,7 +185,10 @@ def test_fit_small_workload_parity(gpu_lib, dev, name):
     rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
     assert rel <= 1e-4, rel
     assert np.allclose(tr[:, 0], ref.f, rtol=1e-5)
-    # the oracle's own step decisions agree with the GPU's until a near-tie
+    # The oracle's own step decisions agree with the GPU's until a near-tie: either
+    # the exact margin of the test is within 1e-4, or Delta is so small that the
+    # FP32 rounding of the iterate (4u(|Omega| + tau|G| + tau lambda) per entry, the
+    # prox bound) is at least 0.1% of ||Delta||, so FP32 cannot resolve the test.
     own = oracle.fit_fbs(x, w.lam, w.iters, L=L)
     taus = tr[1:, 3]
     mism = np.nonzero(~np.isclose(taus, own.tau))[0]
@@ -197,7 +200,9 @@ def test_fit_small_workload_parity(gpu_lib, dev, name):
         d = oracle.prox(om_t, G, tau, w.lam) - om_t
         lhs = np.sum((x @ d) ** 2) / w.n
         rhs = np.sum(d * d) / tau
-        assert abs(lhs - rhs) <= 1e-4 * rhs, (t0, lhs, rhs)
+        fp32_noise = np.linalg.norm(4 * U32 * (np.abs(om_t) + tau * np.abs(G) + tau * w.lam))
+        assert (abs(lhs - rhs) <= 1e-4 * rhs
+                or fp32_noise >= 1e-3 * np.linalg.norm(d)), (t0, lhs, rhs, fp32_noise)
     # trace invariants: monotone objective, tau = tau0 beta^(k-1), floor respected
     assert np.all(np.diff(tr[:, 0]) <= 1e-6 * np.abs(tr[1:, 0]))
     assert np.allclose(tr[1:, 3], 0.5 ** (tr[1:, 4] - 1))
@@ -216,7 +221,7 @@ def test_fit_benchmark_shape_sampled_columns(gpu_lib, dev):
     tr = tr.cpu().numpy()
     assert stats["iters"] == w.iters
     L = oracle.lipschitz(x)
-    assert abs(stats["lipschitz"] - L) <= 1e-6 * L
+    assert abs(stats["lipschitz"] - L) <= 1e-6 * L   # 400 power steps; eigengap 0.974 here
     cols = np.array([0, 1, 499, 500, 2047, 2048, 3333, 4990, 4998, 4999])
     ref = oracle.fit_fbs(x, w.lam, w.iters, L=stats["lipschitz"], tau_replay=tr[1:, 3],
                          columns=cols)
@@ -329,3 +334,78 @@ def test_fit_zero_iterations_returns_start(gpu_lib, dev):
     assert torch.equal(om, torch.eye(30, device=dev))
     assert np.isclose(tr.cpu().numpy()[0, 0],
                       oracle.objective(w.X.astype(np.float64), np.eye(30), 0.1)[2], rtol=1e-6)
+
+
+# ---------------------------------------------------------------------------- precision forms
+@pytest.mark.parametrize("name", ["er200"])
+def test_fit_bf16x3_small_workload(gpu_lib, dev, name):
+    """BF16x3 (hi/lo split, three MFMA passes) meets the FP32 bar: relative Frobenius
+    error <= 1e-4 against the FP64 oracle replaying the GPU's steps."""
+    w = datagen.workload(name)
+    x = w.X.astype(np.float64)
+    L = oracle.lipschitz(x)
+    got, stats, tr, ref = _fit_and_replay(gpu_lib, dev, w.X, w.lam, w.iters, L, precision="bf16x3")
+    assert stats["iters"] == w.iters
+    rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
+    print(f"bf16x3 {name}: rel={rel:.3e}")
+    assert rel <= 1e-4, rel
+    assert np.allclose(tr[:, 0], ref.f, rtol=1e-5)
+
+
+def test_fit_bf16x3_benchmark_shape_sampled_columns(gpu_lib, dev):
+    import torch
+    w = datagen.workload("ba5000")
+    x = w.X.astype(np.float64)
+    om, stats, tr = gpu_lib.accord_fit(_t(w.X, dev), w.lam, w.iters, trace=True,
+                                       precision="bf16x3")
+    torch.cuda.synchronize()
+    tr = tr.cpu().numpy()
+    cols = np.array([0, 1, 499, 500, 2047, 4998, 4999])
+    ref = oracle.fit_fbs(x, w.lam, w.iters, L=stats["lipschitz"], tau_replay=tr[1:, 3],
+                         columns=cols)
+    got = om.cpu().numpy()[cols, :].astype(np.float64).T
+    rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
+    print(f"bf16x3 ba5000: rel={rel:.3e}")
+    assert rel <= 1e-4, rel
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x1"])
+@pytest.mark.parametrize("n,p", [(33, 97), (130, 129), (1, 2)])
+def test_fit_bf16_ragged(gpu_lib, dev, prec, n, p):
+    print(f"{prec} n={n} p={p}", flush=True)
+    rng = np.random.default_rng(n * 7 + p)
+    x32 = rng.normal(size=(n, p)).astype(np.float32)
+    x = x32.astype(np.float64)
+    L = max(oracle.lipschitz(x), 1e-3)
+    got, stats, tr, ref = _fit_and_replay(gpu_lib, dev, x32, 0.1, 20, L, precision=prec)
+    rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
+    assert rel <= (1e-4 if prec == "bf16x3" else 5e-2), rel
+    assert np.all(np.isfinite(tr))
+
+
+def test_bf16x1_then_bf16x3_refinement_reaches_estimate(gpu_lib, dev):
+    """BF16x1 first, then BF16x3 from its result until the stop rule: relative error
+    <= 1e-3 against the converged FP64 estimate, identical support away from ties."""
+    import torch
+    w = datagen.small_random_problem(60, 90, seed=12)
+    x = w.X.astype(np.float64)
+    lam = 0.12
+    L = oracle.lipschitz(x)
+    X = _t(w.X, dev)
+    om1, s1, _ = gpu_lib.accord_fit(X, lam, 300, lipschitz=L, precision="bf16x1")
+    # stop rule at 1e-5: the FP32 iterate cannot resolve steps much below
+    # u * ||Omega||_F * sqrt(p) (about 1e-6 relative here)
+    om2, s2, _ = gpu_lib.accord_fit(X, lam, 5000, lipschitz=L, precision="bf16x3", omega0=om1,
+                                    tol=1e-5, check_every=20)
+    torch.cuda.synchronize()
+    assert s2["converged"] == 1
+    ref = oracle.fit_fbs(x, lam, 50000, tol=1e-15).omega
+    got = _col(om2)
+    rel1 = np.linalg.norm(_col(om1) - ref) / np.linalg.norm(ref)
+    rel2 = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"bf16x1 phase rel={rel1:.3e}  after bf16x3 refinement rel={rel2:.3e}")
+    assert rel2 <= 1e-3
+    G = oracle.grad(x, ref)
+    off = ~np.eye(90, dtype=bool)
+    safe = off & ((np.abs(ref) > 1e-4) | (lam - np.abs(G) > 1e-4))
+    assert np.array_equal((got != 0)[safe], (ref != 0)[safe])
