@@ -15,6 +15,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -52,13 +53,18 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // workspace layout (byte offsets, each region 256-byte aligned).  Regions are
 // ordered so each entry point needs a prefix: prox < grad/objective < fit.
 // ---------------------------------------------------------------------------
+// tile grid of one GEMM launch
+struct Geo {
+    int tilesM, tilesN, splits;
+    int tiles() const { return tilesM * tilesN; }
+};
+
 struct Plan {
     int64_t n, p, n_pad, p_pad;
     int prec;
-    // trial GEMM  (C = W^T:  M = n_pad, N = p, K = p_pad)
-    int t_tilesM, t_tilesN, t_splits;
-    // gradient GEMM  (C = G:  M = p_pad, N = p, K = n_pad)
-    int g_tilesM, g_tilesN;
+    // trial GEMM  (C = W^T:  M = n_pad, N = p, K = p_pad): FP32 geometry (setup
+    // products) and the geometry of the form's own kernel
+    Geo t32, tp;
     int nprox;
     size_t off_ls, off_prox_part, off_norm_part, off_pow_u, off_pow_w, off_pow_pu, off_pow_pw,
         off_trials, off_xp, off_xt, off_xsplit[4], off_wt0, off_wt1, off_wsplit[4], off_split,
@@ -72,13 +78,13 @@ size_t bump(size_t& cur, size_t bytes) {
     return at;
 }
 
-int choose_splits(int tiles, int ksteps64) {
-    // pick S minimising (rounds of kSlots resident workgroups) / S; keep >= 2 steps of 64
+int choose_splits(int tiles, int ksteps64, int slots) {
+    // pick S minimising (rounds of resident workgroups) / S; keep >= 2 steps of 64
     int best = 1;
-    double best_cost = (double)cdiv(tiles, kSlots);
+    double best_cost = (double)cdiv(tiles, slots);
     for (int s = 2; s <= 8; ++s) {
         if (ksteps64 / s < 2) break;
-        const double cost = (double)cdiv((int64_t)tiles * s, kSlots) / s;
+        const double cost = (double)cdiv((int64_t)tiles * s, slots) / s;
         if (cost < best_cost * 0.9) {
             best = s;
             best_cost = cost;
@@ -94,14 +100,23 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     P.prec = prec;
     P.n_pad = round_up(n, kPad);
     P.p_pad = round_up(p, kPad);
-    P.t_tilesM = (int)cdiv(P.n_pad, kBM);
-    P.t_tilesN = (int)cdiv(p, kBN);
-    P.t_splits = choose_splits(P.t_tilesM * P.t_tilesN, (int)(P.p_pad / kPad));
-    P.g_tilesM = (int)cdiv(P.p_pad, kBM);
-    P.g_tilesN = (int)cdiv(p, kBN);
+    P.t32.tilesM = (int)cdiv(P.n_pad, kBM);
+    P.t32.tilesN = (int)cdiv(p, kBN);
+    P.t32.splits = choose_splits(P.t32.tiles(), (int)(P.p_pad / kPad), kSlots);
+    if (prec == PREC_FP32) {
+        P.tp = P.t32;
+    } else {
+        P.tp.tilesM = (int)cdiv(P.n_pad, kWBM);
+        P.tp.tilesN = (int)cdiv(p, kWBN);
+        P.tp.splits = choose_splits(P.tp.tiles(), (int)(P.p_pad / kPad), kWSlots);
+    }
     P.nprox = prox_blocks(p * P.p_pad);
     const bool bf = prec != PREC_FP32;
-    const int ttiles = P.t_tilesM * P.t_tilesN;
+    const int ttiles = P.t32.tiles() > P.tp.tiles() ? P.t32.tiles() : P.tp.tiles();
+    const size_t split_floats =
+        std::max((size_t)(P.t32.splits > 1 ? P.t32.splits : 0) * P.t32.tiles() * kBM * kBN,
+                 (size_t)(P.tp.splits > 1 ? P.tp.splits : 0) * P.tp.tiles() * kWBM * kWBN *
+                     (prec == PREC_FP32 ? 0 : 1));
     const size_t xn = (size_t)(P.n_pad * P.p_pad);   // padded X elements
     const size_t wn = (size_t)(p * P.n_pad);         // W^T elements
     const size_t on = (size_t)(p * P.p_pad);         // p x p_pad elements
@@ -121,8 +136,7 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     P.off_wt0 = bump(cur, wn * sizeof(float));
     P.off_wt1 = bump(cur, wn * sizeof(float));
     for (int k = 0; k < 4; ++k) P.off_wsplit[k] = bump(cur, bf ? wn * sizeof(uint16_t) : 0);
-    P.off_split = bump(cur, P.t_splits > 1 ? (size_t)P.t_splits * ttiles * kBM * kBN * sizeof(float)
-                                           : 0);
+    P.off_split = bump(cur, split_floats * sizeof(float));
     P.off_om0 = bump(cur, on * sizeof(float));
     P.end_grad = cur;
     P.off_g = bump(cur, on * sizeof(float));
@@ -159,9 +173,10 @@ GemmArgs trial_args(const Plan& P, void* ws, int prec, const float* B32, const u
     a.M = (int)P.n_pad;
     a.N = (int)P.p;
     a.K = (int)P.p_pad;
-    a.tilesM = P.t_tilesM;
-    a.tilesN = P.t_tilesN;
-    a.splits = P.t_splits;
+    const Geo& geo = prec == PREC_FP32 ? P.t32 : P.tp;
+    a.tilesM = geo.tilesM;
+    a.tilesN = geo.tilesN;
+    a.splits = geo.splits;
     a.C = Wout;
     if (wslot >= 0) {
         a.Ch = at<uint16_t>(ws, P.off_wsplit[2 * wslot]);
@@ -171,7 +186,7 @@ GemmArgs trial_args(const Plan& P, void* ws, int prec, const float* B32, const u
     a.vec_store = 1;
     a.alpha = 1.f;
     a.Wprev = Wprev;
-    a.P = P.t_splits > 1 ? at<float>(ws, P.off_split) : nullptr;
+    a.P = geo.splits > 1 ? at<float>(ws, P.off_split) : nullptr;
     a.norm_part = at<double>(ws, P.off_norm_part);
     a.ls = ls;
     a.pred = pred;
@@ -183,7 +198,7 @@ GemmArgs trial_args(const Plan& P, void* ws, int prec, const float* B32, const u
 void enqueue_trial(const GemmArgs& a, int prec, hipStream_t st) {
     if (a.splits > 1) {
         launch_gemm(a, EPI_PARTIAL, prec, st);
-        launch_splitk_reduce(a, st);
+        launch_splitk_reduce(a, prec, st);
     } else {
         launch_gemm(a, EPI_TRIAL, prec, st);
     }
@@ -207,8 +222,9 @@ GemmArgs grad_args(const Plan& P, void* ws, int prec, const float* Wt, int wslot
     a.M = M;
     a.N = (int)P.p;
     a.K = (int)P.n_pad;
-    a.tilesM = (int)cdiv(M, kBM);
-    a.tilesN = P.g_tilesN;
+    const int bm = prec == PREC_FP32 ? kBM : kWBM, bn = prec == PREC_FP32 ? kBN : kWBN;
+    a.tilesM = (int)cdiv(M, bm);
+    a.tilesN = (int)cdiv(P.p, bn);
     a.splits = 1;
     a.C = C;
     a.ldc = ldc;
@@ -449,7 +465,7 @@ int accord_objective(const float* X, int64_t n, int64_t p, const float* Omega, d
     const int nb = prox_blocks(a.total);
     launch_prox(a, nb, st);
     launch_combine_objective(a.part, nb, at<double>(ws, P.off_norm_part),
-                             P.t_tilesM * P.t_tilesN, lambda, 1.0 / (double)n, out, st);
+                             P.t32.tiles(), lambda, 1.0 / (double)n, out, st);
     HIP_TRY(hipGetLastError());
     return ACCORD_OK;
 }
@@ -489,7 +505,8 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
     double* prox_part = at<double>(ws, P.off_prox_part);
     double* norm_part = at<double>(ws, P.off_norm_part);
     int32_t* trials_log = at<int32_t>(ws, P.off_trials);
-    const int ttiles = P.t_tilesM * P.t_tilesN;
+    const int ttiles32 = P.t32.tiles();  // setup product W0 = X Omega0 (FP32 kernel)
+    const int ttiles = P.tp.tiles();     // trial products of the form's kernel
     const int64_t total = p * P.p_pad;
 
     // ---- setup: operands, L, W0 = X Omega0, f(Omega0)
@@ -517,7 +534,7 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
         a.reduce_only = 1;
         launch_prox(a, P.nprox, st);
     }
-    launch_fit_init(ls, prox_part, P.nprox, norm_part, ttiles, trace, st);
+    launch_fit_init(ls, prox_part, P.nprox, norm_part, ttiles32, trace, st);
     HIP_TRY(hipGetLastError());
     LsState host = {};
     HIP_TRY(hipMemcpyAsync(&host, ls, sizeof host, hipMemcpyDeviceToHost, st));

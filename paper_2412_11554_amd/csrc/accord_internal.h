@@ -11,14 +11,18 @@ namespace accord {
 // geometry
 // ---------------------------------------------------------------------------
 constexpr int kPad = 64;            // K-dimension padding of every MFMA operand
-constexpr int kBM = 128;            // GEMM workgroup tile (rows of C)
-constexpr int kBN = 128;            // GEMM workgroup tile (columns of C)
+constexpr int kBM = 128;            // FP32 GEMM workgroup tile (rows of C)
+constexpr int kBN = 128;            // FP32 GEMM workgroup tile (columns of C)
+constexpr int kWBM = 256;           // bf16 GEMM workgroup tile (rows of C)
+constexpr int kWBN = 256;           // bf16 GEMM workgroup tile (columns of C)
+constexpr int kWThreads = 512;      // bf16 GEMM threads per workgroup
 constexpr int kBK32 = 32;           // FP32 GEMM K step staged through LDS
 constexpr int kThreads = 256;       // threads per workgroup for every kernel
 constexpr int kMaxProxBlocks = 4096;
 constexpr int kPartCols = 8;        // FP64 partial sums per prox workgroup
 constexpr int kNormCols = 2;        // FP64 partial sums per trial-GEMM tile
-constexpr int kSlots = 512;         // resident GEMM workgroups assumed by the split-K choice
+constexpr int kSlots = 512;         // resident FP32 GEMM workgroups (2 per CU, 256 CUs)
+constexpr int kWSlots = 256;        // resident bf16 GEMM workgroups (1 per CU)
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -116,7 +120,7 @@ void launch_pad_x(const float* X, int64_t n, int64_t p, float* Xp, int64_t p_pad
 void launch_copy_cols(const float* src, int64_t ld_src, float* dst, int64_t ld_dst, int64_t p,
                       int64_t rows, LsState* check_ls, hipStream_t st);
 void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st);
-void launch_splitk_reduce(const GemmArgs& a, hipStream_t st);
+void launch_splitk_reduce(const GemmArgs& a, int prec, hipStream_t st);
 int prox_blocks(int64_t total);
 void launch_prox(ProxArgs a, int nblocks, hipStream_t st);
 void launch_finalize(LsState* ls, const double* prox_part, int nprox, const double* norm_part,

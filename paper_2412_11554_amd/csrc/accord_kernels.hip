@@ -31,9 +31,9 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// Block-wide sum of NV doubles (blockDim.x == kThreads) through the LDS scratch `sh`
-// (kThreads / 64 * NV doubles); result valid in thread 0.
-template <int NV>
+// Block-wide sum of NV doubles over NW waves (blockDim.x == 64 NW) through the LDS
+// scratch `sh` (NW * NV doubles); result valid in thread 0.
+template <int NV, int NW = kThreads / 64>
 __device__ inline void block_sum_in(double (&v)[NV], double* sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -48,17 +48,17 @@ __device__ inline void block_sum_in(double (&v)[NV], double* sh) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             double s = sh[q];
-            for (int w = 1; w < kThreads / 64; ++w) s += sh[w * NV + q];
+            for (int w = 1; w < NW; ++w) s += sh[w * NV + q];
             v[q] = s;
         }
     }
     __syncthreads();
 }
 
-template <int NV>
+template <int NV, int NW = kThreads / 64>
 __device__ inline void block_sum(double (&v)[NV]) {
-    __shared__ double sh[kThreads / 64 * NV];
-    block_sum_in<NV>(v, sh);
+    __shared__ double sh[NW * NV];
+    block_sum_in<NV, NW>(v, sh);
 }
 
 // Sum of `count` rows of a [count][stride] partial array, columns 0..NV-1,
@@ -584,6 +584,203 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_bf16(GemmArgs g) {
     gemm_epilogue<EPI>(g, acc, tile_m, tile_n, split, (double*)&sA[0][0][0]);
 }
 
+// ---------------------------------------------------------------------------
+// Wide bf16 GEMM: 256 x 256 workgroup tile, 8 waves (2 along M x 4 along N), each
+// wave 128 x 64 = 4 x 2 blocks of v_mfma_f32_32x32x16_bf16, the full-rate bf16
+// instruction on gfx950 (the 16x16x32 form issues at about two thirds of it).
+// Twice the flops per byte of operand traffic of the 128 x 128 tile, which the
+// three-pass form needs to stay ahead of L2.  One workgroup per CU (160 KiB LDS for
+// the double-buffered hi/lo stages).
+//   32x32x16 operands: lane l supplies row / column l % 32, K values 8 (l / 32) .. +7.
+//   Accumulator register r of lane l holds C(8 (r / 4) + 4 (l / 32) + r % 4, l % 32).
+// ---------------------------------------------------------------------------
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+template <int PASSES, int EPI>
+__global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16w(GemmArgs g) {
+    if (gemm_skip(g)) return;
+    constexpr int BK = PASSES == 1 ? 64 : 32;
+    constexpr int LDK = BK + 8;
+    constexpr int H = PASSES == 1 ? 1 : 2;
+    constexpr int CPR = BK / 8;
+    constexpr int ROWS = kWThreads / CPR;
+    constexpr int RPT = kWBM / ROWS;
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][H][kWBM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][H][kWBN * LDK];
+
+    int tile_m, tile_n, split;
+    decode_tile(g, tile_m, tile_n, split);
+    const int m0 = tile_m * kWBM, n0 = tile_n * kWBN;
+    const int ksteps = g.K / BK;
+    const int s_begin = (int)((int64_t)ksteps * split / g.splits);
+    const int s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lrow = tid / CPR, lcol = (tid % CPR) * 8;
+    const uint16_t* pa[H][RPT];
+    const uint16_t* pb[H][RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        int ra = m0 + lrow + ROWS * i;
+        ra = ra < g.M ? ra : g.M - 1;
+        int rb = n0 + lrow + ROWS * i;
+        rb = rb < g.N ? rb : g.N - 1;
+        pa[0][i] = g.Ah + (int64_t)ra * g.lda + lcol;
+        pb[0][i] = g.Bh + (int64_t)rb * g.ldb + lcol;
+        if (H == 2) {
+            pa[H - 1][i] = g.Al + (int64_t)ra * g.lda + lcol;
+            pb[H - 1][i] = g.Bl + (int64_t)rb * g.ldb + lcol;
+        }
+    }
+    uint4 va[H][RPT], vb[H][RPT];
+    f16v acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
+    const int r32 = lane & 31, k8 = (lane >> 5) * 8;
+
+    auto gload = [&](int s) {
+        const int64_t ko = (int64_t)s * BK;
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                va[h][i] = *(const uint4*)(pa[h][i] + ko);
+                vb[h][i] = *(const uint4*)(pb[h][i] + ko);
+            }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                *(uint4*)&sA[buf][h][(lrow + ROWS * i) * LDK + lcol] = va[h][i];
+                *(uint4*)&sB[buf][h][(lrow + ROWS * i) * LDK + lcol] = vb[h][i];
+            }
+    };
+
+    if (s_begin < s_end) {
+        gload(s_begin);
+        sstore(0);
+        __syncthreads();
+        int cur = 0;
+        for (int s = s_begin; s < s_end; ++s) {
+            const bool more = s + 1 < s_end;
+            if (more) gload(s + 1);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 16) {
+                bf8 ah[4], bh[2];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    ah[i] = *(const bf8*)&sA[cur][0][(wm + 32 * i + r32) * LDK + kk + k8];
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    bh[j] = *(const bf8*)&sB[cur][0][(wn + 32 * j + r32) * LDK + kk + k8];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j],
+                                                                            acc[i][j], 0, 0, 0);
+                if (PASSES == 3) {
+                    bf8 al[4], bl[2];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        bl[j] = *(const bf8*)&sB[cur][H - 1][(wn + 32 * j + r32) * LDK + kk + k8];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        al[i] = *(const bf8*)&sA[cur][H - 1][(wm + 32 * i + r32) * LDK + kk + k8];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                al[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+            }
+            if (more) sstore(cur ^ 1);
+            __syncthreads();
+            cur ^= 1;
+        }
+    }
+    __syncthreads();
+
+    const int tile = tile_m + tile_n * g.tilesM;
+    if (EPI == EPI_PARTIAL) {
+        f4* P = (f4*)(g.P + ((int64_t)split * g.tilesM * g.tilesN + tile) * (kWBM * kWBN));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    P[((i * 2 + j) * 4 + q) * kWThreads + tid] =
+                        f4{acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2],
+                           acc[i][j][4 * q + 3]};
+        return;
+    }
+    const int mw = m0 + wm + 4 * (lane >> 5), nw = n0 + wn + (lane & 31);
+    double nv[2] = {0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                store_frag<EPI>(g,
+                                f4{acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2],
+                                   acc[i][j][4 * q + 3]},
+                                mw + 32 * i + 8 * q, nw + 32 * j, nv);
+    if (EPI == EPI_TRIAL) {
+        block_sum_in<2, kWThreads / 64>(nv, (double*)&sA[0][0][0]);
+        if (tid == 0) {
+            g.norm_part[(int64_t)tile * kNormCols + 0] = nv[0];
+            g.norm_part[(int64_t)tile * kNormCols + 1] = nv[1];
+        }
+    }
+}
+
+// Split-K reduction for the wide tiles (same thread -> fragment map as k_gemm_bf16w).
+__global__ void __launch_bounds__(kWThreads) k_splitk_reduce_w(GemmArgs g) {
+    if (g.ls) {
+        if (g.pred >= 1 && g.ls->converged) return;
+        if (g.pred >= 2 && g.ls->done) return;
+    }
+    const int tile = blockIdx.x;
+    const int tile_m = tile % g.tilesM, tile_n = tile / g.tilesM;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int mw = tile_m * kWBM + (wave >> 2) * 128 + 4 * (lane >> 5);
+    const int nw = tile_n * kWBN + (wave & 3) * 64 + (lane & 31);
+    const int64_t tiles = (int64_t)g.tilesM * g.tilesN;
+    double nv[2] = {0.0, 0.0};
+#pragma unroll 1
+    for (int idx = 0; idx < 32; ++idx) {
+        const int i = idx >> 3, j = (idx >> 2) & 1, q = idx & 3;
+        f4 v = f4{0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < g.splits; ++s) {
+            const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kWBM * kWBN));
+            v += P[idx * kWThreads + tid];
+        }
+        store_frag<EPI_TRIAL>(g, v, mw + 32 * i + 8 * q, nw + 32 * j, nv);
+    }
+    block_sum<2, kWThreads / 64>(nv);
+    if (tid == 0) {
+        g.norm_part[(int64_t)tile * kNormCols + 0] = nv[0];
+        g.norm_part[(int64_t)tile * kNormCols + 1] = nv[1];
+    }
+}
+
 // Fixed-order sum of the split-K partial tiles, then the trial epilogue.
 // One workgroup per tile; thread t owns the same accumulator slots it had in the
 // GEMM kernel, so (m, n) follow from (t, i, j) exactly as there.
@@ -619,9 +816,9 @@ __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
 template <int EPI>
 static void launch_gemm_epi(const GemmArgs& a, int prec, unsigned blocks, hipStream_t st) {
     if (prec == PREC_BF16X3)
-        k_gemm_bf16<3, EPI><<<blocks, kThreads, 0, st>>>(a);
+        k_gemm_bf16w<3, EPI><<<blocks, kWThreads, 0, st>>>(a);
     else if (prec == PREC_BF16X1)
-        k_gemm_bf16<1, EPI><<<blocks, kThreads, 0, st>>>(a);
+        k_gemm_bf16w<1, EPI><<<blocks, kWThreads, 0, st>>>(a);
     else
         k_gemm_f32<EPI><<<blocks, kThreads, 0, st>>>(a);
 }
@@ -636,9 +833,12 @@ void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st) {
         launch_gemm_epi<EPI_PARTIAL>(a, prec, blocks, st);
 }
 
-void launch_splitk_reduce(const GemmArgs& a, hipStream_t st) {
+void launch_splitk_reduce(const GemmArgs& a, int prec, hipStream_t st) {
     const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN);
-    k_splitk_reduce<<<blocks, kThreads, 0, st>>>(a);
+    if (prec == PREC_FP32)
+        k_splitk_reduce<<<blocks, kThreads, 0, st>>>(a);
+    else
+        k_splitk_reduce_w<<<blocks, kWThreads, 0, st>>>(a);
 }
 
 // ---------------------------------------------------------------------------
