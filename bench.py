@@ -7,8 +7,8 @@ HBM before the timed region.  `value` = prox-grad iterations per second of the
 headline form over the K timed steps.
 
 Forms (the contraction arithmetic; prox, test and sums are the same in all):
-  fp32    FP32 MFMA (the plain FP32 solver)
-  bf16x3  bf16 MFMA on hi/lo splits, three passes (meets the FP32 error bar)
+  bf16x3  bf16 MFMA on hi/lo splits, three passes (meets the FP32 error bar); headline
+  fp32    FP32 MFMA (the plain FP32 solver it is compared with)
 The first form in --forms is the headline.
 
 Also reported per form:
@@ -142,7 +142,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="fp32,bf16x3",
+    ap.add_argument("--forms", default="bf16x3,fp32",
                     help="comma-separated precision forms; the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")

@@ -59,6 +59,12 @@ struct Geo {
     int tiles() const { return tilesM * tilesN; }
 };
 
+// rows of FP64 norm partials a trial product leaves (one per tile, or one per
+// reduction workgroup when the bf16 split-K reduction runs)
+int norm_rows(const Geo& g, int prec) {
+    return (g.splits > 1 && prec != PREC_FP32) ? g.tiles() * kWReduceParts : g.tiles();
+}
+
 struct Plan {
     int64_t n, p, n_pad, p_pad;
     int prec;
@@ -112,7 +118,7 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     }
     P.nprox = prox_blocks(p * P.p_pad);
     const bool bf = prec != PREC_FP32;
-    const int ttiles = P.t32.tiles() > P.tp.tiles() ? P.t32.tiles() : P.tp.tiles();
+    const int ttiles = std::max(norm_rows(P.t32, PREC_FP32), norm_rows(P.tp, prec));
     const size_t split_floats =
         std::max((size_t)(P.t32.splits > 1 ? P.t32.splits : 0) * P.t32.tiles() * kBM * kBN,
                  (size_t)(P.tp.splits > 1 ? P.tp.splits : 0) * P.tp.tiles() * kWBM * kWBN *
@@ -505,8 +511,8 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
     double* prox_part = at<double>(ws, P.off_prox_part);
     double* norm_part = at<double>(ws, P.off_norm_part);
     int32_t* trials_log = at<int32_t>(ws, P.off_trials);
-    const int ttiles32 = P.t32.tiles();  // setup product W0 = X Omega0 (FP32 kernel)
-    const int ttiles = P.tp.tiles();     // trial products of the form's kernel
+    const int ttiles32 = norm_rows(P.t32, PREC_FP32);  // setup product W0 = X Omega0 (FP32)
+    const int ttiles = norm_rows(P.tp, prec);          // trial products of the form
     const int64_t total = p * P.p_pad;
 
     // ---- setup: operands, L, W0 = X Omega0, f(Omega0)

@@ -16,6 +16,7 @@ constexpr int kBN = 128;            // FP32 GEMM workgroup tile (columns of C)
 constexpr int kWBM = 256;           // bf16 GEMM workgroup tile (rows of C)
 constexpr int kWBN = 256;           // bf16 GEMM workgroup tile (columns of C)
 constexpr int kWThreads = 512;      // bf16 GEMM threads per workgroup
+constexpr int kWReduceParts = 4;    // workgroups per tile in the bf16 split-K reduction
 constexpr int kBK32 = 32;           // FP32 GEMM K step staged through LDS
 constexpr int kThreads = 256;       // threads per workgroup for every kernel
 constexpr int kMaxProxBlocks = 4096;

@@ -21,6 +21,7 @@
 namespace accord {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));  // 16-byte staging word
 
 // ---------------------------------------------------------------------------
 // reductions
@@ -422,15 +423,15 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
         __syncthreads();
         int cur = 0;
         for (int s = s_begin; s < s_end; ++s) {
-            const bool more = s + 1 < s_end;
-            if (more) {
-                const int64_t ko = (int64_t)(s + 1) * kBK32;
+            {   // unconditional prefetch (see k_gemm_bf16w)
+                const int64_t ko = (int64_t)(s + 1 < s_end ? s + 1 : s) * kBK32;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     va[i] = *(const f4*)(pa[i] + ko);
                     vb[i] = *(const f4*)(pb[i] + ko);
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
             const float* a_base = &sA[cur][(wm + r16) * kLDK32 + g4];
             const float* b_base = &sB[cur][(wn + r16) * kLDK32 + g4];
 #pragma unroll
@@ -449,12 +450,11 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][q], bf[j][q],
                                                                              acc[i][j], 0, 0, 0);
             }
-            if (more) {
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    *(f4*)&sA[cur ^ 1][(lrow + 32 * i) * kLDK32 + lcol] = va[i];
-                    *(f4*)&sB[cur ^ 1][(lrow + 32 * i) * kLDK32 + lcol] = vb[i];
-                }
+            for (int i = 0; i < 4; ++i) {
+                *(f4*)&sA[cur ^ 1][(lrow + 32 * i) * kLDK32 + lcol] = va[i];
+                *(f4*)&sB[cur ^ 1][(lrow + 32 * i) * kLDK32 + lcol] = vb[i];
             }
             __syncthreads();
             cur ^= 1;
@@ -485,22 +485,23 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_bf16(GemmArgs g) {
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lrow = tid / CPR, lcol = (tid % CPR) * 8;
-    const uint16_t* pa[H][RPT];
-    const uint16_t* pb[H][RPT];
+    // operand half h, row pass i -> flat index h * RPT + i
+    const uint16_t* pa[H * RPT];
+    const uint16_t* pb[H * RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         int ra = m0 + lrow + ROWS * i;
         ra = ra < g.M ? ra : g.M - 1;
         int rb = n0 + lrow + ROWS * i;
         rb = rb < g.N ? rb : g.N - 1;
-        pa[0][i] = g.Ah + (int64_t)ra * g.lda + lcol;
-        pb[0][i] = g.Bh + (int64_t)rb * g.ldb + lcol;
+        pa[i] = g.Ah + (int64_t)ra * g.lda + lcol;
+        pb[i] = g.Bh + (int64_t)rb * g.ldb + lcol;
         if (H == 2) {
-            pa[H - 1][i] = g.Al + (int64_t)ra * g.lda + lcol;
-            pb[H - 1][i] = g.Bl + (int64_t)rb * g.ldb + lcol;
+            pa[(H - 1) * RPT + i] = g.Al + (int64_t)ra * g.lda + lcol;
+            pb[(H - 1) * RPT + i] = g.Bl + (int64_t)rb * g.ldb + lcol;
         }
     }
-    uint4 va[H][RPT], vb[H][RPT];
+    u4 va[H * RPT], vb[H * RPT];
     f4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -510,34 +511,39 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_bf16(GemmArgs g) {
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
     const int r16 = lane & 15, k8 = (lane >> 4) * 8;
 
-    auto gload = [&](int s) {
-        const int64_t ko = (int64_t)s * BK;
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                va[h][i] = *(const uint4*)(pa[h][i] + ko);
-                vb[h][i] = *(const uint4*)(pb[h][i] + ko);
-            }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                *(uint4*)&sA[buf][h][(lrow + ROWS * i) * LDK + lcol] = va[h][i];
-                *(uint4*)&sB[buf][h][(lrow + ROWS * i) * LDK + lcol] = vb[h][i];
-            }
-    };
 
     if (s_begin < s_end) {
-        gload(s_begin);
-        sstore(0);
+        {
+            const int64_t ko = (int64_t)s_begin * BK;
+#pragma unroll
+        for (int q = 0; q < H * RPT; ++q) {
+            va[q] = *(const u4*)(pa[q] + ko);
+            vb[q] = *(const u4*)(pb[q] + ko);
+        }
+        }
+#pragma unroll
+        for (int q = 0; q < H * RPT; ++q) {
+            const int off = (lrow + ROWS * (q % RPT)) * LDK + lcol;
+            *(u4*)&sA[0][q / RPT][off] = va[q];
+            *(u4*)&sB[0][q / RPT][off] = vb[q];
+        }
         __syncthreads();
         int cur = 0;
         for (int s = s_begin; s < s_end; ++s) {
-            const bool more = s + 1 < s_end;
-            if (more) gload(s + 1);
+            // Unconditional prefetch (the last step re-reads its own rows into the idle
+            // buffer): a conditional load would be merged at a branch join, which forces
+            // a wait on it before the MFMAs below.  The scheduling barriers keep the
+            // loads ahead of the MFMAs and their LDS stores after them, so the load
+            // latency hides behind the whole MFMA block.
+            {
+                const int64_t ko = (int64_t)(s + 1 < s_end ? s + 1 : s) * BK;
+#pragma unroll
+            for (int q = 0; q < H * RPT; ++q) {
+                va[q] = *(const u4*)(pa[q] + ko);
+                vb[q] = *(const u4*)(pb[q] + ko);
+            }
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 32) {
                 bf8 ah[4], bh[4];
@@ -575,7 +581,13 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_bf16(GemmArgs g) {
                                 al[i], bh[j], acc[i][j], 0, 0, 0);
                 }
             }
-            if (more) sstore(cur ^ 1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < H * RPT; ++q) {
+                const int off = (lrow + ROWS * (q % RPT)) * LDK + lcol;
+                *(u4*)&sA[cur ^ 1][q / RPT][off] = va[q];
+                *(u4*)&sB[cur ^ 1][q / RPT][off] = vb[q];
+            }
             __syncthreads();
             cur ^= 1;
         }
@@ -617,22 +629,23 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16w(GemmArgs g) {
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lrow = tid / CPR, lcol = (tid % CPR) * 8;
-    const uint16_t* pa[H][RPT];
-    const uint16_t* pb[H][RPT];
+    // operand half h, row pass i -> flat index h * RPT + i
+    const uint16_t* pa[H * RPT];
+    const uint16_t* pb[H * RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         int ra = m0 + lrow + ROWS * i;
         ra = ra < g.M ? ra : g.M - 1;
         int rb = n0 + lrow + ROWS * i;
         rb = rb < g.N ? rb : g.N - 1;
-        pa[0][i] = g.Ah + (int64_t)ra * g.lda + lcol;
-        pb[0][i] = g.Bh + (int64_t)rb * g.ldb + lcol;
+        pa[i] = g.Ah + (int64_t)ra * g.lda + lcol;
+        pb[i] = g.Bh + (int64_t)rb * g.ldb + lcol;
         if (H == 2) {
-            pa[H - 1][i] = g.Al + (int64_t)ra * g.lda + lcol;
-            pb[H - 1][i] = g.Bl + (int64_t)rb * g.ldb + lcol;
+            pa[(H - 1) * RPT + i] = g.Al + (int64_t)ra * g.lda + lcol;
+            pb[(H - 1) * RPT + i] = g.Bl + (int64_t)rb * g.ldb + lcol;
         }
     }
-    uint4 va[H][RPT], vb[H][RPT];
+    u4 va[H * RPT], vb[H * RPT];
     f16v acc[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -644,34 +657,39 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16w(GemmArgs g) {
     const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
     const int r32 = lane & 31, k8 = (lane >> 5) * 8;
 
-    auto gload = [&](int s) {
-        const int64_t ko = (int64_t)s * BK;
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                va[h][i] = *(const uint4*)(pa[h][i] + ko);
-                vb[h][i] = *(const uint4*)(pb[h][i] + ko);
-            }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                *(uint4*)&sA[buf][h][(lrow + ROWS * i) * LDK + lcol] = va[h][i];
-                *(uint4*)&sB[buf][h][(lrow + ROWS * i) * LDK + lcol] = vb[h][i];
-            }
-    };
 
     if (s_begin < s_end) {
-        gload(s_begin);
-        sstore(0);
+        {
+            const int64_t ko = (int64_t)s_begin * BK;
+#pragma unroll
+        for (int q = 0; q < H * RPT; ++q) {
+            va[q] = *(const u4*)(pa[q] + ko);
+            vb[q] = *(const u4*)(pb[q] + ko);
+        }
+        }
+#pragma unroll
+        for (int q = 0; q < H * RPT; ++q) {
+            const int off = (lrow + ROWS * (q % RPT)) * LDK + lcol;
+            *(u4*)&sA[0][q / RPT][off] = va[q];
+            *(u4*)&sB[0][q / RPT][off] = vb[q];
+        }
         __syncthreads();
         int cur = 0;
         for (int s = s_begin; s < s_end; ++s) {
-            const bool more = s + 1 < s_end;
-            if (more) gload(s + 1);
+            // Unconditional prefetch (the last step re-reads its own rows into the idle
+            // buffer): a conditional load would be merged at a branch join, which forces
+            // a wait on it before the MFMAs below.  The scheduling barriers keep the
+            // loads ahead of the MFMAs and their LDS stores after them, so the load
+            // latency hides behind the whole MFMA block.
+            {
+                const int64_t ko = (int64_t)(s + 1 < s_end ? s + 1 : s) * BK;
+#pragma unroll
+            for (int q = 0; q < H * RPT; ++q) {
+                va[q] = *(const u4*)(pa[q] + ko);
+                vb[q] = *(const u4*)(pb[q] + ko);
+            }
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 16) {
                 bf8 ah[4], bh[2];
@@ -709,7 +727,13 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16w(GemmArgs g) {
                                 al[i], bh[j], acc[i][j], 0, 0, 0);
                 }
             }
-            if (more) sstore(cur ^ 1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < H * RPT; ++q) {
+                const int off = (lrow + ROWS * (q % RPT)) * LDK + lcol;
+                *(u4*)&sA[cur ^ 1][q / RPT][off] = va[q];
+                *(u4*)&sB[cur ^ 1][q / RPT][off] = vb[q];
+            }
             __syncthreads();
             cur ^= 1;
         }
@@ -752,20 +776,23 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16w(GemmArgs g) {
 }
 
 // Split-K reduction for the wide tiles (same thread -> fragment map as k_gemm_bf16w).
+// kWReduceParts workgroups per tile, each owning a quarter of the 32 fragments of
+// every thread; norm partial row = part * tiles + tile.
 __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_w(GemmArgs g) {
     if (g.ls) {
         if (g.pred >= 1 && g.ls->converged) return;
         if (g.pred >= 2 && g.ls->done) return;
     }
-    const int tile = blockIdx.x;
+    const int tiles = g.tilesM * g.tilesN;
+    const int tile = blockIdx.x % tiles, part = blockIdx.x / tiles;
     const int tile_m = tile % g.tilesM, tile_n = tile / g.tilesM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int mw = tile_m * kWBM + (wave >> 2) * 128 + 4 * (lane >> 5);
     const int nw = tile_n * kWBN + (wave & 3) * 64 + (lane & 31);
-    const int64_t tiles = (int64_t)g.tilesM * g.tilesN;
+    constexpr int PER = 32 / kWReduceParts;
     double nv[2] = {0.0, 0.0};
 #pragma unroll 1
-    for (int idx = 0; idx < 32; ++idx) {
+    for (int idx = part * PER; idx < (part + 1) * PER; ++idx) {
         const int i = idx >> 3, j = (idx >> 2) & 1, q = idx & 3;
         f4 v = f4{0.f, 0.f, 0.f, 0.f};
         for (int s = 0; s < g.splits; ++s) {
@@ -776,8 +803,9 @@ __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_w(GemmArgs g) {
     }
     block_sum<2, kWThreads / 64>(nv);
     if (tid == 0) {
-        g.norm_part[(int64_t)tile * kNormCols + 0] = nv[0];
-        g.norm_part[(int64_t)tile * kNormCols + 1] = nv[1];
+        const int64_t row = (int64_t)part * tiles + tile;
+        g.norm_part[row * kNormCols + 0] = nv[0];
+        g.norm_part[row * kNormCols + 1] = nv[1];
     }
 }
 
@@ -838,7 +866,7 @@ void launch_splitk_reduce(const GemmArgs& a, int prec, hipStream_t st) {
     if (prec == PREC_FP32)
         k_splitk_reduce<<<blocks, kThreads, 0, st>>>(a);
     else
-        k_splitk_reduce_w<<<blocks, kWThreads, 0, st>>>(a);
+        k_splitk_reduce_w<<<blocks * kWReduceParts, kWThreads, 0, st>>>(a);
 }
 
 // ---------------------------------------------------------------------------
