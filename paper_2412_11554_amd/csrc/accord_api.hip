@@ -62,19 +62,22 @@ struct Geo {
 // rows of FP64 norm partials a trial product leaves (one per tile, or one per
 // reduction workgroup when the bf16 split-K reduction runs)
 int norm_rows(const Geo& g, int prec) {
-    return (g.splits > 1 && prec != PREC_FP32) ? g.tiles() * kWReduceParts : g.tiles();
+    return (g.splits > 1 && prec != PREC_FP32) ? g.tiles() * kFReduceParts : g.tiles();
 }
 
 struct Plan {
     int64_t n, p, n_pad, p_pad;
     int prec;
     // trial GEMM  (C = W^T:  M = n_pad, N = p, K = p_pad): FP32 geometry (setup
-    // products) and the geometry of the form's own kernel
+    // products and the FP32 form) and, for the bf16 forms, the fused prox + trial
+    // kernel's geometry
     Geo t32, tp;
+    int fused;      // bf16 forms: the prox runs inside the trial kernel
+    int prox_rows;  // FP64 prox partial rows left per trial
     int nprox;
     size_t off_ls, off_prox_part, off_norm_part, off_pow_u, off_pow_w, off_pow_pu, off_pow_pw,
         off_trials, off_xp, off_xt, off_xsplit[4], off_wt0, off_wt1, off_wsplit[4], off_split,
-        off_om0, end_grad, off_g, off_d, off_dh, off_dl, off_om1, end_fit;
+        off_om0, end_grad, off_g, off_d, off_om1, end_fit;
     size_t end_prox;
 };
 
@@ -109,26 +112,29 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     P.t32.tilesM = (int)cdiv(P.n_pad, kBM);
     P.t32.tilesN = (int)cdiv(p, kBN);
     P.t32.splits = choose_splits(P.t32.tiles(), (int)(P.p_pad / kPad), kSlots);
-    if (prec == PREC_FP32) {
+    P.fused = prec != PREC_FP32;
+    if (!P.fused) {
         P.tp = P.t32;
     } else {
-        P.tp.tilesM = (int)cdiv(P.n_pad, kWBM);
-        P.tp.tilesN = (int)cdiv(p, kWBN);
+        P.tp.tilesM = (int)cdiv(P.n_pad, kFBM);
+        P.tp.tilesN = (int)cdiv(p, kFBN);
         P.tp.splits = choose_splits(P.tp.tiles(), (int)(P.p_pad / kPad), kWSlots);
     }
     P.nprox = prox_blocks(p * P.p_pad);
+    P.prox_rows = P.fused ? P.tp.tilesN * P.tp.splits : P.nprox;
     const bool bf = prec != PREC_FP32;
     const int ttiles = std::max(norm_rows(P.t32, PREC_FP32), norm_rows(P.tp, prec));
     const size_t split_floats =
         std::max((size_t)(P.t32.splits > 1 ? P.t32.splits : 0) * P.t32.tiles() * kBM * kBN,
-                 (size_t)(P.tp.splits > 1 ? P.tp.splits : 0) * P.tp.tiles() * kWBM * kWBN *
-                     (prec == PREC_FP32 ? 0 : 1));
+                 (size_t)(P.tp.splits > 1 ? P.tp.splits : 0) * P.tp.tiles() * kFBM * kFBN *
+                     (P.fused ? 1 : 0));
     const size_t xn = (size_t)(P.n_pad * P.p_pad);   // padded X elements
     const size_t wn = (size_t)(p * P.n_pad);         // W^T elements
     const size_t on = (size_t)(p * P.p_pad);         // p x p_pad elements
     size_t cur = 0;
     P.off_ls = bump(cur, sizeof(LsState));
-    P.off_prox_part = bump(cur, (size_t)kMaxProxBlocks * kPartCols * sizeof(double));
+    P.off_prox_part = bump(cur, (size_t)std::max(kMaxProxBlocks, P.prox_rows) * kPartCols *
+                                    sizeof(double));
     P.end_prox = cur;
     P.off_norm_part = bump(cur, (size_t)ttiles * kNormCols * sizeof(double));
     P.off_pow_u = bump(cur, (size_t)P.n_pad * sizeof(double));
@@ -146,9 +152,7 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     P.off_om0 = bump(cur, on * sizeof(float));
     P.end_grad = cur;
     P.off_g = bump(cur, on * sizeof(float));
-    P.off_d = bump(cur, bf ? 0 : on * sizeof(float));
-    P.off_dh = bump(cur, bf ? on * sizeof(uint16_t) : 0);
-    P.off_dl = bump(cur, prec == PREC_BF16X3 ? on * sizeof(uint16_t) : 0);
+    P.off_d = bump(cur, bf ? 0 : on * sizeof(float));  // bf16 forms never store Delta
     P.off_om1 = bump(cur, on * sizeof(float));
     P.end_fit = cur;
     return P;
@@ -506,8 +510,6 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
     const int prec = prm->precision;
     const bool bf = prec != PREC_FP32;
     float* D = bf ? nullptr : at<float>(ws, P.off_d);
-    uint16_t* Dh = bf ? at<uint16_t>(ws, P.off_dh) : nullptr;
-    uint16_t* Dl = prec == PREC_BF16X3 ? at<uint16_t>(ws, P.off_dl) : nullptr;
     double* prox_part = at<double>(ws, P.off_prox_part);
     double* norm_part = at<double>(ws, P.off_norm_part);
     int32_t* trials_log = at<int32_t>(ws, P.off_trials);
@@ -574,23 +576,27 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
             a.g = G;
             a.om_new = om[nxt];
             a.d = D;
-            a.dh = Dh;
-            a.dl = Dl;
             a.total = total;
             a.ld = P.p_pad;
             a.p = p;
             a.ls = ls;
             a.part = prox_part;
-            Launch lp = {nullptr, nullptr, t, k};
-            if (timing) { lp.a = pool.get(); lp.b = pool.get(); HIP_TRY(hipEventRecord(lp.a, st)); }
-            launch_prox(a, P.nprox, st);
-            if (timing) { HIP_TRY(hipEventRecord(lp.b, st)); ev_prox.push_back(lp); }
+            GemmArgs ta = trial_args(P, ws, prec, D, nullptr, nullptr, wt[cur], wt[nxt],
+                                     bf ? nxt : -1, ls, 2);
+            if (!bf) {
+                Launch lp = {nullptr, nullptr, t, k};
+                if (timing) { lp.a = pool.get(); lp.b = pool.get(); HIP_TRY(hipEventRecord(lp.a, st)); }
+                launch_prox(a, P.nprox, st);
+                if (timing) { HIP_TRY(hipEventRecord(lp.b, st)); ev_prox.push_back(lp); }
+            }
             Launch lt = {nullptr, nullptr, t, k};
             if (timing) { lt.a = pool.get(); lt.b = pool.get(); HIP_TRY(hipEventRecord(lt.a, st)); }
-            enqueue_trial(trial_args(P, ws, prec, D, Dh, Dl, wt[cur], wt[nxt], bf ? nxt : -1, ls, 2),
-                          prec, st);
+            if (bf)
+                launch_trial_fused(ta, a, prec, st);
+            else
+                enqueue_trial(ta, prec, st);
             if (timing) { HIP_TRY(hipEventRecord(lt.b, st)); ev_trial.push_back(lt); }
-            launch_finalize(ls, prox_part, P.nprox, norm_part, ttiles, trace, trials_log, st);
+            launch_finalize(ls, prox_part, P.prox_rows, norm_part, ttiles, trace, trials_log, st);
         }
         HIP_TRY(hipGetLastError());
         cur = nxt;

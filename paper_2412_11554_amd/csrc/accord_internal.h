@@ -17,6 +17,9 @@ constexpr int kWBM = 256;           // bf16 GEMM workgroup tile (rows of C)
 constexpr int kWBN = 256;           // bf16 GEMM workgroup tile (columns of C)
 constexpr int kWThreads = 512;      // bf16 GEMM threads per workgroup
 constexpr int kWReduceParts = 4;    // workgroups per tile in the bf16 split-K reduction
+constexpr int kFBM = 256;           // fused prox + trial tile (rows of W^T = samples)
+constexpr int kFBN = 128;           // fused prox + trial tile (columns of Omega)
+constexpr int kFReduceParts = 2;    // workgroups per tile in the fused split-K reduction
 constexpr int kBK32 = 32;           // FP32 GEMM K step staged through LDS
 constexpr int kThreads = 256;       // threads per workgroup for every kernel
 constexpr int kMaxProxBlocks = 4096;
@@ -122,6 +125,7 @@ void launch_copy_cols(const float* src, int64_t ld_src, float* dst, int64_t ld_d
                       int64_t rows, LsState* check_ls, hipStream_t st);
 void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st);
 void launch_splitk_reduce(const GemmArgs& a, int prec, hipStream_t st);
+void launch_trial_fused(const GemmArgs& a, const ProxArgs& px, int prec, hipStream_t st);
 int prox_blocks(int64_t total);
 void launch_prox(ProxArgs a, int nblocks, hipStream_t st);
 void launch_finalize(LsState* ls, const double* prox_part, int nprox, const double* norm_part,

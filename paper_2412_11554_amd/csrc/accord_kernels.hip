@@ -1015,6 +1015,318 @@ __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
     }
 }
 
+// B-operand producer of k_trial_fused for stage `buf` holding K step `step`:
+// prox of the 2 x 4 staged Omega / G values, Delta -> bf16 hi (/ lo) into LDS, and
+// for the owning M tile Omega+ to HBM and the line-search sums.  Also stores the
+// staged X rows.  Off-diagonal entries take the FP32 soft threshold without
+// branches; the one diagonal entry a column can have is redone in FP64 under a
+// rarely taken branch.  The owner's sums are FP32 over each group of 4 consecutive
+// entries and FP64 beyond.  Padded rows hold zeros and contribute nothing; columns
+// past p are zeroed.  (A macro keeps every staging array in registers.)
+#define FUSED_PRODUCE(buf, step)                                                          \
+    do {                                                                                  \
+        const int64_t k0_ = (int64_t)(step) * BK;                                         \
+        _Pragma("unroll") for (int q = 0; q < H * 2; ++q)                                 \
+            *(u4*)&sA[(buf)][q >> 1][(arow + 128 * (q & 1)) * LDK + acol] = va[q];         \
+        _Pragma("unroll") for (int q = 0; q < 2; ++q) {                                   \
+            const f4 o_ = vo[q], g_ = vg[q];                                              \
+            f4 nw_;                                                                       \
+            _Pragma("unroll") for (int u = 0; u < 4; ++u) {                               \
+                const float a_ = fmaf(-tau_f, g_[u], o_[u]);                              \
+                const float t_ = fabsf(a_) - thr_f;                                       \
+                nw_[u] = t_ > 0.f ? copysignf(t_, a_) : 0.f;                              \
+            }                                                                             \
+            const int64_t dpos_ = jcol[q] - (k0_ + br);                                   \
+            const bool has_diag_ = dpos_ >= 0 && dpos_ < 4;                               \
+            float dval_ = 0.f;                                                            \
+            if (has_diag_) {                                                              \
+                const int du_ = (int)dpos_;                                               \
+                const float od_ = du_ == 0 ? o_[0] : du_ == 1 ? o_[1] : du_ == 2 ? o_[2] : o_[3]; \
+                const float gd_ = du_ == 0 ? g_[0] : du_ == 1 ? g_[1] : du_ == 2 ? g_[2] : g_[3]; \
+                dval_ = prox_one(od_, gd_, true, tau, lam, tau_f, thr_f);                 \
+                _Pragma("unroll") for (int u = 0; u < 4; ++u)                             \
+                    nw_[u] = (u == du_) ? dval_ : nw_[u];                                 \
+            }                                                                             \
+            uint16_t h_[4], l_[4];                                                        \
+            f4 dv_;                                                                       \
+            _Pragma("unroll") for (int u = 0; u < 4; ++u)                                 \
+                dv_[u] = delta_repr<DOUT>(nw_[u] - o_[u], h_[u], l_[u]);                  \
+            if (!jvalid[q]) {                                                             \
+                _Pragma("unroll") for (int u = 0; u < 4; ++u) h_[u] = l_[u] = 0;          \
+            }                                                                             \
+            const int lo_ = (bc + 64 * q) * LDK + br;                                     \
+            *(uint2*)&sB[(buf)][0][lo_] =                                                 \
+                make_uint2(h_[0] | ((uint32_t)h_[1] << 16), h_[2] | ((uint32_t)h_[3] << 16)); \
+            if (H == 2)                                                                   \
+                *(uint2*)&sB[(buf)][H - 1][lo_] = make_uint2(                             \
+                    l_[0] | ((uint32_t)l_[1] << 16), l_[2] | ((uint32_t)l_[3] << 16));    \
+            if (owner && jvalid[q]) {                                                     \
+                *(f4*)(pn[q] + k0_) = nw_;                                                \
+                float sd2_ = 0.f, sdg_ = 0.f, sl1_ = 0.f, sfr_ = 0.f;                     \
+                int nz_ = 0;                                                              \
+                _Pragma("unroll") for (int u = 0; u < 4; ++u) {                           \
+                    sd2_ = fmaf(dv_[u], dv_[u], sd2_);                                    \
+                    sdg_ = fmaf(dv_[u], g_[u], sdg_);                                     \
+                    sl1_ += fabsf(nw_[u]);                                                \
+                    sfr_ = fmaf(nw_[u], nw_[u], sfr_);                                    \
+                    nz_ += (nw_[u] != 0.f && !(has_diag_ && u == (int)dpos_)) ? 1 : 0;   \
+                }                                                                         \
+                pacc.d2 += (double)sd2_;                                                  \
+                pacc.dg += (double)sdg_;                                                  \
+                pacc.l1 += (double)sl1_;                                                  \
+                pacc.fro += (double)sfr_;                                                 \
+                pacc.nnz += (double)nz_;                                                  \
+                if (has_diag_) pacc.logd += dval_ > 0.f ? log((double)dval_) : -INFINITY; \
+            }                                                                             \
+        }                                                                                 \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Fused trial kernel of the bf16 forms: prox (eq. 3.5) + trial product.
+//
+// The B operand of X Delta is produced in place: each step streams 32 rows of 128
+// columns of Omega and G (FP32, column-major, so K-contiguous), applies the
+// closed-form prox in registers, and writes the bf16 hi (and lo) parts of
+// Delta = Omega+ - Omega straight into the LDS stage.  The workgroup with tile_m 0
+// owns its column block: it also writes Omega+ and keeps the FP64 line-search sums
+// (||Delta||^2, <Delta, G>, ||Omega+||_1, sum log Omega+_jj, nnz, ||Omega+||_F^2);
+// the other M tiles recompute Delta for their rows of X only.  Delta never goes
+// through HBM, and the separate prox pass disappears.
+// Tile 256 x 128, 8 waves (4 along M x 2 along N), each 64 x 64 = 2 x 2 blocks of
+// v_mfma_f32_32x32x16_bf16; tile_m is the fastest tile index, so the M tiles of a
+// column block run together on one XCD and share Omega / G through its L2.
+// ---------------------------------------------------------------------------
+template <int PASSES, int EPI>
+__global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxArgs px) {
+    if (gemm_skip(g)) return;
+    constexpr int BK = 32;
+    constexpr int LDK = BK + 8;                  // bf16 per LDS row (16-byte pad)
+    constexpr int H = PASSES == 1 ? 1 : 2;
+    constexpr int DOUT = PASSES == 1 ? 1 : 2;
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][H][kFBM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][H][kFBN * LDK];
+
+    const double tau = px.ls->tau, lam = px.ls->lambda;
+    const float tau_f = (float)tau, thr_f = (float)(tau * lam);
+
+    // tile order: tile_m fastest, then tile_n, then split (XCD-contiguous ranges)
+    const int nblk = gridDim.x, bid = blockIdx.x;
+    const int xcd = bid & 7, local = bid >> 3, q8 = nblk >> 3, r8 = nblk & 7;
+    const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + local;
+    const int tile_m = logical % g.tilesM;
+    const int tile_n = (logical / g.tilesM) % g.tilesN;
+    const int split = logical / (g.tilesM * g.tilesN);
+    const bool owner = tile_m == 0;
+    const int m0 = tile_m * kFBM, n0 = tile_n * kFBN;
+    const int ksteps = g.K / BK;
+    const int s_begin = (int)((int64_t)ksteps * split / g.splits);
+    const int s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // A loader: 256 rows x 64 bytes per half, 2 row passes of 128 rows
+    const int arow = tid >> 2, acol = (tid & 3) * 8;
+    const uint16_t* pa[H * 2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        int ra = m0 + arow + 128 * i;
+        ra = ra < g.M ? ra : g.M - 1;
+        pa[i] = g.Ah + (int64_t)ra * g.lda + acol;
+        if (H == 2) pa[2 + i] = g.Al + (int64_t)ra * g.lda + acol;
+    }
+    // B producer: columns bc + 64 q (q = 0, 1), rows br .. br + 3 of the step
+    const int bc = tid >> 3, br = (tid & 7) * 4;
+    int64_t jcol[2];
+    bool jvalid[2];
+    const float* po[2];
+    const float* pg[2];
+    float* pn[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int64_t j = (int64_t)n0 + bc + 64 * q;
+        jvalid[q] = j < px.p;
+        jcol[q] = j;
+        const int64_t jc = jvalid[q] ? j : px.p - 1;
+        po[q] = px.om + jc * px.ld + br;
+        pg[q] = px.g + jc * px.ld + br;
+        pn[q] = px.om_new + jc * px.ld + br;
+    }
+    u4 va[H * 2];
+    f4 vo[2], vg[2];
+    f16v acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    ProxAcc pacc;
+
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int r32 = lane & 31, k8 = (lane >> 5) * 8;
+
+    if (s_begin < s_end) {
+        {
+            const int64_t ko = (int64_t)s_begin * BK;
+#pragma unroll
+            for (int q = 0; q < H * 2; ++q) va[q] = *(const u4*)(pa[q] + ko);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                vo[q] = *(const f4*)(po[q] + ko);
+                vg[q] = *(const f4*)(pg[q] + ko);
+            }
+        }
+        FUSED_PRODUCE(0, s_begin);
+        __syncthreads();
+        int cur = 0;
+        for (int s = s_begin; s < s_end; ++s) {
+            const bool more = s + 1 < s_end;
+            {   // unconditional prefetch (see k_gemm_bf16w)
+                const int64_t ko = (int64_t)(more ? s + 1 : s) * BK;
+#pragma unroll
+                for (int q = 0; q < H * 2; ++q) va[q] = *(const u4*)(pa[q] + ko);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    vo[q] = *(const f4*)(po[q] + ko);
+                    vg[q] = *(const f4*)(pg[q] + ko);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 16) {
+                bf8 ah[2], bh[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    ah[i] = *(const bf8*)&sA[cur][0][(wm + 32 * i + r32) * LDK + kk + k8];
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    bh[j] = *(const bf8*)&sB[cur][0][(wn + 32 * j + r32) * LDK + kk + k8];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j],
+                                                                            acc[i][j], 0, 0, 0);
+                if (PASSES == 3) {
+                    bf8 al[2], bl[2];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        bl[j] = *(const bf8*)&sB[cur][H - 1][(wn + 32 * j + r32) * LDK + kk + k8];
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+                        al[i] = *(const bf8*)&sA[cur][H - 1][(wm + 32 * i + r32) * LDK + kk + k8];
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                ah[i], bl[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                al[i], bh[j], acc[i][j], 0, 0, 0);
+                        }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (more) FUSED_PRODUCE(cur ^ 1, s + 1);
+            __syncthreads();
+            cur ^= 1;
+        }
+    }
+    __syncthreads();
+
+    const int tile = tile_m + tile_n * g.tilesM;
+    double* red = (double*)&sA[0][0][0];  // LDS is free after the K loop
+    if (owner) {
+        double v[6] = {pacc.d2, pacc.dg, pacc.l1, pacc.logd, pacc.nnz, pacc.fro};
+        block_sum_in<6, kWThreads / 64>(v, red);
+        if (tid == 0) {
+            double* out = px.part + ((int64_t)tile_n * g.splits + split) * kPartCols;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) out[k] = v[k];
+            out[6] = 0.0;
+            out[7] = 0.0;
+        }
+    }
+    if (EPI == EPI_PARTIAL) {
+        f4* P = (f4*)(g.P + ((int64_t)split * g.tilesM * g.tilesN + tile) * (kFBM * kFBN));
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    P[((i * 2 + j) * 4 + q) * kWThreads + tid] =
+                        f4{acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2],
+                           acc[i][j][4 * q + 3]};
+        return;
+    }
+    const int mw = m0 + wm + 4 * (lane >> 5), nw = n0 + wn + (lane & 31);
+    double nv[2] = {0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                store_frag<EPI_TRIAL>(g,
+                                      f4{acc[i][j][4 * q], acc[i][j][4 * q + 1],
+                                         acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]},
+                                      mw + 32 * i + 8 * q, nw + 32 * j, nv);
+    block_sum_in<2, kWThreads / 64>(nv, red);
+    if (tid == 0) {
+        g.norm_part[(int64_t)tile * kNormCols + 0] = nv[0];
+        g.norm_part[(int64_t)tile * kNormCols + 1] = nv[1];
+    }
+}
+
+// Split-K reduction for the fused tiles (same thread -> fragment map as
+// k_trial_fused); kFReduceParts workgroups per tile, norm row = part * tiles + tile.
+__global__ void __launch_bounds__(kWThreads) k_splitk_reduce_f(GemmArgs g) {
+    if (g.ls) {
+        if (g.pred >= 1 && g.ls->converged) return;
+        if (g.pred >= 2 && g.ls->done) return;
+    }
+    const int tiles = g.tilesM * g.tilesN;
+    const int tile = blockIdx.x % tiles, part = blockIdx.x / tiles;
+    const int tile_m = tile % g.tilesM, tile_n = tile / g.tilesM;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int mw = tile_m * kFBM + (wave >> 1) * 64 + 4 * (lane >> 5);
+    const int nw = tile_n * kFBN + (wave & 1) * 64 + (lane & 31);
+    constexpr int PER = 16 / kFReduceParts;
+    double nv[2] = {0.0, 0.0};
+#pragma unroll 1
+    for (int idx = part * PER; idx < (part + 1) * PER; ++idx) {
+        const int i = idx >> 3, j = (idx >> 2) & 1, q = idx & 3;
+        f4 v = f4{0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < g.splits; ++s) {
+            const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kFBM * kFBN));
+            v += P[idx * kWThreads + tid];
+        }
+        store_frag<EPI_TRIAL>(g, v, mw + 32 * i + 8 * q, nw + 32 * j, nv);
+    }
+    block_sum<2, kWThreads / 64>(nv);
+    if (tid == 0) {
+        const int64_t row = (int64_t)part * tiles + tile;
+        g.norm_part[row * kNormCols + 0] = nv[0];
+        g.norm_part[row * kNormCols + 1] = nv[1];
+    }
+}
+
+void launch_trial_fused(const GemmArgs& a, const ProxArgs& px, int prec, hipStream_t st) {
+    const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
+    if (a.splits > 1) {
+        if (prec == PREC_BF16X3)
+            k_trial_fused<3, EPI_PARTIAL><<<blocks, kWThreads, 0, st>>>(a, px);
+        else
+            k_trial_fused<1, EPI_PARTIAL><<<blocks, kWThreads, 0, st>>>(a, px);
+        k_splitk_reduce_f<<<(unsigned)(a.tilesM * a.tilesN * kFReduceParts), kWThreads, 0, st>>>(a);
+    } else {
+        if (prec == PREC_BF16X3)
+            k_trial_fused<3, EPI_TRIAL><<<blocks, kWThreads, 0, st>>>(a, px);
+        else
+            k_trial_fused<1, EPI_TRIAL><<<blocks, kWThreads, 0, st>>>(a, px);
+    }
+}
+
 int prox_blocks(int64_t total) {
     const int64_t n4 = total >> 2;
     int64_t b = cdiv(n4 > 0 ? n4 : 1, (int64_t)kThreads * 4);
