@@ -98,7 +98,8 @@ typedef struct {
                            ||Delta||_F <= tol * max(1, ||Omega_{t+1}||_F) */
     int32_t max_iter;   /* iterations, >= 0 */
     int32_t precision;  /* accord_precision */
-    int32_t check_every;/* with tol > 0: poll the stop flag every this many iterations (>= 1) */
+    int32_t check_every;/* kept for compatibility (>= 1 when tol > 0): the host now learns the
+                           device's stop flag after every trial, so it is not used */
     int32_t power_iters;/* power-iteration steps when lipschitz == 0 (0 = 400) */
     int32_t timing;     /* 1 = time every kernel launch with HIP events (fills the *_ms fields) */
     int32_t reserved[3];
@@ -166,7 +167,9 @@ int accord_objective(const float* X, int64_t n, int64_t p, const float* Omega, d
  * (the acceptance inequality of Alg. 1, written without subtracting values of g,
  * which is exact because g is quadratic).  stats: host, filled on return (may be
  * NULL).  trace: device double[(max_iter+1) * ACCORD_TRACE_COLS] or NULL.
- * Synchronous. */
+ * Synchronous.  The device posts each trial's outcome to a small pinned host buffer
+ * (allocated once per calling thread and kept), so the host enqueues only the
+ * trials an iteration needs plus one. */
 int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_params* prm,
                accord_stats* stats, double* trace, void* ws, size_t ws_bytes, void* stream);
 

@@ -139,7 +139,7 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     P.off_norm_part = bump(cur, (size_t)ttiles * kNormCols * sizeof(double));
     P.off_pow_u = bump(cur, (size_t)P.n_pad * sizeof(double));
     P.off_pow_w = bump(cur, (size_t)P.p_pad * sizeof(double));
-    P.off_pow_pu = bump(cur, (size_t)cdiv(n, kThreads / 64) * sizeof(double));
+    P.off_pow_pu = bump(cur, (size_t)n * sizeof(double));
     P.off_pow_pw = bump(cur, (size_t)cdiv(p, kThreads / 64) * sizeof(double));
     P.off_trials = bump(cur, (size_t)(max_iter > 0 ? max_iter : 1) * sizeof(int32_t));
     P.off_xp = bump(cur, xn * sizeof(float));
@@ -321,6 +321,27 @@ int max_trials(double tau0, double beta, double inv_L) {
     }
     return k;
 }
+
+// Pinned host mailbox of the calling thread (allocated once per thread and kept:
+// accord_fit is synchronous, so one thread never runs two fits at once).
+Mailbox* host_mailbox(Mailbox** dev) {
+    thread_local Mailbox* host = nullptr;
+    thread_local Mailbox* device = nullptr;
+    if (!host) {
+        void* h = nullptr;
+        if (hipHostMalloc(&h, sizeof(Mailbox), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess)
+            return nullptr;
+        void* d = nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) return nullptr;
+        host = (Mailbox*)h;
+        device = (Mailbox*)d;
+    }
+    *dev = device;
+    return host;
+}
+
+int32_t load_acquire(const int32_t* p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
 
 // HIP event pool for per-kernel timing
 struct EventPool {
@@ -554,23 +575,28 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
     const int ntr = max_trials(prm->tau0, prm->beta, host.inv_L);
 
     // ---- Alg. 1
+    // Trials are enqueued with one trial of look-ahead: the host enqueues trial k+1
+    // and then waits (on the pinned mailbox) for trial k's outcome; it enqueues
+    // trial k+2 only if trial k was rejected.  Every kernel still checks the device
+    // state first, so the one speculative trial after an acceptance does no work.
+    Mailbox* mbox_dev = nullptr;
+    Mailbox* mbox = host_mailbox(&mbox_dev);
+    if (!mbox) return fail(ACCORD_ERR_HIP, "could not allocate the pinned host mailbox");
+    mbox->iter = 0;
+    mbox->stop = 0;
+    __atomic_store_n(&mbox->trials, 0, __ATOMIC_RELEASE);
     struct Launch { hipEvent_t a, b; int iter, trial; };
     std::vector<Launch> ev_grad, ev_trial, ev_prox;
     int cur = 0;
+    int base = 0;  // trials finalised before the current iteration
     for (int t = 0; t < prm->max_iter; ++t) {
-        if (prm->tol > 0.0 && t > 0 && t % prm->check_every == 0) {
-            int32_t conv = 0;
-            HIP_TRY(hipMemcpyAsync(&conv, &ls->converged, sizeof conv, hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            if (conv) break;
-        }
         const int nxt = cur ^ 1;
         GemmArgs ga = grad_args(P, ws, prec, wt[cur], cur, G, P.p_pad, (int)P.p_pad, ls);
         Launch lg = {nullptr, nullptr, t, 0};
         if (timing) { lg.a = pool.get(); lg.b = pool.get(); HIP_TRY(hipEventRecord(lg.a, st)); }
         launch_gemm(ga, EPI_GRAD, prec, st);
         if (timing) { HIP_TRY(hipEventRecord(lg.b, st)); ev_grad.push_back(lg); }
-        for (int k = 0; k < ntr; ++k) {
+        auto enqueue_trial_k = [&](int k) -> int {
             ProxArgs a = {};
             a.om = om[cur];
             a.g = G;
@@ -596,10 +622,43 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
             else
                 enqueue_trial(ta, prec, st);
             if (timing) { HIP_TRY(hipEventRecord(lt.b, st)); ev_trial.push_back(lt); }
-            launch_finalize(ls, prox_part, P.prox_rows, norm_part, ttiles, trace, trials_log, st);
+            launch_finalize(ls, prox_part, P.prox_rows, norm_part, ttiles, trace, trials_log,
+                            mbox_dev, st);
+            HIP_TRY(hipGetLastError());
+            return ACCORD_OK;
+        };
+        int launched = 0;
+        TRY(enqueue_trial_k(launched++));
+        if (launched < ntr) TRY(enqueue_trial_k(launched++));
+        bool stop = false;
+        for (int k = 0;; ++k) {
+            // wait for trial k of this iteration to be finalised
+            const int target = base + k + 1;
+            for (long spins = 1;; ++spins) {
+                if (load_acquire(&mbox->trials) >= target || load_acquire(&mbox->stop)) break;
+                if ((spins & 4095) == 0) {
+                    const hipError_t e = hipStreamQuery(st);
+                    if (e == hipSuccess) {  // stream drained: the outcome must be posted now
+                        if (load_acquire(&mbox->trials) >= target || load_acquire(&mbox->stop))
+                            break;
+                        return fail(ACCORD_ERR_HIP, "device stopped posting trial outcomes");
+                    }
+                    if (e != hipErrorNotReady)
+                        return fail(ACCORD_ERR_HIP, "stream error: %s", hipGetErrorString(e));
+                }
+            }
+            if (load_acquire(&mbox->stop)) {
+                stop = true;
+                break;
+            }
+            if (load_acquire(&mbox->iter) > t) {  // accepted at trial k
+                base = load_acquire(&mbox->trials);
+                break;
+            }
+            if (launched < ntr) TRY(enqueue_trial_k(launched++));
         }
-        HIP_TRY(hipGetLastError());
         cur = nxt;
+        if (stop) break;
     }
     if (timing) HIP_TRY(hipEventRecord(ev_end, st));
     HIP_TRY(hipMemcpyAsync(&host, ls, sizeof host, hipMemcpyDeviceToHost, st));

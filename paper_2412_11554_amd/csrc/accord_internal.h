@@ -58,6 +58,16 @@ struct LsState {
     int32_t pad_;
 };
 
+// Pinned host mailbox: after every executed acceptance test the device posts the
+// trial count, the accepted-iteration count and the stop flag, so the host can
+// enqueue only the trials an iteration needs.
+struct Mailbox {
+    int32_t trials;  // written last (release): the other two fields are current
+    int32_t iter;
+    int32_t stop;
+    int32_t pad;
+};
+
 // ---------------------------------------------------------------------------
 // kernel argument blocks
 // ---------------------------------------------------------------------------
@@ -129,7 +139,8 @@ void launch_trial_fused(const GemmArgs& a, const ProxArgs& px, int prec, hipStre
 int prox_blocks(int64_t total);
 void launch_prox(ProxArgs a, int nblocks, hipStream_t st);
 void launch_finalize(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
-                     int ntiles, double* trace, int32_t* trials_log, hipStream_t st);
+                     int ntiles, double* trace, int32_t* trials_log, Mailbox* mbox,
+                     hipStream_t st);
 void launch_fit_init(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
                      int ntiles, double* trace, hipStream_t st);
 void launch_combine_prox(const double* prox_part, int nprox, double* red, hipStream_t st);

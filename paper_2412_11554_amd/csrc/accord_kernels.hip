@@ -1214,15 +1214,20 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
 #pragma unroll
                     for (int i = 0; i < 2; ++i)
                         al[i] = *(const bf8*)&sA[cur][H - 1][(wm + 32 * i + r32) * LDK + kk + k8];
+                    // one pass at a time: dependent MFMAs on an accumulator stay four
+                    // instructions apart
 #pragma unroll
                     for (int i = 0; i < 2; ++i)
 #pragma unroll
-                        for (int j = 0; j < 2; ++j) {
+                        for (int j = 0; j < 2; ++j)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                                 ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                                 al[i], bh[j], acc[i][j], 0, 0, 0);
-                        }
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -1357,10 +1362,20 @@ void launch_prox(ProxArgs a, int nblocks, hipStream_t st) {
 // On acceptance the iterate's objective pieces come from the same sums:
 // g = ||W+||^2/(2n), h = -sum log Omega+_jj + lambda ||Omega+||_1.
 // ---------------------------------------------------------------------------
+// Posts the line-search state to the host mailbox (system scope; the trial count
+// is released last, after the fields it vouches for).
+__device__ inline void post_mailbox(Mailbox* mb, const LsState* ls) {
+    if (!mb) return;
+    __hip_atomic_store(&mb->iter, ls->iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&mb->stop, ls->converged, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&mb->trials, ls->total_trials, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ void __launch_bounds__(kThreads) k_finalize(LsState* ls, const double* prox_part,
                                                        int nprox, const double* norm_part,
                                                        int ntiles, double* trace,
-                                                       int32_t* trials_log) {
+                                                       int32_t* trials_log, Mailbox* mbox) {
     if (ls->done || ls->converged) return;
     double pv[6];
     sum_partials<6>(prox_part, nprox, kPartCols, pv);
@@ -1379,6 +1394,7 @@ __global__ void __launch_bounds__(kThreads) k_finalize(LsState* ls, const double
     if (!finite) {
         ls->bad |= 2;
         ls->converged = 1;  // stop: every later launch is skipped
+        post_mailbox(mbox, ls);
         return;
     }
     if (canonical || at_floor || ls->fixed_step) {
@@ -1412,12 +1428,14 @@ __global__ void __launch_bounds__(kThreads) k_finalize(LsState* ls, const double
     } else {
         ls->tau = tau * ls->beta;
     }
+    post_mailbox(mbox, ls);
 }
 
 void launch_finalize(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
-                     int ntiles, double* trace, int32_t* trials_log, hipStream_t st) {
+                     int ntiles, double* trace, int32_t* trials_log, Mailbox* mbox,
+                     hipStream_t st) {
     k_finalize<<<1, kThreads, 0, st>>>(ls, prox_part, nprox, norm_part, ntiles, trace,
-                                       trials_log);
+                                       trials_log, mbox);
 }
 
 // Starting point: objective pieces of Omega^(0) (reduce-only prox sums of Omega^(0)
@@ -1510,8 +1528,9 @@ __global__ void __launch_bounds__(kThreads) k_pow_start(double* w, int64_t p) {
     }
 }
 
-// u = X (w / ||w||): one wave per sample row.  ||w||^2 is summed from the previous
-// step's partials by every workgroup in the same fixed order (or is p at step 0).
+// u = X (w / ||w||): one workgroup per sample row (n rows are too few to fill the
+// chip with one wave each).  ||w||^2 is summed from the previous step's partials by
+// every workgroup in the same fixed order (or is p at step 0).
 __global__ void __launch_bounds__(kThreads) k_pow_xv(const float* __restrict__ Xp,
                                                      int64_t ldx, int64_t n, int64_t p,
                                                      const double* __restrict__ w,
@@ -1528,18 +1547,16 @@ __global__ void __launch_bounds__(kThreads) k_pow_xv(const float* __restrict__ X
     if (threadIdx.x == 0) s_scale = ww[0] > 0.0 ? 1.0 / sqrt(ww[0]) : 0.0;
     __syncthreads();
     const double scale = s_scale;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t i = (int64_t)blockIdx.x * (kThreads / 64) + wave;
-    double s = 0.0;
-    if (i < n) {
-        const float* row = Xp + i * ldx;
-        for (int64_t k = lane; k < p; k += 64) s += (double)row[k] * w[k];
-        s = wave_sum(s) * scale;
-        if (lane == 0) u[i] = s;
-    }
-    double v[1] = {(i < n && lane == 0) ? s * s : 0.0};
+    const int64_t i = blockIdx.x;
+    const float* row = Xp + i * ldx;
+    double v[1] = {0.0};
+    for (int64_t k = threadIdx.x; k < p; k += kThreads) v[0] += (double)row[k] * w[k];
     block_sum<1>(v);
-    if (threadIdx.x == 0) part_u[blockIdx.x] = v[0];
+    if (threadIdx.x == 0) {
+        const double ui = v[0] * scale;
+        u[i] = ui;
+        part_u[i] = ui * ui;
+    }
 }
 
 // w = X^T u: one wave per variable row of Xt
@@ -1575,7 +1592,7 @@ __global__ void __launch_bounds__(kThreads) k_pow_finish(const double* part_u, i
 void launch_power_iteration(const float* Xp, int64_t p_pad, const float* Xt, int64_t n_pad,
                             int64_t n, int64_t p, double* w, double* u, double* part_u,
                             double* part_w, int steps, LsState* ls, hipStream_t st) {
-    const int nbu = (int)cdiv(n, kThreads / 64);
+    const int nbu = (int)n;  // one workgroup (and one partial) per sample row
     const int nbw = (int)cdiv(p, kThreads / 64);
     const int64_t sb = cdiv(p, kThreads);
     k_pow_start<<<(unsigned)(sb < 1024 ? sb : 1024), kThreads, 0, st>>>(w, p);
