@@ -19,7 +19,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/accord.h"
+#include "accord.h"
 #include "accord_internal.h"
 
 using namespace accord;
@@ -208,7 +208,7 @@ GemmArgs trial_args(const Plan& P, void* ws, int prec, const float* B32, const u
 void enqueue_trial(const GemmArgs& a, int prec, hipStream_t st) {
     if (a.splits > 1) {
         launch_gemm(a, EPI_PARTIAL, prec, st);
-        launch_splitk_reduce(a, prec, st);
+        launch_splitk_reduce(a, st);
     } else {
         launch_gemm(a, EPI_TRIAL, prec, st);
     }

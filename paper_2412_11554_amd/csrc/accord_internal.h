@@ -16,7 +16,6 @@ constexpr int kBN = 128;            // FP32 GEMM workgroup tile (columns of C)
 constexpr int kWBM = 256;           // bf16 GEMM workgroup tile (rows of C)
 constexpr int kWBN = 256;           // bf16 GEMM workgroup tile (columns of C)
 constexpr int kWThreads = 512;      // bf16 GEMM threads per workgroup
-constexpr int kWReduceParts = 4;    // workgroups per tile in the bf16 split-K reduction
 constexpr int kFBM = 256;           // fused prox + trial tile (rows of W^T = samples)
 constexpr int kFBN = 128;           // fused prox + trial tile (columns of Omega)
 constexpr int kFReduceParts = 2;    // workgroups per tile in the fused split-K reduction
@@ -134,7 +133,7 @@ void launch_pad_x(const float* X, int64_t n, int64_t p, float* Xp, int64_t p_pad
 void launch_copy_cols(const float* src, int64_t ld_src, float* dst, int64_t ld_dst, int64_t p,
                       int64_t rows, LsState* check_ls, hipStream_t st);
 void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st);
-void launch_splitk_reduce(const GemmArgs& a, int prec, hipStream_t st);
+void launch_splitk_reduce(const GemmArgs& a, hipStream_t st);
 void launch_trial_fused(const GemmArgs& a, const ProxArgs& px, int prec, hipStream_t st);
 int prox_blocks(int64_t total);
 void launch_prox(ProxArgs a, int nblocks, hipStream_t st);

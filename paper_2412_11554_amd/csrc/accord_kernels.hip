@@ -2,8 +2,10 @@
 //
 //   k_gemm_f32     FP32 MFMA (v_mfma_f32_16x16x4f32) GEMM, LDS double-buffered
 //                  128x128 tiles, XCD-aware tile order
-//   k_gemm_bf16    the same with v_mfma_f32_16x16x32_bf16 on bf16 (hi) or hi+lo
-//                  split operands (1 or 3 MFMA passes).  Two uses of both:
+//   k_gemm_bf16w   256x256 bf16 GEMM (v_mfma_f32_32x32x16_bf16) on bf16 (hi) or
+//                  hi+lo split operands, 1 or 3 passes: the bf16 forms' gradient
+//   k_trial_fused  bf16 forms: prox (eq. 3.5) fused into the trial product
+//   FP32 uses of k_gemm_f32:
 //                    gradient  G  = X^T W / n              (Remark 3.1, two-step product)
 //                    trial     W+ = W + X Delta, ||X Delta||^2, ||W+||^2 (Alg. 1 test)
 //   k_splitk_reduce fixed-order sum of split-K partial tiles + trial epilogue
@@ -217,7 +219,7 @@ void launch_transpose_w(const float* Wt, int64_t ldt, int64_t n, int64_t p, floa
 // ---------------------------------------------------------------------------
 // GEMMs:  C(m, n) = sum_k A[m, k] * B[n, k]   (both operands K-contiguous)
 //
-// Workgroup tile 128 x 128, 4 waves in a 2 x 2 arrangement, each wave 64 x 64 =
+// FP32: workgroup tile 128 x 128, 4 waves in a 2 x 2 arrangement, each wave 64 x 64 =
 // 4 x 4 blocks of 16 x 16 MFMA outputs.  One K step is staged in LDS and
 // double-buffered: the next step's global loads are in flight while the current
 // step's MFMAs run.  LDS rows are padded by 16 bytes, so the 16 lanes that read
@@ -464,138 +466,6 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
     gemm_epilogue<EPI>(g, acc, tile_m, tile_n, split, (double*)&sA[0][0]);
 }
 
-template <int PASSES, int EPI>
-__global__ void __launch_bounds__(kThreads, 2) k_gemm_bf16(GemmArgs g) {
-    if (gemm_skip(g)) return;
-    constexpr int BK = PASSES == 1 ? 64 : 32;       // K per LDS stage
-    constexpr int LDK = BK + 8;                     // bf16 per LDS row (16-byte pad)
-    constexpr int H = PASSES == 1 ? 1 : 2;          // hi, or hi + lo
-    constexpr int CPR = BK / 8;                     // 16-byte chunks per row
-    constexpr int ROWS = kThreads / CPR;            // rows covered by one load pass
-    constexpr int RPT = kBM / ROWS;                 // load passes per operand half
-    __shared__ __attribute__((aligned(16))) uint16_t sA[2][H][kBM * LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[2][H][kBN * LDK];
-
-    int tile_m, tile_n, split;
-    decode_tile(g, tile_m, tile_n, split);
-    const int m0 = tile_m * kBM, n0 = tile_n * kBN;
-    const int ksteps = g.K / BK;
-    const int s_begin = (int)((int64_t)ksteps * split / g.splits);
-    const int s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lrow = tid / CPR, lcol = (tid % CPR) * 8;
-    // operand half h, row pass i -> flat index h * RPT + i
-    const uint16_t* pa[H * RPT];
-    const uint16_t* pb[H * RPT];
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-        int ra = m0 + lrow + ROWS * i;
-        ra = ra < g.M ? ra : g.M - 1;
-        int rb = n0 + lrow + ROWS * i;
-        rb = rb < g.N ? rb : g.N - 1;
-        pa[i] = g.Ah + (int64_t)ra * g.lda + lcol;
-        pb[i] = g.Bh + (int64_t)rb * g.ldb + lcol;
-        if (H == 2) {
-            pa[(H - 1) * RPT + i] = g.Al + (int64_t)ra * g.lda + lcol;
-            pb[(H - 1) * RPT + i] = g.Bl + (int64_t)rb * g.ldb + lcol;
-        }
-    }
-    u4 va[H * RPT], vb[H * RPT];
-    f4 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-    const int r16 = lane & 15, k8 = (lane >> 4) * 8;
-
-
-    if (s_begin < s_end) {
-        {
-            const int64_t ko = (int64_t)s_begin * BK;
-#pragma unroll
-        for (int q = 0; q < H * RPT; ++q) {
-            va[q] = *(const u4*)(pa[q] + ko);
-            vb[q] = *(const u4*)(pb[q] + ko);
-        }
-        }
-#pragma unroll
-        for (int q = 0; q < H * RPT; ++q) {
-            const int off = (lrow + ROWS * (q % RPT)) * LDK + lcol;
-            *(u4*)&sA[0][q / RPT][off] = va[q];
-            *(u4*)&sB[0][q / RPT][off] = vb[q];
-        }
-        __syncthreads();
-        int cur = 0;
-        for (int s = s_begin; s < s_end; ++s) {
-            // Unconditional prefetch (the last step re-reads its own rows into the idle
-            // buffer): a conditional load would be merged at a branch join, which forces
-            // a wait on it before the MFMAs below.  The scheduling barriers keep the
-            // loads ahead of the MFMAs and their LDS stores after them, so the load
-            // latency hides behind the whole MFMA block.
-            {
-                const int64_t ko = (int64_t)(s + 1 < s_end ? s + 1 : s) * BK;
-#pragma unroll
-            for (int q = 0; q < H * RPT; ++q) {
-                va[q] = *(const u4*)(pa[q] + ko);
-                vb[q] = *(const u4*)(pb[q] + ko);
-            }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 32) {
-                bf8 ah[4], bh[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    ah[i] = *(const bf8*)&sA[cur][0][(wm + 16 * i + r16) * LDK + kk + k8];
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    bh[j] = *(const bf8*)&sB[cur][0][(wn + 16 * j + r16) * LDK + kk + k8];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j],
-                                                                            acc[i][j], 0, 0, 0);
-                if (PASSES == 3) {
-                    bf8 al[4], bl[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        bl[j] = *(const bf8*)&sB[cur][H - 1][(wn + 16 * j + r16) * LDK + kk + k8];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                ah[i], bl[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        al[i] = *(const bf8*)&sA[cur][H - 1][(wm + 16 * i + r16) * LDK + kk + k8];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                al[i], bh[j], acc[i][j], 0, 0, 0);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int q = 0; q < H * RPT; ++q) {
-                const int off = (lrow + ROWS * (q % RPT)) * LDK + lcol;
-                *(u4*)&sA[cur ^ 1][q / RPT][off] = va[q];
-                *(u4*)&sB[cur ^ 1][q / RPT][off] = vb[q];
-            }
-            __syncthreads();
-            cur ^= 1;
-        }
-    }
-    __syncthreads();
-    gemm_epilogue<EPI>(g, acc, tile_m, tile_n, split, (double*)&sA[0][0][0]);
-}
-
 // ---------------------------------------------------------------------------
 // Wide bf16 GEMM: 256 x 256 workgroup tile, 8 waves (2 along M x 4 along N), each
 // wave 128 x 64 = 4 x 2 blocks of v_mfma_f32_32x32x16_bf16, the full-rate bf16
@@ -775,40 +645,6 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16w(GemmArgs g) {
     }
 }
 
-// Split-K reduction for the wide tiles (same thread -> fragment map as k_gemm_bf16w).
-// kWReduceParts workgroups per tile, each owning a quarter of the 32 fragments of
-// every thread; norm partial row = part * tiles + tile.
-__global__ void __launch_bounds__(kWThreads) k_splitk_reduce_w(GemmArgs g) {
-    if (g.ls) {
-        if (g.pred >= 1 && g.ls->converged) return;
-        if (g.pred >= 2 && g.ls->done) return;
-    }
-    const int tiles = g.tilesM * g.tilesN;
-    const int tile = blockIdx.x % tiles, part = blockIdx.x / tiles;
-    const int tile_m = tile % g.tilesM, tile_n = tile / g.tilesM;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int mw = tile_m * kWBM + (wave >> 2) * 128 + 4 * (lane >> 5);
-    const int nw = tile_n * kWBN + (wave & 3) * 64 + (lane & 31);
-    constexpr int PER = 32 / kWReduceParts;
-    double nv[2] = {0.0, 0.0};
-#pragma unroll 1
-    for (int idx = part * PER; idx < (part + 1) * PER; ++idx) {
-        const int i = idx >> 3, j = (idx >> 2) & 1, q = idx & 3;
-        f4 v = f4{0.f, 0.f, 0.f, 0.f};
-        for (int s = 0; s < g.splits; ++s) {
-            const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kWBM * kWBN));
-            v += P[idx * kWThreads + tid];
-        }
-        store_frag<EPI_TRIAL>(g, v, mw + 32 * i + 8 * q, nw + 32 * j, nv);
-    }
-    block_sum<2, kWThreads / 64>(nv);
-    if (tid == 0) {
-        const int64_t row = (int64_t)part * tiles + tile;
-        g.norm_part[row * kNormCols + 0] = nv[0];
-        g.norm_part[row * kNormCols + 1] = nv[1];
-    }
-}
-
 // Fixed-order sum of the split-K partial tiles, then the trial epilogue.
 // One workgroup per tile; thread t owns the same accumulator slots it had in the
 // GEMM kernel, so (m, n) follow from (t, i, j) exactly as there.
@@ -841,32 +677,27 @@ __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
     }
 }
 
-template <int EPI>
-static void launch_gemm_epi(const GemmArgs& a, int prec, unsigned blocks, hipStream_t st) {
-    if (prec == PREC_BF16X3)
-        k_gemm_bf16w<3, EPI><<<blocks, kWThreads, 0, st>>>(a);
-    else if (prec == PREC_BF16X1)
-        k_gemm_bf16w<1, EPI><<<blocks, kWThreads, 0, st>>>(a);
-    else
-        k_gemm_f32<EPI><<<blocks, kThreads, 0, st>>>(a);
-}
-
 void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st) {
     const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
+    if (prec != PREC_FP32) {
+        // bf16 forms: gradient only (their trial products run in k_trial_fused)
+        if (prec == PREC_BF16X3)
+            k_gemm_bf16w<3, EPI_GRAD><<<blocks, kWThreads, 0, st>>>(a);
+        else
+            k_gemm_bf16w<1, EPI_GRAD><<<blocks, kWThreads, 0, st>>>(a);
+        return;
+    }
     if (epi == EPI_GRAD)
-        launch_gemm_epi<EPI_GRAD>(a, prec, blocks, st);
+        k_gemm_f32<EPI_GRAD><<<blocks, kThreads, 0, st>>>(a);
     else if (epi == EPI_TRIAL)
-        launch_gemm_epi<EPI_TRIAL>(a, prec, blocks, st);
+        k_gemm_f32<EPI_TRIAL><<<blocks, kThreads, 0, st>>>(a);
     else
-        launch_gemm_epi<EPI_PARTIAL>(a, prec, blocks, st);
+        k_gemm_f32<EPI_PARTIAL><<<blocks, kThreads, 0, st>>>(a);
 }
 
-void launch_splitk_reduce(const GemmArgs& a, int prec, hipStream_t st) {
+void launch_splitk_reduce(const GemmArgs& a, hipStream_t st) {
     const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN);
-    if (prec == PREC_FP32)
-        k_splitk_reduce<<<blocks, kThreads, 0, st>>>(a);
-    else
-        k_splitk_reduce_w<<<blocks * kWReduceParts, kWThreads, 0, st>>>(a);
+    k_splitk_reduce<<<blocks, kThreads, 0, st>>>(a);
 }
 
 // ---------------------------------------------------------------------------
