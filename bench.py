@@ -23,6 +23,7 @@ and once: cpu_baseline, the FP64 oracle timed on this host on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -69,30 +70,87 @@ def cpu_baseline(w, budget_s: float = 15.0):
                       f"({sum(r.trials)} backtracking trials, {dt:.1f} s, FP64 numpy)"}
 
 
-def kernel_report(stats, form, n, p):
-    flops = 2.0 * n * p * p          # algorithmic flops per launch, both contractions
+def _traffic_table():
+    """HBM bytes per launch measured by rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by a plain
+    copy's reading), valid only while the kernel source is the one that was profiled."""
+    path = os.path.join(ROOT, "profiles", "traffic_ba5000_bench.md")
+    src = os.path.join(ROOT, "paper_2412_11554_amd", "csrc", "accord_kernels.hip")
+    try:
+        line = [l for l in open(path) if l.startswith("traffic-json: ")][-1]
+        tab = json.loads(line[len("traffic-json: "):])
+        with open(src, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()[:16]
+    except (OSError, IndexError, ValueError):
+        return {}
+    return tab["bytes_per_launch"] if tab.get("kernel_sha256_16") == digest else {}
+
+
+def kernel_report(stats, form, n, p, workload_ok_for_traffic):
+    """Per kernel group: mean duration from the library's HIP events, the achieved
+    algorithmic rate and the roofline it is held to.
+
+    gradient  G = X^T W / n: 2 n p^2 flops, MFMA-bound.
+    trial     fp32: the trial GEMM (+ its split-K reduce), 2 n p^2 flops, MFMA-bound.
+              bf16 forms: the fused prox + trial GEMM (+ reduce), which streams Omega, G
+              in and Omega+ out: 12 p^2 algorithmic bytes against HBM, next to its
+              executed MFMA flops; the bound is the larger of the two lower bounds.
+    prox      fp32 form only (fused into the trial otherwise): 16 p^2 bytes
+              (read Omega, G; write Omega+, Delta), HBM-bound."""
+    flops = 2.0 * n * p * p
+    peak = PEAK_TFLOPS[form]
+    traffic = _traffic_table() if workload_ok_for_traffic else {}
     out = {}
-    for key, what in (("grad_gemm", "G = X^T W / n"), ("trial_gemm", "W+ = W + X Delta (+ norms)")):
+
+    def group(key):
         ms = sum(s[key + "_ms"] for s in stats)
         cnt = sum(s[key + "_launches"] for s in stats)
-        if not cnt:
-            continue
-        a = flops / (ms / cnt * 1e-3) / 1e12
-        out[key] = {"what": what, "launches": cnt, "avg_ms": ms / cnt, "achieved": a,
-                    "executed_tflops": a * PASSES[form], "peak": PEAK_TFLOPS[form],
-                    "unit": "TFLOP/s", "frac": a / PEAK_TFLOPS[form],
-                    "executed_frac": a * PASSES[form] / PEAK_TFLOPS[form], "bound": "mfma",
-                    "total_ms": ms}
-    ms = sum(s["prox_ms"] for s in stats)
-    cnt = sum(s["prox_launches"] for s in stats)
-    if cnt:
-        p_pad = p + (-p) % 64
-        dbytes = 2 if form == "bf16x1" else 4    # Delta as written for the trial GEMM
-        bytes_per = (12.0 + dbytes) * p * p_pad  # read Omega, G; write Omega+, Delta
-        a = bytes_per / (ms / cnt * 1e-3) / 1e9
-        out["prox"] = {"what": "fused prox + reductions", "launches": cnt, "avg_ms": ms / cnt,
-                       "achieved": a, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                       "frac": a / PEAK_HBM_GBS, "bound": "hbm", "total_ms": ms}
+        return (ms, cnt, ms / cnt) if cnt else (0.0, 0, None)
+
+    ms, cnt, avg = group("grad_gemm")
+    if avg:
+        a = flops / (avg * 1e-3) / 1e12
+        name = "k_gemm_f32<0>" if form == "fp32" else f"k_gemm_bf16w<{PASSES[form]}, 0>"
+        out["grad_gemm"] = {"what": "G = X^T W / n", "kernels": [name], "launches": cnt,
+                            "avg_ms": avg, "total_ms": ms, "bound": "mfma", "achieved": a,
+                            "peak": peak, "unit": "TFLOP/s", "frac": a / peak,
+                            "executed_tflops": a * PASSES[form],
+                            "executed_frac": a * PASSES[form] / peak}
+    ms, cnt, avg = group("trial_gemm")
+    if avg:
+        a = flops / (avg * 1e-3) / 1e12
+        if form == "fp32":
+            names = ["k_gemm_f32<2>", "k_splitk_reduce"]
+            d = {"what": "W+ = W + X Delta (+ norms)", "bound": "mfma", "achieved": a,
+                 "peak": peak, "unit": "TFLOP/s", "frac": a / peak}
+        else:
+            names = [f"k_trial_fused<{PASSES[form]}, 2>", "k_splitk_reduce_f"]
+            alg = 12.0 * p * p
+            gbs = alg / (avg * 1e-3) / 1e9
+            t_hbm = alg / (PEAK_HBM_GBS * 1e9)
+            t_mfma = flops * PASSES[form] / (peak * 1e12)
+            d = {"what": "fused prox (eq. 3.5) + W+ = W + X Delta (+ norms)",
+                 "algorithmic_bytes": alg,
+                 "mfma": {"achieved": a * PASSES[form], "peak": peak, "unit": "TFLOP/s",
+                          "frac": a * PASSES[form] / peak, "useful_tflops": a}}
+            if t_hbm >= t_mfma:
+                d.update({"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                          "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS})
+            else:
+                d.update({"bound": "mfma", "achieved": a * PASSES[form], "peak": peak,
+                          "unit": "TFLOP/s", "frac": a * PASSES[form] / peak})
+        d.update({"kernels": names, "launches": cnt, "avg_ms": avg, "total_ms": ms})
+        out["trial_gemm"] = d
+    ms, cnt, avg = group("prox")
+    if avg:
+        alg = 16.0 * p * p
+        a = alg / (avg * 1e-3) / 1e9
+        out["prox"] = {"what": "fused prox + reductions", "kernels": ["k_prox<0>"],
+                       "launches": cnt, "avg_ms": avg, "total_ms": ms, "bound": "hbm",
+                       "algorithmic_bytes": alg, "achieved": a, "peak": PEAK_HBM_GBS,
+                       "unit": "GB/s", "frac": a / PEAK_HBM_GBS}
+    for d in out.values():
+        got = [traffic.get(f"void {k}", traffic.get(k)) for k in d["kernels"]]
+        d["traffic"] = sum(got) if got and all(g is not None for g in got) else None
     return out
 
 
@@ -122,7 +180,7 @@ def run_form(form, X, w, iters, ws, om, steps, warmup, check):
     res = {"iters_per_s": sum(s["iters"] for s in stats) / elapsed,
            "ms_per_step": elapsed / steps * 1e3,
            "trials_per_iter": stats[-1]["trials"] / max(1, stats[-1]["iters"]),
-           "kernels": kernel_report(stats, form, w.n, w.p)}
+           "kernels": kernel_report(stats, form, w.n, w.p, iters == w.iters)}
     if check:
         import oracle
         cols = np.array([0, 1, 499, 2500, 4998, 4999])
@@ -191,8 +249,9 @@ def main():
     roofline = None
     if dom:
         d = ks[dom]
-        roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"],
-                    "peak": d["peak"], "unit": d["unit"], "frac": d["frac"], "traffic": None}
+        roofline = {"kernel": " + ".join(d["kernels"]), "bound": d["bound"],
+                    "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
+                    "frac": d["frac"], "traffic": d["traffic"]}
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     out = {
         "metric": METRIC,
