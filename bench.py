@@ -4,7 +4,8 @@ One step = one complete accord_fit (Alg. 1) on the block power-law workload
 n = 500, p = 5000 (10 Barabasi-Albert(m=1) blocks of 500, lambda = 0.05,
 500 iterations, L estimated on the device by power iteration).  X is resident in
 HBM before the timed region.  `value` = prox-grad iterations per second of the
-headline form over the K timed steps.
+headline form over the K timed steps.  --workload ba100k runs the same harness at
+n = 1000, p = 1e5 (200 blocks, lambda = 0.03, 300 iterations; --iters shortens it).
 
 Forms (the contraction arithmetic; prox, test and sums are the same in all):
   bf16x3  bf16 MFMA on hi/lo splits, three passes (meets the FP32 error bar); headline
@@ -180,10 +181,12 @@ def run_form(form, X, w, iters, ws, om, steps, warmup, check):
     res = {"iters_per_s": sum(s["iters"] for s in stats) / elapsed,
            "ms_per_step": elapsed / steps * 1e3,
            "trials_per_iter": stats[-1]["trials"] / max(1, stats[-1]["iters"]),
-           "kernels": kernel_report(stats, form, w.n, w.p, iters == w.iters)}
+           "kernels": kernel_report(stats, form, w.n, w.p,
+                                    w.p == 5000 and iters == w.iters)}
     if check:
         import oracle
-        cols = np.array([0, 1, 499, 2500, 4998, 4999])
+        p = w.p
+        cols = np.array([0, 1, 499, p // 2, p - 2, p - 1])
         taus = trace.cpu().numpy()[1:, 3]
         ref = oracle.fit_fbs(w.X.astype(np.float64), w.lam, len(taus),
                              L=stats[-1]["lipschitz"], tau_replay=taus, columns=cols)
@@ -205,7 +208,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--iters", type=int, default=None,
-                    help="iterations per fit (default: the workload's 500); for short profiles")
+                    help="iterations per fit (default: the workload's own count)")
+    ap.add_argument("--workload", default="ba5000", choices=["ba5000", "ba100k"],
+                    help="ba5000: n=500, p=5000, 10 blocks, lambda 0.05, 500 iterations "
+                         "(default); ba100k: n=1000, p=1e5, 200 blocks, lambda 0.03, "
+                         "300 iterations (the precision-form size)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for byte counters)")
     args = ap.parse_args()
@@ -222,7 +229,7 @@ def main():
 
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     dev = torch.device("cuda:0")
-    w = datagen.workload("ba5000")
+    w = datagen.workload(args.workload)
     n, p, iters = w.n, w.p, (args.iters or w.iters)
     X = torch.from_numpy(w.X).to(dev)
     need = max(accord.accord_workspace_bytes(n, p, accord.default_params(max_iter=iters,
@@ -252,7 +259,8 @@ def main():
         roofline = {"kernel": " + ".join(d["kernels"]), "bound": d["bound"],
                     "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
                     "frac": d["frac"], "traffic": d["traffic"]}
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+    # the oracle's full p x p FP64 iterate is 80 GB at p = 1e5: host baseline on ba5000 only
+    cpu = None if (args.no_cpu_baseline or w.p > 5000) else cpu_baseline(w)
     out = {
         "metric": METRIC,
         "value": head["iters_per_s"],
@@ -267,7 +275,8 @@ def main():
         "dtype": forms[0],
         "data": "synthetic",
         "config": {"workload": f"block power-law ACCORD-FBS fit: n={n}, p={p}, "
-                               f"10 BA(m=1) blocks of 500, lambda={w.lam}, {iters} iterations",
+                               f"{p // 500} BA(m=1) blocks of 500, lambda={w.lam}, "
+                               f"{iters} iterations",
                    "n": n, "p": p, "lambda": w.lam, "iters_per_step": iters,
                    "form": forms[0],
                    "lipschitz": "device power iteration, 400 steps"},

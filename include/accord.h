@@ -52,7 +52,7 @@ extern "C" {
 
 typedef enum {
     ACCORD_OK = 0,
-    ACCORD_ERR_INVALID_ARG = 1,  /* null pointer, size < 1, bad parameter, misalignment */
+    ACCORD_ERR_INVALID_ARG = 1,  /* null pointer, size < 1 or > 2^20, bad parameter, misalignment */
     ACCORD_ERR_DOMAIN = 2,       /* some Omega_jj <= 0 where a positive diagonal is required */
     ACCORD_ERR_NONFINITE = 3,    /* NaN/inf in X or in an iterate */
     ACCORD_ERR_WORKSPACE = 4,    /* workspace null, misaligned or smaller than required */

@@ -260,8 +260,8 @@ XSplit x_split(const Plan& P, void* ws) {
 int check_dims(int64_t n, int64_t p) {
     if (n < 1 || p < 1) return fail(ACCORD_ERR_INVALID_ARG, "n and p must be >= 1 (n=%lld p=%lld)",
                                     (long long)n, (long long)p);
-    // GEMM tile indices and row counts are 32-bit
-    if (n > (1LL << 24) || p > (1LL << 24))
+    // GEMM tile counts (x split-K factor) are 32-bit; 2^20 keeps them below 2^31
+    if (n > (1LL << 20) || p > (1LL << 20))
         return fail(ACCORD_ERR_INVALID_ARG, "n or p too large (n=%lld p=%lld)", (long long)n,
                     (long long)p);
     return ACCORD_OK;

@@ -83,6 +83,7 @@ FAKE = 1 << 20  # a 16-byte aligned non-null address; validation fails before an
     (dict(lam=-1.0), 1), (dict(tau0=0.0), 1), (dict(beta=0.0), 1), (dict(beta=1.5), 1),
     (dict(max_iter=-1), 1), (dict(precision=7), 5), (dict(tol=1e-6, check_every=0), 1),
     (dict(lipschitz=-2.0), 1), (dict(lam=float("nan")), 1),
+    (dict(p=(1 << 20) + 1), 1), (dict(n=(1 << 20) + 1), 1),
 ])
 def test_fit_validation(L, kw, status):
     args = dict(X=FAKE, n=10, p=12, Omega=FAKE, ws=FAKE, ws_bytes=1 << 40, lam=0.1, tau0=1.0,
