@@ -60,7 +60,7 @@ typedef enum {
     ACCORD_ERR_HIP = 6           /* HIP runtime error (see accord_last_error) */
 } accord_status;
 
-/* Arithmetic of the two contractions X Delta and X^T W (a6 of the hot path).  The
+/* Arithmetic of the two contractions X Delta and X^T W (the precision form).  The
  * prox, the acceptance test, the objective sums and the diagonal root are the same in
  * every form (FP32 iterate, FP64 sums and root); W = X Omega is carried in FP32. */
 typedef enum {
@@ -68,9 +68,18 @@ typedef enum {
     ACCORD_BF16X1 = 1,  /* bf16 MFMA on bf16(X), bf16(Delta), bf16(W); FP32 accumulation.
                            About 3 significant digits: use for a first phase, then refine
                            with ACCORD_BF16X3 from its result (Omega in/out). */
-    ACCORD_BF16X3 = 2   /* bf16 MFMA on the split x = hi + lo (hi = bf16(x), lo =
+    ACCORD_BF16X3 = 2,  /* bf16 MFMA on the split x = hi + lo (hi = bf16(x), lo =
                            bf16(x - hi)) of every operand: hi*hi + hi*lo + lo*hi, FP32
                            accumulation; relative product error about 2^-16 */
+    ACCORD_FP8 = 3      /* OCP MX operands on the scaled MFMA (v_mfma_scale_f32_32x32x64_
+                           f8f6f4): E4M3 elements with one power-of-two (E8M0) scale per
+                           32 consecutive values along the contraction index -- X per row
+                           over features for X Delta and per feature over samples for
+                           X^T W, Delta per column, W per column over samples.  Scale
+                           2^s with s = floor(log2(block max)) - 7; elements rounded to
+                           nearest even.  FP32 accumulation.  About 2^-4 relative
+                           rounding per operand: use for a first phase, then refine with
+                           ACCORD_BF16X3 from its result. */
 } accord_precision;
 
 /* Columns of the optional per-iteration trace (device double[(max_iter+1) * 8]).

@@ -137,6 +137,7 @@ def fit_fbs_mx(x, lam, tau_replay, omega0=None, columns=None, quant=mx_quantize)
     xq_grad = quant(x, 0)    # columns of X: blocks of 32 samples (contraction of X^T W)
     w = x @ om
     res = FitResult(omega=om, iters=0, lipschitz=float("nan"))
+    dq_fro = []
     for t in range(len(tau_replay)):
         tau = float(tau_replay[t])
         g = xq_grad.T @ quant(w, 0) / n
@@ -144,14 +145,18 @@ def fit_fbs_mx(x, lam, tau_replay, omega0=None, columns=None, quant=mx_quantize)
         om_new = soft_threshold(a, tau * lam)
         om_new[diag_rows, jj] = diag_root(a[diag_rows, jj], tau, lam)
         d = om_new - om
-        w = w + xq_trial @ quant(d, 0)
+        dq = quant(d, 0)
+        w = w + xq_trial @ dq
         om = om_new
         res.tau.append(tau)
         res.trials.append(1)
         res.delta_fro.append(float(np.linalg.norm(d)))
+        dq_fro.append(float(np.linalg.norm(dq)))
         res.iters = t + 1
     res.omega = om
-    res.extra = {"w": w}
+    # w: the running W; delta_q_fro: ||q(Delta)||_F per iteration (the step the
+    # product and the acceptance sums see)
+    res.extra = {"w": w, "delta_q_fro": dq_fro}
     return res
 
 

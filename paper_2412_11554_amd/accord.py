@@ -26,7 +26,7 @@ ACCORD_OK = 0
 STATUS_NAMES = {0: "ACCORD_OK", 1: "ACCORD_ERR_INVALID_ARG", 2: "ACCORD_ERR_DOMAIN",
                 3: "ACCORD_ERR_NONFINITE", 4: "ACCORD_ERR_WORKSPACE",
                 5: "ACCORD_ERR_UNSUPPORTED", 6: "ACCORD_ERR_HIP"}
-PRECISIONS = {"fp32": 0, "bf16x1": 1, "bf16x3": 2}
+PRECISIONS = {"fp32": 0, "bf16x1": 1, "bf16x3": 2, "fp8": 3}
 TRACE_COLS = 8
 TRACE_FIELDS = ("f", "g", "h", "tau", "trials", "delta_fro", "floor", "nnz")
 

@@ -61,6 +61,8 @@ struct Geo {
 
 // rows of FP64 norm partials a trial product leaves (one per tile, or one per
 // reduction workgroup when the bf16 split-K reduction runs)
+bool is_bf16(int prec) { return prec == PREC_BF16X1 || prec == PREC_BF16X3; }
+
 int norm_rows(const Geo& g, int prec) {
     return (g.splits > 1 && prec != PREC_FP32) ? g.tiles() * kFReduceParts : g.tiles();
 }
@@ -72,11 +74,12 @@ struct Plan {
     // products and the FP32 form) and, for the bf16 forms, the fused prox + trial
     // kernel's geometry
     Geo t32, tp;
-    int fused;      // bf16 forms: the prox runs inside the trial kernel
+    int fused;      // bf16 and FP8 forms: the prox runs inside the trial kernel
     int prox_rows;  // FP64 prox partial rows left per trial
     int nprox;
     size_t off_ls, off_prox_part, off_norm_part, off_pow_u, off_pow_w, off_pow_pu, off_pow_pw,
-        off_trials, off_xp, off_xt, off_xsplit[4], off_wt0, off_wt1, off_wsplit[4], off_split,
+        off_trials, off_xp, off_xt, off_xsplit[4], off_x8, off_x8s, off_xt8, off_xt8s, off_wt0,
+        off_wt1, off_wsplit[4], off_w8, off_w8s, off_split,
         off_om0, end_grad, off_g, off_d, off_om1, end_fit;
     size_t end_prox;
 };
@@ -122,7 +125,8 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     }
     P.nprox = prox_blocks(p * P.p_pad);
     P.prox_rows = P.fused ? P.tp.tilesN * P.tp.splits : P.nprox;
-    const bool bf = prec != PREC_FP32;
+    const bool bf = is_bf16(prec);
+    const bool f8 = prec == PREC_FP8;
     const int ttiles = std::max(norm_rows(P.t32, PREC_FP32), norm_rows(P.tp, prec));
     const size_t split_floats =
         std::max((size_t)(P.t32.splits > 1 ? P.t32.splits : 0) * P.t32.tiles() * kBM * kBN,
@@ -145,14 +149,20 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     P.off_xp = bump(cur, xn * sizeof(float));
     P.off_xt = bump(cur, xn * sizeof(float));
     for (int k = 0; k < 4; ++k) P.off_xsplit[k] = bump(cur, bf ? xn * sizeof(uint16_t) : 0);
+    P.off_x8 = bump(cur, f8 ? xn : 0);
+    P.off_x8s = bump(cur, f8 ? xn / 32 : 0);
+    P.off_xt8 = bump(cur, f8 ? xn : 0);
+    P.off_xt8s = bump(cur, f8 ? xn / 32 : 0);
     P.off_wt0 = bump(cur, wn * sizeof(float));
     P.off_wt1 = bump(cur, wn * sizeof(float));
     for (int k = 0; k < 4; ++k) P.off_wsplit[k] = bump(cur, bf ? wn * sizeof(uint16_t) : 0);
+    P.off_w8 = bump(cur, f8 ? wn : 0);
+    P.off_w8s = bump(cur, f8 ? wn / 32 : 0);
     P.off_split = bump(cur, split_floats * sizeof(float));
     P.off_om0 = bump(cur, on * sizeof(float));
     P.end_grad = cur;
     P.off_g = bump(cur, on * sizeof(float));
-    P.off_d = bump(cur, bf ? 0 : on * sizeof(float));  // bf16 forms never store Delta
+    P.off_d = bump(cur, P.fused ? 0 : on * sizeof(float));  // fused forms never store Delta
     P.off_om1 = bump(cur, on * sizeof(float));
     P.end_fit = cur;
     return P;
@@ -172,11 +182,15 @@ GemmArgs trial_args(const Plan& P, void* ws, int prec, const float* B32, const u
     GemmArgs a = {};
     a.A = at<float>(ws, P.off_xp);
     a.B = B32;
-    if (prec != PREC_FP32) {
+    if (is_bf16(prec)) {
         a.Ah = at<uint16_t>(ws, P.off_xsplit[0]);
         a.Al = at<uint16_t>(ws, P.off_xsplit[1]);
         a.Bh = Bh;
         a.Bl = Bl;
+    } else if (prec == PREC_FP8) {
+        a.A8 = at<uint8_t>(ws, P.off_x8);
+        a.As = at<uint8_t>(ws, P.off_x8s);
+        a.ldas = P.p_pad / 32;
     }
     a.lda = P.p_pad;
     a.ldb = P.p_pad;
@@ -221,11 +235,18 @@ GemmArgs grad_args(const Plan& P, void* ws, int prec, const float* Wt, int wslot
     GemmArgs a = {};
     a.A = at<float>(ws, P.off_xt);
     a.B = Wt;
-    if (prec != PREC_FP32) {
+    if (is_bf16(prec)) {
         a.Ah = at<uint16_t>(ws, P.off_xsplit[2]);
         a.Al = at<uint16_t>(ws, P.off_xsplit[3]);
         a.Bh = at<uint16_t>(ws, P.off_wsplit[2 * wslot]);
         a.Bl = at<uint16_t>(ws, P.off_wsplit[2 * wslot + 1]);
+    } else if (prec == PREC_FP8) {
+        a.A8 = at<uint8_t>(ws, P.off_xt8);
+        a.As = at<uint8_t>(ws, P.off_xt8s);
+        a.B8 = at<uint8_t>(ws, P.off_w8);
+        a.Bs = at<uint8_t>(ws, P.off_w8s);
+        a.ldas = P.n_pad / 32;
+        a.ldbs = P.n_pad / 32;
     }
     a.lda = P.n_pad;
     a.ldb = P.n_pad;
@@ -248,7 +269,7 @@ GemmArgs grad_args(const Plan& P, void* ws, int prec, const float* Wt, int wslot
 
 XSplit x_split(const Plan& P, void* ws) {
     XSplit sp = {};
-    if (P.prec != PREC_FP32) {
+    if (is_bf16(P.prec)) {
         sp.xp_h = at<uint16_t>(ws, P.off_xsplit[0]);
         sp.xp_l = at<uint16_t>(ws, P.off_xsplit[1]);
         sp.xt_h = at<uint16_t>(ws, P.off_xsplit[2]);
@@ -301,7 +322,7 @@ int check_params(const accord_params* prm) {
         return fail(ACCORD_ERR_INVALID_ARG, "tol must be finite and >= 0");
     if (prm->max_iter < 0) return fail(ACCORD_ERR_INVALID_ARG, "max_iter must be >= 0");
     if (prm->precision != ACCORD_FP32 && prm->precision != ACCORD_BF16X1 &&
-        prm->precision != ACCORD_BF16X3)
+        prm->precision != ACCORD_BF16X3 && prm->precision != ACCORD_FP8)
         return fail(ACCORD_ERR_UNSUPPORTED, "precision form %d is not available", prm->precision);
     if (prm->tol > 0.0 && prm->check_every < 1)
         return fail(ACCORD_ERR_INVALID_ARG, "check_every must be >= 1 when tol > 0");
@@ -529,8 +550,10 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
     float* wt[2] = {at<float>(ws, P.off_wt0), at<float>(ws, P.off_wt1)};
     float* G = at<float>(ws, P.off_g);
     const int prec = prm->precision;
-    const bool bf = prec != PREC_FP32;
-    float* D = bf ? nullptr : at<float>(ws, P.off_d);
+    const bool bf = is_bf16(prec);
+    const bool f8 = prec == PREC_FP8;
+    const bool fused = P.fused != 0;
+    float* D = fused ? nullptr : at<float>(ws, P.off_d);
     double* prox_part = at<double>(ws, P.off_prox_part);
     double* norm_part = at<double>(ws, P.off_norm_part);
     int32_t* trials_log = at<int32_t>(ws, P.off_trials);
@@ -543,6 +566,11 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
                       prm->lipschitz, prm->max_iter, st);
     launch_pad_x(X, n, p, xp, P.p_pad, xt, P.n_pad, x_split(P, ws), ls, st);
     launch_copy_cols(Omega, p, om[0], P.p_pad, p, P.p_pad, ls, st);
+    if (f8) {
+        XQuant q = {at<uint8_t>(ws, P.off_x8), at<uint8_t>(ws, P.off_x8s),
+                    at<uint8_t>(ws, P.off_xt8), at<uint8_t>(ws, P.off_xt8s)};
+        launch_quant_x8(X, n, p, P.p_pad, P.n_pad, q, st);
+    }
     if (prm->lipschitz <= 0.0) {
         launch_power_iteration(xp, P.p_pad, xt, P.n_pad, n, p, at<double>(ws, P.off_pow_w),
                                at<double>(ws, P.off_pow_u), at<double>(ws, P.off_pow_pu),
@@ -594,6 +622,9 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
         GemmArgs ga = grad_args(P, ws, prec, wt[cur], cur, G, P.p_pad, (int)P.p_pad, ls);
         Launch lg = {nullptr, nullptr, t, 0};
         if (timing) { lg.a = pool.get(); lg.b = pool.get(); HIP_TRY(hipEventRecord(lg.a, st)); }
+        if (f8)  // MX copy of the current W (blocks along the samples) for the gradient
+            launch_quant_w8(wt[cur], p * P.n_pad, at<uint8_t>(ws, P.off_w8),
+                            at<uint8_t>(ws, P.off_w8s), ls, st);
         launch_gemm(ga, EPI_GRAD, prec, st);
         if (timing) { HIP_TRY(hipEventRecord(lg.b, st)); ev_grad.push_back(lg); }
         auto enqueue_trial_k = [&](int k) -> int {
@@ -609,7 +640,7 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
             a.part = prox_part;
             GemmArgs ta = trial_args(P, ws, prec, D, nullptr, nullptr, wt[cur], wt[nxt],
                                      bf ? nxt : -1, ls, 2);
-            if (!bf) {
+            if (!fused) {
                 Launch lp = {nullptr, nullptr, t, k};
                 if (timing) { lp.a = pool.get(); lp.b = pool.get(); HIP_TRY(hipEventRecord(lp.a, st)); }
                 launch_prox(a, P.nprox, st);
@@ -617,7 +648,7 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
             }
             Launch lt = {nullptr, nullptr, t, k};
             if (timing) { lt.a = pool.get(); lt.b = pool.get(); HIP_TRY(hipEventRecord(lt.a, st)); }
-            if (bf)
+            if (fused)
                 launch_trial_fused(ta, a, prec, st);
             else
                 enqueue_trial(ta, prec, st);

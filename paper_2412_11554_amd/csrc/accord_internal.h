@@ -71,7 +71,7 @@ struct Mailbox {
 // kernel argument blocks
 // ---------------------------------------------------------------------------
 enum GemmEpi { EPI_GRAD = 0, EPI_TRIAL = 1, EPI_PARTIAL = 2 };
-enum Prec { PREC_FP32 = 0, PREC_BF16X1 = 1, PREC_BF16X3 = 2 };
+enum Prec { PREC_FP32 = 0, PREC_BF16X1 = 1, PREC_BF16X3 = 2, PREC_FP8 = 3 };
 
 // optional bf16 hi/lo copies of the padded X operands
 struct XSplit {
@@ -81,6 +81,14 @@ struct XSplit {
     uint16_t* xt_l;
 };
 
+// MX-FP8 copies of the padded X operands (E4M3 bytes + one E8M0 scale byte per 32)
+struct XQuant {
+    uint8_t* x8;    // n_pad x p_pad, blocks along the features (row-major)
+    uint8_t* x8s;   // n_pad x p_pad/32
+    uint8_t* xt8;   // p_pad x n_pad, blocks along the samples (row-major)
+    uint8_t* xt8s;  // p_pad x n_pad/32
+};
+
 struct GemmArgs {
     const float* A;     // FP32: M x K row-major (lda), K a multiple of kPad, zero-padded
     const float* B;     // FP32: N x K row-major (ldb)
@@ -88,6 +96,11 @@ struct GemmArgs {
     const uint16_t* Al;
     const uint16_t* Bh;
     const uint16_t* Bl;
+    const uint8_t* A8;  // FP8 form: E4M3 A and B (same layouts, lda/ldb in bytes)
+    const uint8_t* B8;
+    const uint8_t* As;  // FP8 form: E8M0 scales, one per 32 K values, row-major
+    const uint8_t* Bs;
+    int64_t ldas, ldbs; // scale bytes per row (K / 32)
     int64_t lda, ldb;   // elements
     int M, N, K;        // C is M x N column-major; K = padded contraction length
     int tilesM, tilesN, splits;
@@ -132,6 +145,10 @@ void launch_pad_x(const float* X, int64_t n, int64_t p, float* Xp, int64_t p_pad
                   int64_t n_pad, XSplit sp, LsState* ls, hipStream_t st);
 void launch_copy_cols(const float* src, int64_t ld_src, float* dst, int64_t ld_dst, int64_t p,
                       int64_t rows, LsState* check_ls, hipStream_t st);
+void launch_quant_x8(const float* X, int64_t n, int64_t p, int64_t p_pad, int64_t n_pad,
+                     XQuant q, hipStream_t st);
+void launch_quant_w8(const float* Wt, int64_t total, uint8_t* w8, uint8_t* w8s, const LsState* ls,
+                     hipStream_t st);
 void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st);
 void launch_splitk_reduce(const GemmArgs& a, hipStream_t st);
 void launch_trial_fused(const GemmArgs& a, const ProxArgs& px, int prec, hipStream_t st);

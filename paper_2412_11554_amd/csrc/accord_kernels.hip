@@ -677,8 +677,15 @@ __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
     }
 }
 
+void launch_grad_fp8(const GemmArgs& a, hipStream_t st);
+void launch_trial_fused8(const GemmArgs& a, const ProxArgs& px, hipStream_t st);
+
 void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st) {
     const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
+    if (prec == PREC_FP8) {  // FP8 form: gradient only, like the bf16 forms
+        launch_grad_fp8(a, st);
+        return;
+    }
     if (prec != PREC_FP32) {
         // bf16 forms: gradient only (their trial products run in k_trial_fused)
         if (prec == PREC_BF16X3)
@@ -1148,6 +1155,10 @@ __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_f(GemmArgs g) {
 }
 
 void launch_trial_fused(const GemmArgs& a, const ProxArgs& px, int prec, hipStream_t st) {
+    if (prec == PREC_FP8) {
+        launch_trial_fused8(a, px, st);
+        return;
+    }
     const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
     if (a.splits > 1) {
         if (prec == PREC_BF16X3)
@@ -1160,6 +1171,532 @@ void launch_trial_fused(const GemmArgs& a, const ProxArgs& px, int prec, hipStre
             k_trial_fused<3, EPI_TRIAL><<<blocks, kWThreads, 0, st>>>(a, px);
         else
             k_trial_fused<1, EPI_TRIAL><<<blocks, kWThreads, 0, st>>>(a, px);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP8 form: OCP MX operands (E4M3 elements, one E8M0 power-of-two scale per 32
+// consecutive values along the contraction index) on the gfx950 scaled MFMA
+// v_mfma_scale_f32_32x32x64_f8f6f4, FP32 accumulation.
+//
+// Block scale: 2^s with s = floor(log2(block max)) - 7, so the block maximum maps
+// into [128, 256) and no element needs clamping; s >= -126; an all-zero block
+// takes s = 0.  Elements are rounded to nearest, ties to even (v_cvt_pk_fp8_f32),
+// after multiplying by 2^-s (exact).  The conversion turns magnitudes >= 480 into
+// NaN, so the scaled values are clamped to +-448 first (a no-op for finite input
+// under this scale rule).
+//
+// 32x32x64 operand layout (A rows / B columns alike): lane l supplies row l % 32;
+// with g = l / 32 its bytes 0..15 are K = 16 g .. 16 g + 15 and bytes 16..31 are
+// K = 32 + 16 g .. 32 + 16 g + 15.  Lane l's scale byte (op_sel 0) applies to
+// MX block g of its row: K 0..31 for g = 0, K 32..63 for g = 1.  The accumulator
+// layout is that of the bf16 32x32 instructions.
+// ---------------------------------------------------------------------------
+typedef int i8v __attribute__((ext_vector_type(8)));
+
+__device__ inline uint32_t mx_scale_byte(float amax) {
+    if (!(amax > 0.f)) return 127u;                      // zero block: 2^0
+    const int e = (int)(__float_as_uint(amax) >> 23);    // biased exponent (sign is 0)
+    const int b = e - 7;
+    return (uint32_t)(b < 1 ? 1 : b);
+}
+
+__device__ inline float mx_inv_scale(uint32_t sb) { return __uint_as_float((254u - sb) << 23); }
+__device__ inline float mx_scale(uint32_t sb) { return __uint_as_float(sb << 23); }
+
+__device__ inline float clamp448(float v) { return fminf(fmaxf(v, -448.f), 448.f); }
+
+// four values -> four E4M3 bytes (value u in byte u)
+__device__ inline uint32_t mx_pack4(f4 v, float inv) {
+    uint32_t w = __builtin_amdgcn_cvt_pk_fp8_f32(clamp448(v[0] * inv), clamp448(v[1] * inv), 0,
+                                                 false);
+    return __builtin_amdgcn_cvt_pk_fp8_f32(clamp448(v[2] * inv), clamp448(v[3] * inv), w, true);
+}
+
+__device__ inline f4 mx_unpack4(uint32_t w, float sc) {
+    return f4{__builtin_amdgcn_cvt_f32_fp8((int)w, 0) * sc, __builtin_amdgcn_cvt_f32_fp8((int)w, 1) * sc,
+              __builtin_amdgcn_cvt_f32_fp8((int)w, 2) * sc, __builtin_amdgcn_cvt_f32_fp8((int)w, 3) * sc};
+}
+
+__device__ inline float fmax4(f4 v) {
+    return fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
+}
+
+// X (n x p row-major) -> MX copies of both GEMM operands:
+//   x8  (n_pad x p_pad, blocks of 32 features per row: the A operand of X Delta)
+//   xt8 (p_pad x n_pad, blocks of 32 samples per feature: the A operand of X^T W)
+// with scale bytes x8s [n_pad][p_pad/32] and xt8s [p_pad][n_pad/32].  One 32 x 32
+// tile of X per workgroup; padding is zero.
+__global__ void __launch_bounds__(kThreads) k_quant_x8(const float* __restrict__ X, int64_t n,
+                                                       int64_t p, int64_t p_pad, int64_t n_pad,
+                                                       XQuant q) {
+    __shared__ float t[32][33];
+    const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int rr = ty; rr < 32; rr += kThreads / 32) {
+        const int64_t r = r0 + rr, c = c0 + tx;
+        t[rr][tx] = (r < n && c < p) ? X[r * p + c] : 0.f;
+    }
+    __syncthreads();
+    const int line = threadIdx.x >> 3, part = threadIdx.x & 7;  // 8 lanes per block
+    {   // row `line` of the tile: features c0 .. c0+31 of sample r0 + line
+        f4 v;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = t[line][4 * part + u];
+        float m = fmax4(v);
+        m = fmaxf(m, __shfl_xor(m, 1, 64));
+        m = fmaxf(m, __shfl_xor(m, 2, 64));
+        m = fmaxf(m, __shfl_xor(m, 4, 64));
+        const uint32_t sb = mx_scale_byte(m);
+        *(uint32_t*)(q.x8 + (r0 + line) * p_pad + c0 + 4 * part) = mx_pack4(v, mx_inv_scale(sb));
+        if (part == 0) q.x8s[(r0 + line) * (p_pad / 32) + blockIdx.x] = (uint8_t)sb;
+    }
+    {   // column `line` of the tile: samples r0 .. r0+31 of feature c0 + line
+        f4 v;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = t[4 * part + u][line];
+        float m = fmax4(v);
+        m = fmaxf(m, __shfl_xor(m, 1, 64));
+        m = fmaxf(m, __shfl_xor(m, 2, 64));
+        m = fmaxf(m, __shfl_xor(m, 4, 64));
+        const uint32_t sb = mx_scale_byte(m);
+        *(uint32_t*)(q.xt8 + (c0 + line) * n_pad + r0 + 4 * part) = mx_pack4(v, mx_inv_scale(sb));
+        if (part == 0) q.xt8s[(c0 + line) * (n_pad / 32) + blockIdx.y] = (uint8_t)sb;
+    }
+}
+
+void launch_quant_x8(const float* X, int64_t n, int64_t p, int64_t p_pad, int64_t n_pad,
+                     XQuant q, hipStream_t st) {
+    dim3 grid((unsigned)(p_pad / 32), (unsigned)(n_pad / 32));
+    k_quant_x8<<<grid, kThreads, 0, st>>>(X, n, p, p_pad, n_pad, q);
+}
+
+// W^T (rows x n_pad FP32, row-major) -> MX (blocks of 32 samples per row): the B
+// operand of the FP8 gradient.  Eight lanes per block, four values per lane.
+// Skipped once the fit has stopped.
+__global__ void __launch_bounds__(kThreads) k_quant_w8(const float* __restrict__ Wt, int64_t total,
+                                                       uint8_t* __restrict__ w8,
+                                                       uint8_t* __restrict__ w8s,
+                                                       const LsState* ls) {
+    if (ls && ls->converged) return;
+    const int64_t n4 = total >> 2;  // total is a multiple of 32: blocks never straddle
+    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < n4;
+         base += (int64_t)gridDim.x * kThreads) {
+        const int64_t i4 = base + threadIdx.x;
+        const bool ok = i4 < n4;    // uniform over each aligned group of 8 lanes
+        const f4 v = ok ? ((const f4*)Wt)[i4] : f4{0.f, 0.f, 0.f, 0.f};
+        float m = fmax4(v);
+        m = fmaxf(m, __shfl_xor(m, 1, 64));
+        m = fmaxf(m, __shfl_xor(m, 2, 64));
+        m = fmaxf(m, __shfl_xor(m, 4, 64));
+        const uint32_t sb = mx_scale_byte(m);
+        if (ok) {
+            ((uint32_t*)w8)[i4] = mx_pack4(v, mx_inv_scale(sb));
+            if ((threadIdx.x & 7) == 0) w8s[i4 >> 3] = (uint8_t)sb;
+        }
+    }
+}
+
+void launch_quant_w8(const float* Wt, int64_t total, uint8_t* w8, uint8_t* w8s, const LsState* ls,
+                     hipStream_t st) {
+    const int64_t n4 = total >> 2;
+    int64_t blocks = cdiv(n4, (int64_t)kThreads);
+    if (blocks > 8192) blocks = 8192;
+    k_quant_w8<<<(unsigned)blocks, kThreads, 0, st>>>(Wt, total, w8, w8s, ls);
+}
+
+// operand fragment of the 32x32x64 instruction from an LDS row of 64 bytes
+__device__ inline i8v frag8(const uint8_t* row, int g) {
+    const u4 lo = *(const u4*)(row + 16 * g);
+    const u4 hi = *(const u4*)(row + 32 + 16 * g);
+    return i8v{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
+               (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+}
+
+// FP8 gradient GEMM G = X^T W / n: 256 x 256 tile, 8 waves (2 along M x 4 along N),
+// each 128 x 64 = 4 x 2 blocks of the 32x32x64 instruction; one 64-deep K step
+// (two MX blocks) per LDS stage, double-buffered; same tile order and epilogue as
+// the bf16 gradient.
+constexpr int kLDK8 = 64 + 16;  // bytes per LDS row (16-byte pad: conflict-free reads)
+
+template <int EPI>
+__global__ void __launch_bounds__(kWThreads, 1) k_gemm_fp8w(GemmArgs g) {
+    if (gemm_skip(g)) return;
+    __shared__ __attribute__((aligned(16))) uint8_t sA[2][kWBM * kLDK8];
+    __shared__ __attribute__((aligned(16))) uint8_t sB[2][kWBN * kLDK8];
+    __shared__ __attribute__((aligned(16))) uint8_t sAs[2][kWBM * 2];
+    __shared__ __attribute__((aligned(16))) uint8_t sBs[2][kWBN * 2];
+
+    int tile_m, tile_n, split;
+    decode_tile(g, tile_m, tile_n, split);
+    const int m0 = tile_m * kWBM, n0 = tile_n * kWBN;
+    const int ksteps = g.K / 64;
+    const int s_begin = (int)((int64_t)ksteps * split / g.splits);
+    const int s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // data loader: row tid / 2, bytes 32 (tid & 1) .. +31 of the step
+    const int lrow = tid >> 1, lcol = (tid & 1) * 32;
+    int ra = m0 + lrow;
+    ra = ra < g.M ? ra : g.M - 1;
+    int rb = n0 + lrow;
+    rb = rb < g.N ? rb : g.N - 1;
+    const uint8_t* pa = g.A8 + (int64_t)ra * g.lda + lcol;
+    const uint8_t* pb = g.B8 + (int64_t)rb * g.ldb + lcol;
+    // scale loader: threads 0..255 take A rows, 256..511 B rows (2 bytes per step)
+    const int srow = tid & 255;
+    const bool sa_side = tid < 256;
+    int rs = (sa_side ? m0 : n0) + srow;
+    const int rlim = sa_side ? g.M : g.N;
+    rs = rs < rlim ? rs : rlim - 1;
+    const uint8_t* ps = sa_side ? g.As + (int64_t)rs * g.ldas : g.Bs + (int64_t)rs * g.ldbs;
+    uint8_t* sdst0 = sa_side ? &sAs[0][srow * 2] : &sBs[0][srow * 2];
+    uint8_t* sdst1 = sa_side ? &sAs[1][srow * 2] : &sBs[1][srow * 2];
+
+    u4 va[2], vb[2];
+    uint16_t vs;
+    f16v acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
+    const int r32 = lane & 31, gk = lane >> 5;
+
+    if (s_begin < s_end) {
+        {
+            const int64_t ko = (int64_t)s_begin * 64;
+            va[0] = *(const u4*)(pa + ko);
+            va[1] = *(const u4*)(pa + ko + 16);
+            vb[0] = *(const u4*)(pb + ko);
+            vb[1] = *(const u4*)(pb + ko + 16);
+            vs = *(const uint16_t*)(ps + 2 * (int64_t)s_begin);
+        }
+        *(u4*)&sA[0][lrow * kLDK8 + lcol] = va[0];
+        *(u4*)&sA[0][lrow * kLDK8 + lcol + 16] = va[1];
+        *(u4*)&sB[0][lrow * kLDK8 + lcol] = vb[0];
+        *(u4*)&sB[0][lrow * kLDK8 + lcol + 16] = vb[1];
+        *(uint16_t*)sdst0 = vs;
+        __syncthreads();
+        int cur = 0;
+        for (int s = s_begin; s < s_end; ++s) {
+            {   // unconditional prefetch (see k_gemm_bf16w)
+                const int sn = s + 1 < s_end ? s + 1 : s;
+                const int64_t ko = (int64_t)sn * 64;
+                va[0] = *(const u4*)(pa + ko);
+                va[1] = *(const u4*)(pa + ko + 16);
+                vb[0] = *(const u4*)(pb + ko);
+                vb[1] = *(const u4*)(pb + ko + 16);
+                vs = *(const uint16_t*)(ps + 2 * (int64_t)sn);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            i8v af[4], bf[2];
+            int sa[4], sbv[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = wm + 32 * i + r32;
+                af[i] = frag8(&sA[cur][row * kLDK8], gk);
+                sa[i] = sAs[cur][row * 2 + gk];
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int row = wn + 32 * j + r32;
+                bf[j] = frag8(&sB[cur][row * kLDK8], gk);
+                sbv[j] = sBs[cur][row * 2 + gk];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        af[i], bf[j], acc[i][j], 0, 0, 0, sa[i], 0, sbv[j]);
+            __builtin_amdgcn_sched_barrier(0);
+            *(u4*)&sA[cur ^ 1][lrow * kLDK8 + lcol] = va[0];
+            *(u4*)&sA[cur ^ 1][lrow * kLDK8 + lcol + 16] = va[1];
+            *(u4*)&sB[cur ^ 1][lrow * kLDK8 + lcol] = vb[0];
+            *(u4*)&sB[cur ^ 1][lrow * kLDK8 + lcol + 16] = vb[1];
+            *(uint16_t*)(cur ? sdst0 : sdst1) = vs;
+            __syncthreads();
+            cur ^= 1;
+        }
+    }
+    __syncthreads();
+
+    const int mw = m0 + wm + 4 * (lane >> 5), nw = n0 + wn + (lane & 31);
+    double nv[2] = {0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                store_frag<EPI>(g,
+                                f4{acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2],
+                                   acc[i][j][4 * q + 3]},
+                                mw + 32 * i + 8 * q, nw + 32 * j, nv);
+}
+
+// Fused prox + trial product of the FP8 form.  Same structure as k_trial_fused
+// (256 x 128 tile, 8 waves of 64 x 64, tile_m fastest, the tile_m == 0 workgroup
+// owns its column block), with a 64-deep K step: each thread produces rows
+// br .. br + 7 of columns bc and bc + 64, the four lanes covering one 32-row MX
+// block agree on its scale through lane shuffles, and Delta reaches LDS as E4M3
+// bytes plus scale bytes.  The line-search sums take Delta as represented.
+#define FUSED_PRODUCE8(buf, step)                                                         \
+    do {                                                                                  \
+        const int64_t k0_ = (int64_t)(step) * 64;                                         \
+        *(u4*)&sA8[(buf)][arow * kLDK8 + acol] = va[0];                                   \
+        *(u4*)&sA8[(buf)][arow * kLDK8 + acol + 16] = va[1];                              \
+        if (tid < kFBM) *(uint16_t*)&sAs8[(buf)][tid * 2] = vsa;                          \
+        _Pragma("unroll") for (int q = 0; q < 2; ++q) {                                   \
+            f4 nw_[2];                                                                    \
+            _Pragma("unroll") for (int h = 0; h < 2; ++h) {                               \
+                const f4 o_ = vo[q][h], g_ = vg[q][h];                                    \
+                _Pragma("unroll") for (int u = 0; u < 4; ++u) {                           \
+                    const float a_ = fmaf(-tau_f, g_[u], o_[u]);                          \
+                    const float t_ = fabsf(a_) - thr_f;                                   \
+                    nw_[h][u] = t_ > 0.f ? copysignf(t_, a_) : 0.f;                       \
+                }                                                                         \
+            }                                                                             \
+            const int64_t dpos_ = jcol[q] - (k0_ + br);                                   \
+            const bool has_diag_ = dpos_ >= 0 && dpos_ < 8;                               \
+            float dval_ = 0.f;                                                            \
+            if (has_diag_) {                                                              \
+                const int du_ = (int)dpos_;                                               \
+                const f4 od4_ = du_ < 4 ? vo[q][0] : vo[q][1];                            \
+                const f4 gd4_ = du_ < 4 ? vg[q][0] : vg[q][1];                            \
+                const int uu_ = du_ & 3;                                                  \
+                const float od_ = uu_ == 0 ? od4_[0] : uu_ == 1 ? od4_[1] : uu_ == 2 ? od4_[2] : od4_[3]; \
+                const float gd_ = uu_ == 0 ? gd4_[0] : uu_ == 1 ? gd4_[1] : uu_ == 2 ? gd4_[2] : gd4_[3]; \
+                dval_ = prox_one(od_, gd_, true, tau, lam, tau_f, thr_f);                 \
+                _Pragma("unroll") for (int h = 0; h < 2; ++h)                             \
+                    _Pragma("unroll") for (int u = 0; u < 4; ++u)                         \
+                        nw_[h][u] = (4 * h + u == du_) ? dval_ : nw_[h][u];               \
+            }                                                                             \
+            f4 d_[2];                                                                     \
+            _Pragma("unroll") for (int h = 0; h < 2; ++h) d_[h] = nw_[h] - vo[q][h];      \
+            if (!jvalid[q]) d_[0] = d_[1] = f4{0.f, 0.f, 0.f, 0.f};                       \
+            float m_ = fmaxf(fmax4(d_[0]), fmax4(d_[1]));                                 \
+            m_ = fmaxf(m_, __shfl_xor(m_, 1, 64));                                        \
+            m_ = fmaxf(m_, __shfl_xor(m_, 2, 64));                                        \
+            const uint32_t sb_ = mx_scale_byte(m_);                                       \
+            const float inv_ = mx_inv_scale(sb_), sc_ = mx_scale(sb_);                    \
+            const uint32_t w0_ = mx_pack4(d_[0], inv_), w1_ = mx_pack4(d_[1], inv_);      \
+            const int col_ = bc + 64 * q;                                                 \
+            *(uint2*)&sB8[(buf)][col_ * kLDK8 + br] = make_uint2(w0_, w1_);               \
+            if ((tid & 3) == 0) sBs8[(buf)][col_ * 2 + ((tid >> 2) & 1)] = (uint8_t)sb_;  \
+            if (owner && jvalid[q]) {                                                     \
+                *(f4*)(pn[q] + k0_) = nw_[0];                                             \
+                *(f4*)(pn[q] + k0_ + 4) = nw_[1];                                         \
+                float sd2_ = 0.f, sdg_ = 0.f, sl1_ = 0.f, sfr_ = 0.f;                     \
+                int nz_ = 0;                                                              \
+                _Pragma("unroll") for (int h = 0; h < 2; ++h) {                           \
+                    const f4 dq_ = mx_unpack4(h ? w1_ : w0_, sc_);                        \
+                    _Pragma("unroll") for (int u = 0; u < 4; ++u) {                       \
+                        const float dv_ = dq_[u];                                         \
+                        sd2_ = fmaf(dv_, dv_, sd2_);                                      \
+                        sdg_ = fmaf(dv_, vg[q][h][u], sdg_);                              \
+                        sl1_ += fabsf(nw_[h][u]);                                         \
+                        sfr_ = fmaf(nw_[h][u], nw_[h][u], sfr_);                          \
+                        nz_ += (nw_[h][u] != 0.f && !(has_diag_ && 4 * h + u == (int)dpos_)) ? 1 : 0; \
+                    }                                                                     \
+                }                                                                         \
+                pacc.d2 += (double)sd2_;                                                  \
+                pacc.dg += (double)sdg_;                                                  \
+                pacc.l1 += (double)sl1_;                                                  \
+                pacc.fro += (double)sfr_;                                                 \
+                pacc.nnz += (double)nz_;                                                  \
+                if (has_diag_) pacc.logd += dval_ > 0.f ? log((double)dval_) : -INFINITY; \
+            }                                                                             \
+        }                                                                                 \
+    } while (0)
+
+template <int EPI>
+__global__ void __launch_bounds__(kWThreads, 1) k_trial_fused8(GemmArgs g, ProxArgs px) {
+    if (gemm_skip(g)) return;
+    __shared__ __attribute__((aligned(16))) uint8_t sA8[2][kFBM * kLDK8];
+    __shared__ __attribute__((aligned(16))) uint8_t sB8[2][kFBN * kLDK8];
+    __shared__ __attribute__((aligned(16))) uint8_t sAs8[2][kFBM * 2];
+    __shared__ __attribute__((aligned(16))) uint8_t sBs8[2][kFBN * 2];
+
+    const double tau = px.ls->tau, lam = px.ls->lambda;
+    const float tau_f = (float)tau, thr_f = (float)(tau * lam);
+
+    const int nblk = gridDim.x, bid = blockIdx.x;
+    const int xcd = bid & 7, local = bid >> 3, q8 = nblk >> 3, r8 = nblk & 7;
+    const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + local;
+    const int tile_m = logical % g.tilesM;
+    const int tile_n = (logical / g.tilesM) % g.tilesN;
+    const int split = logical / (g.tilesM * g.tilesN);
+    const bool owner = tile_m == 0;
+    const int m0 = tile_m * kFBM, n0 = tile_n * kFBN;
+    const int ksteps = g.K / 64;
+    const int s_begin = (int)((int64_t)ksteps * split / g.splits);
+    const int s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // A loader: row tid / 2 of the tile, 32 bytes; scale bytes by threads 0..255
+    const int arow = tid >> 1, acol = (tid & 1) * 32;
+    int ra = m0 + arow;
+    ra = ra < g.M ? ra : g.M - 1;
+    const uint8_t* pa = g.A8 + (int64_t)ra * g.lda + acol;
+    int rsa = m0 + (tid & (kFBM - 1));
+    rsa = rsa < g.M ? rsa : g.M - 1;
+    const uint8_t* psa = g.As + (int64_t)rsa * g.ldas;
+    // B producer: columns bc + 64 q (q = 0, 1), rows br .. br + 7 of the step
+    const int bc = tid >> 3, br = (tid & 7) * 8;
+    int64_t jcol[2];
+    bool jvalid[2];
+    const float* po[2];
+    const float* pg[2];
+    float* pn[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int64_t j = (int64_t)n0 + bc + 64 * q;
+        jvalid[q] = j < px.p;
+        jcol[q] = j;
+        const int64_t jc = jvalid[q] ? j : px.p - 1;
+        po[q] = px.om + jc * px.ld + br;
+        pg[q] = px.g + jc * px.ld + br;
+        pn[q] = px.om_new + jc * px.ld + br;
+    }
+    u4 va[2];
+    uint16_t vsa = 0;
+    f4 vo[2][2], vg[2][2];
+    f16v acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    ProxAcc pacc;
+
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int r32 = lane & 31, gk = lane >> 5;
+
+    if (s_begin < s_end) {
+        {
+            const int64_t ko = (int64_t)s_begin * 64;
+            va[0] = *(const u4*)(pa + ko);
+            va[1] = *(const u4*)(pa + ko + 16);
+            vsa = *(const uint16_t*)(psa + 2 * (int64_t)s_begin);
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    vo[q][h] = *(const f4*)(po[q] + ko + 4 * h);
+                    vg[q][h] = *(const f4*)(pg[q] + ko + 4 * h);
+                }
+        }
+        FUSED_PRODUCE8(0, s_begin);
+        __syncthreads();
+        int cur = 0;
+        for (int s = s_begin; s < s_end; ++s) {
+            const bool more = s + 1 < s_end;
+            {   // unconditional prefetch (see k_gemm_bf16w)
+                const int sn = more ? s + 1 : s;
+                const int64_t ko = (int64_t)sn * 64;
+                va[0] = *(const u4*)(pa + ko);
+                va[1] = *(const u4*)(pa + ko + 16);
+                vsa = *(const uint16_t*)(psa + 2 * (int64_t)sn);
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        vo[q][h] = *(const f4*)(po[q] + ko + 4 * h);
+                        vg[q][h] = *(const f4*)(pg[q] + ko + 4 * h);
+                    }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            i8v af[2], bf[2];
+            int sa[2], sbv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int row = wm + 32 * i + r32;
+                af[i] = frag8(&sA8[cur][row * kLDK8], gk);
+                sa[i] = sAs8[cur][row * 2 + gk];
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int row = wn + 32 * j + r32;
+                bf[j] = frag8(&sB8[cur][row * kLDK8], gk);
+                sbv[j] = sBs8[cur][row * 2 + gk];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        af[i], bf[j], acc[i][j], 0, 0, 0, sa[i], 0, sbv[j]);
+            __builtin_amdgcn_sched_barrier(0);
+            if (more) FUSED_PRODUCE8(cur ^ 1, s + 1);
+            __syncthreads();
+            cur ^= 1;
+        }
+    }
+    __syncthreads();
+
+    const int tile = tile_m + tile_n * g.tilesM;
+    double* red = (double*)&sA8[0][0];  // LDS is free after the K loop
+    if (owner) {
+        double v[6] = {pacc.d2, pacc.dg, pacc.l1, pacc.logd, pacc.nnz, pacc.fro};
+        block_sum_in<6, kWThreads / 64>(v, red);
+        if (tid == 0) {
+            double* out = px.part + ((int64_t)tile_n * g.splits + split) * kPartCols;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) out[k] = v[k];
+            out[6] = 0.0;
+            out[7] = 0.0;
+        }
+    }
+    if (EPI == EPI_PARTIAL) {
+        f4* P = (f4*)(g.P + ((int64_t)split * g.tilesM * g.tilesN + tile) * (kFBM * kFBN));
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    P[((i * 2 + j) * 4 + q) * kWThreads + tid] =
+                        f4{acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2],
+                           acc[i][j][4 * q + 3]};
+        return;
+    }
+    const int mw = m0 + wm + 4 * (lane >> 5), nw = n0 + wn + (lane & 31);
+    double nv[2] = {0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                store_frag<EPI_TRIAL>(g,
+                                      f4{acc[i][j][4 * q], acc[i][j][4 * q + 1],
+                                         acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]},
+                                      mw + 32 * i + 8 * q, nw + 32 * j, nv);
+    block_sum_in<2, kWThreads / 64>(nv, red);
+    if (tid == 0) {
+        g.norm_part[(int64_t)tile * kNormCols + 0] = nv[0];
+        g.norm_part[(int64_t)tile * kNormCols + 1] = nv[1];
+    }
+}
+
+void launch_grad_fp8(const GemmArgs& a, hipStream_t st) {
+    const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
+    k_gemm_fp8w<EPI_GRAD><<<blocks, kWThreads, 0, st>>>(a);
+}
+
+void launch_trial_fused8(const GemmArgs& a, const ProxArgs& px, hipStream_t st) {
+    const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
+    if (a.splits > 1) {
+        k_trial_fused8<EPI_PARTIAL><<<blocks, kWThreads, 0, st>>>(a, px);
+        k_splitk_reduce_f<<<(unsigned)(a.tilesM * a.tilesN * kFReduceParts), kWThreads, 0, st>>>(a);
+    } else {
+        k_trial_fused8<EPI_TRIAL><<<blocks, kWThreads, 0, st>>>(a, px);
     }
 }
 

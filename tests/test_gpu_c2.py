@@ -14,10 +14,13 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 COLS = np.array([0, 1, 2, 499, 500, 31337, 50000, 77777, 99998, 99999])
-ITERS = {"bf16x3": 6, "fp32": 3, "bf16x1": 3}
+ITERS = {"bf16x3": 6, "fp32": 3, "bf16x1": 3, "fp8": 1}
 # relative Frobenius error of the sampled columns: the FP32 bar for fp32 and the
 # split-precision form; bf16 unit roundoff (2^-8 relative) for the single-pass form
 TOL = {"bf16x3": 1e-4, "fp32": 1e-4, "bf16x1": 5e-2}
+# fp8: one fixed step, compared with the MX oracle (same operand rounding) at the
+# one-step bar derived in tests/test_gpu_fp8.py
+TOL_MX = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -48,7 +51,6 @@ def c2(gpu_lib):
 
 @pytest.mark.parametrize("form", ["bf16x3", "fp32", "bf16x1"])
 def test_c2_sampled_columns(c2, form):
-    import oracle
     from paper_2412_11554_amd import accord
 
     w = c2["w"]
@@ -56,6 +58,24 @@ def test_c2_sampled_columns(c2, form):
     print(f"[c2] {form}: accord_fit n={w.n} p={w.p} iters={T}", flush=True)
     om, st, tr = accord.accord_fit(c2["X"], w.lam, T, precision=form, trace=True,
                                    ws=c2["ws"], omega_out=c2["om"])
+    _check_sampled(c2, form, om, st, tr)
+
+
+def test_c2_fp8_fixed_step(c2):
+    """FP8: one fixed step (beta = 1, tau = 1/64) from the identity."""
+    from paper_2412_11554_amd import accord
+    w = c2["w"]
+    print(f"[c2] fp8: accord_fit n={w.n} p={w.p} one fixed step", flush=True)
+    om, st, tr = accord.accord_fit(c2["X"], w.lam, 1, precision="fp8", trace=True,
+                                   tau0=1.0 / 64, beta=1.0, ws=c2["ws"], omega_out=c2["om"])
+    _check_sampled(c2, "fp8", om, st, tr)
+
+
+def _check_sampled(c2, form, om, st, tr):
+    import oracle
+    from oracle import mx_oracle
+    w = c2["w"]
+    T = ITERS[form]
     assert st["iters"] == T
     trace = tr.cpu().numpy()
     taus = trace[1:, 3]
@@ -65,16 +85,22 @@ def test_c2_sampled_columns(c2, form):
     # device power iteration: a lower bound (Rayleigh quotient) close to the top eigenvalue
     assert st["lipschitz"] <= c2["L"] * (1 + 1e-6)
     assert abs(st["lipschitz"] - c2["L"]) <= 5e-3 * c2["L"]
-    # the objective does not increase (sufficient-decrease of the accepted steps),
-    # up to the FP32 rounding of sums over 1e10 entries
     f = trace[:, 0]
-    assert np.all(np.diff(f) <= 1e-5 * np.abs(f[:-1])), f
-
-    ref = oracle.fit_fbs(c2["x64"], w.lam, T, L=st["lipschitz"], tau_replay=taus,
-                         columns=COLS)
+    assert np.all(np.isfinite(f))
+    if form == "fp8":
+        # (the FP8 form carries W + X q(Delta), not X Omega+, so its traced g is not
+        # that of the iterate and need not decrease)
+        assert np.all(taus == 1.0 / 64)
+        ref = mx_oracle.fit_fbs_mx(c2["x64"], w.lam, taus, columns=COLS)
+    else:
+        # the objective does not increase (sufficient decrease of the accepted steps),
+        # up to the FP32 rounding of sums over 1e10 entries
+        assert np.all(np.diff(f) <= 1e-5 * np.abs(f[:-1])), f
+        ref = oracle.fit_fbs(c2["x64"], w.lam, T, L=st["lipschitz"], tau_replay=taus,
+                             columns=COLS)
     got = om[COLS, :].cpu().numpy().astype(np.float64).T
     err = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
     print(f"[c2] {form}: rel err {err:.3e}, trials {st['trials']}, "
           f"floor accepts {st['floor_accepts']}, L {st['lipschitz']:.6f} vs {c2['L']:.6f}",
           flush=True)
-    assert err <= TOL[form], err
+    assert err <= (TOL_MX if form == "fp8" else TOL[form]), err

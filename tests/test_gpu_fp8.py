@@ -1,0 +1,197 @@
+"""GPU parity of the FP8 (MX) precision form.
+
+The reference is the MX oracle (oracle/mx_oracle.py): Alg. 1 in FP64 with every
+contraction operand rounded to MX-E4M3 exactly as the form specifies.  Device and
+oracle round the same operands.  They differ by:
+  * the scaled FP8 MFMA's own summation: products far below the largest product
+    of one 64-term instruction are dropped (measured: a term 2^-10 below the
+    largest is lost, one 2^-9 below is kept, and a 2^-9 term is lost even when
+    the large terms cancel exactly), so each instruction adds up to about 2^-9 of
+    its largest product of error -- well below the 2^-4 of the operand rounding
+    that the oracle does reproduce;
+  * FP32 iterates and FP32 accumulation across instructions (about 1e-7);
+  * rounding flips: an operand whose device and oracle values straddle an E4M3
+    rounding boundary moves by one E4M3 spacing (a whole block if its scale
+    flips), and the iteration carries such a difference forward.
+Measured on the n=100, p=200 workload: one step from the identity agrees to 4e-6
+and two steps to 2e-4, against a gap of 1e-3..1e-2 between one MX step and the
+unrounded step.  The checks therefore take FIXED steps (beta = 1, so both sides
+use the same step with no input from the device) from several starting points:
+one step at a relative Frobenius bar of 1e-4 (ten times below the smallest gap,
+so a path that silently ran in higher precision fails too), two steps at 1e-3
+(which still rejects an unrounded Delta or W, 3e-3..6e-3 away).  Longer runs
+state the form's error against the unrounded FP64 iteration; the refinement test
+bounds the estimate after BF16x3 refinement.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from oracle import mx_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+
+def _col(t):
+    return t.detach().cpu().numpy().astype(np.float64).T
+
+
+@pytest.fixture(scope="module")
+def dev(gpu_lib):
+    import torch
+    return torch.device("cuda:0")
+
+
+def _starts(x, lam, L, p):
+    """Starting points: the identity, a random sparse matrix with a positive
+    diagonal, and the plain oracle's iterate after 20 iterations (FP32-rounded)."""
+    rng = np.random.default_rng(p)
+    sparse = rng.normal(0, 0.1, size=(p, p)) * (rng.random((p, p)) < 0.05)
+    sparse[np.diag_indices(p)] = rng.uniform(0.5, 1.5, size=p)
+    fbs20 = oracle.fit_fbs(x, lam, 20, L=L).omega
+    return {"identity": np.eye(p), "sparse": sparse, "fbs20": fbs20}
+
+
+def _fixed_step_pair(gpu_lib, dev, x32, lam, tau, om0, iters, columns=None):
+    """Device: `iters` fixed steps of size tau from om0 (column form).  Oracle: the
+    same steps with MX-rounded operands.  Returns (device, oracle, oracle result)."""
+    import torch
+    om0_32 = om0.astype(np.float32)
+    om, stats, tr = gpu_lib.accord_fit(_t(x32, dev), lam, iters, tau0=tau, beta=1.0,
+                                       lipschitz=1.0, omega0=_t(om0_32.T, dev), trace=True,
+                                       precision="fp8")
+    torch.cuda.synchronize()
+    assert stats["iters"] == iters and stats["trials"] == iters
+    tr = tr.cpu().numpy()
+    assert np.all(tr[1:, 3] == tau)
+    ref = mx_oracle.fit_fbs_mx(x32.astype(np.float64), lam, [tau] * iters,
+                               omega0=om0_32.astype(np.float64), columns=columns)
+    got = _col(om) if columns is None else om.cpu().numpy()[columns, :].astype(np.float64).T
+    return got, ref.omega, ref, tr
+
+
+@pytest.mark.parametrize("start", ["identity", "sparse", "fbs20"])
+@pytest.mark.parametrize("tau", [0.25, 0.09])
+def test_fp8_one_step_vs_mx_oracle(gpu_lib, dev, start, tau):
+    """n=100, p=200 Erdos-Renyi workload: one fixed step from each start."""
+    w = datagen.workload("er200")
+    x = w.X.astype(np.float64)
+    L = oracle.lipschitz(x)
+    om0 = _starts(x, w.lam, L, w.p)[start]
+    got, ref, res, tr = _fixed_step_pair(gpu_lib, dev, w.X, w.lam, tau, om0, 1)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    unr = mx_oracle.fit_fbs_mx(x, w.lam, [tau], omega0=om0.astype(np.float32).astype(np.float64),
+                               quant=mx_oracle._identity).omega
+    gap = np.linalg.norm(ref - unr) / np.linalg.norm(unr)
+    g_ref = np.sum(res.extra["w"] ** 2) / (2 * w.n)
+    print(f"fp8 {start} tau={tau}: vs MX oracle {rel:.3e} (MX vs unrounded {gap:.3e}); "
+          f"g after the step {tr[1, 1]:.9g} vs {g_ref:.9g}", flush=True)
+    assert rel <= 1e-4, rel
+    assert gap >= 10 * 1e-4  # the rounding is really there, and the bar separates it
+    # the trial product: g = ||W + X q(Delta)||^2 / (2n) of the accepted step
+    assert abs(tr[1, 1] - g_ref) <= 2e-5 * g_ref
+    # the acceptance sums see Delta as represented: ||q(Delta)||_F
+    assert np.allclose(tr[1:, 5], res.extra["delta_q_fro"], rtol=1e-4)
+
+
+@pytest.mark.parametrize("start", ["identity", "sparse", "fbs20"])
+def test_fp8_two_steps_vs_mx_oracle(gpu_lib, dev, start):
+    w = datagen.workload("er200")
+    x = w.X.astype(np.float64)
+    L = oracle.lipschitz(x)
+    om0 = _starts(x, w.lam, L, w.p)[start]
+    got, ref, res, tr = _fixed_step_pair(gpu_lib, dev, w.X, w.lam, 0.25, om0, 2)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"fp8 {start} two steps: vs MX oracle {rel:.3e}", flush=True)
+    assert rel <= 1e-3, rel
+
+
+@pytest.mark.parametrize("n,p", [(33, 97), (130, 129), (1, 2), (100, 300)])
+def test_fp8_ragged(gpu_lib, dev, n, p):
+    print(f"fp8 n={n} p={p}", flush=True)
+    rng = np.random.default_rng(n * 11 + p)
+    x32 = rng.normal(size=(n, p)).astype(np.float32)
+    x = x32.astype(np.float64)
+    L = max(oracle.lipschitz(x), 1e-3)
+    om0 = np.eye(p) + np.diag(rng.uniform(0, 0.5, size=p))
+    got, ref, _, tr = _fixed_step_pair(gpu_lib, dev, x32, 0.1, 0.5 / L, om0, 1)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel <= 1e-4, rel
+    assert np.all(np.isfinite(tr))
+
+
+def test_fp8_benchmark_shape_sampled_columns(gpu_lib, dev):
+    """n=500, p=5000 block power-law workload (split-K trial tiles): one and two
+    fixed steps from the identity and from a sparse start, sampled columns."""
+    w = datagen.workload("ba5000")
+    x = w.X.astype(np.float64)
+    cols = np.array([0, 1, 499, 500, 2047, 2048, 3333, 4990, 4998, 4999])
+    rng = np.random.default_rng(5000)
+    sparse = np.eye(w.p) * rng.uniform(0.5, 1.5, size=w.p)
+    idx = rng.integers(0, w.p, size=(20 * w.p, 2))
+    sparse[idx[:, 0], idx[:, 1]] = rng.normal(0, 0.05, size=len(idx))
+    sparse[np.diag_indices(w.p)] = np.abs(np.diagonal(sparse)) + 0.5
+    for name, om0 in (("identity", np.eye(w.p)), ("sparse", sparse)):
+        for steps, bar in ((1, 1e-4), (2, 1e-3)):
+            got, ref, _, _ = _fixed_step_pair(gpu_lib, dev, w.X, w.lam, 0.04, om0, steps,
+                                              columns=cols)
+            rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            print(f"fp8 ba5000 {name} {steps} step(s): vs MX oracle {rel:.3e}", flush=True)
+            assert rel <= bar, rel
+
+
+def test_fp8_full_run_error_statement(gpu_lib, dev):
+    """The full 200-iteration fit of the n=100, p=200 workload in FP8 (backtracking),
+    against the unrounded FP64 iteration on the same steps, and against the MX
+    oracle on the same steps: the form's error, stated (bounded loosely)."""
+    import torch
+    w = datagen.workload("er200")
+    x = w.X.astype(np.float64)
+    L = oracle.lipschitz(x)
+    om, stats, tr = gpu_lib.accord_fit(_t(w.X, dev), w.lam, w.iters, lipschitz=L, trace=True,
+                                       precision="fp8")
+    torch.cuda.synchronize()
+    tr = tr.cpu().numpy()
+    taus = tr[1:, 3]
+    plain = oracle.fit_fbs(x, w.lam, w.iters, L=L, tau_replay=taus).omega
+    mxr = mx_oracle.fit_fbs_mx(x, w.lam, taus).omega
+    rel = np.linalg.norm(_col(om) - plain) / np.linalg.norm(plain)
+    rel_mx = np.linalg.norm(_col(om) - mxr) / np.linalg.norm(mxr)
+    print(f"fp8 er200 {w.iters} iterations: vs FP64 FBS {rel:.3e}, vs MX oracle {rel_mx:.3e}")
+    assert rel <= 0.1, rel
+    assert np.all(np.isfinite(tr))
+    assert np.allclose(tr[1:, 3], 0.5 ** (tr[1:, 4] - 1))
+
+
+def test_fp8_then_bf16x3_refinement_reaches_estimate(gpu_lib, dev):
+    """FP8 first, then BF16x3 from its result until the stop rule: relative error
+    <= 1e-3 against the converged FP64 estimate, identical support away from ties."""
+    import torch
+    w = datagen.small_random_problem(60, 90, seed=12)
+    x = w.X.astype(np.float64)
+    lam = 0.12
+    L = oracle.lipschitz(x)
+    X = _t(w.X, dev)
+    om1, s1, _ = gpu_lib.accord_fit(X, lam, 300, lipschitz=L, precision="fp8")
+    om2, s2, _ = gpu_lib.accord_fit(X, lam, 5000, lipschitz=L, precision="bf16x3", omega0=om1,
+                                    tol=1e-5, check_every=20)
+    torch.cuda.synchronize()
+    assert s2["converged"] == 1
+    ref = oracle.fit_fbs(x, lam, 50000, tol=1e-15).omega
+    got = _col(om2)
+    rel1 = np.linalg.norm(_col(om1) - ref) / np.linalg.norm(ref)
+    rel2 = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"fp8 phase rel={rel1:.3e} ({s1['iters']} it)  after bf16x3 refinement "
+          f"rel={rel2:.3e} ({s2['iters']} it)")
+    assert rel2 <= 1e-3
+    G = oracle.grad(x, ref)
+    off = ~np.eye(90, dtype=bool)
+    safe = off & ((np.abs(ref) > 1e-4) | (lam - np.abs(G) > 1e-4))
+    assert np.array_equal((got != 0)[safe], (ref != 0)[safe])
