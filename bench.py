@@ -10,6 +10,8 @@ n = 1000, p = 1e5 (200 blocks, lambda = 0.03, 300 iterations; --iters shortens i
 Forms (the contraction arithmetic; prox, test and sums are the same in all):
   bf16x3  bf16 MFMA on hi/lo splits, three passes (meets the FP32 error bar); headline
   fp32    FP32 MFMA (the plain FP32 solver it is compared with)
+  bf16x1  bf16 MFMA, one pass (about 3 digits; a first phase before refinement)
+  fp8     MX-E4M3 operands on the scaled FP8 MFMA (about 1-2 digits; first phase)
 The first form in --forms is the headline.
 
 Also reported per form:
@@ -35,8 +37,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "bf16x1": 2500.0}  # MI355X dense matrix peaks
-PASSES = {"fp32": 1, "bf16x3": 3, "bf16x1": 1}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "bf16x1": 2500.0,  # MI355X dense matrix peaks
+               "fp8": 5000.0}
+PASSES = {"fp32": 1, "bf16x3": 3, "bf16x1": 1, "fp8": 1}
 PEAK_HBM_GBS = 8000.0                                               # MI355X HBM3E
 METRIC = "prox-grad iters/sec + X^T(XΩ) MFMA TFLOP/s, mixed vs FP32 at matched error"
 
@@ -110,7 +113,8 @@ def kernel_report(stats, form, n, p, workload_ok_for_traffic):
     ms, cnt, avg = group("grad_gemm")
     if avg:
         a = flops / (avg * 1e-3) / 1e12
-        name = "k_gemm_f32<0>" if form == "fp32" else f"k_gemm_bf16w<{PASSES[form]}, 0>"
+        name = {"fp32": "k_gemm_f32<0>", "fp8": "k_gemm_fp8w<0>"}.get(
+            form, f"k_gemm_bf16w<{PASSES[form]}, 0>")
         out["grad_gemm"] = {"what": "G = X^T W / n", "kernels": [name], "launches": cnt,
                             "avg_ms": avg, "total_ms": ms, "bound": "mfma", "achieved": a,
                             "peak": peak, "unit": "TFLOP/s", "frac": a / peak,
@@ -124,7 +128,8 @@ def kernel_report(stats, form, n, p, workload_ok_for_traffic):
             d = {"what": "W+ = W + X Delta (+ norms)", "bound": "mfma", "achieved": a,
                  "peak": peak, "unit": "TFLOP/s", "frac": a / peak}
         else:
-            names = [f"k_trial_fused<{PASSES[form]}, 2>", "k_splitk_reduce_f"]
+            names = (["k_trial_fused8<2>", "k_splitk_reduce_f"] if form == "fp8" else
+                     [f"k_trial_fused<{PASSES[form]}, 2>", "k_splitk_reduce_f"])
             alg = 12.0 * p * p
             gbs = alg / (avg * 1e-3) / 1e9
             t_hbm = alg / (PEAK_HBM_GBS * 1e9)
@@ -203,7 +208,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="bf16x3,fp32",
+    ap.add_argument("--forms", default="bf16x3,fp32,bf16x1,fp8",
                     help="comma-separated precision forms; the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
