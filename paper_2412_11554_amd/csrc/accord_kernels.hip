@@ -861,7 +861,7 @@ __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
 // rarely taken branch.  The owner's sums are FP32 over each group of 4 consecutive
 // entries and FP64 beyond.  Padded rows hold zeros and contribute nothing; columns
 // past p are zeroed.  (A macro keeps every staging array in registers.)
-#define FUSED_PRODUCE(buf, step)                                                          \
+#define FUSED_PRODUCE(buf, step, vo, vg)                                                  \
     do {                                                                                  \
         const int64_t k0_ = (int64_t)(step) * BK;                                         \
         _Pragma("unroll") for (int q = 0; q < H * 2; ++q)                                 \
@@ -874,7 +874,7 @@ __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
                 const float t_ = fabsf(a_) - thr_f;                                       \
                 nw_[u] = t_ > 0.f ? copysignf(t_, a_) : 0.f;                              \
             }                                                                             \
-            const int64_t dpos_ = jcol[q] - (k0_ + br);                                   \
+            const int dpos_ = jcol[q] - (int)(k0_ + br);                                  \
             const bool has_diag_ = dpos_ >= 0 && dpos_ < 4;                               \
             float dval_ = 0.f;                                                            \
             if (has_diag_) {                                                              \
@@ -899,7 +899,7 @@ __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
                 *(uint2*)&sB[(buf)][H - 1][lo_] = make_uint2(                             \
                     l_[0] | ((uint32_t)l_[1] << 16), l_[2] | ((uint32_t)l_[3] << 16));    \
             if (owner && jvalid[q]) {                                                     \
-                *(f4*)(pn[q] + k0_) = nw_;                                                \
+                *(f4*)(b_on + (ob[q] + (uint32_t)k0_ * 4)) = nw_;                         \
                 float sd2_ = 0.f, sdg_ = 0.f, sl1_ = 0.f, sfr_ = 0.f;                     \
                 int nz_ = 0;                                                              \
                 _Pragma("unroll") for (int u = 0; u < 4; ++u) {                           \
@@ -963,33 +963,40 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // A loader: 256 rows x 64 bytes per half, 2 row passes of 128 rows
     const int arow = tid >> 2, acol = (tid & 3) * 8;
-    const uint16_t* pa[H * 2];
+    // Per-workgroup (scalar) base addresses plus 32-bit per-thread byte offsets: the
+    // loads use scalar-base addressing and the offsets take one VGPR each.  A tile
+    // spans at most 256 rows (or 128 columns) of a matrix whose leading dimension is
+    // below 2^20 + 64 elements, so every offset stays below 2^31.
+    const char* a_h = (const char*)(g.Ah + (int64_t)m0 * g.lda);
+    const char* a_l = H == 2 ? (const char*)(g.Al + (int64_t)m0 * g.lda) : a_h;
+    uint32_t oa[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         int ra = m0 + arow + 128 * i;
         ra = ra < g.M ? ra : g.M - 1;
-        pa[i] = g.Ah + (int64_t)ra * g.lda + acol;
-        if (H == 2) pa[2 + i] = g.Al + (int64_t)ra * g.lda + acol;
+        oa[i] = (uint32_t)(((int64_t)(ra - m0) * g.lda + acol) * 2);
     }
     // B producer: columns bc + 64 q (q = 0, 1), rows br .. br + 3 of the step
     const int bc = tid >> 3, br = (tid & 7) * 4;
-    int64_t jcol[2];
+    const char* b_om = (const char*)(px.om + (int64_t)n0 * px.ld);
+    const char* b_g = (const char*)(px.g + (int64_t)n0 * px.ld);
+    char* b_on = (char*)(px.om_new + (int64_t)n0 * px.ld);
+    int jcol[2];  // p < 2^20 + 64
     bool jvalid[2];
-    const float* po[2];
-    const float* pg[2];
-    float* pn[2];
+    uint32_t ob[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const int64_t j = (int64_t)n0 + bc + 64 * q;
+        const int j = n0 + bc + 64 * q;
         jvalid[q] = j < px.p;
         jcol[q] = j;
-        const int64_t jc = jvalid[q] ? j : px.p - 1;
-        po[q] = px.om + jc * px.ld + br;
-        pg[q] = px.g + jc * px.ld + br;
-        pn[q] = px.om_new + jc * px.ld + br;
+        const int jc = jvalid[q] ? j : (int)px.p - 1;
+        ob[q] = (uint32_t)(((int64_t)(jc - n0) * px.ld + br) * 4);
     }
+    // X rows are staged one step ahead; the Omega / G columns (the HBM stream) two
+    // steps ahead in two register sets, so each of their loads has a whole step
+    // (MFMAs + prox) to arrive
     u4 va[H * 2];
-    f4 vo[2], vg[2];
+    f4 vo0[2], vg0[2], vo1[2], vg1[2];
     f16v acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -1002,78 +1009,89 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
     const int r32 = lane & 31, k8 = (lane >> 5) * 8;
 
+#define FUSED_LOAD_A(step)                                                                \
+    do {                                                                                  \
+        const uint32_t ko_ = (uint32_t)(step) * (BK * 2);                                 \
+        _Pragma("unroll") for (int q = 0; q < H * 2; ++q)                                 \
+            va[q] = *(const u4*)(((q >> 1) ? a_l : a_h) + (oa[q & 1] + ko_));             \
+    } while (0)
+
+#define FUSED_LOAD_OG(VO, VG, step)                                                       \
+    do {                                                                                  \
+        const uint32_t ko_ = (uint32_t)(step) * (BK * 4);                                 \
+        _Pragma("unroll") for (int q = 0; q < 2; ++q) {                                   \
+            VO[q] = *(const f4*)(b_om + (ob[q] + ko_));                                   \
+            VG[q] = *(const f4*)(b_g + (ob[q] + ko_));                                    \
+        }                                                                                 \
+    } while (0)
+
+#define FUSED_MMA(buf)                                                                    \
+    do {                                                                                  \
+        _Pragma("unroll") for (int kk = 0; kk < BK; kk += 16) {                           \
+            bf8 ah[2], bh[2];                                                             \
+            _Pragma("unroll") for (int i = 0; i < 2; ++i)                                 \
+                ah[i] = *(const bf8*)&sA[(buf)][0][(wm + 32 * i + r32) * LDK + kk + k8];  \
+            _Pragma("unroll") for (int j = 0; j < 2; ++j)                                 \
+                bh[j] = *(const bf8*)&sB[(buf)][0][(wn + 32 * j + r32) * LDK + kk + k8];  \
+            _Pragma("unroll") for (int i = 0; i < 2; ++i)                                 \
+                _Pragma("unroll") for (int j = 0; j < 2; ++j)                             \
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j],     \
+                                                                        acc[i][j], 0, 0, 0); \
+            if (PASSES == 3) {                                                            \
+                bf8 al[2], bl[2];                                                         \
+                _Pragma("unroll") for (int j = 0; j < 2; ++j)                             \
+                    bl[j] = *(const bf8*)&sB[(buf)][H - 1][(wn + 32 * j + r32) * LDK + kk + k8]; \
+                _Pragma("unroll") for (int i = 0; i < 2; ++i)                             \
+                    al[i] = *(const bf8*)&sA[(buf)][H - 1][(wm + 32 * i + r32) * LDK + kk + k8]; \
+                /* one pass at a time: dependent MFMAs on an accumulator stay four  */    \
+                /* instructions apart                                                */    \
+                _Pragma("unroll") for (int i = 0; i < 2; ++i)                             \
+                    _Pragma("unroll") for (int j = 0; j < 2; ++j)                         \
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(              \
+                            ah[i], bl[j], acc[i][j], 0, 0, 0);                            \
+                _Pragma("unroll") for (int i = 0; i < 2; ++i)                             \
+                    _Pragma("unroll") for (int j = 0; j < 2; ++j)                         \
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(              \
+                            al[i], bh[j], acc[i][j], 0, 0, 0);                            \
+            }                                                                             \
+        }                                                                                 \
+    } while (0)
+
     if (s_begin < s_end) {
-        {
-            const int64_t ko = (int64_t)s_begin * BK;
-#pragma unroll
-            for (int q = 0; q < H * 2; ++q) va[q] = *(const u4*)(pa[q] + ko);
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                vo[q] = *(const f4*)(po[q] + ko);
-                vg[q] = *(const f4*)(pg[q] + ko);
-            }
-        }
-        FUSED_PRODUCE(0, s_begin);
+        const int last = s_end - 1;
+        // Loads past the range re-read the last step (unconditional prefetch, see
+        // k_gemm_bf16w); only steps inside the range are produced.
+        FUSED_LOAD_A(s_begin);
+        FUSED_LOAD_OG(vo0, vg0, s_begin);
+        FUSED_LOAD_OG(vo1, vg1, s_begin + 1 < last ? s_begin + 1 : last);
+        FUSED_PRODUCE(0, s_begin, vo0, vg0);
         __syncthreads();
         int cur = 0;
-        for (int s = s_begin; s < s_end; ++s) {
-            const bool more = s + 1 < s_end;
-            {   // unconditional prefetch (see k_gemm_bf16w)
-                const int64_t ko = (int64_t)(more ? s + 1 : s) * BK;
-#pragma unroll
-                for (int q = 0; q < H * 2; ++q) va[q] = *(const u4*)(pa[q] + ko);
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    vo[q] = *(const f4*)(po[q] + ko);
-                    vg[q] = *(const f4*)(pg[q] + ko);
-                }
-            }
+        for (int s = s_begin; s < s_end; s += 2) {
+            // step s is in LDS[cur]; set 1 holds step s + 1
+            FUSED_LOAD_A(s + 1 < last ? s + 1 : last);
+            FUSED_LOAD_OG(vo0, vg0, s + 2 < last ? s + 2 : last);
             __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 16) {
-                bf8 ah[2], bh[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-                    ah[i] = *(const bf8*)&sA[cur][0][(wm + 32 * i + r32) * LDK + kk + k8];
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    bh[j] = *(const bf8*)&sB[cur][0][(wn + 32 * j + r32) * LDK + kk + k8];
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j],
-                                                                            acc[i][j], 0, 0, 0);
-                if (PASSES == 3) {
-                    bf8 al[2], bl[2];
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        bl[j] = *(const bf8*)&sB[cur][H - 1][(wn + 32 * j + r32) * LDK + kk + k8];
-#pragma unroll
-                    for (int i = 0; i < 2; ++i)
-                        al[i] = *(const bf8*)&sA[cur][H - 1][(wm + 32 * i + r32) * LDK + kk + k8];
-                    // one pass at a time: dependent MFMAs on an accumulator stay four
-                    // instructions apart
-#pragma unroll
-                    for (int i = 0; i < 2; ++i)
-#pragma unroll
-                        for (int j = 0; j < 2; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                ah[i], bl[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-                    for (int i = 0; i < 2; ++i)
-#pragma unroll
-                        for (int j = 0; j < 2; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                al[i], bh[j], acc[i][j], 0, 0, 0);
-                }
-            }
+            FUSED_MMA(cur);
             __builtin_amdgcn_sched_barrier(0);
-            if (more) FUSED_PRODUCE(cur ^ 1, s + 1);
+            if (s + 1 < s_end) FUSED_PRODUCE(cur ^ 1, s + 1, vo1, vg1);
+            __syncthreads();
+            cur ^= 1;
+            if (s + 1 >= s_end) break;
+            // step s + 1 is in LDS[cur]; set 0 holds step s + 2
+            FUSED_LOAD_A(s + 2 < last ? s + 2 : last);
+            FUSED_LOAD_OG(vo1, vg1, s + 3 < last ? s + 3 : last);
+            __builtin_amdgcn_sched_barrier(0);
+            FUSED_MMA(cur);
+            __builtin_amdgcn_sched_barrier(0);
+            if (s + 2 < s_end) FUSED_PRODUCE(cur ^ 1, s + 2, vo0, vg0);
             __syncthreads();
             cur ^= 1;
         }
     }
+#undef FUSED_LOAD_A
+#undef FUSED_LOAD_OG
+#undef FUSED_MMA
     __syncthreads();
 
     const int tile = tile_m + tile_n * g.tilesM;
