@@ -20,8 +20,12 @@ Also reported per form:
                 run on) against the form's matrix peak, and executed MFMA flops;
                 the prox kernel's algorithmic bytes against HBM bandwidth
   error_vs_oracle  relative Frobenius error of sampled columns of the final iterate
-                against the FP64 oracle replaying the form's step sizes (untimed)
-and once: cpu_baseline, the FP64 oracle timed on this host on a bounded sample.
+                against the FP64 oracle replaying the form's step sizes (the MX-FP8
+                oracle for fp8) (untimed)
+  error_vs_estimate  the same columns against the oracle's estimate (the minimiser)
+and once: cpu_baseline, the FP64 oracle timed on this host on a bounded sample, and
+time_to_error: wall time of fp32, bf16x3 and two-phase (bf16x1 or fp8, then bf16x3)
+runs from the identity to the stop rule, with their error against the estimate.
 """
 from __future__ import annotations
 
@@ -190,17 +194,90 @@ def run_form(form, X, w, iters, ws, om, steps, warmup, check):
                                     w.p == 5000 and iters == w.iters)}
     if check:
         import oracle
-        p = w.p
-        cols = np.array([0, 1, 499, p // 2, p - 2, p - 1])
+        from oracle import mx_oracle
+        cols = sample_cols(w.p)
         taus = trace.cpu().numpy()[1:, 3]
-        ref = oracle.fit_fbs(w.X.astype(np.float64), w.lam, len(taus),
-                             L=stats[-1]["lipschitz"], tau_replay=taus, columns=cols)
+        x = w.X.astype(np.float64)
         got = om.cpu().numpy()[cols, :].astype(np.float64).T
+        if form == "fp8":
+            # the form's own arithmetic (MX-rounded operands); the unrounded iteration
+            # is not stable on the FP8 run's steps
+            ref = mx_oracle.fit_fbs_mx(x, w.lam, taus, columns=cols).omega
+            what = "MX-FP8 oracle replaying this form's step sizes"
+        else:
+            ref = oracle.fit_fbs(x, w.lam, len(taus), L=stats[-1]["lipschitz"],
+                                 tau_replay=taus, columns=cols).omega
+            what = "FP64 oracle replaying this form's step sizes"
         res["error_vs_oracle"] = {
-            "rel_fro_sampled_cols": float(np.linalg.norm(got - ref.omega) /
-                                          np.linalg.norm(ref.omega)),
-            "cols": cols.tolist(), "reference": "FP64 oracle replaying this form's step sizes"}
+            "rel_fro_sampled_cols": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "cols": cols.tolist(), "reference": what}
+        res["_sampled_cols"] = got
     return res
+
+
+def sample_cols(p):
+    return np.array([0, 1, 499, p // 2, p - 2, p - 1])
+
+
+ESTIMATE_ITERS = 6000
+
+
+def estimate_cols(w):
+    """The estimate (the minimiser of eq. 3.2) on sampled columns, by the FP64 oracle:
+    fixed steps 1/L on those columns only (the objective separates over columns);
+    6000 steps leave a relative distance of about 3e-7 on n=500, p=5000."""
+    import oracle
+    x = w.X.astype(np.float64)
+    L = oracle.lipschitz(x)
+    cols = sample_cols(w.p)
+    r = oracle.fit_fbs(x, w.lam, ESTIMATE_ITERS, tau_replay=[1.0 / L] * ESTIMATE_ITERS,
+                       columns=cols, L=L)
+    return cols, r.omega, L
+
+
+def time_to_error(X, w, ws, om, est, tol=1e-6, first_iters=150):
+    """Time to the estimate: plain runs from the identity until the stop rule
+    ||Delta||_F <= tol max(1, ||Omega||_F), and two-phase runs (a low-precision first
+    phase of `first_iters` iterations, then BF16x3 from its iterate until the same
+    stop rule).  Wall time on the device stream (warm run), iterations, and the
+    relative error of sampled columns against the oracle's estimate."""
+    import torch
+
+    from paper_2412_11554_amd import accord
+    cols, ref, L = est
+    need = max(accord.accord_workspace_bytes(w.n, w.p, accord.default_params(
+        max_iter=5000, precision=f)) for f in ("fp32", "bf16x3", "bf16x1", "fp8"))
+    if ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=X.device)
+    bufs = (om, torch.empty_like(om))
+    plans = {"fp32": [("fp32", 5000, tol)], "bf16x3": [("bf16x3", 5000, tol)],
+             "bf16x1>bf16x3": [("bf16x1", first_iters, 0.0), ("bf16x3", 5000, tol)],
+             "fp8>bf16x3": [("fp8", first_iters, 0.0), ("bf16x3", 5000, tol)]}
+    out = {}
+    for name, phases in plans.items():
+        for rep in range(2):  # the first run warms up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cur, iters = None, []
+            for k, (form, it, t) in enumerate(phases):
+                cur, st, _ = accord.accord_fit(X, w.lam, it, omega0=cur, tol=t, precision=form,
+                                               lipschitz=L, ws=ws, omega_out=bufs[k])
+                iters.append(st["iters"])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        got = cur.cpu().numpy()[cols, :].astype(np.float64).T
+        out[name] = {"seconds": dt, "iters": iters,
+                     "rel_err_vs_estimate": float(np.linalg.norm(got - ref) /
+                                                  np.linalg.norm(ref))}
+        log(f"[time-to-error] {name}: {dt * 1e3:.1f} ms, iters {iters}, "
+            f"err {out[name]['rel_err_vs_estimate']:.2e}")
+    base = out["fp32"]["seconds"]
+    for v in out.values():
+        v["speedup_vs_fp32"] = base / v["seconds"]
+    return {"tol": tol, "first_phase_iters": first_iters,
+            "estimate": f"FP64 oracle, fixed steps 1/L on the sampled columns, "
+                        f"{ESTIMATE_ITERS} iterations", "cols": cols.tolist(),
+            "pipelines": out}
 
 
 def main():
@@ -266,6 +343,15 @@ def main():
                     "frac": d["frac"], "traffic": d["traffic"]}
     # the oracle's full p x p FP64 iterate is 80 GB at p = 1e5: host baseline on ba5000 only
     cpu = None if (args.no_cpu_baseline or w.p > 5000) else cpu_baseline(w)
+    tte = None
+    if not args.no_check and w.p <= 5000:
+        est = estimate_cols(w)
+        for f, r in results.items():
+            got = r.pop("_sampled_cols")
+            r["error_vs_estimate"] = float(np.linalg.norm(got - est[1]) / np.linalg.norm(est[1]))
+        tte = time_to_error(X, w, ws, om, est)
+    for r in results.values():
+        r.pop("_sampled_cols", None)
     out = {
         "metric": METRIC,
         "value": head["iters_per_s"],
@@ -289,6 +375,7 @@ def main():
         "roofline": roofline,
         "forms": results,
         "cpu_baseline": cpu,
+        "time_to_error": tte,
     }
     if "fp32" in results and forms[0] != "fp32":
         out["speedup_vs_fp32"] = head["iters_per_s"] / results["fp32"]["iters_per_s"]
