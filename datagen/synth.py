@@ -189,6 +189,41 @@ def bootstrap_rows(n_base: int, count: int, lo: int, hi: int, rng: np.random.Gen
     return [rng.integers(0, n_base, size=int(s)) for s in sizes]
 
 
+@dataclass
+class BatchWorkload:
+    """Several data sets sharing p, and a lambda grid: problem k = b * len(lams) + l
+    fits data set b at lams[l]."""
+    name: str
+    p: int
+    xs: list            # float32 [n_b, p] per data set (centred, unit mean square)
+    lams: np.ndarray    # float64 [nlam]
+    iters: int
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self):
+        return [x.shape[0] for x in self.xs]
+
+    def stacked(self) -> np.ndarray:
+        return np.ascontiguousarray(np.concatenate(self.xs, axis=0), dtype=np.float32)
+
+
+def batch_workload(p: int = 2000, nsub: int = 16, nlam: int = 32, n_base: int = 400,
+                   lo: int = 100, hi: int = 400, prob: float = 0.005, lam_lo: float = 0.02,
+                   lam_hi: float = 0.5, iters: int = 300, key: int = 3) -> BatchWorkload:
+    """Bootstrap lambda-path workload: one Erdos-Renyi Theta (edge prob ``prob``,
+    weights +-U[0.2, 0.4], lambda_min = 0.1), one base sample of ``n_base`` rows,
+    ``nsub`` subsamples of U{lo..hi} rows drawn with replacement, each re-centred
+    and re-standardised, and ``nlam`` log-spaced penalties in [lam_lo, lam_hi]."""
+    r_theta, r_data, r_aux = rngs(key)
+    theta = er_precision(p, prob, 0.2, 0.4, 0.1, r_theta)
+    base = sample_gaussian(theta, n_base, r_data)
+    rows = bootstrap_rows(n_base, nsub, lo, hi, r_aux)
+    xs = [_f32(standardise(base[r])) for r in rows]
+    return BatchWorkload(f"batch_p{p}_{nsub}x{nlam}", p, xs, lambda_grid(lam_lo, lam_hi, nlam),
+                         iters, {"graph": "erdos-renyi", "edge_prob": prob, "n_base": n_base})
+
+
 # the named workloads (sizes as used by tests and the benchmark)
 def workload(name: str) -> Workload:
     if name == "er200":
@@ -197,4 +232,6 @@ def workload(name: str) -> Workload:
         return ba_block_workload(500, 10, 500, 0.05, 500, key=1)
     if name == "ba100k":
         return ba_block_workload(1000, 200, 500, 0.03, 300, key=2)
+    if name == "batch":
+        return batch_workload()
     raise KeyError(name)

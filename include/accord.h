@@ -182,6 +182,44 @@ int accord_objective(const float* X, int64_t n, int64_t p, const float* Omega, d
 int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_params* prm,
                accord_stats* stats, double* trace, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Batched form: many independent fits in one call (a lambda path over several
+ * data sets, e.g. bootstrap subsamples).  nsub data sets X_b (n[b] x p, row-major
+ * FP32, centred) are stacked row-wise in one device array: X_b starts at row
+ * n[0] + ... + n[b-1].  nlam penalties lambda[l] (host).  Problem k = b * nlam + l
+ * is the fit of (X_b, lambda[l]) by Alg. 1 with its own step, acceptance and stop;
+ * every problem advances one iteration per sweep, and the kernels of a sweep cover
+ * all problems at once (the gradients and trial products of one data set form a
+ * single wide product over its nlam problems).
+ *   Omega: device, nsub*nlam matrices of p x p (column form as in accord_fit),
+ *          problem k at offset k*p*p; in: starting points (diagonal > 0), out: the
+ *          last iterates.
+ *   prm: tau0, beta, tol, max_iter, power_iters as in accord_fit; prm->lambda is
+ *        not used; precision must be ACCORD_FP32 (else ACCORD_ERR_UNSUPPORTED).
+ *   lipschitz: host double[nsub] (L of each data set) or NULL (power iteration).
+ *   stats: host accord_batch_stats[nsub*nlam] or NULL.
+ *   trials: device int32[nsub*nlam*max_iter] or NULL: the trials each iteration
+ *           used (the accepted step of iteration t of problem k is
+ *           tau0 * beta^(trials[k*max_iter + t] - 1)); entries past a problem's
+ *           last iteration are left unspecified.
+ * ws: device, 256-byte aligned, at least accord_batch_workspace_bytes() bytes.
+ * Synchronous.  Errors as accord_fit; the first failing problem is named in
+ * accord_last_error(). */
+typedef struct {
+    int32_t iters, trials, floor_accepts, converged;
+    int64_t nnz_offdiag;
+    double f, g, h, tau_last, delta_fro, lipschitz;
+} accord_batch_stats;
+
+/* Workspace bytes of accord_fit_batch (0 for invalid sizes). */
+size_t accord_batch_workspace_bytes(const int64_t* n, int64_t nsub, int64_t p, int64_t nlam,
+                                    const accord_params* prm);
+
+int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
+                     const double* lambda, int64_t nlam, float* Omega,
+                     const accord_params* prm, const double* lipschitz,
+                     accord_batch_stats* stats, int32_t* trials, void* ws, size_t ws_bytes,
+                     void* stream);
+
 /* Static description of a status code. */
 const char* accord_status_str(int status);
 

@@ -55,6 +55,17 @@ class accord_stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class accord_batch_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("trials", ctypes.c_int32),
+                ("floor_accepts", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("nnz_offdiag", ctypes.c_int64), ("f", ctypes.c_double),
+                ("g", ctypes.c_double), ("h", ctypes.c_double), ("tau_last", ctypes.c_double),
+                ("delta_fro", ctypes.c_double), ("lipschitz", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class AccordError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
@@ -86,6 +97,15 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(accord_stats), _vp, _vp, _sz, _vp]
         for f in ("accord_grad", "accord_prox", "accord_objective", "accord_fit"):
             getattr(L, f).restype = ctypes.c_int
+        _pi64 = ctypes.POINTER(ctypes.c_int64)
+        _pd = ctypes.POINTER(ctypes.c_double)
+        L.accord_batch_workspace_bytes.argtypes = [_pi64, _i64, _i64, _i64,
+                                                   ctypes.POINTER(accord_params)]
+        L.accord_batch_workspace_bytes.restype = _sz
+        L.accord_fit_batch.argtypes = [_vp, _pi64, _i64, _i64, _pd, _i64, _vp,
+                                       ctypes.POINTER(accord_params), _pd,
+                                       ctypes.POINTER(accord_batch_stats), _vp, _vp, _sz, _vp]
+        L.accord_fit_batch.restype = ctypes.c_int
         L.accord_status_str.argtypes = [ctypes.c_int]
         L.accord_status_str.restype = ctypes.c_char_p
         L.accord_last_error.argtypes = []
@@ -219,3 +239,50 @@ def accord_fit(X: torch.Tensor, lam: float, max_iter: int, *, omega0: torch.Tens
     if tr is not None:
         tr = tr.view(max_iter + 1, TRACE_COLS)[: stats["iters"] + 1]
     return omega_out, stats, tr
+
+
+def accord_batch_workspace_bytes(n, p: int, nlam: int, params: accord_params | None = None) -> int:
+    na = (ctypes.c_int64 * len(n))(*[int(v) for v in n])
+    return int(lib().accord_batch_workspace_bytes(na, len(n), p, nlam,
+                                                  ctypes.byref(params) if params else None))
+
+
+def accord_fit_batch(X: torch.Tensor, n, lambdas, max_iter: int, *,
+                     omega0: torch.Tensor | None = None, tau0: float = 1.0, beta: float = 0.5,
+                     tol: float = 0.0, power_iters: int = 0, lipschitz=None, trials: bool = False,
+                     ws=None, omega_out=None):
+    """Batched ACCORD-FBS: X is the row-wise stack of the data sets (sum(n) x p),
+    n their row counts, lambdas the penalties.  Problem k = b * len(lambdas) + l.
+    Returns (Omega [nprob, p, p] paper form, list of stats dicts, trials
+    [nprob, max_iter] int32 device tensor or None).  omega0 defaults to identities."""
+    n = [int(v) for v in n]
+    nsub, p = len(n), X.shape[1]
+    if X.shape[0] != sum(n):
+        raise ValueError(f"X has {X.shape[0]} rows, n sums to {sum(n)}")
+    lam = [float(v) for v in lambdas]
+    nlam = len(lam)
+    nprob = nsub * nlam
+    dev = X.device
+    prm = default_params(max_iter=max_iter, tau0=tau0, beta=beta, tol=tol,
+                         power_iters=power_iters)
+    if omega_out is None:
+        omega_out = torch.empty((nprob, p, p), dtype=torch.float32, device=dev)
+    if omega0 is None:
+        omega_out.zero_()
+        omega_out.diagonal(dim1=1, dim2=2).fill_(1.0)
+    else:
+        omega_out.copy_(omega0)
+    need = accord_batch_workspace_bytes(n, p, nlam, prm)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    tr = (torch.zeros((nprob, max(max_iter, 1)), dtype=torch.int32, device=dev)
+          if trials else None)
+    na = (ctypes.c_int64 * nsub)(*n)
+    la = (ctypes.c_double * nlam)(*lam)
+    lp = (ctypes.c_double * nsub)(*[float(v) for v in lipschitz]) if lipschitz is not None else None
+    st = (accord_batch_stats * nprob)()
+    _check(lib().accord_fit_batch(_dev(X, "X"), na, nsub, p, la, nlam, _dev(omega_out, "Omega"),
+                                  ctypes.byref(prm), lp, st,
+                                  tr.data_ptr() if tr is not None else None,
+                                  ws.data_ptr(), ws.numel(), _stream(dev)))
+    return omega_out, [s.as_dict() for s in st], tr

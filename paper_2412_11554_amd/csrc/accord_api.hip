@@ -5,11 +5,12 @@
 // the kernels of accord_kernels.hip on the caller's stream.
 //
 // accord_fit runs Alg. 1 with the backtracking loop predicated on the device:
-// per iteration the host enqueues the gradient GEMM and then, for each step in
-// tau0, beta tau0, ... down to the first one at or below 1/L (the floor at which
-// Alg. 1 always accepts), a prox / trial-GEMM / acceptance triple.  Once a trial
-// is accepted, the remaining triples of that iteration return immediately, so
-// the host never waits for the device inside the loop.
+// per iteration the host enqueues the gradient GEMM and the trials of tau0,
+// beta tau0, ... (prox / trial product / acceptance) one trial ahead of the
+// device, reading each trial's outcome from a pinned host mailbox; every kernel
+// checks the device state first, so a trial enqueued after an acceptance does no
+// work.  accord_fit_batch advances many independent fits in lockstep with the
+// same kernels in batched form.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -746,6 +747,361 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
     if (host.bad & 2) return fail(ACCORD_ERR_NONFINITE, "non-finite value in an iterate");
     if (host.bad & 1) return fail(ACCORD_ERR_DOMAIN, "non-positive diagonal in an iterate");
     return ACCORD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched form
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchPlan {
+    int64_t p, p_pad, p_c, nsub, nlam, nprob;
+    int max_iter, tpp, nprox, max_tiles_trial, tiles_grad;
+    std::vector<int64_t> n, n_pad, row_off, norm_off;
+    std::vector<int> tilesM;
+    size_t off_ls, off_lam, off_inv_n, off_L, off_args_w0, off_args_grad, off_args_trial,
+        off_prox_init, off_prox_args, off_fin, off_prox_part, off_norm_part, off_trials,
+        off_pow_u, off_pow_w, off_pow_pu, off_pow_pw, off_om[2], off_g, off_d, end;
+    std::vector<size_t> off_xp, off_xt, off_wt[2];
+};
+
+constexpr int kBatchProxBlocks = 64;  // prox workgroups per problem
+
+int make_batch_plan(const int64_t* n, int64_t nsub, int64_t p, int64_t nlam, int max_iter,
+                    BatchPlan& B) {
+    B = BatchPlan{};
+    B.p = p;
+    B.p_pad = round_up(p, kPad);
+    B.p_c = round_up(p, kBN);  // columns per problem in the concatenated layout
+    B.nsub = nsub;
+    B.nlam = nlam;
+    B.nprob = nsub * nlam;
+    B.max_iter = max_iter;
+    B.tpp = (int)(B.p_c / kBN);
+    B.nprox = kBatchProxBlocks;
+    B.tiles_grad = (int)(cdiv(B.p_pad, kBM) * nlam * B.tpp);
+    B.max_tiles_trial = 0;
+    int64_t rows = 0, nmax = 0, norm_rows_total = 0;
+    for (int64_t b = 0; b < nsub; ++b) {
+        B.n.push_back(n[b]);
+        B.n_pad.push_back(round_up(n[b], kPad));
+        B.row_off.push_back(rows);
+        rows += n[b];
+        nmax = std::max(nmax, n[b]);
+        const int tm = (int)cdiv(B.n_pad[b], kBM);
+        B.tilesM.push_back(tm);
+        B.norm_off.push_back(norm_rows_total);
+        norm_rows_total += (int64_t)nlam * tm * B.tpp;
+        B.max_tiles_trial = std::max(B.max_tiles_trial, (int)(tm * nlam * B.tpp));
+    }
+    size_t cur = 0;
+    const int64_t np = B.nprob;
+    B.off_ls = bump(cur, (size_t)np * sizeof(LsState));
+    B.off_lam = bump(cur, (size_t)nlam * sizeof(double));
+    B.off_inv_n = bump(cur, (size_t)nsub * sizeof(double));
+    B.off_L = bump(cur, (size_t)nsub * sizeof(double));
+    B.off_args_w0 = bump(cur, (size_t)nsub * sizeof(GemmArgs));
+    B.off_args_grad = bump(cur, (size_t)2 * nsub * sizeof(GemmArgs));
+    B.off_args_trial = bump(cur, (size_t)2 * nsub * sizeof(GemmArgs));
+    B.off_prox_init = bump(cur, (size_t)np * sizeof(ProxArgs));
+    B.off_prox_args = bump(cur, (size_t)2 * np * sizeof(ProxArgs));
+    B.off_fin = bump(cur, (size_t)np * sizeof(FinArgs));
+    B.off_prox_part = bump(cur, (size_t)np * B.nprox * kPartCols * sizeof(double));
+    B.off_norm_part = bump(cur, (size_t)norm_rows_total * kNormCols * sizeof(double));
+    B.off_trials = bump(cur, (size_t)np * std::max(max_iter, 1) * sizeof(int32_t));
+    const int64_t nmax_pad = round_up(nmax, kPad);
+    B.off_pow_u = bump(cur, (size_t)nmax_pad * sizeof(double));
+    B.off_pow_w = bump(cur, (size_t)B.p_pad * sizeof(double));
+    B.off_pow_pu = bump(cur, (size_t)nmax * sizeof(double));
+    B.off_pow_pw = bump(cur, (size_t)cdiv(p, kThreads / 64) * sizeof(double));
+    for (int64_t b = 0; b < nsub; ++b) {
+        const size_t xn = (size_t)(B.n_pad[b] * B.p_pad);
+        B.off_xp.push_back(bump(cur, xn * sizeof(float)));
+        B.off_xt.push_back(bump(cur, xn * sizeof(float)));
+        for (int par = 0; par < 2; ++par)
+            B.off_wt[par].push_back(bump(cur, (size_t)(nlam * B.p_c * B.n_pad[b]) * sizeof(float)));
+    }
+    const size_t mat = (size_t)(np * B.p_c * B.p_pad) * sizeof(float);
+    B.off_om[0] = bump(cur, mat);
+    B.off_om[1] = bump(cur, mat);
+    B.off_g = bump(cur, mat);
+    B.off_d = bump(cur, mat);
+    B.end = cur;
+    return ACCORD_OK;
+}
+
+int check_batch_dims(const int64_t* n, int64_t nsub, int64_t p, int64_t nlam) {
+    if (!n) return fail(ACCORD_ERR_INVALID_ARG, "n is null");
+    if (nsub < 1 || nlam < 1 || nsub > 65535)
+        return fail(ACCORD_ERR_INVALID_ARG, "need 1 <= nsub <= 65535 and nlam >= 1 (nsub=%lld nlam=%lld)",
+                    (long long)nsub, (long long)nlam);
+    for (int64_t b = 0; b < nsub; ++b) TRY(check_dims(n[b], p));
+    // column and tile counts of one group (nlam problems of p_c columns) stay 32-bit
+    const double cols = (double)nlam * (double)round_up(p, kBN);
+    if (cols > 2147483647.0 ||
+        (double)cdiv(round_up(p, kPad), kBM) * nlam * cdiv(p, kBN) > 2147483647.0)
+        return fail(ACCORD_ERR_INVALID_ARG, "nlam * p too large for one batched launch");
+    return ACCORD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t accord_batch_workspace_bytes(const int64_t* n, int64_t nsub, int64_t p, int64_t nlam,
+                                    const accord_params* prm) {
+    if (check_batch_dims(n, nsub, p, nlam) != ACCORD_OK) return 0;
+    accord_params d;
+    if (!prm) {
+        accord_default_params(&d);
+        prm = &d;
+    }
+    BatchPlan B;
+    make_batch_plan(n, nsub, p, nlam, prm->max_iter, B);
+    return B.end;
+}
+
+int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
+                     const double* lambda, int64_t nlam, float* Omega, const accord_params* prm,
+                     const double* lipschitz, accord_batch_stats* stats, int32_t* trials,
+                     void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    TRY(check_batch_dims(n, nsub, p, nlam));
+    TRY(check_ptr(X, "X"));
+    TRY(check_ptr(Omega, "Omega"));
+    TRY(check_params(prm));
+    if (prm->precision != ACCORD_FP32)
+        return fail(ACCORD_ERR_UNSUPPORTED, "the batched form runs in FP32 only");
+    if (!lambda) return fail(ACCORD_ERR_INVALID_ARG, "lambda is null");
+    for (int64_t l = 0; l < nlam; ++l)
+        if (!(lambda[l] >= 0.0) || !isfinite(lambda[l]))
+            return fail(ACCORD_ERR_INVALID_ARG, "lambda[%lld] must be finite and >= 0", (long long)l);
+    if (lipschitz)
+        for (int64_t b = 0; b < nsub; ++b)
+            if (!(lipschitz[b] > 0.0) || !isfinite(lipschitz[b]))
+                return fail(ACCORD_ERR_INVALID_ARG, "lipschitz[%lld] must be finite and > 0",
+                            (long long)b);
+    if (trials && !aligned(trials, 4)) return fail(ACCORD_ERR_INVALID_ARG, "trials must be 4-byte aligned");
+    BatchPlan B;
+    TRY(make_batch_plan(n, nsub, p, nlam, prm->max_iter, B));
+    TRY(check_ws(ws, ws_bytes, B.end));
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t np = B.nprob, mat = B.p_c * B.p_pad;
+
+    LsState* ls = at<LsState>(ws, B.off_ls);
+    float* om[2] = {at<float>(ws, B.off_om[0]), at<float>(ws, B.off_om[1])};
+    float* G = at<float>(ws, B.off_g);
+    float* D = at<float>(ws, B.off_d);
+    double* prox_part = at<double>(ws, B.off_prox_part);
+    double* norm_part = at<double>(ws, B.off_norm_part);
+    int32_t* trials_log = at<int32_t>(ws, B.off_trials);
+
+    // ---- host-built argument blocks, copied once
+    std::vector<double> h_inv_n(nsub), h_L(nsub, 0.0);
+    for (int64_t b = 0; b < nsub; ++b) {
+        h_inv_n[b] = 1.0 / (double)B.n[b];
+        if (lipschitz) h_L[b] = lipschitz[b];
+    }
+    std::vector<GemmArgs> a_w0(nsub), a_grad(2 * nsub), a_trial(2 * nsub);
+    std::vector<ProxArgs> a_prox_init(np), a_prox(2 * np);
+    std::vector<FinArgs> a_fin(np);
+    const int64_t pstep = 4 * (int64_t)kThreads;
+    for (int64_t b = 0; b < nsub; ++b) {
+        const int64_t k0 = b * nlam;
+        const float* xp = at<float>(ws, B.off_xp[b]);
+        const float* xt = at<float>(ws, B.off_xt[b]);
+        for (int par = 0; par < 3; ++par) {
+            // par 0, 1: the trial of an iteration with the current buffers in `par`;
+            // par 2: the setup product W0 = X Omega0
+            GemmArgs t = {};
+            const int cur = par == 2 ? 0 : par, nxt = par == 2 ? 0 : par ^ 1;
+            t.A = xp;
+            t.lda = B.p_pad;
+            t.B = par == 2 ? om[0] + k0 * mat : D + k0 * mat;
+            t.ldb = B.p_pad;
+            t.M = (int)B.n_pad[b];
+            t.N = (int)(nlam * B.p_c);
+            t.K = (int)B.p_pad;
+            t.tilesM = B.tilesM[b];
+            t.tilesN = (int)(nlam * B.tpp);
+            t.splits = 1;
+            t.C = at<float>(ws, B.off_wt[nxt][b]);
+            t.ldc = B.n_pad[b];
+            t.vec_store = 1;
+            t.alpha = 1.f;
+            t.Wprev = par == 2 ? nullptr : at<float>(ws, B.off_wt[cur][b]);
+            t.norm_part = norm_part + B.norm_off[b] * kNormCols;
+            t.ls = ls + k0;
+            t.pred = par == 2 ? 0 : 2;
+            t.Mvalid = (int)B.n[b];
+            t.Nvalid = t.N;  // padding columns of Delta and Omega are zero
+            if (par == 2)
+                a_w0[b] = t;
+            else
+                a_trial[par * nsub + b] = t;
+        }
+        for (int par = 0; par < 2; ++par) {
+            GemmArgs g = {};
+            g.A = xt;
+            g.lda = B.n_pad[b];
+            g.B = at<float>(ws, B.off_wt[par][b]);
+            g.ldb = B.n_pad[b];
+            g.M = (int)B.p_pad;
+            g.N = (int)(nlam * B.p_c);
+            g.K = (int)B.n_pad[b];
+            g.tilesM = (int)cdiv(B.p_pad, kBM);
+            g.tilesN = (int)(nlam * B.tpp);
+            g.splits = 1;
+            g.C = G + k0 * mat;
+            g.ldc = B.p_pad;
+            g.vec_store = 1;
+            g.alpha = (float)(1.0 / (double)B.n[b]);
+            g.norm_part = norm_part + B.norm_off[b] * kNormCols;  // unused by the gradient
+            g.ls = ls + k0;
+            g.pred = 1;
+            g.begin_iter = 1;
+            a_grad[par * nsub + b] = g;
+        }
+        for (int64_t l = 0; l < nlam; ++l) {
+            const int64_t k = k0 + l;
+            ProxArgs a = {};
+            a.total = p * B.p_pad;
+            a.ld = B.p_pad;
+            a.p = p;
+            a.step_col = pstep / a.ld;
+            a.step_row = pstep - a.step_col * a.ld;
+            a.part = prox_part + k * B.nprox * kPartCols;
+            ProxArgs r = a;
+            r.om = om[0] + k * mat;
+            r.reduce_only = 1;
+            a_prox_init[k] = r;
+            for (int par = 0; par < 2; ++par) {
+                ProxArgs q = a;
+                q.om = om[par] + k * mat;
+                q.g = G + k * mat;
+                q.om_new = om[par ^ 1] + k * mat;
+                q.d = D + k * mat;
+                q.ls = ls + k;
+                a_prox[par * np + k] = q;
+            }
+            FinArgs f = {};
+            f.ls = ls + k;
+            f.prox_part = prox_part + k * B.nprox * kPartCols;
+            f.nprox = B.nprox;
+            f.ntiles = B.tilesM[b] * B.tpp;
+            f.norm_part = norm_part + (B.norm_off[b] + l * (int64_t)f.ntiles) * kNormCols;
+            f.trials_log = trials_log + k * std::max(B.max_iter, 1);
+            a_fin[k] = f;
+        }
+    }
+    GemmArgs* d_w0 = at<GemmArgs>(ws, B.off_args_w0);
+    GemmArgs* d_grad = at<GemmArgs>(ws, B.off_args_grad);
+    GemmArgs* d_trial = at<GemmArgs>(ws, B.off_args_trial);
+    ProxArgs* d_prox_init = at<ProxArgs>(ws, B.off_prox_init);
+    ProxArgs* d_prox = at<ProxArgs>(ws, B.off_prox_args);
+    FinArgs* d_fin = at<FinArgs>(ws, B.off_fin);
+    HIP_TRY(hipMemcpyAsync(d_w0, a_w0.data(), a_w0.size() * sizeof(GemmArgs), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_grad, a_grad.data(), a_grad.size() * sizeof(GemmArgs), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_trial, a_trial.data(), a_trial.size() * sizeof(GemmArgs), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_prox_init, a_prox_init.data(), a_prox_init.size() * sizeof(ProxArgs), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_prox, a_prox.data(), a_prox.size() * sizeof(ProxArgs), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_fin, a_fin.data(), a_fin.size() * sizeof(FinArgs), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(at<double>(ws, B.off_lam), lambda, nlam * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(at<double>(ws, B.off_inv_n), h_inv_n.data(), nsub * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(at<double>(ws, B.off_L), h_L.data(), nsub * sizeof(double), hipMemcpyHostToDevice, st));
+
+    // ---- setup: state, operands, L, W0 = X_b Omega0, f(Omega0)
+    launch_init_state_batch(ls, (int)np, (int)nlam, at<double>(ws, B.off_lam),
+                            at<double>(ws, B.off_inv_n), at<double>(ws, B.off_L), prm->tau0,
+                            prm->beta, prm->tol, prm->max_iter, st);
+    // padding columns of every problem's Omega and Delta must read as zero
+    HIP_TRY(hipMemsetAsync(om[0], 0, (size_t)(np * mat) * sizeof(float), st));
+    HIP_TRY(hipMemsetAsync(om[1], 0, (size_t)(np * mat) * sizeof(float), st));
+    HIP_TRY(hipMemsetAsync(D, 0, (size_t)(np * mat) * sizeof(float), st));
+    for (int64_t b = 0; b < nsub; ++b) {
+        const int64_t k0 = b * nlam;
+        launch_pad_x(X + B.row_off[b] * p, B.n[b], p, at<float>(ws, B.off_xp[b]), B.p_pad,
+                     at<float>(ws, B.off_xt[b]), B.n_pad[b], XSplit{}, ls + k0, st);
+        if (!lipschitz)
+            launch_power_iteration(at<float>(ws, B.off_xp[b]), B.p_pad, at<float>(ws, B.off_xt[b]),
+                                   B.n_pad[b], B.n[b], p, at<double>(ws, B.off_pow_w),
+                                   at<double>(ws, B.off_pow_u), at<double>(ws, B.off_pow_pu),
+                                   at<double>(ws, B.off_pow_pw),
+                                   prm->power_iters > 0 ? prm->power_iters : 400, ls + k0, st);
+    }
+    if (!lipschitz) launch_share_L_batch(ls, (int)np, (int)nlam, st);
+    for (int64_t k = 0; k < np; ++k)
+        launch_copy_cols(Omega + k * p * p, p, om[0] + k * mat, B.p_pad, p, B.p_pad, ls + k, st);
+    launch_gemm_f32_batch(d_w0, (int)nsub, B.max_tiles_trial, B.tpp, EPI_TRIAL, st);
+    launch_prox_batch(d_prox_init, (int)np, B.nprox, st);
+    launch_fit_init_batch(d_fin, (int)np, st);
+    HIP_TRY(hipGetLastError());
+    std::vector<LsState> host((size_t)np);
+    HIP_TRY(hipMemcpyAsync(host.data(), ls, np * sizeof(LsState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int ntr = 1;
+    for (int64_t k = 0; k < np; ++k) {
+        const int b = (int)(k / nlam);
+        if (host[k].bad & 2)
+            return fail(ACCORD_ERR_NONFINITE, "non-finite value in X (subsample %d) or Omega0 (problem %lld)",
+                        b, (long long)k);
+        if (host[k].bad & 1)
+            return fail(ACCORD_ERR_DOMAIN, "Omega0 of problem %lld has a non-positive diagonal entry",
+                        (long long)k);
+        if (!(host[k].L > 0.0) || !isfinite(host[k].L))
+            return fail(ACCORD_ERR_NONFINITE, "Lipschitz estimate of subsample %d is not positive", b);
+        ntr = std::max(ntr, max_trials(prm->tau0, prm->beta, host[k].inv_L));
+    }
+
+    // ---- Alg. 1 for every problem, one iteration per sweep.  Each sweep enqueues the
+    // gradient and ntr trials (enough for the problem whose floor is lowest); a
+    // problem that accepted, or stopped, skips the rest of the sweep.
+    for (int t = 0; t < prm->max_iter; ++t) {
+        const int par = t & 1;
+        launch_gemm_f32_batch(d_grad + par * nsub, (int)nsub, B.tiles_grad, B.tpp, EPI_GRAD, st);
+        for (int k = 0; k < ntr; ++k) {
+            launch_prox_batch(d_prox + par * np, (int)np, B.nprox, st);
+            launch_gemm_f32_batch(d_trial + par * nsub, (int)nsub, B.max_tiles_trial, B.tpp,
+                                  EPI_TRIAL, st);
+            launch_finalize_batch(d_fin, (int)np, st);
+        }
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipMemcpyAsync(host.data(), ls, np * sizeof(LsState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t k = 0; k < np; ++k)
+        launch_copy_cols(om[host[k].iter & 1] + k * mat, B.p_pad, Omega + k * p * p, p, p, p,
+                         nullptr, st);
+    if (trials && prm->max_iter > 0)
+        HIP_TRY(hipMemcpyAsync(trials, trials_log, (size_t)np * prm->max_iter * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    int status = ACCORD_OK;
+    for (int64_t k = 0; k < np; ++k) {
+        const LsState& h = host[k];
+        if (stats) {
+            accord_batch_stats& s = stats[k];
+            s.iters = h.iter;
+            s.trials = h.total_trials;
+            s.floor_accepts = h.floor_accepts;
+            s.converged = (prm->tol > 0.0 && h.iter < prm->max_iter && h.converged && !h.bad) ? 1 : 0;
+            s.nnz_offdiag = h.nnz_off;
+            s.f = h.f_cur;
+            s.g = h.g_cur;
+            s.h = h.h_cur;
+            s.tau_last = h.tau_acc;
+            s.delta_fro = h.delta_fro;
+            s.lipschitz = h.L;
+        }
+        if (status == ACCORD_OK && (h.bad & 2))
+            status = fail(ACCORD_ERR_NONFINITE, "non-finite value in an iterate of problem %lld", (long long)k);
+        if (status == ACCORD_OK && (h.bad & 1))
+            status = fail(ACCORD_ERR_DOMAIN, "non-positive diagonal in an iterate of problem %lld", (long long)k);
+    }
+    return status;
 }
 
 }  // extern "C"

@@ -136,6 +136,16 @@ struct ProxArgs {
     int reduce_only;    // 1: no writes, statistics of om itself
 };
 
+// acceptance-test arguments of one problem of the batched form
+struct FinArgs {
+    LsState* ls;
+    const double* prox_part;
+    int nprox;
+    const double* norm_part;
+    int ntiles;
+    int32_t* trials_log;
+};
+
 // ---------------------------------------------------------------------------
 // launchers (accord_kernels.hip)
 // ---------------------------------------------------------------------------
@@ -167,5 +177,16 @@ void launch_transpose_w(const float* Wt, int64_t ldt, int64_t n, int64_t p, floa
 void launch_power_iteration(const float* Xp, int64_t p_pad, const float* Xt, int64_t n_pad,
                             int64_t n, int64_t p, double* w, double* u, double* part_u,
                             double* part_w, int steps, LsState* ls, hipStream_t st);
+
+// batched form (argument blocks in device memory)
+void launch_gemm_f32_batch(const GemmArgs* batch, int ngroups, int max_tiles, int tpp, int epi,
+                           hipStream_t st);
+void launch_prox_batch(const ProxArgs* batch, int nprob, int nblocks, hipStream_t st);
+void launch_finalize_batch(const FinArgs* batch, int nprob, hipStream_t st);
+void launch_fit_init_batch(const FinArgs* batch, int nprob, hipStream_t st);
+void launch_init_state_batch(LsState* ls, int nprob, int nlam, const double* lam,
+                             const double* inv_n, const double* L, double tau0, double beta,
+                             double tol, int max_iter, hipStream_t st);
+void launch_share_L_batch(LsState* ls, int nprob, int nlam, hipStream_t st);
 
 }  // namespace accord

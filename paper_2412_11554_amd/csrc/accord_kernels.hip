@@ -343,7 +343,7 @@ __device__ inline void store_frag(const GemmArgs& g, f4 v, int m, int n, double 
 // Epilogue shared by all GEMM kernels (thread t owns fragments (i, j) of its wave).
 template <int EPI>
 __device__ inline void gemm_epilogue(const GemmArgs& g, f4 (&acc)[4][4], int tile_m, int tile_n,
-                                     int split, double* red_lds) {
+                                     int split, double* red_lds, double* nrm) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tile = tile_m + tile_n * g.tilesM;
     if (EPI == EPI_PARTIAL) {
@@ -364,22 +364,21 @@ __device__ inline void gemm_epilogue(const GemmArgs& g, f4 (&acc)[4][4], int til
     if (EPI == EPI_TRIAL) {
         block_sum_in<2>(nv, red_lds);  // the tile LDS is free after the K loop
         if (tid == 0) {
-            g.norm_part[(int64_t)tile * kNormCols + 0] = nv[0];
-            g.norm_part[(int64_t)tile * kNormCols + 1] = nv[1];
+            nrm[0] = nv[0];
+            nrm[1] = nv[1];
         }
     }
 }
 
 constexpr int kLDK32 = kBK32 + 4;  // FP32 LDS row stride (floats)
 
+// One 128 x 128 tile of the FP32 GEMM (tile_m, tile_n, split); nrm receives the
+// tile's FP64 norm sums (EPI_TRIAL).
 template <int EPI>
-__global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
-    if (gemm_skip(g)) return;
+__device__ __forceinline__ void gemm_f32_tile(const GemmArgs& g, int tile_m, int tile_n,
+                                              int split, double* nrm) {
     __shared__ __attribute__((aligned(16))) float sA[2][kBM * kLDK32];
     __shared__ __attribute__((aligned(16))) float sB[2][kBN * kLDK32];
-
-    int tile_m, tile_n, split;
-    decode_tile(g, tile_m, tile_n, split);
     const int m0 = tile_m * kBM, n0 = tile_n * kBN;
     const int ksteps = g.K / kBK32;
     const int s_begin = (int)((int64_t)ksteps * split / g.splits);
@@ -463,7 +462,16 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
         }
     }
     __syncthreads();
-    gemm_epilogue<EPI>(g, acc, tile_m, tile_n, split, (double*)&sA[0][0]);
+    gemm_epilogue<EPI>(g, acc, tile_m, tile_n, split, (double*)&sA[0][0], nrm);
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
+    if (gemm_skip(g)) return;
+    int tile_m, tile_n, split;
+    decode_tile(g, tile_m, tile_n, split);
+    gemm_f32_tile<EPI>(g, tile_m, tile_n, split,
+                       g.norm_part + (int64_t)(tile_m + tile_n * g.tilesM) * kNormCols);
 }
 
 // ---------------------------------------------------------------------------
@@ -764,7 +772,7 @@ __device__ inline float delta_repr(float dl, uint16_t& h, uint16_t& l) {
 }
 
 template <int DOUT>
-__global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
+__device__ __forceinline__ void prox_run(const ProxArgs& a) {
     double tau = a.tau, lam = a.lambda;
     if (a.ls) {
         if (a.ls->done || a.ls->converged) return;
@@ -851,6 +859,11 @@ __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
         out[6] = 0.0;
         out[7] = 0.0;
     }
+}
+
+template <int DOUT>
+__global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
+    prox_run<DOUT>(a);
 }
 
 // B-operand producer of k_trial_fused for stage `buf` holding K step `step`:
@@ -1758,10 +1771,9 @@ __device__ inline void post_mailbox(Mailbox* mb, const LsState* ls) {
                        __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-__global__ void __launch_bounds__(kThreads) k_finalize(LsState* ls, const double* prox_part,
-                                                       int nprox, const double* norm_part,
-                                                       int ntiles, double* trace,
-                                                       int32_t* trials_log, Mailbox* mbox) {
+__device__ __forceinline__ void finalize_run(LsState* ls, const double* prox_part, int nprox,
+                                             const double* norm_part, int ntiles, double* trace,
+                                             int32_t* trials_log, Mailbox* mbox) {
     if (ls->done || ls->converged) return;
     double pv[6];
     sum_partials<6>(prox_part, nprox, kPartCols, pv);
@@ -1817,6 +1829,13 @@ __global__ void __launch_bounds__(kThreads) k_finalize(LsState* ls, const double
     post_mailbox(mbox, ls);
 }
 
+__global__ void __launch_bounds__(kThreads) k_finalize(LsState* ls, const double* prox_part,
+                                                       int nprox, const double* norm_part,
+                                                       int ntiles, double* trace,
+                                                       int32_t* trials_log, Mailbox* mbox) {
+    finalize_run(ls, prox_part, nprox, norm_part, ntiles, trace, trials_log, mbox);
+}
+
 void launch_finalize(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
                      int ntiles, double* trace, int32_t* trials_log, Mailbox* mbox,
                      hipStream_t st) {
@@ -1826,9 +1845,9 @@ void launch_finalize(LsState* ls, const double* prox_part, int nprox, const doub
 
 // Starting point: objective pieces of Omega^(0) (reduce-only prox sums of Omega^(0)
 // and the norm sums of W0 = X Omega^(0)).
-__global__ void __launch_bounds__(kThreads) k_fit_init(LsState* ls, const double* prox_part,
-                                                       int nprox, const double* norm_part,
-                                                       int ntiles, double* trace) {
+__device__ __forceinline__ void fit_init_run(LsState* ls, const double* prox_part, int nprox,
+                                             const double* norm_part, int ntiles,
+                                             double* trace) {
     double pv[6];
     sum_partials<6>(prox_part, nprox, kPartCols, pv);
     double nv[2];
@@ -1851,6 +1870,12 @@ __global__ void __launch_bounds__(kThreads) k_fit_init(LsState* ls, const double
         trace[6] = 0.0;
         trace[7] = pv[P_NNZ];
     }
+}
+
+__global__ void __launch_bounds__(kThreads) k_fit_init(LsState* ls, const double* prox_part,
+                                                       int nprox, const double* norm_part,
+                                                       int ntiles, double* trace) {
+    fit_init_run(ls, prox_part, nprox, norm_part, ntiles, trace);
 }
 
 void launch_fit_init(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
@@ -1988,6 +2013,135 @@ void launch_power_iteration(const float* Xp, int64_t p_pad, const float* Xt, int
         if (s + 1 < steps) k_pow_xtu<<<nbw, kThreads, 0, st>>>(Xt, n_pad, p, n, u, w, part_w);
     }
     k_pow_finish<<<1, kThreads, 0, st>>>(part_u, nbu, ls);
+}
+
+}  // namespace accord
+
+// ---------------------------------------------------------------------------
+// Batched form: many independent fits advanced in lockstep, one iteration per
+// sweep.  A group (one data set X_b) holds nlam problems whose column blocks are
+// concatenated along N, each padded to a whole number of 128-column tiles, so a
+// tile belongs to exactly one problem: problem = tile_n / tpp.  Every problem
+// keeps its own line-search state; a tile, prox block or acceptance workgroup of a
+// problem that has accepted (or stopped) returns at once.  Argument blocks live in
+// device memory, one per group (GEMM) or per problem (prox, acceptance).
+// ---------------------------------------------------------------------------
+namespace accord {
+
+template <int EPI>
+__global__ void __launch_bounds__(kThreads, 2) k_gemm_f32_batch(const GemmArgs* __restrict__ batch,
+                                                               int tpp) {
+    const GemmArgs g = batch[blockIdx.y];
+    const int tiles = g.tilesM * g.tilesN;
+    // XCD-contiguous logical order (see decode_tile), grouped 8 tiles along M
+    const int nblk = gridDim.x, bid = blockIdx.x;
+    const int xcd = bid & 7, local = bid >> 3, q8 = nblk >> 3, r8 = nblk & 7;
+    const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + local;
+    if (logical >= tiles) return;
+    constexpr int GM = 8;
+    const int per_group = GM * g.tilesN;
+    const int group = logical / per_group;
+    const int first_m = group * GM;
+    const int gsize = (g.tilesM - first_m) < GM ? (g.tilesM - first_m) : GM;
+    const int in_group = logical - group * per_group;
+    const int tile_m = first_m + in_group % gsize;
+    const int tile_n = in_group / gsize;
+    const int prob = tile_n / tpp;
+    LsState* ls = g.ls + prob;
+    if (g.pred >= 1 && ls->converged) return;
+    if (g.pred >= 2 && ls->done) return;
+    if (g.begin_iter && tile_m == 0 && tile_n == prob * tpp && threadIdx.x == 0) {
+        // a new iteration of this problem starts from tau0 (Alg. 1)
+        ls->done = 0;
+        ls->trials = 0;
+        ls->tau = ls->tau0;
+    }
+    double* nrm = g.norm_part +
+                  ((int64_t)prob * g.tilesM * tpp + tile_m + (int64_t)(tile_n - prob * tpp) * g.tilesM) *
+                      kNormCols;
+    gemm_f32_tile<EPI>(g, tile_m, tile_n, 0, nrm);
+}
+
+template <int DOUT>
+__global__ void __launch_bounds__(kThreads) k_prox_batch(const ProxArgs* __restrict__ batch) {
+    const ProxArgs a = batch[blockIdx.y];
+    prox_run<DOUT>(a);
+}
+
+__global__ void __launch_bounds__(kThreads) k_finalize_batch(const FinArgs* __restrict__ batch) {
+    const FinArgs f = batch[blockIdx.x];
+    finalize_run(f.ls, f.prox_part, f.nprox, f.norm_part, f.ntiles, nullptr, f.trials_log,
+                 nullptr);
+}
+
+__global__ void __launch_bounds__(kThreads) k_fit_init_batch(const FinArgs* __restrict__ batch) {
+    const FinArgs f = batch[blockIdx.x];
+    fit_init_run(f.ls, f.prox_part, f.nprox, f.norm_part, f.ntiles, nullptr);
+}
+
+// Line-search state of every problem k = b * nlam + l: lambda[l], 1/n_b, and L_b
+// (0 = taken later from the power iteration of group b).
+__global__ void k_init_state_batch(LsState* ls, int nprob, int nlam, const double* lam,
+                                   const double* inv_n, const double* L, double tau0,
+                                   double beta, double tol, int max_iter) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nprob) return;
+    const int b = k / nlam;
+    LsState s = {};
+    s.tau = tau0;
+    s.tau0 = tau0;
+    s.beta = beta;
+    s.lambda = lam[k - b * nlam];
+    s.tol = tol;
+    s.inv_n = inv_n[b];
+    s.L = L[b];
+    s.inv_L = L[b] > 0 ? 1.0 / L[b] : 0.0;
+    s.max_iter = max_iter;
+    s.fixed_step = beta >= 1.0;
+    ls[k] = s;
+}
+
+// L of group b (estimated into its first problem's state) -> every problem of b
+__global__ void k_share_L_batch(LsState* ls, int nprob, int nlam) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nprob) return;
+    const int first = (k / nlam) * nlam;
+    if (k == first) return;
+    ls[k].L = ls[first].L;
+    ls[k].inv_L = ls[first].inv_L;
+}
+
+void launch_gemm_f32_batch(const GemmArgs* batch, int ngroups, int max_tiles, int tpp, int epi,
+                           hipStream_t st) {
+    dim3 grid((unsigned)max_tiles, (unsigned)ngroups);
+    if (epi == EPI_GRAD)
+        k_gemm_f32_batch<EPI_GRAD><<<grid, kThreads, 0, st>>>(batch, tpp);
+    else
+        k_gemm_f32_batch<EPI_TRIAL><<<grid, kThreads, 0, st>>>(batch, tpp);
+}
+
+void launch_prox_batch(const ProxArgs* batch, int nprob, int nblocks, hipStream_t st) {
+    dim3 grid((unsigned)nblocks, (unsigned)nprob);
+    k_prox_batch<0><<<grid, kThreads, 0, st>>>(batch);
+}
+
+void launch_finalize_batch(const FinArgs* batch, int nprob, hipStream_t st) {
+    k_finalize_batch<<<(unsigned)nprob, kThreads, 0, st>>>(batch);
+}
+
+void launch_fit_init_batch(const FinArgs* batch, int nprob, hipStream_t st) {
+    k_fit_init_batch<<<(unsigned)nprob, kThreads, 0, st>>>(batch);
+}
+
+void launch_init_state_batch(LsState* ls, int nprob, int nlam, const double* lam,
+                             const double* inv_n, const double* L, double tau0, double beta,
+                             double tol, int max_iter, hipStream_t st) {
+    k_init_state_batch<<<(unsigned)cdiv(nprob, 256), 256, 0, st>>>(ls, nprob, nlam, lam, inv_n, L,
+                                                                   tau0, beta, tol, max_iter);
+}
+
+void launch_share_L_batch(LsState* ls, int nprob, int nlam, hipStream_t st) {
+    k_share_L_batch<<<(unsigned)cdiv(nprob, 256), 256, 0, st>>>(ls, nprob, nlam);
 }
 
 }  // namespace accord

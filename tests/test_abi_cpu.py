@@ -37,7 +37,8 @@ def test_struct_layout_matches_header(tmp_path):
         '#include <stdio.h>\n#include <stddef.h>\n#include "accord.h"\n'
         "int main(void){printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(accord_params), sizeof(accord_stats),"
         " offsetof(accord_stats, grad_gemm_ms), offsetof(accord_stats, total_ms),"
-        " offsetof(accord_params, timing)); return 0;}\n")
+        " offsetof(accord_params, timing)); printf(\"%zu %zu\\n\", sizeof(accord_batch_stats),"
+        " offsetof(accord_batch_stats, lipschitz)); return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
@@ -47,6 +48,8 @@ def test_struct_layout_matches_header(tmp_path):
     assert vals[2] == accord.accord_stats.grad_gemm_ms.offset
     assert vals[3] == accord.accord_stats.total_ms.offset
     assert vals[4] == accord.accord_params.timing.offset
+    assert vals[5] == ctypes.sizeof(accord.accord_batch_stats)
+    assert vals[6] == accord.accord_batch_stats.lipschitz.offset
 
 
 def test_default_params(L):
@@ -121,3 +124,39 @@ def test_binding_rejects_host_tensors(L):
     import torch
     with pytest.raises(TypeError):
         accord.accord_fit(torch.zeros(4, 5), 0.1, 2)
+
+
+def test_batch_workspace_bytes(L):
+    assert accord.accord_batch_workspace_bytes([100, 200], 0, 4) == 0
+    assert accord.accord_batch_workspace_bytes([0, 200], 50, 4) == 0
+    small = accord.accord_batch_workspace_bytes([60, 90], 100, 3)
+    assert small > 0
+    # at least the four per-problem matrices (Omega x2, G, Delta) of every problem
+    assert small >= 4 * 6 * 128 * 128 * 4
+    # 16 data sets x 32 penalties at p = 2000 fit one device
+    assert accord.accord_batch_workspace_bytes([400] * 16, 2000, 32) < 60e9
+
+
+def test_fit_batch_validation(L):
+    prm = accord.default_params(max_iter=3)
+    n = (ctypes.c_int64 * 2)(10, 12)
+    lam = (ctypes.c_double * 2)(0.1, 0.2)
+    st = (accord.accord_batch_stats * 4)()
+
+    def call(X=FAKE, nn=n, nsub=2, p=7, la=lam, nlam=2, Om=FAKE, pr=prm, lip=None, ws=FAKE,
+             ws_bytes=1 << 40):
+        return L.accord_fit_batch(X, nn, nsub, p, la, nlam, Om, ctypes.byref(pr), lip, st, None,
+                                  ws, ws_bytes, None)
+    assert call(X=None) == 1
+    assert call(nn=None) == 1
+    assert call(nsub=0) == 1
+    assert call(nlam=0) == 1
+    assert call(la=None) == 1
+    assert call(la=(ctypes.c_double * 2)(0.1, -1.0)) == 1
+    assert call(lip=(ctypes.c_double * 2)(1.0, 0.0)) == 1
+    assert call(nn=(ctypes.c_int64 * 2)(10, 0)) == 1
+    assert call(ws=None) == 4
+    assert call(ws_bytes=16) == 4
+    assert call(pr=accord.default_params(max_iter=3, precision=2)) == 5
+    assert call(pr=accord.default_params(beta=0.0)) == 1
+    assert L.accord_last_error()
