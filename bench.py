@@ -280,21 +280,111 @@ def time_to_error(X, w, ws, om, est, tol=1e-6, first_iters=150):
             "pipelines": out}
 
 
+def run_batch(args):
+    """The batched form: one step = one accord_fit_batch over every (subsample,
+    penalty) problem.  value = problem-iterations per second; the FLOP rate counts
+    the useful 2 n_b p^2 of every gradient and every executed trial product."""
+    import torch
+
+    import datagen
+    from paper_2412_11554_amd import accord
+
+    w = datagen.workload("batch")
+    iters = args.iters or w.iters
+    nsub, nlam, p = len(w.xs), len(w.lams), w.p
+    nprob = nsub * nlam
+    X = torch.from_numpy(w.stacked()).to("cuda:0")
+    prm = accord.default_params(max_iter=iters)
+    ws = torch.empty(accord.accord_batch_workspace_bytes(w.n, p, nlam, prm), dtype=torch.uint8,
+                     device="cuda:0")
+    om = torch.empty((nprob, p, p), dtype=torch.float32, device="cuda:0")
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        accord.accord_fit_batch(X, w.n, w.lams, iters, ws=ws, omega_out=om)
+    torch.cuda.synchronize()
+    log("[batch] warmup done")
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, stats, tr = accord.accord_fit_batch(X, w.n, w.lams, iters, ws=ws, omega_out=om,
+                                               trials=True)
+        log(f"[batch] step {i + 1}/{args.steps}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    trials = tr.cpu().numpy()
+    ns = np.repeat(np.array(w.n, dtype=np.float64), nlam)
+    products = iters + trials[:, :iters].sum(axis=1)     # gradients + executed trials
+    flops = float(np.sum(2.0 * ns * p * p * products))
+    tflops = flops * args.steps / elapsed / 1e12
+    res = {
+        "metric": "batched prox-grad problem-iterations/sec (FP32)",
+        "value": nprob * iters * args.steps / elapsed,
+        "unit": "problem-iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"{nsub} bootstrap subsamples (n {min(w.n)}..{max(w.n)}) x "
+                               f"{nlam} penalties in [0.02, 0.5], p={p}, {iters} iterations",
+                   "p": p, "nsub": nsub, "nlam": nlam, "iters": iters},
+        "trials_per_iter": float(trials[:, :iters].mean()),
+        "roofline": {"bound": "mfma", "kernel": "whole fit (batched FP32 GEMMs, prox, tests)",
+                     "achieved": tflops, "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                     "frac": tflops / PEAK_TFLOPS["fp32"], "traffic": None},
+    }
+    if not args.no_check:
+        import oracle
+        cols = np.array([0, 1, p // 2, p - 2, p - 1])
+        errs = []
+        out = om.cpu().numpy()
+        for k in (0, nlam - 1, 5 * nlam + 13, nprob - 1):
+            b, l = divmod(k, nlam)
+            taus = 0.5 ** (trials[k, :stats[k]["iters"]].astype(np.float64) - 1)
+            ref = oracle.fit_fbs(w.xs[b].astype(np.float64), w.lams[l], len(taus),
+                                 L=stats[k]["lipschitz"], tau_replay=taus, columns=cols).omega
+            got = out[k][cols, :].astype(np.float64).T
+            errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+        res["error_vs_oracle"] = {"max_rel_fro_sampled": max(errs),
+                                  "problems": [0, nlam - 1, 5 * nlam + 13, nprob - 1],
+                                  "reference": "FP64 oracle replaying each problem's steps"}
+    if not args.no_cpu_baseline:
+        import oracle
+        x = w.xs[0].astype(np.float64)
+        L = oracle.lipschitz(x)
+        t1 = time.perf_counter()
+        r = oracle.fit_fbs(x, w.lams[0], 10, L=L)
+        dt = time.perf_counter() - t1
+        threads = os.cpu_count()
+        try:
+            import threadpoolctl
+            info = threadpoolctl.threadpool_info()
+            if info:
+                threads = max(i.get("num_threads", 0) for i in info) or threads
+        except Exception:
+            pass
+        res["cpu_baseline"] = {"value": 10 / dt, "unit": "problem-iters/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"first 10 iterations of problem 0 (n={w.n[0]}, "
+                                         f"p={p}, {sum(r.trials)} trials, {dt:.1f} s)"}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 5; batch 1)")
+    ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (default 2; batch 1)")
     ap.add_argument("--forms", default="bf16x3,fp32,bf16x1,fp8",
                     help="comma-separated precision forms; the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--iters", type=int, default=None,
                     help="iterations per fit (default: the workload's own count)")
-    ap.add_argument("--workload", default="ba5000", choices=["ba5000", "ba100k"],
+    ap.add_argument("--workload", default="ba5000", choices=["ba5000", "ba100k", "batch"],
                     help="ba5000: n=500, p=5000, 10 blocks, lambda 0.05, 500 iterations "
                          "(default); ba100k: n=1000, p=1e5, 200 blocks, lambda 0.03, "
-                         "300 iterations (the precision-form size)")
+                         "300 iterations (the precision-form size); batch: 16 bootstrap "
+                         "subsamples x 32 penalties at p=2000, 300 iterations, FP32, in "
+                         "one accord_fit_batch call")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for byte counters)")
     args = ap.parse_args()
@@ -303,6 +393,12 @@ def main():
               "(the estimator's columns shard across GPUs, but no multi-GPU path is built)",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        args.steps = 1 if args.steps is None else args.steps
+        args.warmup = 1 if args.warmup is None else args.warmup
+        return run_batch(args)
+    args.steps = 5 if args.steps is None else args.steps
+    args.warmup = 2 if args.warmup is None else args.warmup
 
     import torch
 

@@ -2033,10 +2033,13 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32_batch(const GemmArgs* 
                                                                int tpp) {
     const GemmArgs g = batch[blockIdx.y];
     const int tiles = g.tilesM * g.tilesN;
-    // XCD-contiguous logical order (see decode_tile), grouped 8 tiles along M
-    const int nblk = gridDim.x, bid = blockIdx.x;
-    const int xcd = bid & 7, local = bid >> 3, q8 = nblk >> 3, r8 = nblk & 7;
-    const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + local;
+    // Plain block order: consecutive tiles land on different XCDs (blocks are
+    // dispatched round-robin over the 8 XCDs), so the tiles of every problem spread
+    // over all of them.  Problems finish their line searches at different trials; an
+    // XCD-contiguous order would leave the XCDs of finished problems idle while the
+    // others carry the problems still searching.  The operand shared by a group's
+    // tiles (its X) is a few MB and stays in every XCD's L2.
+    const int logical = blockIdx.x;
     if (logical >= tiles) return;
     constexpr int GM = 8;
     const int per_group = GM * g.tilesN;
