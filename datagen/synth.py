@@ -224,6 +224,17 @@ def batch_workload(p: int = 2000, nsub: int = 16, nlam: int = 32, n_base: int = 
                          iters, {"graph": "erdos-renyi", "edge_prob": prob, "n_base": n_base})
 
 
+def diff_workload(n_train: int = 300, n_val: int = 150, nblocks: int = 6, b: int = 500,
+                  lam: float = 0.05, iters: int = 50, every: int = 10, key: int = 4):
+    """Held-out workload: one block power-law Theta (``nblocks`` BA(m=1) blocks of
+    ``b``), n_train + n_val samples; training and validation rows are centred and
+    scaled separately."""
+    r_theta, r_data, _ = rngs(key)
+    x = block_diag_sample(nblocks, b, n_train + n_val, 0.2, 0.5, 0.1, r_theta, r_data)
+    return {"x_train": _f32(standardise(x[:n_train])), "x_val": _f32(standardise(x[n_train:])),
+            "lam": lam, "iters": iters, "every": every, "p": nblocks * b}
+
+
 # the named workloads (sizes as used by tests and the benchmark)
 def workload(name: str) -> Workload:
     if name == "er200":

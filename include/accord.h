@@ -220,6 +220,44 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
                      accord_batch_stats* stats, int32_t* trials, void* ws, size_t ws_bytes,
                      void* stream);
 
+/* ---- Differentiation form: gradients of a held-out loss through K unrolled
+ * iterations with the step sizes held fixed (recorded from a backtracking fit and
+ * replayed).  The forward map of one step is Alg. 1's iteration at a given tau,
+ *     Omega_t+1 = prox(Omega_t - tau_t S Omega_t; tau_t, lambda)    (eq. 3.5),
+ * with S = X^T X / n computed through X as everywhere else (G = X^T (X Omega) / n,
+ * W recomputed from Omega_t at every step).  The held-out loss is the pseudolikelihood
+ * part of eq. 3.2 on validation data X_v (n_v rows), without the penalty:
+ *     l_val(Omega) = -sum_j log Omega_jj + ||X_v Omega||_F^2 / (2 n_v).
+ * All matrices in the column form of accord_fit; all calls FP32, asynchronous and
+ * stream-ordered; ws: device, 256-byte aligned, at least
+ * accord_adjoint_workspace_bytes(n, p) bytes (enough for all three calls with
+ * n = max(n, n_v)). */
+size_t accord_adjoint_workspace_bytes(int64_t n, int64_t p);
+
+/* nsteps fixed steps of sizes taus[0..nsteps-1] (host) from Omega (device p x p; in:
+ * Omega_start, out: Omega_end).  Omega_seq: device float[nsteps * p * p] receiving
+ * Omega_start+1 ... Omega_end, or NULL. */
+int accord_fbs_replay(const float* X, int64_t n, int64_t p, float* Omega, const double* taus,
+                      int64_t nsteps, double lambda, float* Omega_seq, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Held-out loss and its gradient at Omega: out (device double[3]) = { ||X_v Omega||^2/(2 n_v),
+ * -sum_j log Omega_jj, l_val }; Obar (device p x p) = S_v Omega - diag(1 / Omega_jj). */
+int accord_val_loss_grad(const float* Xv, int64_t nv, int64_t p, const float* Omega,
+                         double* out, float* Obar, void* ws, size_t ws_bytes, void* stream);
+
+/* Reverse of one step at (Omega_t, tau): given Obar = dl/dOmega_t+1 (device p x p),
+ * overwrites Obar with dl/dOmega_t and accumulates lbar[0] += dl/dlambda (device
+ * double) and Xbar += dl/dX (device n x p, row-major, FP32).  The prox Jacobian is
+ * taken entry by entry: off-diagonal 1{|a| > tau lambda} (0 at the kink), diagonal
+ * (1 + b / sqrt(b^2 + 4 tau)) / 2 with b = a - tau lambda; then
+ *     Abar = Obar * J,  dl/dlambda += sum(Obar * dOmega+/dlambda),
+ *     dl/dOmega_t = Abar - tau S Abar,
+ *     dl/dX += -(tau / n) (X Omega_t Abar^T + X Abar Omega_t^T). */
+int accord_fbs_adjoint_step(const float* X, int64_t n, int64_t p, const float* Omega_t,
+                            double tau, double lambda, float* Obar, double* lbar, float* Xbar,
+                            void* ws, size_t ws_bytes, void* stream);
+
 /* Static description of a status code. */
 const char* accord_status_str(int status);
 

@@ -106,6 +106,14 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(accord_params), _pd,
                                        ctypes.POINTER(accord_batch_stats), _vp, _vp, _sz, _vp]
         L.accord_fit_batch.restype = ctypes.c_int
+        L.accord_adjoint_workspace_bytes.argtypes = [_i64, _i64]
+        L.accord_adjoint_workspace_bytes.restype = _sz
+        L.accord_fbs_replay.argtypes = [_vp, _i64, _i64, _vp, _pd, _i64, _d, _vp, _vp, _sz, _vp]
+        L.accord_val_loss_grad.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.accord_fbs_adjoint_step.argtypes = [_vp, _i64, _i64, _vp, _d, _d, _vp, _vp, _vp, _vp,
+                                              _sz, _vp]
+        for f in ("accord_fbs_replay", "accord_val_loss_grad", "accord_fbs_adjoint_step"):
+            getattr(L, f).restype = ctypes.c_int
         L.accord_status_str.argtypes = [ctypes.c_int]
         L.accord_status_str.restype = ctypes.c_char_p
         L.accord_last_error.argtypes = []
@@ -286,3 +294,54 @@ def accord_fit_batch(X: torch.Tensor, n, lambdas, max_iter: int, *,
                                   tr.data_ptr() if tr is not None else None,
                                   ws.data_ptr(), ws.numel(), _stream(dev)))
     return omega_out, [s.as_dict() for s in st], tr
+
+
+def accord_adjoint_workspace_bytes(n: int, p: int) -> int:
+    return int(lib().accord_adjoint_workspace_bytes(n, p))
+
+
+def _adj_ws(n, p, device, ws):
+    need = accord_adjoint_workspace_bytes(n, p)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=device)
+    return ws
+
+
+def accord_fbs_replay(X: torch.Tensor, omega: torch.Tensor, taus, lam: float, *,
+                      seq: torch.Tensor | None = None, ws=None):
+    """Fixed steps taus from omega (paper-form [p, p], updated in place); seq
+    ([len(taus), p, p] or None) receives every iterate.  Returns omega."""
+    n, p = X.shape
+    taus = [float(t) for t in taus]
+    ta = (ctypes.c_double * max(len(taus), 1))(*taus)
+    ws = _adj_ws(n, p, X.device, ws)
+    _check(lib().accord_fbs_replay(_dev(X, "X"), n, p, _dev(omega, "Omega"), ta, len(taus),
+                                   float(lam), _dev(seq, "seq") if seq is not None else None,
+                                   ws.data_ptr(), ws.numel(), _stream(X.device)))
+    return omega
+
+
+def accord_val_loss_grad(Xv: torch.Tensor, omega: torch.Tensor, *, obar=None, out=None, ws=None):
+    """(out = [g_v, -sum log diag, loss] float64 device tensor, obar = dloss/dOmega)."""
+    nv, p = Xv.shape
+    if obar is None:
+        obar = torch.empty((p, p), dtype=torch.float32, device=Xv.device)
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=Xv.device)
+    ws = _adj_ws(nv, p, Xv.device, ws)
+    _check(lib().accord_val_loss_grad(_dev(Xv, "Xv"), nv, p, _dev(omega, "Omega"),
+                                      _dev(out, "out", torch.float64), _dev(obar, "Obar"),
+                                      ws.data_ptr(), ws.numel(), _stream(Xv.device)))
+    return out, obar
+
+
+def accord_fbs_adjoint_step(X: torch.Tensor, omega_t: torch.Tensor, tau: float, lam: float,
+                            obar: torch.Tensor, lbar: torch.Tensor, xbar: torch.Tensor, *, ws=None):
+    """One reverse step: obar <- dl/dOmega_t (in place), lbar += dl/dlambda,
+    xbar += dl/dX."""
+    n, p = X.shape
+    ws = _adj_ws(n, p, X.device, ws)
+    _check(lib().accord_fbs_adjoint_step(_dev(X, "X"), n, p, _dev(omega_t, "Omega_t"), float(tau),
+                                         float(lam), _dev(obar, "Obar"),
+                                         _dev(lbar, "lbar", torch.float64), _dev(xbar, "Xbar"),
+                                         ws.data_ptr(), ws.numel(), _stream(X.device)))

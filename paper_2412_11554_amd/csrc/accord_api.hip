@@ -1105,3 +1105,217 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Differentiation form
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kAdjBlocks = 1024;  // workgroups of the prox adjoint (FP64 partial rows)
+
+struct AdjPlan {
+    Plan P;
+    Geo gx;  // X bar product: M = p, N = n, K = 2 p_pad
+    size_t off_at, off_bw, off_xsplit, off_xnorm, off_adjpart, end;
+};
+
+AdjPlan make_adj_plan(int64_t n, int64_t p) {
+    AdjPlan A;
+    A.P = make_plan(n, p, 1, PREC_FP32);
+    const int64_t k2 = 2 * A.P.p_pad;
+    A.gx.tilesM = (int)cdiv(p, kBM);
+    A.gx.tilesN = (int)cdiv(n, kBN);
+    A.gx.splits = choose_splits(A.gx.tiles(), (int)(k2 / kPad), kSlots);
+    size_t cur = A.P.end_fit;
+    A.off_at = bump(cur, (size_t)(A.P.p_pad * k2) * sizeof(float));
+    A.off_bw = bump(cur, (size_t)(A.P.n_pad * k2) * sizeof(float));
+    A.off_xsplit = bump(cur, (size_t)(A.gx.splits > 1 ? A.gx.splits : 0) * A.gx.tiles() * kBM *
+                                 kBN * sizeof(float));
+    A.off_xnorm = bump(cur, (size_t)A.gx.tiles() * kNormCols * sizeof(double));
+    A.off_adjpart = bump(cur, (size_t)kAdjBlocks * sizeof(double));
+    A.end = cur;
+    return A;
+}
+
+int check_taus(const double* taus, int64_t nsteps) {
+    if (nsteps < 0) return fail(ACCORD_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (nsteps > 0 && !taus) return fail(ACCORD_ERR_INVALID_ARG, "taus is null");
+    for (int64_t t = 0; t < nsteps; ++t)
+        if (!(taus[t] > 0.0) || !isfinite(taus[t]))
+            return fail(ACCORD_ERR_INVALID_ARG, "taus[%lld] must be finite and > 0", (long long)t);
+    return ACCORD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t accord_adjoint_workspace_bytes(int64_t n, int64_t p) {
+    if (n < 1 || p < 1 || n > (1LL << 20) || p > (1LL << 20)) return 0;
+    return make_adj_plan(n, p).end;
+}
+
+int accord_fbs_replay(const float* X, int64_t n, int64_t p, float* Omega, const double* taus,
+                      int64_t nsteps, double lambda, float* Omega_seq, void* ws, size_t ws_bytes,
+                      void* stream) {
+    g_last_error.clear();
+    TRY(check_dims(n, p));
+    TRY(check_ptr(X, "X"));
+    TRY(check_ptr(Omega, "Omega"));
+    TRY(check_taus(taus, nsteps));
+    if (!(lambda >= 0.0) || !isfinite(lambda))
+        return fail(ACCORD_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+    if (Omega_seq) TRY(check_ptr(Omega_seq, "Omega_seq"));
+    const Plan P = make_plan(n, p, 1, PREC_FP32);
+    TRY(check_ws(ws, ws_bytes, P.end_fit));
+    hipStream_t st = (hipStream_t)stream;
+    LsState* ls = at<LsState>(ws, P.off_ls);
+    launch_init_state(ls, 1.0, 1.0, lambda, 0.0, 1.0 / (double)n, 1.0, 0, st);
+    launch_pad_x(X, n, p, at<float>(ws, P.off_xp), P.p_pad, at<float>(ws, P.off_xt), P.n_pad,
+                 XSplit{}, ls, st);
+    float* om[2] = {at<float>(ws, P.off_om0), at<float>(ws, P.off_om1)};
+    float* wt = at<float>(ws, P.off_wt0);
+    float* G = at<float>(ws, P.off_g);
+    launch_copy_cols(Omega, p, om[0], P.p_pad, p, P.p_pad, nullptr, st);
+    int cur = 0;
+    for (int64_t t = 0; t < nsteps; ++t) {
+        // fresh W = X Omega_t and G = X^T W / n, then the prox at tau_t (eq. 3.5)
+        enqueue_trial(trial_args(P, ws, PREC_FP32, om[cur], nullptr, nullptr, nullptr, wt, -1,
+                                 nullptr, 0),
+                      PREC_FP32, st);
+        launch_gemm(grad_args(P, ws, PREC_FP32, wt, 0, G, P.p_pad, (int)P.p_pad, nullptr),
+                    EPI_GRAD, PREC_FP32, st);
+        ProxArgs a = {};
+        a.om = om[cur];
+        a.g = G;
+        a.om_new = om[cur ^ 1];
+        a.total = p * P.p_pad;
+        a.ld = P.p_pad;
+        a.p = p;
+        a.tau = taus[t];
+        a.lambda = lambda;
+        a.part = at<double>(ws, P.off_prox_part);
+        launch_prox(a, P.nprox, st);
+        cur ^= 1;
+        if (Omega_seq) launch_copy_cols(om[cur], P.p_pad, Omega_seq + t * p * p, p, p, p, nullptr, st);
+    }
+    launch_copy_cols(om[cur], P.p_pad, Omega, p, p, p, nullptr, st);
+    HIP_TRY(hipGetLastError());
+    return ACCORD_OK;
+}
+
+int accord_val_loss_grad(const float* Xv, int64_t nv, int64_t p, const float* Omega, double* out,
+                         float* Obar, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    TRY(check_dims(nv, p));
+    TRY(check_ptr(Xv, "Xv"));
+    TRY(check_ptr(Omega, "Omega"));
+    TRY(check_ptr(Obar, "Obar"));
+    if (!out || !aligned(out, 8)) return fail(ACCORD_ERR_INVALID_ARG, "out must be non-null, 8-byte aligned");
+    const Plan P = make_plan(nv, p, 1, PREC_FP32);
+    TRY(check_ws(ws, ws_bytes, P.end_grad));
+    hipStream_t st = (hipStream_t)stream;
+    TRY(enqueue_w(P, Xv, Omega, ws, st));
+    const float* wt = at<float>(ws, P.off_wt0);
+    launch_gemm(grad_args(P, ws, PREC_FP32, wt, 0, Obar, p, (int)p, nullptr), EPI_GRAD, PREC_FP32, st);
+    launch_sub_inv_diag(Obar, p, at<float>(ws, P.off_om0), P.p_pad, p, st);
+    ProxArgs a = {};
+    a.om = at<float>(ws, P.off_om0);
+    a.total = p * P.p_pad;
+    a.ld = P.p_pad;
+    a.p = p;
+    a.part = at<double>(ws, P.off_prox_part);
+    a.reduce_only = 1;
+    launch_prox(a, P.nprox, st);
+    launch_combine_objective(a.part, P.nprox, at<double>(ws, P.off_norm_part), P.t32.tiles(), 0.0,
+                             1.0 / (double)nv, out, st);
+    HIP_TRY(hipGetLastError());
+    return ACCORD_OK;
+}
+
+int accord_fbs_adjoint_step(const float* X, int64_t n, int64_t p, const float* Omega_t, double tau,
+                            double lambda, float* Obar, double* lbar, float* Xbar, void* ws,
+                            size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    TRY(check_dims(n, p));
+    TRY(check_ptr(X, "X"));
+    TRY(check_ptr(Omega_t, "Omega_t"));
+    TRY(check_ptr(Obar, "Obar"));
+    TRY(check_ptr(Xbar, "Xbar"));
+    if (!lbar || !aligned(lbar, 8)) return fail(ACCORD_ERR_INVALID_ARG, "lbar must be non-null, 8-byte aligned");
+    if (!(tau > 0.0) || !isfinite(tau)) return fail(ACCORD_ERR_INVALID_ARG, "tau must be finite and > 0");
+    if (!(lambda >= 0.0) || !isfinite(lambda))
+        return fail(ACCORD_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+    const AdjPlan A = make_adj_plan(n, p);
+    const Plan& P = A.P;
+    TRY(check_ws(ws, ws_bytes, A.end));
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t k2 = 2 * P.p_pad;
+    float* om = at<float>(ws, P.off_om0);
+    float* wt0 = at<float>(ws, P.off_wt0);
+    float* wt1 = at<float>(ws, P.off_wt1);
+    float* G = at<float>(ws, P.off_g);
+    float* abar = at<float>(ws, P.off_d);
+    float* AT = at<float>(ws, A.off_at);
+    float* BW = at<float>(ws, A.off_bw);
+    double* part = at<double>(ws, A.off_adjpart);
+    // forward quantities of step t: W = X Omega_t, G = S Omega_t (the same kernels and
+    // inputs as the replay, so the same bits)
+    TRY(enqueue_w(P, X, Omega_t, ws, st));
+    launch_gemm(grad_args(P, ws, PREC_FP32, wt0, 0, G, P.p_pad, (int)P.p_pad, nullptr), EPI_GRAD,
+                PREC_FP32, st);
+    // through the prox: Abar and the lambda derivative
+    AdjArgs a = {};
+    a.om = om;
+    a.g = G;
+    a.obar = Obar;
+    a.ld = P.p_pad;
+    a.ld_obar = p;
+    a.p = p;
+    a.tau = tau;
+    a.lambda = lambda;
+    a.abar = abar;
+    a.part = part;
+    launch_prox_adjoint(a, kAdjBlocks, st);
+    launch_accumulate_scalar(part, kAdjBlocks, lbar, st);
+    // V = X Abar (W^T layout), then S Abar = X^T V / n into G
+    enqueue_trial(trial_args(P, ws, PREC_FP32, abar, nullptr, nullptr, nullptr, wt1, -1, nullptr, 0),
+                  PREC_FP32, st);
+    launch_gemm(grad_args(P, ws, PREC_FP32, wt1, 0, G, P.p_pad, (int)P.p_pad, nullptr), EPI_GRAD,
+                PREC_FP32, st);
+    // Omega_t bar = Abar - tau S Abar  (written over Obar)
+    launch_adjoint_combine(abar, G, P.p_pad, p, (float)tau, Obar, p, st);
+    // X bar += -(tau/n) (W Abar^T + V Omega_t^T) as one product with K = 2 p_pad:
+    // rows i of [Abar | Omega_t] against rows m of [W | V]
+    HIP_TRY(hipMemsetAsync(AT, 0, (size_t)(P.p_pad * k2) * sizeof(float), st));
+    HIP_TRY(hipMemsetAsync(BW, 0, (size_t)(P.n_pad * k2) * sizeof(float), st));
+    launch_transpose_ld(abar, P.p_pad, p, p, AT, k2, st);
+    launch_transpose_ld(om, P.p_pad, p, p, AT + P.p_pad, k2, st);
+    launch_transpose_ld(wt0, P.n_pad, p, n, BW, k2, st);
+    launch_transpose_ld(wt1, P.n_pad, p, n, BW + P.p_pad, k2, st);
+    GemmArgs x = {};
+    x.A = AT;
+    x.lda = k2;
+    x.B = BW;
+    x.ldb = k2;
+    x.M = (int)p;
+    x.N = (int)n;
+    x.K = (int)k2;
+    x.tilesM = A.gx.tilesM;
+    x.tilesN = A.gx.tilesN;
+    x.splits = A.gx.splits;
+    x.C = Xbar;
+    x.ldc = p;
+    x.vec_store = (p % 4 == 0) && aligned(Xbar, 16);
+    x.alpha = (float)(-tau / (double)n);
+    x.Wprev = Xbar;
+    x.P = A.gx.splits > 1 ? at<float>(ws, A.off_xsplit) : nullptr;
+    x.norm_part = at<double>(ws, A.off_xnorm);
+    x.Mvalid = (int)p;
+    x.Nvalid = (int)n;
+    enqueue_trial(x, PREC_FP32, st);
+    HIP_TRY(hipGetLastError());
+    return ACCORD_OK;
+}
+
+}  // extern "C"

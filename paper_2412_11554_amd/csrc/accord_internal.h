@@ -146,6 +146,17 @@ struct FinArgs {
     int32_t* trials_log;
 };
 
+// reverse of one prox step (differentiation form)
+struct AdjArgs {
+    const float* om;    // Omega_t, p columns x ld
+    const float* g;     // G_t = S Omega_t, same layout
+    const float* obar;  // dl/dOmega_t+1, p columns x ld_obar
+    int64_t ld, ld_obar, p;
+    double tau, lambda;
+    float* abar;        // out: p columns x ld (zero padded rows)
+    double* part;       // out: [gridDim.x] FP64 partials of dl/dlambda
+};
+
 // ---------------------------------------------------------------------------
 // launchers (accord_kernels.hip)
 // ---------------------------------------------------------------------------
@@ -177,6 +188,16 @@ void launch_transpose_w(const float* Wt, int64_t ldt, int64_t n, int64_t p, floa
 void launch_power_iteration(const float* Xp, int64_t p_pad, const float* Xt, int64_t n_pad,
                             int64_t n, int64_t p, double* w, double* u, double* part_u,
                             double* part_w, int steps, LsState* ls, hipStream_t st);
+
+// differentiation form
+void launch_prox_adjoint(const AdjArgs& a, int nblocks, hipStream_t st);
+void launch_adjoint_combine(const float* abar, const float* sa, int64_t ld, int64_t p, float tau,
+                            float* out, int64_t ld_out, hipStream_t st);
+void launch_transpose_ld(const float* src, int64_t ld_src, int64_t rows, int64_t cols, float* dst,
+                         int64_t ld_dst, hipStream_t st);
+void launch_accumulate_scalar(const double* part, int count, double* acc, hipStream_t st);
+void launch_sub_inv_diag(float* obar, int64_t ld_obar, const float* om, int64_t ld_om, int64_t p,
+                         hipStream_t st);
 
 // batched form (argument blocks in device memory)
 void launch_gemm_f32_batch(const GemmArgs* batch, int ngroups, int max_tiles, int tpp, int epi,

@@ -284,16 +284,16 @@ __device__ inline bool gemm_skip(const GemmArgs& g) {
 
 // Stores one 4-row accumulator fragment (rows m..m+3 of column n).
 //   EPI_GRAD:  C = alpha * acc
-//   EPI_TRIAL: C = Wprev + acc, with FP64 sums of acc^2 and C^2 over the valid extent
+//   EPI_TRIAL: C = Wprev + alpha * acc, with FP64 sums of (alpha acc)^2 and C^2 over the
+//              valid extent (alpha = 1 in the trial products)
 // With Ch/Cl set, the bf16 hi/lo split of the stored value is written as well.
 template <int EPI>
 __device__ inline void store_frag(const GemmArgs& g, f4 v, int m, int n, double (&nv)[2]) {
     if (n >= g.N || m >= g.M) return;
     const int64_t off = (int64_t)n * g.ldc + m;
     const bool vec = g.vec_store && m + 3 < g.M;
-    if (EPI == EPI_GRAD) {
-        v = v * g.alpha;
-    } else {
+    v = v * g.alpha;  // EPI_GRAD: 1/n; EPI_TRIAL: 1 (or the adjoint's -tau/n)
+    if (EPI != EPI_GRAD) {
         f4 w = f4{0.f, 0.f, 0.f, 0.f};
         if (g.Wprev) {
             if (vec) {
@@ -2145,6 +2145,128 @@ void launch_init_state_batch(LsState* ls, int nprob, int nlam, const double* lam
 
 void launch_share_L_batch(LsState* ls, int nprob, int nlam, hipStream_t st) {
     k_share_L_batch<<<(unsigned)cdiv(nprob, 256), 256, 0, st>>>(ls, nprob, nlam);
+}
+
+}  // namespace accord
+
+// ---------------------------------------------------------------------------
+// Differentiation form: reverse pass of the fixed-step iteration (the adjoint of
+// one prox-gradient step) and the held-out loss gradient.
+// ---------------------------------------------------------------------------
+namespace accord {
+
+// Reverse of eq. 3.5 at a = Omega - tau G (same FP32 arithmetic as the forward
+// prox, so the active set matches it):
+//   off-diagonal  abar = obar 1{|a| > tau lambda},  dl = -tau sign(a) 1{...}
+//   diagonal      b = a - tau lambda, r = sqrt(b^2 + 4 tau), d = (1 + b/r)/2 (FP64):
+//                 abar = obar d,  dl = -tau d
+// abar -> p x ld (zero in padded rows); per-workgroup FP64 partials of sum(obar dl).
+__global__ void __launch_bounds__(kThreads) k_prox_adjoint(AdjArgs a) {
+    const float tau_f = (float)a.tau, thr_f = (float)(a.tau * a.lambda);
+    double s = 0.0;
+    const int64_t total = a.p * a.ld;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kThreads) {
+        const int64_t j = e / a.ld, i = e - j * a.ld;
+        float out = 0.f;
+        if (i < a.p) {
+            const float o = a.om[e], gv = a.g[e];
+            const float ob = a.obar[j * a.ld_obar + i];
+            if (i == j) {
+                const double y = (double)o - a.tau * (double)gv;
+                const double b = y - a.tau * a.lambda;
+                const double r = sqrt(b * b + 4.0 * a.tau);
+                const double d = 0.5 * (1.0 + b / r);
+                out = (float)((double)ob * d);
+                s += (double)ob * (-a.tau * d);
+            } else {
+                const float av = fmaf(-tau_f, gv, o);
+                if (fabsf(av) - thr_f > 0.f) {
+                    out = ob;
+                    s += (double)ob * (av > 0.f ? -a.tau : a.tau);
+                }
+            }
+        }
+        a.abar[e] = out;
+    }
+    double v[1] = {s};
+    block_sum<1>(v);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = v[0];
+}
+
+// obar_t = abar - tau * SA  (p x p, ld_out) from the padded abar / SA (ld)
+__global__ void __launch_bounds__(kThreads) k_adjoint_combine(const float* __restrict__ abar,
+                                                              const float* __restrict__ sa,
+                                                              int64_t ld, int64_t p, float tau,
+                                                              float* __restrict__ out,
+                                                              int64_t ld_out) {
+    const int64_t total = p * p;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kThreads) {
+        const int64_t j = e / p, i = e - j * p;
+        out[j * ld_out + i] = fmaf(-tau, sa[j * ld + i], abar[j * ld + i]);
+    }
+}
+
+// dst[c * ld_dst + r] = src[r * ld_src + c]  for r < rows, c < cols (32 x 32 LDS tiles)
+__global__ void __launch_bounds__(kThreads) k_transpose_ld(const float* __restrict__ src,
+                                                           int64_t ld_src, int64_t rows,
+                                                           int64_t cols, float* __restrict__ dst,
+                                                           int64_t ld_dst) {
+    __shared__ float tile[32][33];
+    const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int rr = ty; rr < 32; rr += kThreads / 32) {
+        const int64_t r = r0 + rr, c = c0 + tx;
+        tile[rr][tx] = (r < rows && c < cols) ? src[r * ld_src + c] : 0.f;
+    }
+    __syncthreads();
+    for (int cc = ty; cc < 32; cc += kThreads / 32) {
+        const int64_t c = c0 + cc, r = r0 + tx;
+        if (c < cols && r < rows) dst[c * ld_dst + r] = tile[tx][cc];
+    }
+}
+
+// acc[0] += sum of the partials (fixed order)
+__global__ void __launch_bounds__(kThreads) k_accumulate_scalar(const double* part, int count,
+                                                                double* acc) {
+    double v[1];
+    sum_partials<1>(part, count, 1, v);
+    if (threadIdx.x == 0) acc[0] += v[0];
+}
+
+// obar_jj -= 1 / Omega_jj  (the -sum log Omega_jj term of the held-out loss)
+__global__ void k_sub_inv_diag(float* obar, int64_t ld_obar, const float* om, int64_t ld_om,
+                               int64_t p) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= p) return;
+    obar[j * ld_obar + j] -= (float)(1.0 / (double)om[j * ld_om + j]);
+}
+
+void launch_prox_adjoint(const AdjArgs& a, int nblocks, hipStream_t st) {
+    k_prox_adjoint<<<(unsigned)nblocks, kThreads, 0, st>>>(a);
+}
+
+void launch_adjoint_combine(const float* abar, const float* sa, int64_t ld, int64_t p, float tau,
+                            float* out, int64_t ld_out, hipStream_t st) {
+    int64_t b = cdiv(p * p, (int64_t)kThreads * 8);
+    if (b > 16384) b = 16384;
+    k_adjoint_combine<<<(unsigned)b, kThreads, 0, st>>>(abar, sa, ld, p, tau, out, ld_out);
+}
+
+void launch_transpose_ld(const float* src, int64_t ld_src, int64_t rows, int64_t cols, float* dst,
+                         int64_t ld_dst, hipStream_t st) {
+    dim3 grid((unsigned)cdiv(cols, 32), (unsigned)cdiv(rows, 32));
+    k_transpose_ld<<<grid, kThreads, 0, st>>>(src, ld_src, rows, cols, dst, ld_dst);
+}
+
+void launch_accumulate_scalar(const double* part, int count, double* acc, hipStream_t st) {
+    k_accumulate_scalar<<<1, kThreads, 0, st>>>(part, count, acc);
+}
+
+void launch_sub_inv_diag(float* obar, int64_t ld_obar, const float* om, int64_t ld_om, int64_t p,
+                         hipStream_t st) {
+    k_sub_inv_diag<<<(unsigned)cdiv(p, 256), 256, 0, st>>>(obar, ld_obar, om, ld_om, p);
 }
 
 }  // namespace accord
