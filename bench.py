@@ -368,6 +368,66 @@ def run_batch(args):
     print(json.dumps(res), flush=True)
 
 
+def run_diff(args):
+    """The differentiation form: one step = recording fit (Alg. 1, FP32) + forward
+    replay of K fixed steps with checkpoints + held-out loss + reverse pass (dl/dX,
+    dl/dlambda).  value = unrolled iterations per second (forward and reverse)."""
+    import torch
+
+    import datagen
+    from paper_2412_11554_amd.diff import unrolled_val_loss
+
+    d = datagen.diff_workload()
+    K, every, lam = (args.iters or d["iters"]), d["every"], d["lam"]
+    n, p = d["x_train"].shape
+    X = torch.from_numpy(d["x_train"]).to("cuda:0").requires_grad_(True)
+    Xv = torch.from_numpy(d["x_val"]).to("cuda:0")
+
+    def step():
+        X.grad = None
+        lam_t = torch.tensor(lam, dtype=torch.float64, device="cuda:0", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = unrolled_val_loss(X, lam_t, Xv, iters=K, checkpoint_every=every)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return loss.detach(), lam_t.grad, t1 - t0, t2 - t1
+
+    for _ in range(args.warmup):
+        step()
+    log("[diff] warmup done")
+    fw = bw = 0.0
+    for i in range(args.steps):
+        loss, glam, a, b = step()
+        fw += a
+        bw += b
+        log(f"[diff] step {i + 1}/{args.steps}: forward {a * 1e3:.1f} ms, backward {b * 1e3:.1f} ms")
+    total = fw + bw
+    # useful flops: forward replay 2 products of 2 n p^2 per step; reverse: the
+    # segment replay (2), W and G again (2), X Abar and X^T V (2), and the X bar
+    # product with K = 2p (2) -> 8 products; the recording fit is timed but not counted
+    flops = args.steps * K * (2 + 8) * 2.0 * n * p * p
+    tflops = flops / total / 1e12
+    res = {
+        "metric": "unrolled prox-grad iterations/sec, forward + reverse (FP32)",
+        "value": K * args.steps / total, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": f"held-out loss gradient: n_train={n}, n_val={Xv.shape[0]}, p={p} "
+                               f"(6 power-law blocks), lambda={lam}, K={K}, checkpoint every {every}",
+                   "n": n, "p": p, "K": K},
+        "forward_ms": fw / args.steps * 1e3, "backward_ms": bw / args.steps * 1e3,
+        "roofline": {"bound": "mfma", "kernel": "whole forward + reverse (FP32 GEMMs)",
+                     "achieved": tflops, "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                     "frac": tflops / PEAK_TFLOPS["fp32"], "traffic": None},
+        "loss": float(loss), "dloss_dlambda": float(glam),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,12 +439,13 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--iters", type=int, default=None,
                     help="iterations per fit (default: the workload's own count)")
-    ap.add_argument("--workload", default="ba5000", choices=["ba5000", "ba100k", "batch"],
+    ap.add_argument("--workload", default="ba5000", choices=["ba5000", "ba100k", "batch", "diff"],
                     help="ba5000: n=500, p=5000, 10 blocks, lambda 0.05, 500 iterations "
                          "(default); ba100k: n=1000, p=1e5, 200 blocks, lambda 0.03, "
                          "300 iterations (the precision-form size); batch: 16 bootstrap "
                          "subsamples x 32 penalties at p=2000, 300 iterations, FP32, in "
-                         "one accord_fit_batch call")
+                         "one accord_fit_batch call; diff: held-out loss gradient through "
+                         "50 unrolled steps, n=300 (+150 held out), p=3000")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for byte counters)")
     args = ap.parse_args()
@@ -393,10 +454,10 @@ def main():
               "(the estimator's columns shard across GPUs, but no multi-GPU path is built)",
               file=sys.stderr)
         sys.exit(2)
-    if args.workload == "batch":
+    if args.workload in ("batch", "diff"):
         args.steps = 1 if args.steps is None else args.steps
         args.warmup = 1 if args.warmup is None else args.warmup
-        return run_batch(args)
+        return run_batch(args) if args.workload == "batch" else run_diff(args)
     args.steps = 5 if args.steps is None else args.steps
     args.warmup = 2 if args.warmup is None else args.warmup
 

@@ -160,3 +160,23 @@ def test_fit_batch_validation(L):
     assert call(pr=accord.default_params(max_iter=3, precision=2)) == 5
     assert call(pr=accord.default_params(beta=0.0)) == 1
     assert L.accord_last_error()
+
+
+def test_differentiation_validation(L):
+    taus = (ctypes.c_double * 2)(0.5, -0.1)
+    ws_ok = 1 << 40
+    assert accord.accord_adjoint_workspace_bytes(0, 5) == 0
+    assert accord.accord_adjoint_workspace_bytes(10, 20) > 0
+    assert L.accord_fbs_replay(FAKE, 10, 5, FAKE, taus, 2, 0.1, None, FAKE, ws_ok, None) == 1
+    assert L.accord_fbs_replay(FAKE, 10, 5, FAKE, None, 2, 0.1, None, FAKE, ws_ok, None) == 1
+    assert L.accord_fbs_replay(FAKE, 10, 5, FAKE, taus, 1, -0.1, None, FAKE, ws_ok, None) == 1
+    assert L.accord_fbs_replay(FAKE, 10, 5, FAKE, taus, 1, 0.1, None, FAKE, 16, None) == 4
+    assert L.accord_val_loss_grad(FAKE, 10, 5, FAKE, None, FAKE, FAKE, ws_ok, None) == 1
+    assert L.accord_val_loss_grad(FAKE, 10, 5, FAKE, FAKE, None, FAKE, ws_ok, None) == 1
+    assert L.accord_fbs_adjoint_step(FAKE, 10, 5, FAKE, 0.0, 0.1, FAKE, FAKE, FAKE, FAKE, ws_ok,
+                                     None) == 1
+    assert L.accord_fbs_adjoint_step(FAKE, 10, 5, FAKE, 0.5, 0.1, FAKE, None, FAKE, FAKE, ws_ok,
+                                     None) == 1
+    assert L.accord_fbs_adjoint_step(FAKE, 10, 5, FAKE, 0.5, 0.1, FAKE, FAKE, FAKE, FAKE, 64,
+                                     None) == 4
+    assert L.accord_last_error()
