@@ -7,3 +7,4 @@ from .accord_oracle import (FitResult, brute_column, diag_root, fit_cd, fit_fbs,
 from .mx_oracle import (E4M3_MAX, MX_BLOCK, e4m3_round, e4m3_value, fit_fbs_mx,  # noqa: F401
                         mx_quantize, mx_scale_exp)
 from . import adjoint_oracle  # noqa: F401
+from . import tuning_oracle  # noqa: F401
