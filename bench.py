@@ -428,6 +428,114 @@ def run_diff(args):
     print(json.dumps(res), flush=True)
 
 
+def run_refit(args):
+    """The steps around the solver at n = 500, p = 5000: one step = the refit of
+    eq. 3.8 (Alg. 1 in the FP32 form with the support mask, 200 iterations, from a
+    synthetic first-stage estimate on the true graph's support, L by power iteration)
+    followed by the reparametrisation (Theta and the partial correlations).
+    value = refit iterations per second, the reparametrisation's time included."""
+    import torch
+
+    import datagen
+    from paper_2412_11554_amd import accord
+
+    d = datagen.refit_workload()
+    iters = args.iters or d["iters"]
+    n, p = d["x"].shape
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(d["x"]).to(dev)
+    H = torch.from_numpy(np.ascontiguousarray(d["omega_hat"].T)).to(dev)
+    prm = accord.default_params(lam=d["lam"], max_iter=iters)
+    ws = torch.empty(accord.accord_refit_workspace_bytes(n, p, prm), dtype=torch.uint8, device=dev)
+    om = torch.empty((p, p), dtype=torch.float32, device=dev)
+    theta, rho = torch.empty_like(om), torch.empty_like(om)
+
+    def step(timing):
+        _, st, tr = accord.accord_refit(X, H, d["lam"], d["phi"], iters, ws=ws, omega_out=om,
+                                        timing=timing, trace=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        accord.accord_reparam(om, theta_out=theta, rho_out=rho)
+        e1.record()
+        return st, tr, (e0, e1)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log("[refit] warmup done")
+    stats, events = [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        st, tr, ev = step(True)
+        stats.append(st)
+        events.append(ev)
+        log(f"[refit] step {i + 1}/{args.steps}: {st['iters']} iters, {st['trials']} trials, "
+            f"{st['total_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    rep_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    rep_bytes = 12.0 * p * p      # read Omega, write Theta and rho (FP32)
+    rep_gbs = rep_bytes / (rep_ms * 1e-3) / 1e9
+    kern = kernel_report(stats, "fp32", n, p, False)
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    r = kern[dom]
+    res = {
+        "metric": "refit prox-grad iters/sec on the estimated support (FP32) + reparametrisation",
+        "value": sum(s["iters"] for s in stats) / elapsed, "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"refit (eq. 3.8) on n={n}, p={p} power-law data, support of the "
+                               f"true graph, lambda={d['lam']}, phi={d['phi']}, {iters} iterations, "
+                               "then Theta and rho",
+                   "n": n, "p": p, "iters": iters},
+        "trials_per_iter": stats[-1]["trials"] / max(1, stats[-1]["iters"]),
+        "roofline": {"bound": r["bound"], "kernel": " + ".join(r["kernels"]),
+                     "achieved": r["achieved"], "peak": r["peak"], "unit": r["unit"],
+                     "frac": r["frac"], "traffic": None},
+        "kernels": kern,
+        "reparam": {"kernels": ["k_reparam"], "avg_ms": rep_ms, "bound": "hbm",
+                    "algorithmic_bytes": rep_bytes, "achieved": rep_gbs, "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": rep_gbs / PEAK_HBM_GBS},
+        "nnz_offdiag": stats[-1]["nnz_offdiag"],
+    }
+    if not args.no_check:
+        from oracle import tuning_oracle as tu
+        cols = sample_cols(p)
+        taus = tr.cpu().numpy()[1:, 3]
+        ref = tu.refit(d["x"].astype(np.float64), d["omega_hat"].astype(np.float64), d["lam"],
+                       d["phi"], len(taus), L=stats[-1]["lipschitz"], tau_replay=taus,
+                       columns=cols).omega
+        got = om.cpu().numpy()[cols, :].astype(np.float64).T
+        res["error_vs_oracle"] = {
+            "rel_fro_sampled_cols": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "cols": cols.tolist(), "reference": "FP64 oracle refit replaying the step sizes"}
+    if not args.no_cpu_baseline:
+        from oracle import tuning_oracle as tu
+        k = 3
+        t1 = time.perf_counter()
+        rr = tu.refit(d["x"].astype(np.float64), d["omega_hat"].astype(np.float64), d["lam"],
+                      d["phi"], k, L=stats[-1]["lipschitz"])
+        dt = time.perf_counter() - t1
+        res["cpu_baseline"] = {"value": k / dt, "unit": "iters/s", "cores": _threads(),
+                               "kind": "oracle",
+                               "sample": f"first {k} refit iterations at n={n}, p={p} "
+                                         f"({sum(rr.trials)} trials, {dt:.1f} s)"}
+    print(json.dumps(res), flush=True)
+
+
+def _threads():
+    threads = os.cpu_count()
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        if info:
+            threads = max(i.get("num_threads", 0) for i in info) or threads
+    except Exception:
+        pass
+    return threads
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -439,13 +547,16 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--iters", type=int, default=None,
                     help="iterations per fit (default: the workload's own count)")
-    ap.add_argument("--workload", default="ba5000", choices=["ba5000", "ba100k", "batch", "diff"],
+    ap.add_argument("--workload", default="ba5000",
+                    choices=["ba5000", "ba100k", "batch", "diff", "refit"],
                     help="ba5000: n=500, p=5000, 10 blocks, lambda 0.05, 500 iterations "
                          "(default); ba100k: n=1000, p=1e5, 200 blocks, lambda 0.03, "
                          "300 iterations (the precision-form size); batch: 16 bootstrap "
                          "subsamples x 32 penalties at p=2000, 300 iterations, FP32, in "
                          "one accord_fit_batch call; diff: held-out loss gradient through "
-                         "50 unrolled steps, n=300 (+150 held out), p=3000")
+                         "50 unrolled steps, n=300 (+150 held out), p=3000; refit: the "
+                         "support-restricted refit (200 iterations) and Theta / rho at "
+                         "n=500, p=5000")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for byte counters)")
     args = ap.parse_args()
@@ -454,10 +565,10 @@ def main():
               "(the estimator's columns shard across GPUs, but no multi-GPU path is built)",
               file=sys.stderr)
         sys.exit(2)
-    if args.workload in ("batch", "diff"):
-        args.steps = 1 if args.steps is None else args.steps
+    if args.workload in ("batch", "diff", "refit"):
+        args.steps = (1 if args.workload != "refit" else 3) if args.steps is None else args.steps
         args.warmup = 1 if args.warmup is None else args.warmup
-        return run_batch(args) if args.workload == "batch" else run_diff(args)
+        return {"batch": run_batch, "diff": run_diff, "refit": run_refit}[args.workload](args)
     args.steps = 5 if args.steps is None else args.steps
     args.warmup = 2 if args.warmup is None else args.warmup
 

@@ -235,6 +235,23 @@ def diff_workload(n_train: int = 300, n_val: int = 150, nblocks: int = 6, b: int
             "lam": lam, "iters": iters, "every": every, "p": nblocks * b}
 
 
+def refit_workload(lam: float = 0.05, phi: float = 0.5, iters: int = 200, key: int = 1):
+    """The n = 500, p = 5000 power-law data (the same X as the "ba5000" workload) with a
+    synthetic first-stage estimate whose support is the true graph's: diagonal 1,
+    off-diagonal entries on the edges +-U[0.01, 0.05] (column form, float32)."""
+    w = ba_block_workload(500, 10, 500, lam, iters, key=key, keep_theta=True)
+    _, _, r_aux = rngs(key)
+    om = np.zeros((w.p, w.p), dtype=np.float32)
+    for k, th in enumerate(w.meta["thetas"]):
+        b = th.shape[0]
+        blk = np.where(th != 0, r_aux.uniform(0.01, 0.05, (b, b)) * r_aux.choice([-1.0, 1.0], (b, b)),
+                       0.0)
+        np.fill_diagonal(blk, 1.0)
+        om[k * b:(k + 1) * b, k * b:(k + 1) * b] = blk
+    return {"x": w.X, "omega_hat": om, "lam": lam, "phi": phi, "iters": iters, "n": w.n,
+            "p": w.p}
+
+
 # the named workloads (sizes as used by tests and the benchmark)
 def workload(name: str) -> Workload:
     if name == "er200":

@@ -32,8 +32,9 @@
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = default stream).
  * accord_grad, accord_prox and accord_objective are asynchronous and
  * stream-ordered; problems found on the device (non-finite values, a
- * non-positive diagonal) show up as NaN / inf in their outputs.  accord_fit is
- * synchronous: it returns after its work on `stream` has completed.
+ * non-positive diagonal) show up as NaN / inf in their outputs.  accord_fit,
+ * accord_fit_batch and accord_refit are synchronous: they return after their work on
+ * `stream` has completed.
  *
  * Errors.  Every entry point returns an accord_status.  Argument, alignment and
  * workspace-size problems are detected on the host and returned before any
@@ -130,6 +131,8 @@ typedef struct {
     double trial_gemm_ms;   int32_t trial_gemm_launches;  /* W+ = W + X Delta       */
     double prox_ms;         int32_t prox_launches;        /* fused prox + reductions */
     double total_ms;        /* event time of the whole fit on the stream */
+    double log_det_d;       /* sum_j log Omega_jj at the result (log det of the diagonal) */
+    double l1;              /* ||Omega||_1 at the result (all entries) */
 } accord_stats;
 
 /* Fills `prm` with defaults: lambda 0.1, tau0 1, beta 0.5, lipschitz 0 (estimate),
@@ -208,6 +211,7 @@ typedef struct {
     int32_t iters, trials, floor_accepts, converged;
     int64_t nnz_offdiag;
     double f, g, h, tau_last, delta_fro, lipschitz;
+    double log_det_d, l1;   /* as in accord_stats */
 } accord_batch_stats;
 
 /* Workspace bytes of accord_fit_batch (0 for invalid sizes). */
@@ -257,6 +261,59 @@ int accord_val_loss_grad(const float* Xv, int64_t nv, int64_t p, const float* Om
 int accord_fbs_adjoint_step(const float* X, int64_t n, int64_t p, const float* Omega_t,
                             double tau, double lambda, float* Obar, double* lbar, float* Xbar,
                             void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Steps around the solver: tuning by epBIC (eq. 3.7), the refit on the estimated
+ * support (eq. 3.8) and the reparametrisation of Sec. 2. */
+
+/* Extended pseudo-BIC of eq. 3.7 of one estimate from the statistics of its fit
+ * (host arithmetic in FP64):
+ *     out = 2n (-log_det_d + g) + nnz_offdiag (log n + 4 gamma log p),
+ * log_det_d = sum_j log Omega_jj, g = ||X Omega||_F^2 / (2n) (so the bracket is the
+ * loss of eq. 3.2 without the penalty, tr(Omega^T Omega S)/2 in the paper's
+ * orientation), nnz_offdiag = number of nonzero off-diagonal entries.
+ * gamma in (0, 1] (the extended-BIC weight), 0 <= nnz_offdiag <= p (p - 1). */
+int accord_epbic(int64_t n, int64_t p, double g, double log_det_d, int64_t nnz_offdiag,
+                 double gamma, double* out);
+
+/* epBIC of every problem of a batched fit (stats: host, nsub * nlam entries as
+ * returned by accord_fit_batch; n: host row counts of the nsub data sets) into
+ * epbic (host double[nsub * nlam], problem k = b * nlam + l), and for each data set b
+ * the penalty index with the smallest value into best[b] (host int64[nsub], may be
+ * NULL; the first index on ties). */
+int accord_epbic_path(const accord_batch_stats* stats, const int64_t* n, int64_t nsub,
+                      int64_t nlam, int64_t p, double gamma, double* epbic, int64_t* best);
+
+/* Workspace bytes of accord_refit (0 for invalid sizes). */
+size_t accord_refit_workspace_bytes(int64_t n, int64_t p, const accord_params* prm);
+
+/* Refit of eq. 3.8: minimises -sum_j log Omega_jj + g(Omega) + phi * lambda ||Omega||_1
+ * over Omega that vanish off the support of the first-stage estimate, by Alg. 1 with
+ * the per-entry penalty phi * lambda on the support and infinity off it.
+ *   Omega_hat: device p x p column form, the first-stage estimate; its support is
+ *     its nonzero entries plus the diagonal.  Read once, before any iteration (it may
+ *     be the same buffer as Omega).
+ *   phi in [0, 1]; lambda = prm->lambda (the first-stage penalty).
+ *   Omega: device p x p, in: the starting point (its entries off the support are set
+ *     to zero first; Omega_hat itself is the natural start), out: the last iterate.
+ *     Entries off the support are exactly zero in every iterate.
+ * Everything else (parameters, stats with phi * lambda as the penalty, trace, errors,
+ * synchronous behaviour) as accord_fit.  FP32 form only (else ACCORD_ERR_UNSUPPORTED).
+ * ws: device, 256-byte aligned, at least accord_refit_workspace_bytes() bytes. */
+int accord_refit(const float* X, int64_t n, int64_t p, const float* Omega_hat, double phi,
+                 float* Omega, const accord_params* prm, accord_stats* stats, double* trace,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* Reparametrisation of Sec. 2 from an estimate Omega (device p x p column form, positive
+ * diagonal):
+ *   Theta = Omega_D Omega in the paper's orientation, the inverse of the map
+ *     T: Theta -> Theta_D^{-1/2} Theta; written in the column form like Omega
+ *     (Theta^T column-major: column j of Omega times Omega_jj), or NULL;
+ *   Rho: partial correlations rho_ij = -(w_ij / w_jj + w_ji / w_ii) / 2 (w in the paper's
+ *     orientation), symmetric, with rho_ii = 1, p x p, or NULL.
+ * One of the two may be NULL, not both; neither may overlap Omega or the other.
+ * Theta is correctly rounded; Rho is computed with FP64 reciprocals of the diagonal
+ * and one final rounding.  Asynchronous, stream-ordered; no workspace. */
+int accord_reparam(const float* Omega, int64_t p, float* Theta, float* Rho, void* stream);
 
 /* Static description of a status code. */
 const char* accord_status_str(int status);

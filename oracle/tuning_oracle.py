@@ -24,8 +24,8 @@ in the paper's orientation.
 
 Pins: tests/test_oracle_tuning_pins.py (a hand-worked 2 x 2 epBIC, the refit at
 phi = 0 against its closed form per column, the refit with full support against
-the plain fit, the restricted optimality conditions of eq. 3.8, and T^{-1}(T(Theta))
-= Theta with the partial correlations of Theta itself).
+the plain fit, the restricted optimality conditions of eq. 3.8, the column-subset
+replay, and T^{-1}(T(Theta)) = Theta with the partial correlations of Theta itself).
 """
 from __future__ import annotations
 
@@ -87,7 +87,7 @@ def support(om):
 
 
 def fit_fbs_weighted(x, lam_mat, iters, omega0=None, tau0=1.0, beta=0.5, L=None, tol=0.0,
-                     tau_replay=None):
+                     tau_replay=None, columns=None):
     """Alg. 1 for the objective -sum_j log om_jj + g(Om) + sum_ij lam_ij |om_ij|.
 
     The prox of eq. 3.5 is elementwise, so a per-entry penalty changes only each
@@ -97,31 +97,39 @@ def fit_fbs_weighted(x, lam_mat, iters, omega0=None, tau0=1.0, beta=0.5, L=None,
     with a finite penalty (the others are zero from the first iterate on).
 
     omega0: start (default I); entries with an infinite penalty are set to zero
-    first (the start is projected onto the constraint set).  tau_replay, tol: as in
-    ``fit_fbs``."""
+    first (the start is projected onto the constraint set).  tau_replay, tol and
+    columns: as in ``fit_fbs`` (with the steps fixed, column j depends only on
+    column j of the start, of the penalty and on X)."""
     x = _f64(x)
     n, p = x.shape
     lam_mat = _f64(lam_mat)
-    finite = np.isfinite(lam_mat)
-    if np.any(~finite[np.diag_indices(p)]):
+    if np.any(~np.isfinite(lam_mat[np.diag_indices(p)])):
         raise ValueError("the diagonal needs a finite penalty (it is positive on the domain)")
     if L is None:
         L = lipschitz(x)
     om = np.eye(p) if omega0 is None else _f64(omega0).copy()
+    if columns is not None:
+        if tau_replay is None:
+            raise ValueError("columns= needs tau_replay (the shared step couples columns)")
+        cols = np.asarray(columns)
+        om, lam_mat = om[:, cols].copy(), lam_mat[:, cols]
+    else:
+        cols = np.arange(p)
+    finite = np.isfinite(lam_mat)
     om[~finite] = 0.0
-    jj = np.arange(p)
-    lam_d = lam_mat[jj, jj]
+    jj = np.arange(len(cols))
+    lam_d = lam_mat[cols, jj]
 
     def _prox(o, g, tau):
         a = o - tau * g
         out = soft_threshold(a, tau * lam_mat)
-        out[jj, jj] = diag_root(a[jj, jj], tau, lam_d)
+        out[cols, jj] = diag_root(a[cols, jj], tau, lam_d)
         return out
 
     def _obj(o):
         w = x @ o
         g = float(np.sum(w * w) / (2 * n))
-        d = np.diagonal(o)
+        d = o[cols, jj]
         if np.any(d <= 0):
             return g, np.inf
         pen = float(np.sum(lam_mat[finite] * np.abs(o[finite])))

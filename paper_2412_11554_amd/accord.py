@@ -49,7 +49,8 @@ class accord_stats(ctypes.Structure):
                 ("grad_gemm_ms", ctypes.c_double), ("grad_gemm_launches", ctypes.c_int32),
                 ("trial_gemm_ms", ctypes.c_double), ("trial_gemm_launches", ctypes.c_int32),
                 ("prox_ms", ctypes.c_double), ("prox_launches", ctypes.c_int32),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("log_det_d", ctypes.c_double),
+                ("l1", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -60,7 +61,8 @@ class accord_batch_stats(ctypes.Structure):
                 ("floor_accepts", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("nnz_offdiag", ctypes.c_int64), ("f", ctypes.c_double),
                 ("g", ctypes.c_double), ("h", ctypes.c_double), ("tau_last", ctypes.c_double),
-                ("delta_fro", ctypes.c_double), ("lipschitz", ctypes.c_double)]
+                ("delta_fro", ctypes.c_double), ("lipschitz", ctypes.c_double),
+                ("log_det_d", ctypes.c_double), ("l1", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -113,6 +115,16 @@ def lib() -> ctypes.CDLL:
         L.accord_fbs_adjoint_step.argtypes = [_vp, _i64, _i64, _vp, _d, _d, _vp, _vp, _vp, _vp,
                                               _sz, _vp]
         for f in ("accord_fbs_replay", "accord_val_loss_grad", "accord_fbs_adjoint_step"):
+            getattr(L, f).restype = ctypes.c_int
+        L.accord_epbic.argtypes = [_i64, _i64, _d, _d, _i64, _d, _pd]
+        L.accord_epbic_path.argtypes = [ctypes.POINTER(accord_batch_stats), _pi64, _i64, _i64,
+                                        _i64, _d, _pd, _pi64]
+        L.accord_refit_workspace_bytes.argtypes = [_i64, _i64, ctypes.POINTER(accord_params)]
+        L.accord_refit_workspace_bytes.restype = _sz
+        L.accord_refit.argtypes = [_vp, _i64, _i64, _vp, _d, _vp, ctypes.POINTER(accord_params),
+                                   ctypes.POINTER(accord_stats), _vp, _vp, _sz, _vp]
+        L.accord_reparam.argtypes = [_vp, _i64, _vp, _vp, _vp]
+        for f in ("accord_epbic", "accord_epbic_path", "accord_refit", "accord_reparam"):
             getattr(L, f).restype = ctypes.c_int
         L.accord_status_str.argtypes = [ctypes.c_int]
         L.accord_status_str.restype = ctypes.c_char_p
@@ -345,3 +357,84 @@ def accord_fbs_adjoint_step(X: torch.Tensor, omega_t: torch.Tensor, tau: float, 
                                          float(lam), _dev(obar, "Obar"),
                                          _dev(lbar, "lbar", torch.float64), _dev(xbar, "Xbar"),
                                          ws.data_ptr(), ws.numel(), _stream(X.device)))
+
+
+# ---------------------------------------------------------------------------
+# steps around the solver: epBIC (eq. 3.7), refit (eq. 3.8), reparametrisation
+# ---------------------------------------------------------------------------
+def accord_epbic(n: int, p: int, g: float, log_det_d: float, nnz_offdiag: int,
+                 gamma: float) -> float:
+    """Extended pseudo-BIC of one estimate from its fit statistics."""
+    out = ctypes.c_double()
+    _check(lib().accord_epbic(n, p, g, log_det_d, nnz_offdiag, gamma, ctypes.byref(out)))
+    return out.value
+
+
+def accord_epbic_path(stats, n, nlam: int, p: int, gamma: float):
+    """epBIC of every problem of a batched fit (stats: the list of dicts
+    accord_fit_batch returns) and, per data set, the index of the best penalty.
+    Returns (epbic [nsub, nlam] list of lists, best list)."""
+    n = [int(v) for v in n]
+    nsub = len(n)
+    if len(stats) != nsub * nlam:
+        raise ValueError(f"{len(stats)} stats for {nsub} x {nlam} problems")
+    st = (accord_batch_stats * len(stats))()
+    for k, d in enumerate(stats):
+        for name, _ in accord_batch_stats._fields_:
+            setattr(st[k], name, d[name])
+    na = (ctypes.c_int64 * nsub)(*n)
+    out = (ctypes.c_double * len(stats))()
+    best = (ctypes.c_int64 * nsub)()
+    _check(lib().accord_epbic_path(st, na, nsub, nlam, p, gamma, out, best))
+    return [[out[b * nlam + l] for l in range(nlam)] for b in range(nsub)], list(best)
+
+
+def accord_refit_workspace_bytes(n: int, p: int, params: accord_params | None = None) -> int:
+    return int(lib().accord_refit_workspace_bytes(n, p, ctypes.byref(params) if params else None))
+
+
+def accord_refit(X: torch.Tensor, omega_hat: torch.Tensor, lam: float, phi: float, max_iter: int,
+                 *, omega0: torch.Tensor | None = None, tau0: float = 1.0, beta: float = 0.5,
+                 lipschitz: float = 0.0, tol: float = 0.0, power_iters: int = 0,
+                 trace: bool = False, timing: bool = False, ws=None, omega_out=None):
+    """Refit on the support of omega_hat with penalty phi * lam there (eq. 3.8).
+    Returns (Omega [p, p] paper form, stats dict, trace or None); the start defaults
+    to omega_hat."""
+    n, p = X.shape
+    dev = X.device
+    prm = default_params(lam=lam, max_iter=max_iter, tau0=tau0, beta=beta, lipschitz=lipschitz,
+                         tol=tol, power_iters=power_iters, timing=1 if timing else 0)
+    if omega_out is None:
+        omega_out = torch.empty((p, p), dtype=torch.float32, device=dev)
+    omega_out.copy_(omega_hat if omega0 is None else omega0)
+    tr = torch.zeros(((max_iter + 1) * TRACE_COLS,), dtype=torch.float64, device=dev) if trace else None
+    need = accord_refit_workspace_bytes(n, p, prm)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    st = accord_stats()
+    _check(lib().accord_refit(_dev(X, "X"), n, p, _dev(omega_hat, "Omega_hat"), phi,
+                              _dev(omega_out, "Omega"), ctypes.byref(prm), ctypes.byref(st),
+                              _dev(tr, "trace", torch.float64) if tr is not None else None,
+                              ws.data_ptr(), ws.numel(), _stream(dev)))
+    stats = st.as_dict()
+    if tr is not None:
+        tr = tr.view(max_iter + 1, TRACE_COLS)[: stats["iters"] + 1]
+    return omega_out, stats, tr
+
+
+def accord_reparam(omega: torch.Tensor, *, theta: bool = True, rho: bool = True,
+                   theta_out=None, rho_out=None):
+    """Theta = Omega_D Omega and the partial correlations of an estimate (paper form
+    [p, p] tensors, like Omega).  Returns (Theta or None, Rho or None)."""
+    p = omega.shape[0]
+    dev = omega.device
+    if theta and theta_out is None:
+        theta_out = torch.empty((p, p), dtype=torch.float32, device=dev)
+    if rho and rho_out is None:
+        rho_out = torch.empty((p, p), dtype=torch.float32, device=dev)
+    t = theta_out if theta else None
+    r = rho_out if rho else None
+    _check(lib().accord_reparam(_dev(omega, "Omega"), p,
+                                _dev(t, "Theta") if t is not None else None,
+                                _dev(r, "Rho") if r is not None else None, _stream(dev)))
+    return t, r

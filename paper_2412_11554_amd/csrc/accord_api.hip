@@ -82,6 +82,7 @@ struct Plan {
         off_trials, off_xp, off_xt, off_xsplit[4], off_x8, off_x8s, off_xt8, off_xt8s, off_wt0,
         off_wt1, off_wsplit[4], off_w8, off_w8s, off_split,
         off_om0, end_grad, off_g, off_d, off_om1, end_fit;
+    size_t off_mask, end_refit;  // refit: support bytes in the padded layout of Omega
     size_t end_prox;
 };
 
@@ -166,6 +167,8 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     P.off_d = bump(cur, P.fused ? 0 : on * sizeof(float));  // fused forms never store Delta
     P.off_om1 = bump(cur, on * sizeof(float));
     P.end_fit = cur;
+    P.off_mask = bump(cur, on);
+    P.end_refit = cur;
     return P;
 }
 
@@ -523,17 +526,20 @@ int accord_objective(const float* X, int64_t n, int64_t p, const float* Omega, d
     return ACCORD_OK;
 }
 
-int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_params* prm,
-               accord_stats* stats, double* trace, void* ws, size_t ws_bytes, void* stream) {
-    g_last_error.clear();
+// Alg. 1; with support_src set, the refit of eq. 3.8: penalty phi * lambda on the
+// support of support_src (its nonzero entries and the diagonal), infinite off it.
+static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const accord_params* prm,
+                    accord_stats* stats, double* trace, void* ws, size_t ws_bytes, void* stream,
+                    const float* support_src, double phi) {
     TRY(check_dims(n, p));
     TRY(check_ptr(X, "X"));
     TRY(check_ptr(Omega, "Omega"));
     TRY(check_params(prm));
     if (trace && !aligned(trace, 8)) return fail(ACCORD_ERR_INVALID_ARG, "trace must be 8-byte aligned");
     const Plan P = make_plan(n, p, prm->max_iter, prm->precision);
-    TRY(check_ws(ws, ws_bytes, P.end_fit));
+    TRY(check_ws(ws, ws_bytes, support_src ? P.end_refit : P.end_fit));
     if (stats) memset(stats, 0, sizeof *stats);
+    const double lambda = support_src ? phi * prm->lambda : prm->lambda;
     hipStream_t st = (hipStream_t)stream;
     const bool timing = prm->timing != 0;
     EventPool pool;
@@ -563,10 +569,12 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
     const int64_t total = p * P.p_pad;
 
     // ---- setup: operands, L, W0 = X Omega0, f(Omega0)
-    launch_init_state(ls, prm->tau0, prm->beta, prm->lambda, prm->tol, 1.0 / (double)n,
+    launch_init_state(ls, prm->tau0, prm->beta, lambda, prm->tol, 1.0 / (double)n,
                       prm->lipschitz, prm->max_iter, st);
     launch_pad_x(X, n, p, xp, P.p_pad, xt, P.n_pad, x_split(P, ws), ls, st);
     launch_copy_cols(Omega, p, om[0], P.p_pad, p, P.p_pad, ls, st);
+    uint8_t* mask = support_src ? at<uint8_t>(ws, P.off_mask) : nullptr;
+    if (mask) launch_support_mask(support_src, p, P.p_pad, mask, om[0], st);
     if (f8) {
         XQuant q = {at<uint8_t>(ws, P.off_x8), at<uint8_t>(ws, P.off_x8s),
                     at<uint8_t>(ws, P.off_xt8), at<uint8_t>(ws, P.off_xt8s)};
@@ -639,6 +647,7 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
             a.p = p;
             a.ls = ls;
             a.part = prox_part;
+            a.mask = mask;
             GemmArgs ta = trial_args(P, ws, prec, D, nullptr, nullptr, wt[cur], wt[nxt],
                                      bf ? nxt : -1, ls, 2);
             if (!fused) {
@@ -716,6 +725,8 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
         stats->tau_last = host.tau_acc;
         stats->delta_fro = host.delta_fro;
         stats->lipschitz = host.L;
+        stats->log_det_d = host.logd_cur;
+        stats->l1 = host.l1_cur;
         if (timing) {
             std::vector<int32_t> tl((size_t)(host.iter > 0 ? host.iter : 1), 0);
             if (host.iter > 0)
@@ -746,6 +757,83 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
     }
     if (host.bad & 2) return fail(ACCORD_ERR_NONFINITE, "non-finite value in an iterate");
     if (host.bad & 1) return fail(ACCORD_ERR_DOMAIN, "non-positive diagonal in an iterate");
+    return ACCORD_OK;
+}
+
+int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_params* prm,
+               accord_stats* stats, double* trace, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return fit_impl(X, n, p, Omega, prm, stats, trace, ws, ws_bytes, stream, nullptr, 1.0);
+}
+
+// ---------------------------------------------------------------------------
+// Steps around the solver: refit (eq. 3.8), epBIC (eq. 3.7), reparametrisation
+// ---------------------------------------------------------------------------
+size_t accord_refit_workspace_bytes(int64_t n, int64_t p, const accord_params* prm) {
+    if (n < 1 || p < 1 || n > (1LL << 24) || p > (1LL << 24)) return 0;
+    accord_params d;
+    if (!prm) {
+        accord_default_params(&d);
+        prm = &d;
+    }
+    return make_plan(n, p, prm->max_iter, ACCORD_FP32).end_refit;
+}
+
+int accord_refit(const float* X, int64_t n, int64_t p, const float* Omega_hat, double phi,
+                 float* Omega, const accord_params* prm, accord_stats* stats, double* trace,
+                 void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    TRY(check_ptr(Omega_hat, "Omega_hat"));
+    if (!(phi >= 0.0 && phi <= 1.0)) return fail(ACCORD_ERR_INVALID_ARG, "phi must lie in [0, 1]");
+    if (prm && prm->precision != ACCORD_FP32)
+        return fail(ACCORD_ERR_UNSUPPORTED, "the refit runs in the FP32 form only");
+    return fit_impl(X, n, p, Omega, prm, stats, trace, ws, ws_bytes, stream, Omega_hat, phi);
+}
+
+int accord_epbic(int64_t n, int64_t p, double g, double log_det_d, int64_t nnz_offdiag,
+                 double gamma, double* out) {
+    g_last_error.clear();
+    TRY(check_dims(n, p));
+    if (!out) return fail(ACCORD_ERR_INVALID_ARG, "out is null");
+    if (!(gamma > 0.0 && gamma <= 1.0)) return fail(ACCORD_ERR_INVALID_ARG, "gamma must lie in (0, 1]");
+    if (nnz_offdiag < 0 || nnz_offdiag > p * (p - 1))
+        return fail(ACCORD_ERR_INVALID_ARG, "nnz_offdiag must lie in [0, p(p-1)]");
+    const double k = (double)nnz_offdiag;
+    *out = 2.0 * (double)n * (-log_det_d + g) + k * log((double)n) +
+           4.0 * gamma * k * log((double)p);
+    return ACCORD_OK;
+}
+
+int accord_epbic_path(const accord_batch_stats* stats, const int64_t* n, int64_t nsub,
+                      int64_t nlam, int64_t p, double gamma, double* epbic, int64_t* best) {
+    g_last_error.clear();
+    if (!stats || !n || !epbic) return fail(ACCORD_ERR_INVALID_ARG, "stats, n and epbic must be non-null");
+    if (nsub < 1 || nlam < 1) return fail(ACCORD_ERR_INVALID_ARG, "nsub and nlam must be >= 1");
+    for (int64_t b = 0; b < nsub; ++b) {
+        int64_t arg = 0;
+        for (int64_t l = 0; l < nlam; ++l) {
+            const int64_t k = b * nlam + l;
+            const accord_batch_stats& s = stats[k];
+            TRY(accord_epbic(n[b], p, s.g, s.log_det_d, s.nnz_offdiag, gamma, &epbic[k]));
+            if (epbic[k] < epbic[b * nlam + arg]) arg = l;
+        }
+        if (best) best[b] = arg;
+    }
+    return ACCORD_OK;
+}
+
+int accord_reparam(const float* Omega, int64_t p, float* Theta, float* Rho, void* stream) {
+    g_last_error.clear();
+    TRY(check_dims(1, p));
+    TRY(check_ptr(Omega, "Omega"));
+    if (!Theta && !Rho) return fail(ACCORD_ERR_INVALID_ARG, "Theta and Rho are both null");
+    if (Theta) TRY(check_ptr(Theta, "Theta"));
+    if (Rho) TRY(check_ptr(Rho, "Rho"));
+    if ((const void*)Theta == (const void*)Omega || (const void*)Rho == (const void*)Omega ||
+        (Theta && Theta == Rho))
+        return fail(ACCORD_ERR_INVALID_ARG, "outputs must not alias Omega or each other");
+    launch_reparam(Omega, p, Theta, Rho, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
     return ACCORD_OK;
 }
 
@@ -1095,6 +1183,8 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
             s.tau_last = h.tau_acc;
             s.delta_fro = h.delta_fro;
             s.lipschitz = h.L;
+            s.log_det_d = h.logd_cur;
+            s.l1 = h.l1_cur;
         }
         if (status == ACCORD_OK && (h.bad & 2))
             status = fail(ACCORD_ERR_NONFINITE, "non-finite value in an iterate of problem %lld", (long long)k);

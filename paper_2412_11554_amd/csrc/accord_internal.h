@@ -44,6 +44,7 @@ struct LsState {
     double g_cur, h_cur, f_cur;  // objective pieces at the current iterate
     double delta_fro;            // ||Delta||_F of the last accepted step
     double tau_acc;              // accepted step of the last iteration
+    double logd_cur, l1_cur;     // sum_j log Omega_jj and ||Omega||_1 at the current iterate
     int64_t nnz_off;
     int32_t done;       // current iteration accepted a trial: later trials are skipped
     int32_t converged;  // stop: every later launch is skipped
@@ -134,6 +135,8 @@ struct ProxArgs {
     const LsState* ls;  // if set: tau/lambda from here; skip if done or converged
     double* part;       // [gridDim.x][kPartCols]
     int reduce_only;    // 1: no writes, statistics of om itself
+    const uint8_t* mask;// optional support (same layout, one byte per entry): an
+                        // off-diagonal entry whose byte is 0 takes an infinite penalty
 };
 
 // acceptance-test arguments of one problem of the batched form
@@ -188,6 +191,11 @@ void launch_transpose_w(const float* Wt, int64_t ldt, int64_t n, int64_t p, floa
 void launch_power_iteration(const float* Xp, int64_t p_pad, const float* Xt, int64_t n_pad,
                             int64_t n, int64_t p, double* w, double* u, double* part_u,
                             double* part_w, int steps, LsState* ls, hipStream_t st);
+
+// steps around the solver: support mask of a refit, reparametrisation
+void launch_support_mask(const float* om_hat, int64_t p, int64_t p_pad, uint8_t* mask,
+                         float* om0, hipStream_t st);
+void launch_reparam(const float* om, int64_t p, float* theta, float* rho, hipStream_t st);
 
 // differentiation form
 void launch_prox_adjoint(const AdjArgs& a, int nblocks, hipStream_t st);

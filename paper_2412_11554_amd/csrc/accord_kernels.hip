@@ -795,9 +795,11 @@ __device__ __forceinline__ void prox_run(const ProxArgs& a) {
     int64_t q = q_begin + threadIdx.x;
     int64_t e = q << 2;
     int64_t col = e / a.ld, row = e - col * a.ld;
+    const uint32_t* m4p = (const uint32_t*)a.mask;
     for (; q < q_end; q += kThreads) {
         const f4 o = om4[q];
         const f4 gv = a.reduce_only ? f4{0.f, 0.f, 0.f, 0.f} : g4[q];
+        const uint32_t m4 = m4p ? m4p[q] : 0x01010101u;
         f4 nw, dv;
         uint16_t h[4], l[4];
 #pragma unroll
@@ -809,6 +811,7 @@ __device__ __forceinline__ void prox_run(const ProxArgs& a) {
             }
             const bool diag = (r == c);
             nw[u] = a.reduce_only ? o[u] : prox_one(o[u], gv[u], diag, tau, lam, tau_f, thr_f);
+            if (!diag && ((m4 >> (8 * u)) & 0xffu) == 0u) nw[u] = 0.f;  // off the support
             dv[u] = delta_repr<DOUT>(nw[u] - o[u], h[u], l[u]);
             prox_account(acc, dv[u], gv[u], nw[u], diag, r < a.p, a.reduce_only);
         }
@@ -836,7 +839,8 @@ __device__ __forceinline__ void prox_run(const ProxArgs& a) {
         const float o = a.om[ee];
         const float gv = a.reduce_only ? 0.f : a.g[ee];
         const bool diag = (r == c);
-        const float nw = a.reduce_only ? o : prox_one(o, gv, diag, tau, lam, tau_f, thr_f);
+        float nw = a.reduce_only ? o : prox_one(o, gv, diag, tau, lam, tau_f, thr_f);
+        if (!diag && a.mask && a.mask[ee] == 0) nw = 0.f;
         uint16_t h, l;
         const float dv = delta_repr<DOUT>(nw - o, h, l);
         prox_account(acc, dv, gv, nw, diag, r < a.p, a.reduce_only);
@@ -1804,6 +1808,8 @@ __device__ __forceinline__ void finalize_run(LsState* ls, const double* prox_par
         ls->g_cur = 0.5 * w2 * ls->inv_n;
         ls->h_cur = -logd + ls->lambda * l1;
         ls->f_cur = ls->g_cur + ls->h_cur;
+        ls->logd_cur = logd;
+        ls->l1_cur = l1;
         ls->delta_fro = sqrt(d2);
         ls->nnz_off = (int64_t)pv[P_NNZ];
         if (trials_log) trials_log[it] = ls->trials;
@@ -1856,6 +1862,8 @@ __device__ __forceinline__ void fit_init_run(LsState* ls, const double* prox_par
     ls->g_cur = 0.5 * nv[1] * ls->inv_n;
     ls->h_cur = -pv[P_LOGD] + ls->lambda * pv[P_L1];
     ls->f_cur = ls->g_cur + ls->h_cur;
+    ls->logd_cur = pv[P_LOGD];
+    ls->l1_cur = pv[P_L1];
     ls->nnz_off = (int64_t)pv[P_NNZ];
     if (!isfinite(nv[1]) || !isfinite(pv[P_L1])) ls->bad |= 2;
     if (!isfinite(ls->f_cur)) ls->bad |= 1;
@@ -2145,6 +2153,122 @@ void launch_init_state_batch(LsState* ls, int nprob, int nlam, const double* lam
 
 void launch_share_L_batch(LsState* ls, int nprob, int nlam, hipStream_t st) {
     k_share_L_batch<<<(unsigned)cdiv(nprob, 256), 256, 0, st>>>(ls, nprob, nlam);
+}
+
+// ---------------------------------------------------------------------------
+// Steps around the solver.
+//
+// Support mask of the refit (eq. 3.8): byte (r, c) of the padded p x p_pad layout is
+// 1 where the first-stage estimate is nonzero or r == c (the diagonal is positive on
+// the domain), 0 elsewhere and on the padded rows.  The refit's starting iterate (already
+// copied into the padded layout) is projected onto the support in the same pass.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_support_mask(const float* __restrict__ om_hat,
+                                                           int64_t p, int64_t p_pad,
+                                                           uint8_t* __restrict__ mask,
+                                                           float* __restrict__ om0) {
+    const int64_t n4 = p * p_pad / 4;  // p_pad is a multiple of 4: quads never cross columns
+    for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < n4;
+         q += (int64_t)gridDim.x * kThreads) {
+        const int64_t e = q * 4;
+        const int64_t c = e / p_pad, r0 = e - c * p_pad;
+        f4 o = ((const f4*)om0)[q];
+        uint32_t m4 = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t r = r0 + u;
+            const bool in = r < p && (r == c || om_hat[r + c * p] != 0.f);
+            m4 |= (in ? 1u : 0u) << (8 * u);
+            if (!in) o[u] = 0.f;
+        }
+        ((uint32_t*)mask)[q] = m4;
+        ((f4*)om0)[q] = o;
+    }
+}
+
+void launch_support_mask(const float* om_hat, int64_t p, int64_t p_pad, uint8_t* mask,
+                         float* om0, hipStream_t st) {
+    int64_t b = cdiv(p * p_pad / 4, kThreads);
+    if (b > 16384) b = 16384;
+    k_support_mask<<<(unsigned)b, kThreads, 0, st>>>(om_hat, p, p_pad, mask, om0);
+}
+
+// ---------------------------------------------------------------------------
+// Reparametrisation (Sec. 2): Theta = Omega_D Omega (the inverse of the map T) and the
+// partial correlations rho_ij = -(w_ij / w_jj + w_ji / w_ii) / 2, w in the paper's
+// orientation.  In the column form (Om = Omega^T, column-major) that is
+//     Theta^T(i, j) = Om(j, j) Om(i, j)            (column j scaled by its diagonal)
+//     rho(i, j)     = -(Om(j, i) / Om(j, j) + Om(i, j) / Om(i, i)) / 2,   rho(i, i) = 1.
+// rho needs Om and Om^T, so one workgroup owns a pair of 64 x 64 tiles (I, J), (J, I)
+// with I <= J: both are staged through LDS once (padded rows, no bank conflicts), and
+// all four output tiles are written with columns along the lanes.  Omega is read once
+// and each output written once: HBM-bound.  The ratios use FP64 reciprocals of the
+// diagonal and one rounding to FP32; the Theta product of two FP32 values is exact in
+// FP64, so Theta is correctly rounded.
+// ---------------------------------------------------------------------------
+constexpr int kRT = 64;
+
+__global__ void __launch_bounds__(kThreads) k_reparam(const float* __restrict__ om, int64_t p,
+                                                      float* __restrict__ theta,
+                                                      float* __restrict__ rho) {
+    __shared__ float sa[kRT][kRT + 1];   // sa[c][r] = Om(I0 + r, J0 + c)
+    __shared__ float sb[kRT][kRT + 1];   // sb[c][r] = Om(J0 + r, I0 + c)
+    __shared__ float dI[kRT], dJ[kRT];
+    __shared__ double iI[kRT], iJ[kRT];
+    // pair k = J (J + 1) / 2 + I, 0 <= I <= J
+    const int64_t k = blockIdx.x;
+    int64_t J = (int64_t)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
+    while ((J + 1) * (J + 2) / 2 <= k) ++J;
+    while (J * (J + 1) / 2 > k) --J;
+    const int64_t I = k - J * (J + 1) / 2;
+    const int64_t I0 = I * kRT, J0 = J * kRT;
+    const int r = threadIdx.x & (kRT - 1);
+    const int c4 = threadIdx.x >> 6;   // 0..3
+    const bool rI = I0 + r < p, rJ = J0 + r < p;
+    for (int c = c4; c < kRT; c += kThreads / kRT) {
+        const bool cJ = J0 + c < p, cI = I0 + c < p;
+        sa[c][r] = (rI && cJ) ? om[(I0 + r) + (J0 + c) * p] : 0.f;
+        sb[c][r] = (rJ && cI) ? om[(J0 + r) + (I0 + c) * p] : 0.f;
+    }
+    if (threadIdx.x < kRT) {
+        const float di = rI ? om[(I0 + r) * (p + 1)] : 1.f;
+        const float dj = rJ ? om[(J0 + r) * (p + 1)] : 1.f;
+        dI[r] = di;
+        dJ[r] = dj;
+        iI[r] = 1.0 / (double)di;
+        iJ[r] = 1.0 / (double)dj;
+    }
+    __syncthreads();
+    // tile (I, J): row I0 + r, column J0 + c
+    if (rI) {
+        for (int c = c4; c < kRT; c += kThreads / kRT) {
+            if (J0 + c >= p) break;
+            const int64_t o = (I0 + r) + (J0 + c) * p;
+            if (theta) theta[o] = (float)((double)dJ[c] * (double)sa[c][r]);
+            if (rho) {
+                const double v = -0.5 * ((double)sb[r][c] * iJ[c] + (double)sa[c][r] * iI[r]);
+                rho[o] = (I0 + r == J0 + c) ? 1.f : (float)v;
+            }
+        }
+    }
+    if (I == J) return;
+    // tile (J, I): row J0 + r, column I0 + c
+    if (rJ) {
+        for (int c = c4; c < kRT; c += kThreads / kRT) {
+            if (I0 + c >= p) break;
+            const int64_t o = (J0 + r) + (I0 + c) * p;
+            if (theta) theta[o] = (float)((double)dI[c] * (double)sb[c][r]);
+            if (rho) {
+                const double v = -0.5 * ((double)sb[c][r] * iJ[r] + (double)sa[r][c] * iI[c]);
+                rho[o] = (float)v;
+            }
+        }
+    }
+}
+
+void launch_reparam(const float* om, int64_t p, float* theta, float* rho, hipStream_t st) {
+    const int64_t nt = cdiv(p, kRT);
+    k_reparam<<<(unsigned)(nt * (nt + 1) / 2), kThreads, 0, st>>>(om, p, theta, rho);
 }
 
 }  // namespace accord

@@ -38,7 +38,9 @@ def test_struct_layout_matches_header(tmp_path):
         "int main(void){printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(accord_params), sizeof(accord_stats),"
         " offsetof(accord_stats, grad_gemm_ms), offsetof(accord_stats, total_ms),"
         " offsetof(accord_params, timing)); printf(\"%zu %zu\\n\", sizeof(accord_batch_stats),"
-        " offsetof(accord_batch_stats, lipschitz)); return 0;}\n")
+        " offsetof(accord_batch_stats, lipschitz)); printf(\"%zu %zu\\n\","
+        " offsetof(accord_stats, log_det_d), offsetof(accord_batch_stats, log_det_d));"
+        " return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
@@ -50,6 +52,8 @@ def test_struct_layout_matches_header(tmp_path):
     assert vals[4] == accord.accord_params.timing.offset
     assert vals[5] == ctypes.sizeof(accord.accord_batch_stats)
     assert vals[6] == accord.accord_batch_stats.lipschitz.offset
+    assert vals[7] == accord.accord_stats.log_det_d.offset
+    assert vals[8] == accord.accord_batch_stats.log_det_d.offset
 
 
 def test_default_params(L):
@@ -180,3 +184,78 @@ def test_differentiation_validation(L):
     assert L.accord_fbs_adjoint_step(FAKE, 10, 5, FAKE, 0.5, 0.1, FAKE, FAKE, FAKE, FAKE, 64,
                                      None) == 4
     assert L.accord_last_error()
+
+
+# ---- steps around the solver ---------------------------------------------------
+def test_refit_validation(L):
+    prm = accord.default_params(lam=0.1, max_iter=3)
+    st = accord.accord_stats()
+    need = accord.accord_refit_workspace_bytes(10, 12, prm)
+    assert need > accord.accord_workspace_bytes(10, 12, prm) > 0
+    assert accord.accord_refit_workspace_bytes(0, 12, prm) == 0
+
+    def call(X=FAKE, om_hat=FAKE, phi=0.5, prm=prm, ws_bytes=1 << 40):
+        return L.accord_refit(X, 10, 12, om_hat, phi, FAKE, ctypes.byref(prm), ctypes.byref(st),
+                              None, FAKE, ws_bytes, None)
+    assert call(om_hat=None) == 1
+    assert call(om_hat=FAKE + 4) == 1
+    assert call(phi=-0.1) == 1 and call(phi=1.5) == 1 and call(phi=float("nan")) == 1
+    assert call(X=None) == 1
+    assert call(prm=accord.default_params(lam=0.1, precision="bf16x3")) == 5
+    assert call(ws_bytes=accord.accord_workspace_bytes(10, 12, prm)) == 4  # fit size: too small
+    assert L.accord_last_error()
+
+
+def test_epbic_matches_oracle(L):
+    """The library's epBIC from (g, log det, nnz) equals the oracle's eq. 3.7 value."""
+    import numpy as np
+    import datagen
+    import oracle
+    from oracle import tuning_oracle as tu
+    x = datagen.small_random_problem(50, 15, 3).X.astype(np.float64)
+    for lam in (0.05, 0.2):
+        om = oracle.fit_fbs(x, lam, 300).omega
+        g = oracle.smooth(x, om)
+        logd = float(np.sum(np.log(np.diagonal(om))))
+        for gamma in (0.5, 1.0):
+            v = accord.accord_epbic(50, 15, g, logd, tu.nnz_offdiag(om), gamma)
+            assert v == pytest.approx(tu.epbic(x, om, gamma), rel=1e-13)
+    out = ctypes.c_double()
+    assert L.accord_epbic(50, 15, 1.0, 0.0, 3, 0.0, ctypes.byref(out)) == 1   # gamma in (0, 1]
+    assert L.accord_epbic(50, 15, 1.0, 0.0, 3, 1.5, ctypes.byref(out)) == 1
+    assert L.accord_epbic(50, 15, 1.0, 0.0, 15 * 14 + 1, 0.5, ctypes.byref(out)) == 1
+    assert L.accord_epbic(0, 15, 1.0, 0.0, 3, 0.5, ctypes.byref(out)) == 1
+    assert L.accord_epbic(50, 15, 1.0, 0.0, 3, 0.5, None) == 1
+
+
+def test_epbic_path_matches_oracle(L):
+    import numpy as np
+    import datagen
+    import oracle
+    from oracle import tuning_oracle as tu
+    lams = [0.02, 0.08, 0.2, 0.5]
+    xs = [datagen.small_random_problem(n, 12, 10 + n).X.astype(np.float64) for n in (30, 70)]
+    stats, want, best = [], [], []
+    for x in xs:
+        oms = [oracle.fit_fbs(x, l, 300).omega for l in lams]
+        v, b = tu.epbic_path(x, oms, 0.5)
+        want.append(list(v))
+        best.append(b)
+        for om in oms:
+            d = {name: 0 for name, _ in accord.accord_batch_stats._fields_}
+            d.update(g=oracle.smooth(x, om), log_det_d=float(np.sum(np.log(np.diagonal(om)))),
+                     nnz_offdiag=tu.nnz_offdiag(om))
+            stats.append(d)
+    got, gbest = accord.accord_epbic_path(stats, [30, 70], len(lams), 12, 0.5)
+    assert gbest == best
+    assert np.allclose(got, want, rtol=1e-13)
+
+
+def test_reparam_validation(L):
+    assert L.accord_reparam(FAKE, 10, None, None, None) == 1
+    assert L.accord_reparam(FAKE, 10, FAKE, None, None) == 1        # Theta aliases Omega
+    assert L.accord_reparam(FAKE, 10, None, FAKE, None) == 1        # Rho aliases Omega
+    assert L.accord_reparam(FAKE, 10, FAKE + 256, FAKE + 256, None) == 1
+    assert L.accord_reparam(FAKE, 0, FAKE + 256, None, None) == 1
+    assert L.accord_reparam(FAKE, 10, FAKE + 4, None, None) == 1    # misaligned
+    assert L.accord_reparam(None, 10, FAKE + 256, None, None) == 1

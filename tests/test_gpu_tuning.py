@@ -1,0 +1,211 @@
+"""GPU parity of the steps around the solver: the refit on an estimated support
+(eq. 3.8), epBIC over a batched lambda path (eq. 3.7) and the reparametrisation
+(Sec. 2), against the FP64 oracle.
+
+Bars.  The refit is Alg. 1 in the FP32 form with a support mask, so it takes the FP32
+fit's bar: relative Frobenius error <= 1e-4 against the oracle replaying its steps;
+entries off the support are exactly zero.  The first-stage estimate that defines the
+support is the oracle's own fit rounded to FP32 (or a synthetic matrix on the true
+graph), never a device result.  Theta is a product of two FP32 values, exact in FP64,
+so the device's correctly rounded Theta equals the oracle's rounded to FP32 bit for
+bit; rho differs from the oracle's FP64 value rounded to FP32 by at most one unit in
+the last place (FP64 reciprocals instead of divisions, one final rounding).  epBIC
+sums 2n times the loss, whose FP32 iterate carries the fit's 1e-4-level error, plus
+exact integer terms; the bar is written in the test.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from oracle import tuning_oracle as tu
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _col_form(t):
+    """Device tensor (paper form) -> column-form float64 numpy matrix."""
+    return t.cpu().numpy().astype(np.float64).T
+
+
+@pytest.mark.parametrize("n,p,phi,iters", [(60, 150, 0.0, 80), (60, 150, 0.5, 80),
+                                           (90, 200, 1.0, 60), (40, 64, 0.5, 40),
+                                           (33, 97, 0.25, 50)])
+def test_refit_small_vs_oracle(gpu_lib, n, p, phi, iters):
+    w = datagen.small_random_problem(n, p, seed=p + int(10 * phi))
+    x = w.X.astype(np.float64)
+    lam = 0.15
+    hat = oracle.fit_fbs(x, lam, 150).omega.astype(np.float32)   # first stage (oracle)
+    L = oracle.lipschitz(x)
+    om, st, tr = gpu_lib.accord_refit(_dev(w.X), _dev(hat.T), lam, phi, iters, lipschitz=L,
+                                      trace=True)
+    taus = tr[1:, 3].cpu().numpy()
+    assert st["iters"] == iters and len(taus) == iters
+    ref = tu.refit(x, hat.astype(np.float64), lam, phi, iters, L=L, tau_replay=taus)
+    got = _col_form(om)
+    rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
+    sup = tu.support(hat)
+    print(f"refit n={n} p={p} phi={phi}: rel {rel:.2e}, support {int(sup.sum()) - p} "
+          f"off-diagonal, result nnz {st['nnz_offdiag']}", flush=True)
+    assert rel <= 1e-4
+    assert np.all(got[~sup] == 0.0)
+    assert st["nnz_offdiag"] == tu.nnz_offdiag(got)
+    assert st["log_det_d"] == pytest.approx(np.sum(np.log(np.diagonal(ref.omega))), rel=1e-5,
+                                            abs=1e-4)
+    assert st["l1"] == pytest.approx(np.sum(np.abs(ref.omega)), rel=1e-4)
+    assert st["f"] == pytest.approx(ref.f[-1], rel=1e-5)
+    # every accepted step is one of tau0 beta^k and no smaller than the floor rule allows
+    assert np.all(taus >= 0.5 / L * (1 - 1e-12))
+
+
+def test_refit_converges_to_restricted_optimum(gpu_lib):
+    """With a tolerance the refit stops at the optimum of eq. 3.8 on the support: the
+    oracle's restricted optimality conditions hold at the device result to FP32 level."""
+    w = datagen.small_random_problem(80, 120, seed=3)
+    x = w.X.astype(np.float64)
+    lam, phi = 0.2, 0.5
+    hat = oracle.fit_fbs(x, lam, 400, tol=1e-10).omega.astype(np.float32)
+    om, st, _ = gpu_lib.accord_refit(_dev(w.X), _dev(hat.T), lam, phi, 3000, tol=1e-7)
+    assert st["converged"] == 1
+    ref = tu.refit(x, hat.astype(np.float64), lam, phi, 20000, tol=1e-13)
+    got = _col_form(om)
+    assert np.linalg.norm(got - ref.omega) <= 1e-4 * np.linalg.norm(ref.omega)
+    assert np.all(got[~tu.support(hat)] == 0.0)
+
+
+def test_refit_full_size_sampled(gpu_lib):
+    """n = 500, p = 5000 power-law data, a synthetic first-stage estimate on the true
+    graph (block-diagonal support), phi = 0.5, 200 iterations, L by power iteration:
+    sampled columns against the oracle replaying the steps; the support holds
+    everywhere."""
+    d = datagen.refit_workload()
+    x32, hat = d["x"], d["omega_hat"]
+    om, st, tr = gpu_lib.accord_refit(_dev(x32), _dev(hat.T), d["lam"], d["phi"], d["iters"],
+                                      trace=True)
+    taus = tr[1:, 3].cpu().numpy()
+    got_all = om.cpu().numpy().T          # column form, float32
+    sup = tu.support(hat)
+    assert np.all(got_all[~sup] == 0.0)
+    cols = np.array([0, 1, 499, 2500, 4998, 4999])
+    ref = tu.refit(x32.astype(np.float64), hat.astype(np.float64), d["lam"], d["phi"], len(taus),
+                   L=st["lipschitz"], tau_replay=taus, columns=cols)
+    got = got_all[:, cols].astype(np.float64)
+    rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
+    print(f"refit p={d['p']}: {st['iters']} iterations, {st['trials']} trials, "
+          f"rel {rel:.2e}", flush=True)
+    assert rel <= 1e-4
+
+
+def test_refit_errors(gpu_lib):
+    from paper_2412_11554_amd import accord
+    w = datagen.small_random_problem(30, 40, seed=1)
+    hat = np.eye(40, dtype=np.float32)
+    hat[3, 3] = -1.0
+    with pytest.raises(accord.AccordError) as e:
+        gpu_lib.accord_refit(_dev(w.X), _dev(hat), 0.1, 0.5, 5)
+    assert e.value.status == 2
+    with pytest.raises(accord.AccordError) as e:
+        gpu_lib.accord_refit(_dev(w.X), _dev(np.eye(40, dtype=np.float32)), 0.1, 1.5, 5)
+    assert e.value.status == 1
+
+
+# ---------------------------------------------------------------- reparametrisation
+def _random_estimate(p, seed, density=0.1):
+    rng = np.random.default_rng(seed)
+    om = np.where(rng.random((p, p)) < density, rng.normal(0, 0.3, (p, p)), 0.0)
+    np.fill_diagonal(om, rng.uniform(0.5, 2.0, p))
+    return om.astype(np.float32)        # column form
+
+
+def _check_reparam(gpu_lib, om32):
+    theta, rho = gpu_lib.accord_reparam(_dev(om32.T))
+    th_dev = theta.cpu().numpy().T        # column form (Theta^T in the paper's orientation)
+    rho_dev = rho.cpu().numpy()
+    om = om32.astype(np.float64)
+    th_ref = tu.theta_hat(om).astype(np.float32)
+    rho_ref64 = tu.partial_correlations(om)
+    assert np.array_equal(th_dev, th_ref)
+    P = om.T
+    d = np.diagonal(P)
+    slack = 1e-15 * (np.abs(P / d[None, :]) + np.abs(P.T / d[:, None]))
+    err = np.abs(rho_dev.astype(np.float64) - rho_ref64.astype(np.float32).astype(np.float64))
+    ulp = np.spacing(np.abs(rho_ref64.astype(np.float32))).astype(np.float64)
+    assert np.all(err <= ulp + slack)
+    assert np.array_equal(rho_dev, rho_dev.T)
+    assert np.all(np.diagonal(rho_dev) == 1.0)
+
+
+@pytest.mark.parametrize("p", [1, 2, 63, 64, 65, 130, 333])
+def test_reparam_small_vs_oracle(gpu_lib, p):
+    _check_reparam(gpu_lib, _random_estimate(p, p))
+
+
+def test_reparam_single_output(gpu_lib):
+    om = _random_estimate(70, 5)
+    t, r = gpu_lib.accord_reparam(_dev(om.T), rho=False)
+    assert r is None
+    assert np.array_equal(t.cpu().numpy().T, tu.theta_hat(om.astype(np.float64)).astype(np.float32))
+    t, r = gpu_lib.accord_reparam(_dev(om.T), theta=False)
+    assert t is None and np.all(np.diagonal(r.cpu().numpy()) == 1.0)
+
+
+def test_reparam_full_size(gpu_lib):
+    """p = 5000 (the n = 500, p = 5000 workload's estimate size), every entry."""
+    print("reparam p=5000", flush=True)
+    _check_reparam(gpu_lib, _random_estimate(5000, 11, density=0.01))
+
+
+# ---------------------------------------------------------------- epBIC over a path
+def _near_kink(x, lam, taus, L):
+    """Off-diagonal entries of the last step whose |a| lies within 1e-4 max|a| of the
+    threshold tau lambda (from the oracle side): the only ones whose zero / nonzero
+    state an FP32 iterate can change."""
+    prev = oracle.fit_fbs(x, lam, len(taus) - 1, L=L, tau_replay=taus[:-1]).omega
+    a = prev - taus[-1] * (x.T @ (x @ prev) / x.shape[0])
+    off = ~np.eye(a.shape[0], dtype=bool)
+    return int(np.sum(off & (np.abs(np.abs(a) - taus[-1] * lam) <= 1e-4 * np.abs(a).max())))
+
+
+def test_epbic_path_from_batched_fit(gpu_lib):
+    """3 data sets x 6 penalties at p = 200: the epBIC of each batched result against
+    the oracle's eq. 3.7 at the oracle's replay of that problem's steps."""
+    import torch
+    w = datagen.batch_workload(p=200, nsub=3, nlam=6, n_base=150, lo=60, hi=140, prob=0.02,
+                               lam_lo=0.05, lam_hi=0.6, iters=60, key=41)
+    Ls = [oracle.lipschitz(x.astype(np.float64)) for x in w.xs]
+    X = torch.from_numpy(w.stacked()).cuda()
+    om, stats, tr = gpu_lib.accord_fit_batch(X, w.n, w.lams, w.iters, trials=True, lipschitz=Ls)
+    torch.cuda.synchronize()
+    tr = tr.cpu().numpy()
+    nlam = len(w.lams)
+    gamma = 0.5
+    vals, best = gpu_lib.accord_epbic_path(stats, w.n, nlam, w.p, gamma)
+    for b in range(len(w.xs)):
+        x = w.xs[b].astype(np.float64)
+        refs = []
+        for l in range(nlam):
+            k = b * nlam + l
+            taus = 0.5 ** (tr[k, :stats[k]["iters"]].astype(np.float64) - 1)
+            ref = oracle.fit_fbs(x, w.lams[l], len(taus), L=Ls[b], tau_replay=taus).omega
+            refs.append(ref)
+            flips = abs(stats[k]["nnz_offdiag"] - tu.nnz_offdiag(ref))
+            near = _near_kink(x, w.lams[l], taus, Ls[b])
+            assert flips <= near, (b, l, flips, near)
+            want = tu.epbic(x, ref, gamma)
+            # the loss part carries the FP32 iterate's error (<= 1e-4 relative in Omega);
+            # each entry that lands on the other side of the threshold moves the
+            # complexity term by log n + 4 gamma log p
+            bar = (2 * w.n[b] * 1e-5 * (abs(tu.loss_part(x, ref)) + 1.0)
+                   + flips * (np.log(w.n[b]) + 4 * gamma * np.log(w.p)))
+            assert abs(vals[b][l] - want) <= bar, (b, l, vals[b][l], want)
+        ref_vals, ref_best = tu.epbic_path(x, refs, gamma)
+        print(f"data set {b} (n={w.n[b]}): epBIC {np.round(vals[b], 2)}, best {best[b]}",
+              flush=True)
+        gap = np.sort(ref_vals)[1] - np.sort(ref_vals)[0]
+        if gap > 1e-3 * abs(ref_vals).max():
+            assert best[b] == ref_best

@@ -236,3 +236,14 @@ def test_mutation_unmasked_refit_breaks_t2(monkeypatch):
                         lambda om_hat, lam, phi: np.full(np.shape(om_hat), phi * lam))
     with pytest.raises(AssertionError):
         test_t2_refit_phi0_closed_form(40, 8, 0.3, 1)
+
+
+def test_t8_refit_column_subset_replay():
+    """With the steps fixed, a column subset of the refit reproduces those columns of
+    the full run (the objective separates over columns)."""
+    x = _x(45, 30, 9)
+    om_hat = _random_support(30, 0.2, 9)
+    full = tu.refit(x, om_hat, 0.1, 0.5, iters=40)
+    cols = [0, 7, 29]
+    sub = tu.refit(x, om_hat, 0.1, 0.5, iters=40, tau_replay=full.tau, columns=cols)
+    assert np.allclose(sub.omega, full.omega[:, cols], rtol=1e-12, atol=1e-14)
