@@ -164,14 +164,14 @@ def kernel_report(stats, form, n, p, workload_ok_for_traffic):
     return out
 
 
-def run_form(form, X, w, iters, ws, om, steps, warmup, check):
+def run_form(form, X, w, iters, ws, om, steps, warmup, check, warm_tau=False):
     import torch
 
     from paper_2412_11554_amd import accord
 
     def step(timing: bool):
         return accord.accord_fit(X, w.lam, iters, ws=ws, omega_out=om, timing=timing,
-                                 trace=True, precision=form)
+                                 trace=True, precision=form, warm_tau=warm_tau)
 
     for _ in range(warmup):
         step(False)
@@ -250,18 +250,23 @@ def time_to_error(X, w, ws, om, est, tol=1e-6, first_iters=150):
     if ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=X.device)
     bufs = (om, torch.empty_like(om))
-    plans = {"fp32": [("fp32", 5000, tol)], "bf16x3": [("bf16x3", 5000, tol)],
-             "bf16x1>bf16x3": [("bf16x1", first_iters, 0.0), ("bf16x3", 5000, tol)],
-             "fp8>bf16x3": [("fp8", first_iters, 0.0), ("bf16x3", 5000, tol)]}
+    plans = {"fp32": [("fp32", 5000, tol, False)], "bf16x3": [("bf16x3", 5000, tol, False)],
+             "bf16x1>bf16x3": [("bf16x1", first_iters, 0.0, False), ("bf16x3", 5000, tol, False)],
+             "fp8>bf16x3": [("fp8", first_iters, 0.0, False), ("bf16x3", 5000, tol, False)],
+             # the warm-started step variant (departs from Alg. 1; same fixed point)
+             "bf16x3 warm-tau": [("bf16x3", 5000, tol, True)],
+             "bf16x1>bf16x3 warm-tau": [("bf16x1", first_iters, 0.0, True),
+                                        ("bf16x3", 5000, tol, True)]}
     out = {}
     for name, phases in plans.items():
         for rep in range(2):  # the first run warms up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             cur, iters = None, []
-            for k, (form, it, t) in enumerate(phases):
+            for k, (form, it, t, warm) in enumerate(phases):
                 cur, st, _ = accord.accord_fit(X, w.lam, it, omega0=cur, tol=t, precision=form,
-                                               lipschitz=L, ws=ws, omega_out=bufs[k])
+                                               lipschitz=L, ws=ws, omega_out=bufs[k],
+                                               warm_tau=warm)
                 iters.append(st["iters"])
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
@@ -599,6 +604,10 @@ def main():
     results = {}
     for f in forms:
         results[f] = run_form(f, X, w, iters, ws, om, args.steps, args.warmup, not args.no_check)
+    # the headline form with the warm-started step variant (not Alg. 1: reported beside it)
+    variant = run_form(forms[0], X, w, iters, ws, om, args.steps, args.warmup, not args.no_check,
+                       warm_tau=True)
+    variant.pop("_sampled_cols", None)
 
     head = results[forms[0]]
     ks = head["kernels"]
@@ -642,6 +651,7 @@ def main():
         "xtw_tflops": ks.get("grad_gemm", {}).get("achieved"),
         "roofline": roofline,
         "forms": results,
+        "variants": {f"{forms[0]} warm-tau": variant},
         "cpu_baseline": cpu,
         "time_to_error": tte,
     }

@@ -112,7 +112,14 @@ typedef struct {
                            device's stop flag after every trial, so it is not used */
     int32_t power_iters;/* power-iteration steps when lipschitz == 0 (0 = 400) */
     int32_t timing;     /* 1 = time every kernel launch with HIP events (fills the *_ms fields) */
-    int32_t reserved[3];
+    int32_t warm_tau;   /* 0 = every iteration's first trial is tau0 (Alg. 1).  1 = a variant
+                           that departs from Alg. 1: after the first iteration, the first
+                           trial is min(tau0, tau_{t-1} / beta) (one step above the last
+                           accepted one).  The acceptance test and the step floor are
+                           unchanged, so every accepted step still satisfies Alg. 1's
+                           inequality (or tau <= 1/L); the iterates differ, the fixed point
+                           does not.  Fewer trials per iteration. */
+    int32_t reserved[2];
 } accord_params;
 
 /* Results of accord_fit (host memory, filled on return). */
@@ -202,8 +209,9 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
  *   stats: host accord_batch_stats[nsub*nlam] or NULL.
  *   trials: device int32[nsub*nlam*max_iter] or NULL: the trials each iteration
  *           used (the accepted step of iteration t of problem k is
- *           tau0 * beta^(trials[k*max_iter + t] - 1)); entries past a problem's
- *           last iteration are left unspecified.
+ *           tau0 * beta^(trials[k*max_iter + t] - 1); with prm->warm_tau it is
+ *           s_t * beta^(trials - 1), s_0 = tau0, s_t = min(tau0, tau_{t-1} / beta));
+ *           entries past a problem's last iteration are left unspecified.
  * ws: device, 256-byte aligned, at least accord_batch_workspace_bytes() bytes.
  * Synchronous.  Errors as accord_fit; the first failing problem is named in
  * accord_last_error(). */

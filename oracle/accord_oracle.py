@@ -155,7 +155,7 @@ class FitResult:
 
 
 def fit_fbs(x, lam, iters, omega0=None, tau0=1.0, beta=0.5, L=None, tol=0.0,
-            tau_replay=None, columns=None):
+            tau_replay=None, columns=None, warm_tau=False):
     """ACCORD-FBS (Alg. 1) in float64.
 
     For t = 0, 1, ...: compute G = grad g(Om_t) once (it does not depend on tau);
@@ -171,6 +171,9 @@ def fit_fbs(x, lam, iters, omega0=None, tau0=1.0, beta=0.5, L=None, tol=0.0,
       Om and on X (the objective separates over columns; supplement, proof of
       Theorem 3.2), so this reproduces those columns of the full run.
     tol > 0: stop once ||Delta||_F <= tol * max(1, ||Om+||_F).
+    warm_tau: a variant that departs from Alg. 1 (which restarts every iteration at
+      tau0): after the first iteration the trials start at min(tau0, tau_{t-1} / beta).
+      The acceptance test and the floor are unchanged.
     """
     x = _f64(x)
     n, p = x.shape
@@ -209,7 +212,12 @@ def fit_fbs(x, lam, iters, omega0=None, tau0=1.0, beta=0.5, L=None, tol=0.0,
     res.f.append(f_cur)
     for t in range(iters):
         G = x.T @ (x @ om) / n
-        tau = tau0 if tau_replay is None else float(tau_replay[t])
+        if tau_replay is not None:
+            tau = float(tau_replay[t])
+        elif warm_tau and t > 0:
+            tau = min(tau0, res.tau[-1] / beta)
+        else:
+            tau = tau0
         k = 0
         while True:
             k += 1

@@ -331,6 +331,8 @@ int check_params(const accord_params* prm) {
     if (prm->tol > 0.0 && prm->check_every < 1)
         return fail(ACCORD_ERR_INVALID_ARG, "check_every must be >= 1 when tol > 0");
     if (prm->power_iters < 0) return fail(ACCORD_ERR_INVALID_ARG, "power_iters must be >= 0");
+    if (prm->warm_tau != 0 && prm->warm_tau != 1)
+        return fail(ACCORD_ERR_INVALID_ARG, "warm_tau must be 0 or 1");
     return ACCORD_OK;
 }
 
@@ -570,7 +572,7 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
 
     // ---- setup: operands, L, W0 = X Omega0, f(Omega0)
     launch_init_state(ls, prm->tau0, prm->beta, lambda, prm->tol, 1.0 / (double)n,
-                      prm->lipschitz, prm->max_iter, st);
+                      prm->lipschitz, prm->max_iter, st, prm->warm_tau);
     launch_pad_x(X, n, p, xp, P.p_pad, xt, P.n_pad, x_split(P, ws), ls, st);
     launch_copy_cols(Omega, p, om[0], P.p_pad, p, P.p_pad, ls, st);
     uint8_t* mask = support_src ? at<uint8_t>(ws, P.off_mask) : nullptr;
@@ -1103,7 +1105,7 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
     // ---- setup: state, operands, L, W0 = X_b Omega0, f(Omega0)
     launch_init_state_batch(ls, (int)np, (int)nlam, at<double>(ws, B.off_lam),
                             at<double>(ws, B.off_inv_n), at<double>(ws, B.off_L), prm->tau0,
-                            prm->beta, prm->tol, prm->max_iter, st);
+                            prm->beta, prm->tol, prm->max_iter, st, prm->warm_tau);
     // padding columns of every problem's Omega and Delta must read as zero
     HIP_TRY(hipMemsetAsync(om[0], 0, (size_t)(np * mat) * sizeof(float), st));
     HIP_TRY(hipMemsetAsync(om[1], 0, (size_t)(np * mat) * sizeof(float), st));

@@ -55,7 +55,7 @@ struct LsState {
     int32_t bad;        // bit 0: diagonal <= 0, bit 1: non-finite value
     int32_t max_iter;
     int32_t fixed_step; // beta == 1: the single trial is accepted
-    int32_t pad_;
+    int32_t warm_tau;   // 1: an iteration starts from min(tau0, tau_acc / beta), not tau0
 };
 
 // Pinned host mailbox: after every executed acceptance test the device posts the
@@ -164,7 +164,7 @@ struct AdjArgs {
 // launchers (accord_kernels.hip)
 // ---------------------------------------------------------------------------
 void launch_init_state(LsState* ls, double tau0, double beta, double lambda, double tol,
-                       double inv_n, double L, int max_iter, hipStream_t st);
+                       double inv_n, double L, int max_iter, hipStream_t st, int warm_tau = 0);
 void launch_pad_x(const float* X, int64_t n, int64_t p, float* Xp, int64_t p_pad, float* Xt,
                   int64_t n_pad, XSplit sp, LsState* ls, hipStream_t st);
 void launch_copy_cols(const float* src, int64_t ld_src, float* dst, int64_t ld_dst, int64_t p,
@@ -215,7 +215,7 @@ void launch_finalize_batch(const FinArgs* batch, int nprob, hipStream_t st);
 void launch_fit_init_batch(const FinArgs* batch, int nprob, hipStream_t st);
 void launch_init_state_batch(LsState* ls, int nprob, int nlam, const double* lam,
                              const double* inv_n, const double* L, double tau0, double beta,
-                             double tol, int max_iter, hipStream_t st);
+                             double tol, int max_iter, hipStream_t st, int warm_tau = 0);
 void launch_share_L_batch(LsState* ls, int nprob, int nlam, hipStream_t st);
 
 }  // namespace accord

@@ -89,7 +89,7 @@ __device__ inline void split_bf16(float x, uint16_t& h, uint16_t& l) {
 // state
 // ---------------------------------------------------------------------------
 __global__ void k_init_state(LsState* ls, double tau0, double beta, double lambda, double tol,
-                             double inv_n, double L, int max_iter) {
+                             double inv_n, double L, int max_iter, int warm_tau) {
     if (threadIdx.x != 0) return;
     LsState s = {};
     s.tau = tau0;
@@ -102,12 +102,13 @@ __global__ void k_init_state(LsState* ls, double tau0, double beta, double lambd
     s.inv_L = L > 0 ? 1.0 / L : 0.0;
     s.max_iter = max_iter;
     s.fixed_step = beta >= 1.0;
+    s.warm_tau = warm_tau;
     *ls = s;
 }
 
 void launch_init_state(LsState* ls, double tau0, double beta, double lambda, double tol,
-                       double inv_n, double L, int max_iter, hipStream_t st) {
-    k_init_state<<<1, 64, 0, st>>>(ls, tau0, beta, lambda, tol, inv_n, L, max_iter);
+                       double inv_n, double L, int max_iter, hipStream_t st, int warm_tau) {
+    k_init_state<<<1, 64, 0, st>>>(ls, tau0, beta, lambda, tol, inv_n, L, max_iter, warm_tau);
 }
 
 // ---------------------------------------------------------------------------
@@ -267,6 +268,16 @@ __device__ inline void decode_tile(const GemmArgs& g, int& tile_m, int& tile_n, 
     }
 }
 
+// First trial step of an iteration: tau0 (Alg. 1), or with the warm-start variant
+// min(tau0, tau_{t-1} / beta) once an iteration has been accepted.
+__device__ inline double start_tau(const LsState& s) {
+    if (s.warm_tau && s.iter > 0) {
+        const double t = s.tau_acc / s.beta;
+        return t < s.tau0 ? t : s.tau0;
+    }
+    return s.tau0;
+}
+
 // Predication and iteration start; returns true if the launch has nothing to do.
 __device__ inline bool gemm_skip(const GemmArgs& g) {
     if (g.ls) {
@@ -277,7 +288,7 @@ __device__ inline bool gemm_skip(const GemmArgs& g) {
         // a new iteration starts from tau0 (Alg. 1); nothing else reads these now
         g.ls->done = 0;
         g.ls->trials = 0;
-        g.ls->tau = g.ls->tau0;
+        g.ls->tau = start_tau(*g.ls);
     }
     return false;
 }
@@ -2065,7 +2076,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32_batch(const GemmArgs* 
         // a new iteration of this problem starts from tau0 (Alg. 1)
         ls->done = 0;
         ls->trials = 0;
-        ls->tau = ls->tau0;
+        ls->tau = start_tau(*ls);
     }
     double* nrm = g.norm_part +
                   ((int64_t)prob * g.tilesM * tpp + tile_m + (int64_t)(tile_n - prob * tpp) * g.tilesM) *
@@ -2094,7 +2105,7 @@ __global__ void __launch_bounds__(kThreads) k_fit_init_batch(const FinArgs* __re
 // (0 = taken later from the power iteration of group b).
 __global__ void k_init_state_batch(LsState* ls, int nprob, int nlam, const double* lam,
                                    const double* inv_n, const double* L, double tau0,
-                                   double beta, double tol, int max_iter) {
+                                   double beta, double tol, int max_iter, int warm_tau) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nprob) return;
     const int b = k / nlam;
@@ -2109,6 +2120,7 @@ __global__ void k_init_state_batch(LsState* ls, int nprob, int nlam, const doubl
     s.inv_L = L[b] > 0 ? 1.0 / L[b] : 0.0;
     s.max_iter = max_iter;
     s.fixed_step = beta >= 1.0;
+    s.warm_tau = warm_tau;
     ls[k] = s;
 }
 
@@ -2146,9 +2158,10 @@ void launch_fit_init_batch(const FinArgs* batch, int nprob, hipStream_t st) {
 
 void launch_init_state_batch(LsState* ls, int nprob, int nlam, const double* lam,
                              const double* inv_n, const double* L, double tau0, double beta,
-                             double tol, int max_iter, hipStream_t st) {
+                             double tol, int max_iter, hipStream_t st, int warm_tau) {
     k_init_state_batch<<<(unsigned)cdiv(nprob, 256), 256, 0, st>>>(ls, nprob, nlam, lam, inv_n, L,
-                                                                   tau0, beta, tol, max_iter);
+                                                                   tau0, beta, tol, max_iter,
+                                                                   warm_tau);
 }
 
 void launch_share_L_batch(LsState* ls, int nprob, int nlam, hipStream_t st) {

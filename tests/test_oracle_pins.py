@@ -14,6 +14,9 @@ the mathematics fixes independently of the oracle's own formulas.
   P10 brute force (generic quasi-Newton) for p <= 20
   P11 linear convergence, backtracking faster than the fixed step 1/L (Sec. 5.1)
   P12 column-subset replay reproduces the full run's columns (separability)
+  P13 the warm-started step variant: each accepted step is the first passing one from
+      min(tau0, tau_{t-1}/beta), f decreases, fewer trials, and the same fixed point
+      (KKT, coordinate descent)
 plus mutation tests: a planted mistake in the oracle makes a pin fail.
 """
 import numpy as np
@@ -333,3 +336,37 @@ def test_mutation_sign_flip_breaks_p1():
     x, a = 2.0, 0.5
     psi = lambda w: a * abs(w) + (w - x) ** 2 / 2
     assert psi(bad(x, a)) > psi(oracle.soft_threshold(x, a)) + 1.0
+
+
+# ---------------------------------------------------------------- P13
+@pytest.mark.parametrize("seed,n,p,lam", [(1, 40, 15, 0.1), (2, 25, 30, 0.2)])
+def test_p13_warm_started_steps(seed, n, p, lam):
+    x = _problem(n, p, seed)
+    L = oracle.lipschitz(x)
+    tau0, beta = 1.0, 0.5
+    r = oracle.fit_fbs(x, lam, 80, L=L, tau0=tau0, beta=beta, warm_tau=True)
+    om = np.eye(p)
+    for t in range(r.iters):
+        G = oracle.grad(x, om)
+        start = tau0 if t == 0 else min(tau0, r.tau[t - 1] / beta)
+        # the accepted step is start beta^(k-1); every earlier candidate failed the
+        # inequality and the accepted one passes it (or sits at the floor)
+        k = r.trials[t]
+        assert np.isclose(r.tau[t], start * beta ** (k - 1), rtol=1e-14)
+        for j in range(k):
+            tau = start * beta ** j
+            nxt = oracle.prox(om, G, tau, lam)
+            v = x @ (nxt - om)
+            ok = np.sum(v * v) / n <= np.sum((nxt - om) ** 2) / tau
+            assert ok == (j == k - 1) or (j == k - 1 and tau <= 1 / L)
+        om_next = oracle.prox(om, G, r.tau[t], lam)
+        assert oracle.objective(x, om_next, lam)[2] <= oracle.objective(x, om, lam)[2] + 1e-12
+        om = om_next
+    # with tau0 well above the accepted steps, the plain rule pays the same backtracking
+    # every iteration and the warm start does not (a property of these inputs)
+    plain = oracle.fit_fbs(x, lam, 80, L=L, tau0=8.0, beta=beta)
+    warm = oracle.fit_fbs(x, lam, 80, L=L, tau0=8.0, beta=beta, warm_tau=True)
+    assert sum(warm.trials) < 0.7 * sum(plain.trials)
+    conv = oracle.fit_fbs(x, lam, 50000, L=L, tol=1e-15, warm_tau=True)
+    assert oracle.kkt_residual(x, conv.omega, lam)[0] < 1e-9
+    assert np.allclose(conv.omega, oracle.fit_cd(x, lam, tol=1e-12), atol=1e-8)
