@@ -70,6 +70,7 @@ int norm_rows(const Geo& g, int prec) {
 
 struct Plan {
     int64_t n, p, n_pad, p_pad;
+    int64_t p_cols;  // columns allocated for Omega, G and Omega+ (>= p)
     int prec;
     // trial GEMM  (C = W^T:  M = n_pad, N = p, K = p_pad): FP32 geometry (setup
     // products and the FP32 form) and, for the bf16 forms, the fused prox + trial
@@ -137,6 +138,10 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     const size_t xn = (size_t)(P.n_pad * P.p_pad);   // padded X elements
     const size_t wn = (size_t)(p * P.n_pad);         // W^T elements
     const size_t on = (size_t)(p * P.p_pad);         // p x p_pad elements
+    // the fused trial kernels read and write whole 128-column blocks of Omega, G and
+    // Omega+: their buffers carry zero padding columns up to tilesN * 128
+    P.p_cols = P.fused ? round_up(p, kFBN) : p;
+    const size_t onc = (size_t)(P.p_cols * P.p_pad);
     size_t cur = 0;
     P.off_ls = bump(cur, sizeof(LsState));
     P.off_prox_part = bump(cur, (size_t)std::max(kMaxProxBlocks, P.prox_rows) * kPartCols *
@@ -161,11 +166,11 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     P.off_w8 = bump(cur, f8 ? wn : 0);
     P.off_w8s = bump(cur, f8 ? wn / 32 : 0);
     P.off_split = bump(cur, split_floats * sizeof(float));
-    P.off_om0 = bump(cur, on * sizeof(float));
+    P.off_om0 = bump(cur, onc * sizeof(float));
     P.end_grad = cur;
-    P.off_g = bump(cur, on * sizeof(float));
+    P.off_g = bump(cur, onc * sizeof(float));
     P.off_d = bump(cur, P.fused ? 0 : on * sizeof(float));  // fused forms never store Delta
-    P.off_om1 = bump(cur, on * sizeof(float));
+    P.off_om1 = bump(cur, onc * sizeof(float));
     P.end_fit = cur;
     P.off_mask = bump(cur, on);
     P.end_refit = cur;
@@ -577,6 +582,10 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
     launch_copy_cols(Omega, p, om[0], P.p_pad, p, P.p_pad, ls, st);
     uint8_t* mask = support_src ? at<uint8_t>(ws, P.off_mask) : nullptr;
     if (mask) launch_support_mask(support_src, p, P.p_pad, mask, om[0], st);
+    if (P.p_cols > p) {  // zero padding columns (the fused kernels keep them zero)
+        const size_t pad = (size_t)((P.p_cols - p) * P.p_pad) * sizeof(float);
+        for (float* b : {om[0], om[1], G}) HIP_TRY(hipMemsetAsync(b + p * P.p_pad, 0, pad, st));
+    }
     if (f8) {
         XQuant q = {at<uint8_t>(ws, P.off_x8), at<uint8_t>(ws, P.off_x8s),
                     at<uint8_t>(ws, P.off_xt8), at<uint8_t>(ws, P.off_xt8s)};

@@ -881,44 +881,35 @@ __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
     prox_run<DOUT>(a);
 }
 
-// B-operand producer of k_trial_fused for stage `buf` holding K step `step`:
-// prox of the 2 x 4 staged Omega / G values, Delta -> bf16 hi (/ lo) into LDS, and
-// for the owning M tile Omega+ to HBM and the line-search sums.  Also stores the
-// staged X rows.  Off-diagonal entries take the FP32 soft threshold without
-// branches; the one diagonal entry a column can have is redone in FP64 under a
-// rarely taken branch.  The owner's sums are FP32 over each group of 4 consecutive
-// entries and FP64 beyond.  Padded rows hold zeros and contribute nothing; columns
-// past p are zeroed.  (A macro keeps every staging array in registers.)
-#define FUSED_PRODUCE(buf, step, vo, vg)                                                  \
+// B-operand producer of k_trial_fused for stage `buf` holding K step `step`, written
+// without branches so that it shares one basic block with the MFMAs of the previous
+// stage and the scheduler can interleave the two: prox of the 2 x 4 staged Omega / G
+// values with the FP32 soft threshold, Delta -> bf16 hi (/ lo) into LDS, Omega+ kept
+// in `onw` for the owner's store, and the line-search sums (FP32 over the 8 entries,
+// FP64 beyond; multiplied by `live`, 0 for the clamped copy of the last step).  Also
+// stores the staged X rows.  The one diagonal entry a column can have is corrected
+// after the block by FUSED_DIAG.  Columns past p read and write the zero padding
+// columns of Omega, G and Omega+, so they produce zeros without a test.  (Macros keep
+// every staging array in registers.)
+#define FUSED_PRODUCE(buf, step, vo, vg, va, live)                                        \
     do {                                                                                  \
-        const int64_t k0_ = (int64_t)(step) * BK;                                         \
         _Pragma("unroll") for (int q = 0; q < H * 2; ++q)                                 \
             *(u4*)&sA[(buf)][q >> 1][(arow + 128 * (q & 1)) * LDK + acol] = va[q];         \
+        float sd2_ = 0.f, sdg_ = 0.f, sl1_ = 0.f, sfr_ = 0.f, snz_ = 0.f;                \
         _Pragma("unroll") for (int q = 0; q < 2; ++q) {                                   \
             const f4 o_ = vo[q], g_ = vg[q];                                              \
-            f4 nw_;                                                                       \
+            uint16_t h_[4], l_[4];                                                        \
             _Pragma("unroll") for (int u = 0; u < 4; ++u) {                               \
                 const float a_ = fmaf(-tau_f, g_[u], o_[u]);                              \
                 const float t_ = fabsf(a_) - thr_f;                                       \
-                nw_[u] = t_ > 0.f ? copysignf(t_, a_) : 0.f;                              \
-            }                                                                             \
-            const int dpos_ = jcol[q] - (int)(k0_ + br);                                  \
-            const bool has_diag_ = dpos_ >= 0 && dpos_ < 4;                               \
-            float dval_ = 0.f;                                                            \
-            if (has_diag_) {                                                              \
-                const int du_ = (int)dpos_;                                               \
-                const float od_ = du_ == 0 ? o_[0] : du_ == 1 ? o_[1] : du_ == 2 ? o_[2] : o_[3]; \
-                const float gd_ = du_ == 0 ? g_[0] : du_ == 1 ? g_[1] : du_ == 2 ? g_[2] : g_[3]; \
-                dval_ = prox_one(od_, gd_, true, tau, lam, tau_f, thr_f);                 \
-                _Pragma("unroll") for (int u = 0; u < 4; ++u)                             \
-                    nw_[u] = (u == du_) ? dval_ : nw_[u];                                 \
-            }                                                                             \
-            uint16_t h_[4], l_[4];                                                        \
-            f4 dv_;                                                                       \
-            _Pragma("unroll") for (int u = 0; u < 4; ++u)                                 \
-                dv_[u] = delta_repr<DOUT>(nw_[u] - o_[u], h_[u], l_[u]);                  \
-            if (!jvalid[q]) {                                                             \
-                _Pragma("unroll") for (int u = 0; u < 4; ++u) h_[u] = l_[u] = 0;          \
+                const float nw_ = t_ > 0.f ? copysignf(t_, a_) : 0.f;                     \
+                const float dv_ = delta_repr<DOUT>(nw_ - o_[u], h_[u], l_[u]);            \
+                sd2_ = fmaf(dv_, dv_, sd2_);                                              \
+                sdg_ = fmaf(dv_, g_[u], sdg_);                                            \
+                sl1_ += fabsf(nw_);                                                       \
+                sfr_ = fmaf(nw_, nw_, sfr_);                                              \
+                snz_ += nw_ != 0.f ? 1.f : 0.f;                                           \
+                onw[q][u] = nw_;                                                          \
             }                                                                             \
             const int lo_ = (bc + 64 * q) * LDK + br;                                     \
             *(uint2*)&sB[(buf)][0][lo_] =                                                 \
@@ -926,24 +917,62 @@ __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
             if (H == 2)                                                                   \
                 *(uint2*)&sB[(buf)][H - 1][lo_] = make_uint2(                             \
                     l_[0] | ((uint32_t)l_[1] << 16), l_[2] | ((uint32_t)l_[3] << 16));    \
-            if (owner && jvalid[q]) {                                                     \
-                *(f4*)(b_on + (ob[q] + (uint32_t)k0_ * 4)) = nw_;                         \
-                float sd2_ = 0.f, sdg_ = 0.f, sl1_ = 0.f, sfr_ = 0.f;                     \
-                int nz_ = 0;                                                              \
-                _Pragma("unroll") for (int u = 0; u < 4; ++u) {                           \
-                    sd2_ = fmaf(dv_[u], dv_[u], sd2_);                                    \
-                    sdg_ = fmaf(dv_[u], g_[u], sdg_);                                     \
-                    sl1_ += fabsf(nw_[u]);                                                \
-                    sfr_ = fmaf(nw_[u], nw_[u], sfr_);                                    \
-                    nz_ += (nw_[u] != 0.f && !(has_diag_ && u == (int)dpos_)) ? 1 : 0;   \
+        }                                                                                 \
+        const float lv_ = (live) ? 1.f : 0.f;                                             \
+        pacc.d2 += (double)(sd2_ * lv_);                                                  \
+        pacc.dg += (double)(sdg_ * lv_);                                                  \
+        pacc.l1 += (double)(sl1_ * lv_);                                                  \
+        pacc.fro += (double)(sfr_ * lv_);                                                 \
+        pacc.nnz += (double)(snz_ * lv_);                                                 \
+    } while (0)
+
+// Diagonal entries of stage `buf` (rows step*BK + br .. + 3 of column jcol[q]): the
+// positive root of eq. 3.5 in FP64 replaces the soft-threshold value in LDS, in `onw`
+// and in the sums (the diagonal is not an off-diagonal nonzero; it adds log w).  Only
+// a few stages of a column block hold diagonal entries, so this is a rarely taken,
+// wave-uniform branch after the producer's block.
+#define FUSED_DIAG(buf, step, vo, vg, live)                                               \
+    do {                                                                                  \
+        const int k0_ = (step) * BK + br;                                                 \
+        bool hd_[2];                                                                      \
+        _Pragma("unroll") for (int q = 0; q < 2; ++q)                                     \
+            hd_[q] = (live) && jvalid[q] && (unsigned)(jcol[q] - k0_) < 4u;               \
+        if (__builtin_amdgcn_ballot_w64(hd_[0] || hd_[1])) {                              \
+            _Pragma("unroll") for (int q = 0; q < 2; ++q) {                               \
+                if (hd_[q]) {                                                             \
+                    const int du_ = jcol[q] - k0_;                                        \
+                    const f4 o_ = vo[q], g_ = vg[q];                                      \
+                    const float od_ = du_ == 0 ? o_[0] : du_ == 1 ? o_[1] : du_ == 2 ? o_[2] : o_[3]; \
+                    const float gd_ = du_ == 0 ? g_[0] : du_ == 1 ? g_[1] : du_ == 2 ? g_[2] : g_[3]; \
+                    const float sv_ = du_ == 0 ? onw[q][0] : du_ == 1 ? onw[q][1]         \
+                                    : du_ == 2 ? onw[q][2] : onw[q][3];                   \
+                    const float dv_ = prox_one(od_, gd_, true, tau, lam, tau_f, thr_f);   \
+                    uint16_t hs_, ls_, hd2_, ld2_;                                        \
+                    const double es_ = delta_repr<DOUT>(sv_ - od_, hs_, ls_);             \
+                    const double ed_ = delta_repr<DOUT>(dv_ - od_, hd2_, ld2_);           \
+                    const int lo_ = (bc + 64 * q) * LDK + br + du_;                       \
+                    sB[(buf)][0][lo_] = hd2_;                                             \
+                    if (H == 2) sB[(buf)][H - 1][lo_] = ld2_;                             \
+                    _Pragma("unroll") for (int u = 0; u < 4; ++u)                         \
+                        onw[q][u] = u == du_ ? dv_ : onw[q][u];                           \
+                    pacc.d2 += ed_ * ed_ - es_ * es_;                                     \
+                    pacc.dg += (ed_ - es_) * (double)gd_;                                 \
+                    pacc.l1 += fabs((double)dv_) - fabs((double)sv_);                     \
+                    pacc.fro += (double)dv_ * (double)dv_ - (double)sv_ * (double)sv_;    \
+                    pacc.nnz -= sv_ != 0.f ? 1.0 : 0.0;                                   \
+                    pacc.logd += dv_ > 0.f ? log((double)dv_) : -INFINITY;                \
                 }                                                                         \
-                pacc.d2 += (double)sd2_;                                                  \
-                pacc.dg += (double)sdg_;                                                  \
-                pacc.l1 += (double)sl1_;                                                  \
-                pacc.fro += (double)sfr_;                                                 \
-                pacc.nnz += (double)nz_;                                                  \
-                if (has_diag_) pacc.logd += dval_ > 0.f ? log((double)dval_) : -INFINITY; \
             }                                                                             \
+        }                                                                                 \
+    } while (0)
+
+// The owning M tile writes Omega+ of stage `step` (padding columns included: zeros).
+#define FUSED_STORE(step, live)                                                           \
+    do {                                                                                  \
+        if (owner && (live)) {                                                            \
+            const uint32_t ko_ = (uint32_t)(step) * (BK * 4);                             \
+            _Pragma("unroll") for (int q = 0; q < 2; ++q)                                 \
+                *(f4*)(b_on + (ob[q] + ko_)) = onw[q];                                    \
         }                                                                                 \
     } while (0)
 
@@ -1014,17 +1043,18 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
     uint32_t ob[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
+        // columns past p are the zero padding columns (Omega, G and Omega+ hold
+        // tilesN * 128 columns)
         const int j = n0 + bc + 64 * q;
         jvalid[q] = j < px.p;
         jcol[q] = j;
-        const int jc = jvalid[q] ? j : (int)px.p - 1;
-        ob[q] = (uint32_t)(((int64_t)(jc - n0) * px.ld + br) * 4);
+        ob[q] = (uint32_t)(((int64_t)(j - n0) * px.ld + br) * 4);
     }
-    // X rows are staged one step ahead; the Omega / G columns (the HBM stream) two
-    // steps ahead in two register sets, so each of their loads has a whole step
-    // (MFMAs + prox) to arrive
-    u4 va[H * 2];
+    // X rows and the Omega / G columns (the HBM stream) are staged two steps ahead in
+    // two register sets, so each load has a whole step (MFMAs + prox) to arrive
+    u4 va0[H * 2], va1[H * 2];
     f4 vo0[2], vg0[2], vo1[2], vg1[2];
+    f4 onw[2];
     f16v acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -1037,11 +1067,11 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
     const int r32 = lane & 31, k8 = (lane >> 5) * 8;
 
-#define FUSED_LOAD_A(step)                                                                \
+#define FUSED_LOAD_A(VA, step)                                                            \
     do {                                                                                  \
         const uint32_t ko_ = (uint32_t)(step) * (BK * 2);                                 \
         _Pragma("unroll") for (int q = 0; q < H * 2; ++q)                                 \
-            va[q] = *(const u4*)(((q >> 1) ? a_l : a_h) + (oa[q & 1] + ko_));             \
+            VA[q] = *(const u4*)(((q >> 1) ? a_l : a_h) + (oa[q & 1] + ko_));             \
     } while (0)
 
 #define FUSED_LOAD_OG(VO, VG, step)                                                       \
@@ -1088,31 +1118,39 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
     if (s_begin < s_end) {
         const int last = s_end - 1;
         // Loads past the range re-read the last step (unconditional prefetch, see
-        // k_gemm_bf16w); only steps inside the range are produced.
-        FUSED_LOAD_A(s_begin);
+        // k_gemm_bf16w).  The producer always runs (no branch between it and the
+        // MFMAs); past the range it fills the idle stage and neither counts nor stores.
+        FUSED_LOAD_A(va0, s_begin);
         FUSED_LOAD_OG(vo0, vg0, s_begin);
+        FUSED_LOAD_A(va1, s_begin + 1 < last ? s_begin + 1 : last);
         FUSED_LOAD_OG(vo1, vg1, s_begin + 1 < last ? s_begin + 1 : last);
-        FUSED_PRODUCE(0, s_begin, vo0, vg0);
+        FUSED_PRODUCE(0, s_begin, vo0, vg0, va0, true);
+        FUSED_DIAG(0, s_begin, vo0, vg0, true);
+        FUSED_STORE(s_begin, true);
         __syncthreads();
         int cur = 0;
         for (int s = s_begin; s < s_end; s += 2) {
             // step s is in LDS[cur]; set 1 holds step s + 1
-            FUSED_LOAD_A(s + 1 < last ? s + 1 : last);
+            const int s1 = s + 1 < last ? s + 1 : last;
+            const bool live1 = s + 1 < s_end;
+            FUSED_LOAD_A(va0, s + 2 < last ? s + 2 : last);
             FUSED_LOAD_OG(vo0, vg0, s + 2 < last ? s + 2 : last);
-            __builtin_amdgcn_sched_barrier(0);
             FUSED_MMA(cur);
-            __builtin_amdgcn_sched_barrier(0);
-            if (s + 1 < s_end) FUSED_PRODUCE(cur ^ 1, s + 1, vo1, vg1);
+            FUSED_PRODUCE(cur ^ 1, s1, vo1, vg1, va1, live1);
+            FUSED_DIAG(cur ^ 1, s1, vo1, vg1, live1);
+            FUSED_STORE(s1, live1);
             __syncthreads();
             cur ^= 1;
-            if (s + 1 >= s_end) break;
+            if (!live1) break;
             // step s + 1 is in LDS[cur]; set 0 holds step s + 2
-            FUSED_LOAD_A(s + 2 < last ? s + 2 : last);
+            const int s2 = s + 2 < last ? s + 2 : last;
+            const bool live2 = s + 2 < s_end;
+            FUSED_LOAD_A(va1, s + 3 < last ? s + 3 : last);
             FUSED_LOAD_OG(vo1, vg1, s + 3 < last ? s + 3 : last);
-            __builtin_amdgcn_sched_barrier(0);
             FUSED_MMA(cur);
-            __builtin_amdgcn_sched_barrier(0);
-            if (s + 2 < s_end) FUSED_PRODUCE(cur ^ 1, s + 2, vo0, vg0);
+            FUSED_PRODUCE(cur ^ 1, s2, vo0, vg0, va0, live2);
+            FUSED_DIAG(cur ^ 1, s2, vo0, vg0, live2);
+            FUSED_STORE(s2, live2);
             __syncthreads();
             cur ^= 1;
         }
