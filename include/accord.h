@@ -119,7 +119,15 @@ typedef struct {
                            unchanged, so every accepted step still satisfies Alg. 1's
                            inequality (or tau <= 1/L); the iterates differ, the fixed point
                            does not.  Fewer trials per iteration. */
-    int32_t reserved[2];
+    int32_t graph;      /* accord_fit_batch only: 1 = capture one sweep of each parity into a
+                           HIP graph once and replay the graphs, instead of enqueuing every
+                           launch (same kernels, same results; needs a non-default stream,
+                           ignored on the default stream).  Ignored by accord_fit. */
+    int32_t refresh_every; /* accord_fit / accord_refit: 0 = W = X Omega is carried across
+                           iterations (W_{t+1} = W_t + X Delta_t, the trial product); k > 0 =
+                           after every k-th accepted iteration W is recomputed as X Omega
+                           in FP32 (one extra product), which bounds the drift of the carried
+                           W (in the BF16X1 / FP8 forms the carried W sums rounded steps). */
 } accord_params;
 
 /* Results of accord_fit (host memory, filled on return). */

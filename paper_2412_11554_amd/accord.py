@@ -37,7 +37,8 @@ class accord_params(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("power_iters", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("warm_tau", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("warm_tau", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("refresh_every", ctypes.c_int32)]
 
 
 class accord_stats(ctypes.Structure):
@@ -234,8 +235,8 @@ def accord_objective(X: torch.Tensor, Omega: torch.Tensor, lam: float, *, out=No
 def accord_fit(X: torch.Tensor, lam: float, max_iter: int, *, omega0: torch.Tensor | None = None,
                tau0: float = 1.0, beta: float = 0.5, lipschitz: float = 0.0, tol: float = 0.0,
                check_every: int = 10, power_iters: int = 0, precision: str = "fp32",
-               trace: bool = False, timing: bool = False, warm_tau: bool = False, ws=None,
-               omega_out=None):
+               trace: bool = False, timing: bool = False, warm_tau: bool = False,
+               refresh_every: int = 0, ws=None, omega_out=None):
     """ACCORD-FBS (Alg. 1).  Returns (Omega [p, p] paper form, stats dict, trace or None).
     omega0 defaults to the identity.  warm_tau selects the warm-started step variant."""
     n, p = X.shape
@@ -243,7 +244,7 @@ def accord_fit(X: torch.Tensor, lam: float, max_iter: int, *, omega0: torch.Tens
     prm = default_params(lam=lam, max_iter=max_iter, tau0=tau0, beta=beta, lipschitz=lipschitz,
                          tol=tol, check_every=check_every, power_iters=power_iters,
                          precision=precision, timing=1 if timing else 0,
-                         warm_tau=1 if warm_tau else 0)
+                         warm_tau=1 if warm_tau else 0, refresh_every=refresh_every)
     if omega_out is None:
         omega_out = torch.empty((p, p), dtype=torch.float32, device=dev)
     if omega0 is None:
@@ -272,7 +273,7 @@ def accord_batch_workspace_bytes(n, p: int, nlam: int, params: accord_params | N
 def accord_fit_batch(X: torch.Tensor, n, lambdas, max_iter: int, *,
                      omega0: torch.Tensor | None = None, tau0: float = 1.0, beta: float = 0.5,
                      tol: float = 0.0, power_iters: int = 0, lipschitz=None, trials: bool = False,
-                     warm_tau: bool = False, ws=None, omega_out=None):
+                     warm_tau: bool = False, graph: bool = False, ws=None, omega_out=None):
     """Batched ACCORD-FBS: X is the row-wise stack of the data sets (sum(n) x p),
     n their row counts, lambdas the penalties.  Problem k = b * len(lambdas) + l.
     Returns (Omega [nprob, p, p] paper form, list of stats dicts, trials
@@ -286,7 +287,8 @@ def accord_fit_batch(X: torch.Tensor, n, lambdas, max_iter: int, *,
     nprob = nsub * nlam
     dev = X.device
     prm = default_params(max_iter=max_iter, tau0=tau0, beta=beta, tol=tol,
-                         power_iters=power_iters, warm_tau=1 if warm_tau else 0)
+                         power_iters=power_iters, warm_tau=1 if warm_tau else 0,
+                         graph=1 if graph else 0)
     if omega_out is None:
         omega_out = torch.empty((nprob, p, p), dtype=torch.float32, device=dev)
     if omega0 is None:

@@ -338,6 +338,9 @@ int check_params(const accord_params* prm) {
     if (prm->power_iters < 0) return fail(ACCORD_ERR_INVALID_ARG, "power_iters must be >= 0");
     if (prm->warm_tau != 0 && prm->warm_tau != 1)
         return fail(ACCORD_ERR_INVALID_ARG, "warm_tau must be 0 or 1");
+    if (prm->graph != 0 && prm->graph != 1)
+        return fail(ACCORD_ERR_INVALID_ARG, "graph must be 0 or 1");
+    if (prm->refresh_every < 0) return fail(ACCORD_ERR_INVALID_ARG, "refresh_every must be >= 0");
     return ACCORD_OK;
 }
 
@@ -711,6 +714,14 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
         }
         cur = nxt;
         if (stop) break;
+        if (prm->refresh_every > 0 && (t + 1) % prm->refresh_every == 0) {
+            // W = X Omega afresh (FP32), with the bf16 split the next gradient reads; the
+            // next trial's sums then describe the refreshed W
+            enqueue_trial(trial_args(P, ws, PREC_FP32, om[cur], nullptr, nullptr, nullptr,
+                                     wt[cur], bf ? cur : -1, nullptr, 0),
+                          PREC_FP32, st);
+            HIP_TRY(hipGetLastError());
+        }
     }
     if (timing) HIP_TRY(hipEventRecord(ev_end, st));
     HIP_TRY(hipMemcpyAsync(&host, ls, sizeof host, hipMemcpyDeviceToHost, st));
@@ -1157,8 +1168,10 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
     // ---- Alg. 1 for every problem, one iteration per sweep.  Each sweep enqueues the
     // gradient and ntr trials (enough for the problem whose floor is lowest); a
     // problem that accepted, or stopped, skips the rest of the sweep.
-    for (int t = 0; t < prm->max_iter; ++t) {
-        const int par = t & 1;
+    // Sweep t uses the argument blocks of parity t & 1 (ping-pong buffers); nothing in a
+    // sweep depends on the host, so with prm->graph the two sweeps are captured once and
+    // replayed.
+    auto enqueue_sweep = [&](int par) {
         launch_gemm_f32_batch(d_grad + par * nsub, (int)nsub, B.tiles_grad, B.tpp, EPI_GRAD, st);
         for (int k = 0; k < ntr; ++k) {
             launch_prox_batch(d_prox + par * np, (int)np, B.nprox, st);
@@ -1166,7 +1179,35 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
                                   EPI_TRIAL, st);
             launch_finalize_batch(d_fin, (int)np, st);
         }
-        HIP_TRY(hipGetLastError());
+    };
+    if (prm->graph && st != nullptr && prm->max_iter > 0) {
+        struct Graphs {
+            hipGraph_t g[2] = {nullptr, nullptr};
+            hipGraphExec_t e[2] = {nullptr, nullptr};
+            ~Graphs() {
+                for (int i = 0; i < 2; ++i) {
+                    if (e[i]) (void)hipGraphExecDestroy(e[i]);
+                    if (g[i]) (void)hipGraphDestroy(g[i]);
+                }
+            }
+        } G;
+        const int nsweep = prm->max_iter < 2 ? prm->max_iter : 2;
+        for (int par = 0; par < nsweep; ++par) {
+            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            enqueue_sweep(par);
+            const hipError_t cap = hipGetLastError();
+            const hipError_t end = hipStreamEndCapture(st, &G.g[par]);
+            if (cap != hipSuccess) return fail(ACCORD_ERR_HIP, "sweep capture: %s", hipGetErrorString(cap));
+            if (end != hipSuccess) return fail(ACCORD_ERR_HIP, "sweep capture: %s", hipGetErrorString(end));
+            HIP_TRY(hipGraphInstantiate(&G.e[par], G.g[par], nullptr, nullptr, 0));
+        }
+        for (int t = 0; t < prm->max_iter; ++t) HIP_TRY(hipGraphLaunch(G.e[t & 1], st));
+        HIP_TRY(hipStreamSynchronize(st));  // before the graphs are destroyed
+    } else {
+        for (int t = 0; t < prm->max_iter; ++t) {
+            enqueue_sweep(t & 1);
+            HIP_TRY(hipGetLastError());
+        }
     }
     HIP_TRY(hipMemcpyAsync(host.data(), ls, np * sizeof(LsState), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

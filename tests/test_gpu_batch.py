@@ -128,3 +128,27 @@ def test_batch_errors(gpu_lib):
     with pytest.raises(accord.AccordError) as e:
         gpu_lib.accord_fit_batch(Xbad, w.n, w.lams, 5)
     assert e.value.status == 3
+
+
+def test_batch_graph_replay_matches_eager(gpu_lib):
+    """The captured sweeps (params.graph) replay the same kernels on the same device
+    state: results equal the eagerly enqueued run bit for bit, on two calls in a row
+    (fresh capture each call) with eager work and synchronisation in between."""
+    import torch
+    w = datagen.batch_workload(p=130, nsub=2, nlam=3, n_base=90, lo=40, hi=90, prob=0.03,
+                               iters=25, key=34)
+    X = torch.from_numpy(w.stacked()).cuda()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ref, st_ref, tr_ref = gpu_lib.accord_fit_batch(X, w.n, w.lams, w.iters, trials=True)
+        ref, tr_ref = ref.clone(), tr_ref.clone()
+        for rep in range(2):
+            om, st, tr = gpu_lib.accord_fit_batch(X, w.n, w.lams, w.iters, trials=True, graph=True)
+            s.synchronize()
+            assert torch.equal(om, ref), rep
+            assert torch.equal(tr, tr_ref), rep
+            assert [d["f"] for d in st] == [d["f"] for d in st_ref]
+            assert [d["iters"] for d in st] == [d["iters"] for d in st_ref]
+            # eager work on the same stream between the graph calls
+            _ = (X * 2.0).sum().item()
+    s.synchronize()

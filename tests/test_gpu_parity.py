@@ -409,3 +409,24 @@ def test_bf16x1_then_bf16x3_refinement_reaches_estimate(gpu_lib, dev):
     off = ~np.eye(90, dtype=bool)
     safe = off & ((np.abs(ref) > 1e-4) | (lam - np.abs(G) > 1e-4))
     assert np.array_equal((got != 0)[safe], (ref != 0)[safe])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x1"])
+def test_fit_refresh_every(gpu_lib, dev, prec):
+    """params.refresh_every = 7: W = X Omega is recomputed in FP32 after every 7th
+    iteration.  The iterates still replay in the oracle at the form's bar, and the
+    objective's g (from ||W||^2) follows the oracle's fresh g."""
+    w = datagen.workload("er200")
+    x = w.X.astype(np.float64)
+    L = oracle.lipschitz(x)
+    om, st, tr = gpu_lib.accord_fit(_t(w.X, dev), w.lam, 120, lipschitz=L, trace=True,
+                                    precision=prec, refresh_every=7)
+    tr = tr.cpu().numpy()
+    ref = oracle.fit_fbs(x, w.lam, 120, L=L, tau_replay=tr[1:, 3])
+    got = om.cpu().numpy().astype(np.float64).T
+    rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
+    bar = {"fp32": 1e-4, "bf16x3": 1e-4, "bf16x1": 5e-2}[prec]
+    gerr = np.max(np.abs(tr[:, 1] - np.array(ref.g)) / np.abs(np.array(ref.g)))
+    print(f"{prec}: rel {rel:.2e}, max rel g error {gerr:.2e}", flush=True)
+    assert rel <= bar
+    assert gerr <= {"fp32": 1e-5, "bf16x3": 1e-4, "bf16x1": 5e-2}[prec]
