@@ -259,3 +259,14 @@ def test_reparam_validation(L):
     assert L.accord_reparam(FAKE, 0, FAKE + 256, None, None) == 1
     assert L.accord_reparam(FAKE, 10, FAKE + 4, None, None) == 1    # misaligned
     assert L.accord_reparam(None, 10, FAKE + 256, None, None) == 1
+
+
+@pytest.mark.parametrize("field,value", [("warm_tau", 2), ("warm_tau", -1), ("graph", 3),
+                                         ("refresh_every", -1)])
+def test_variant_params_validation(L, field, value):
+    prm = accord.default_params(lam=0.1, max_iter=3)
+    setattr(prm, field, value)
+    st = accord.accord_stats()
+    r = L.accord_fit(FAKE, 10, 12, FAKE, ctypes.byref(prm), ctypes.byref(st), None, FAKE, 1 << 40,
+                     None)
+    assert r == 1 and field.encode() in L.accord_last_error()
