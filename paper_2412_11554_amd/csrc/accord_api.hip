@@ -376,7 +376,16 @@ Mailbox* host_mailbox(Mailbox** dev) {
     return host;
 }
 
-int32_t load_acquire(const int32_t* p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
+// one snapshot of the device's mailbox word
+struct Posted {
+    int32_t trials, iter;
+    bool stop;
+};
+Posted read_mailbox(const Mailbox* mb) {
+    const uint64_t w = __atomic_load_n(&mb->word, __ATOMIC_ACQUIRE);
+    return {(int32_t)(uint32_t)(w & 0xffffffffu), (int32_t)((w >> 32) & 0x7fffffffu),
+            (w >> 63) != 0};
+}
 
 // HIP event pool for per-kernel timing
 struct EventPool {
@@ -633,9 +642,7 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
     Mailbox* mbox_dev = nullptr;
     Mailbox* mbox = host_mailbox(&mbox_dev);
     if (!mbox) return fail(ACCORD_ERR_HIP, "could not allocate the pinned host mailbox");
-    mbox->iter = 0;
-    mbox->stop = 0;
-    __atomic_store_n(&mbox->trials, 0, __ATOMIC_RELEASE);
+    __atomic_store_n(&mbox->word, mailbox_word(0, 0, 0), __ATOMIC_RELEASE);
     struct Launch { hipEvent_t a, b; int iter, trial; };
     std::vector<Launch> ev_grad, ev_trial, ev_prox;
     int cur = 0;
@@ -689,25 +696,25 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
         for (int k = 0;; ++k) {
             // wait for trial k of this iteration to be finalised
             const int target = base + k + 1;
-            for (long spins = 1;; ++spins) {
-                if (load_acquire(&mbox->trials) >= target || load_acquire(&mbox->stop)) break;
+            Posted m = read_mailbox(mbox);
+            for (long spins = 1; !(m.trials >= target || m.stop); ++spins, m = read_mailbox(mbox)) {
                 if ((spins & 4095) == 0) {
                     const hipError_t e = hipStreamQuery(st);
                     if (e == hipSuccess) {  // stream drained: the outcome must be posted now
-                        if (load_acquire(&mbox->trials) >= target || load_acquire(&mbox->stop))
-                            break;
+                        m = read_mailbox(mbox);
+                        if (m.trials >= target || m.stop) break;
                         return fail(ACCORD_ERR_HIP, "device stopped posting trial outcomes");
                     }
                     if (e != hipErrorNotReady)
                         return fail(ACCORD_ERR_HIP, "stream error: %s", hipGetErrorString(e));
                 }
             }
-            if (load_acquire(&mbox->stop)) {
+            if (m.stop) {
                 stop = true;
                 break;
             }
-            if (load_acquire(&mbox->iter) > t) {  // accepted at trial k
-                base = load_acquire(&mbox->trials);
+            if (m.iter > t) {  // accepted at trial k
+                base = m.trials;
                 break;
             }
             if (launched < ntr) TRY(enqueue_trial_k(launched++));

@@ -60,13 +60,18 @@ struct LsState {
 
 // Pinned host mailbox: after every executed acceptance test the device posts the
 // trial count, the accepted-iteration count and the stop flag, so the host can
-// enqueue only the trials an iteration needs.
+// enqueue only the trials an iteration needs.  The three travel in one 64-bit word
+// (one system-scope store, read whole by the host), so no release fence -- which
+// would write back the whole L2 -- is needed to keep them consistent.
 struct Mailbox {
-    int32_t trials;  // written last (release): the other two fields are current
-    int32_t iter;
-    int32_t stop;
-    int32_t pad;
+    uint64_t word;   // bits 0-31 trials, 32-62 accepted iterations, 63 stop
+    uint64_t pad;
 };
+
+inline __host__ __device__ uint64_t mailbox_word(int32_t trials, int32_t iter, int32_t stop) {
+    return (uint64_t)(uint32_t)trials | ((uint64_t)((uint32_t)iter & 0x7fffffffu) << 32) |
+           ((uint64_t)(stop ? 1u : 0u) << 63);
+}
 
 // ---------------------------------------------------------------------------
 // kernel argument blocks

@@ -1818,10 +1818,10 @@ void launch_prox(ProxArgs a, int nblocks, hipStream_t st) {
 // is released last, after the fields it vouches for).
 __device__ inline void post_mailbox(Mailbox* mb, const LsState* ls) {
     if (!mb) return;
-    __hip_atomic_store(&mb->iter, ls->iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&mb->stop, ls->converged, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&mb->trials, ls->total_trials, __ATOMIC_RELEASE,
-                       __HIP_MEMORY_SCOPE_SYSTEM);
+    // relaxed: the host acts on this word alone; everything it then enqueues on the
+    // stream is ordered after this kernel anyway
+    __hip_atomic_store(&mb->word, mailbox_word(ls->total_trials, ls->iter, ls->converged),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __device__ __forceinline__ void finalize_run(LsState* ls, const double* prox_part, int nprox,
