@@ -151,7 +151,8 @@ typedef struct {
 } accord_stats;
 
 /* Fills `prm` with defaults: lambda 0.1, tau0 1, beta 0.5, lipschitz 0 (estimate),
- * tol 0, max_iter 100, FP32, check_every 10, power_iters 400, timing 0. */
+ * tol 0, max_iter 100, FP32, check_every 10, power_iters 400, timing 0, warm_tau 0,
+ * graph 0, refresh_every 0. */
 void accord_default_params(accord_params* prm);
 
 /* Workspace bytes needed by accord_fit for an n x p problem with `prm` (NULL =
