@@ -257,6 +257,14 @@ def time_to_error(X, w, ws, om, est, tol=1e-6, first_iters=150):
              "bf16x3 warm-tau": [("bf16x3", 5000, tol, True)],
              "bf16x1>bf16x3 warm-tau": [("bf16x1", first_iters, 0.0, True),
                                         ("bf16x3", 5000, tol, True)]}
+    # support of the estimate on the sampled columns, and each entry's margin: |w| for
+    # a nonzero, lambda - |G| for a zero (the KKT slack, eq. 3.3)
+    x64 = w.X.astype(np.float64)
+    G = x64.T @ (x64 @ ref) / w.n
+    nz_ref = ref != 0
+    margin = np.where(nz_ref, np.abs(ref), w.lam - np.abs(G))
+    diag = np.zeros_like(nz_ref)
+    diag[cols, np.arange(len(cols))] = True
     out = {}
     for name, phases in plans.items():
         for rep in range(2):  # the first run warms up
@@ -271,9 +279,12 @@ def time_to_error(X, w, ws, om, est, tol=1e-6, first_iters=150):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
         got = cur.cpu().numpy()[cols, :].astype(np.float64).T
+        flips = ((got != 0) != nz_ref) & ~diag
         out[name] = {"seconds": dt, "iters": iters,
                      "rel_err_vs_estimate": float(np.linalg.norm(got - ref) /
-                                                  np.linalg.norm(ref))}
+                                                  np.linalg.norm(ref)),
+                     "support_flips": int(flips.sum()),
+                     "support_flips_margin_gt_1e-4": int((flips & (margin > 1e-4)).sum())}
         log(f"[time-to-error] {name}: {dt * 1e3:.1f} ms, iters {iters}, "
             f"err {out[name]['rel_err_vs_estimate']:.2e}")
     base = out["fp32"]["seconds"]
@@ -282,6 +293,10 @@ def time_to_error(X, w, ws, om, est, tol=1e-6, first_iters=150):
     return {"tol": tol, "first_phase_iters": first_iters,
             "estimate": f"FP64 oracle, fixed steps 1/L on the sampled columns, "
                         f"{ESTIMATE_ITERS} iterations", "cols": cols.tolist(),
+            "support": "off-diagonal entries of the sampled columns whose zero / nonzero "
+                       "state differs from the estimate's; the second count keeps those "
+                       "whose margin (|w|, or lambda - |G| for a zero) exceeds 1e-4",
+            "estimate_offdiag_nonzeros": int((nz_ref & ~diag).sum()),
             "pipelines": out}
 
 
