@@ -461,9 +461,10 @@ def run_diff(args):
 
 def run_refit(args):
     """The steps around the solver at n = 500, p = 5000: one step = the refit of
-    eq. 3.8 (Alg. 1 in the FP32 form with the support mask, 200 iterations, from a
+    eq. 3.8 (Alg. 1 with the gradient zeroed off the support, 200 iterations, from a
     synthetic first-stage estimate on the true graph's support, L by power iteration)
-    followed by the reparametrisation (Theta and the partial correlations).
+    followed by the reparametrisation (Theta and the partial correlations).  Each form
+    of --forms is timed; the first is the headline.
     value = refit iterations per second, the reparametrisation's time included."""
     import torch
 
@@ -476,77 +477,101 @@ def run_refit(args):
     dev = torch.device("cuda:0")
     X = torch.from_numpy(d["x"]).to(dev)
     H = torch.from_numpy(np.ascontiguousarray(d["omega_hat"].T)).to(dev)
-    prm = accord.default_params(lam=d["lam"], max_iter=iters)
-    ws = torch.empty(accord.accord_refit_workspace_bytes(n, p, prm), dtype=torch.uint8, device=dev)
     om = torch.empty((p, p), dtype=torch.float32, device=dev)
     theta, rho = torch.empty_like(om), torch.empty_like(om)
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    per_form, rep_ms_all = {}, []
+    for form in forms:
+        prm = accord.default_params(lam=d["lam"], max_iter=iters, precision=form)
+        ws = torch.empty(accord.accord_refit_workspace_bytes(n, p, prm), dtype=torch.uint8,
+                         device=dev)
 
-    def step(timing):
-        _, st, tr = accord.accord_refit(X, H, d["lam"], d["phi"], iters, ws=ws, omega_out=om,
-                                        timing=timing, trace=True)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        accord.accord_reparam(om, theta_out=theta, rho_out=rho)
-        e1.record()
-        return st, tr, (e0, e1)
+        def step(timing):
+            _, st, tr = accord.accord_refit(X, H, d["lam"], d["phi"], iters, ws=ws,
+                                            omega_out=om, timing=timing, trace=True,
+                                            precision=form)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            accord.accord_reparam(om, theta_out=theta, rho_out=rho)
+            e1.record()
+            return st, tr, (e0, e1)
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    log("[refit] warmup done")
-    stats, events = [], []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        st, tr, ev = step(True)
-        stats.append(st)
-        events.append(ev)
-        log(f"[refit] step {i + 1}/{args.steps}: {st['iters']} iters, {st['trials']} trials, "
-            f"{st['total_ms']:.1f} ms")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    rep_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+        for _ in range(args.warmup):
+            step(False)
+        torch.cuda.synchronize()
+        log(f"[refit {form}] warmup done")
+        stats, events = [], []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            st, tr, ev = step(True)
+            stats.append(st)
+            events.append(ev)
+            log(f"[refit {form}] step {i + 1}/{args.steps}: {st['iters']} iters, "
+                f"{st['trials']} trials, {st['total_ms']:.1f} ms")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        rep_ms_all += [a.elapsed_time(b) for a, b in events]
+        kern = kernel_report(stats, form, n, p, False)
+        r = {"value": sum(s["iters"] for s in stats) / elapsed,
+             "ms_per_step": elapsed / args.steps * 1e3,
+             "trials_per_iter": stats[-1]["trials"] / max(1, stats[-1]["iters"]),
+             "nnz_offdiag": stats[-1]["nnz_offdiag"], "kernels": kern}
+        if not args.no_check:
+            from oracle import tuning_oracle as tu
+            cols = sample_cols(p)
+            taus = tr.cpu().numpy()[1:, 3]
+            ref = tu.refit(d["x"].astype(np.float64), d["omega_hat"].astype(np.float64),
+                           d["lam"], d["phi"], len(taus), L=stats[-1]["lipschitz"],
+                           tau_replay=taus, columns=cols).omega
+            got = om.cpu().numpy()[cols, :].astype(np.float64).T
+            r["error_vs_oracle"] = {
+                "rel_fro_sampled_cols": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                "cols": cols.tolist(),
+                "reference": "FP64 oracle refit replaying the step sizes (unrounded operands)"}
+        r["lipschitz"] = stats[-1]["lipschitz"]
+        per_form[form] = r
+        del ws
+        torch.cuda.empty_cache()
+    head = per_form[forms[0]]
+    kern = head["kernels"]
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    rk = kern[dom]
+    rep_ms = float(np.mean(rep_ms_all))
     rep_bytes = 12.0 * p * p      # read Omega, write Theta and rho (FP32)
     rep_gbs = rep_bytes / (rep_ms * 1e-3) / 1e9
-    kern = kernel_report(stats, "fp32", n, p, False)
-    dom = max(kern, key=lambda k: kern[k]["total_ms"])
-    r = kern[dom]
     res = {
-        "metric": "refit prox-grad iters/sec on the estimated support (FP32) + reparametrisation",
-        "value": sum(s["iters"] for s in stats) / elapsed, "unit": "iters/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
-        "data": "synthetic",
+        "metric": f"refit prox-grad iters/sec on the estimated support ({forms[0]}) "
+                  "+ reparametrisation",
+        "value": head["value"], "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": forms[0], "data": "synthetic",
         "config": {"workload": f"refit (eq. 3.8) on n={n}, p={p} power-law data, support of the "
                                f"true graph, lambda={d['lam']}, phi={d['phi']}, {iters} iterations, "
                                "then Theta and rho",
-                   "n": n, "p": p, "iters": iters},
-        "trials_per_iter": stats[-1]["trials"] / max(1, stats[-1]["iters"]),
-        "roofline": {"bound": r["bound"], "kernel": " + ".join(r["kernels"]),
-                     "achieved": r["achieved"], "peak": r["peak"], "unit": r["unit"],
-                     "frac": r["frac"], "traffic": None},
+                   "n": n, "p": p, "iters": iters, "precision": forms[0]},
+        "trials_per_iter": head["trials_per_iter"],
+        "roofline": {"bound": rk["bound"], "kernel": " + ".join(rk["kernels"]),
+                     "achieved": rk["achieved"], "peak": rk["peak"], "unit": rk["unit"],
+                     "frac": rk["frac"], "traffic": None},
         "kernels": kern,
         "reparam": {"kernels": ["k_reparam"], "avg_ms": rep_ms, "bound": "hbm",
                     "algorithmic_bytes": rep_bytes, "achieved": rep_gbs, "peak": PEAK_HBM_GBS,
                     "unit": "GB/s", "frac": rep_gbs / PEAK_HBM_GBS},
-        "nnz_offdiag": stats[-1]["nnz_offdiag"],
+        "nnz_offdiag": head["nnz_offdiag"],
+        "forms": {f: {k: v for k, v in r.items() if k != "kernels"} | {
+            "trial_ms": r["kernels"].get("trial_gemm", {}).get("avg_ms"),
+            "grad_ms": r["kernels"].get("grad_gemm", {}).get("avg_ms"),
+            "prox_ms": r["kernels"].get("prox", {}).get("avg_ms")} for f, r in per_form.items()},
     }
-    if not args.no_check:
-        from oracle import tuning_oracle as tu
-        cols = sample_cols(p)
-        taus = tr.cpu().numpy()[1:, 3]
-        ref = tu.refit(d["x"].astype(np.float64), d["omega_hat"].astype(np.float64), d["lam"],
-                       d["phi"], len(taus), L=stats[-1]["lipschitz"], tau_replay=taus,
-                       columns=cols).omega
-        got = om.cpu().numpy()[cols, :].astype(np.float64).T
-        res["error_vs_oracle"] = {
-            "rel_fro_sampled_cols": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
-            "cols": cols.tolist(), "reference": "FP64 oracle refit replaying the step sizes"}
+    if "error_vs_oracle" in head:
+        res["error_vs_oracle"] = head["error_vs_oracle"]
     if not args.no_cpu_baseline:
         from oracle import tuning_oracle as tu
         k = 3
         t1 = time.perf_counter()
         rr = tu.refit(d["x"].astype(np.float64), d["omega_hat"].astype(np.float64), d["lam"],
-                      d["phi"], k, L=stats[-1]["lipschitz"])
+                      d["phi"], k, L=head["lipschitz"])
         dt = time.perf_counter() - t1
         res["cpu_baseline"] = {"value": k / dt, "unit": "iters/s", "cores": _threads(),
                                "kind": "oracle",

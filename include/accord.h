@@ -313,9 +313,14 @@ size_t accord_refit_workspace_bytes(int64_t n, int64_t p, const accord_params* p
  *   Omega: device p x p, in: the starting point (its entries off the support are set
  *     to zero first; Omega_hat itself is the natural start), out: the last iterate.
  *     Entries off the support are exactly zero in every iterate.
+ * Every precision form of accord_fit runs the refit: the gradient is set to zero off
+ * the support as it is stored, so the prox (eq. 3.5, whose soft threshold maps the
+ * zero argument Omega_ij - tau G_ij = 0 to 0) keeps those entries at zero, which is
+ * exactly what the infinite penalty gives.
  * Everything else (parameters, stats with phi * lambda as the penalty, trace, errors,
- * synchronous behaviour) as accord_fit.  FP32 form only (else ACCORD_ERR_UNSUPPORTED).
- * ws: device, 256-byte aligned, at least accord_refit_workspace_bytes() bytes. */
+ * synchronous behaviour) as accord_fit.
+ * ws: device, 256-byte aligned, at least accord_refit_workspace_bytes() bytes (which
+ * depends on prm->precision). */
 int accord_refit(const float* X, int64_t n, int64_t p, const float* Omega_hat, double phi,
                  float* Omega, const accord_params* prm, accord_stats* stats, double* trace,
                  void* ws, size_t ws_bytes, void* stream);

@@ -400,14 +400,16 @@ def accord_refit_workspace_bytes(n: int, p: int, params: accord_params | None = 
 def accord_refit(X: torch.Tensor, omega_hat: torch.Tensor, lam: float, phi: float, max_iter: int,
                  *, omega0: torch.Tensor | None = None, tau0: float = 1.0, beta: float = 0.5,
                  lipschitz: float = 0.0, tol: float = 0.0, power_iters: int = 0,
-                 trace: bool = False, timing: bool = False, ws=None, omega_out=None):
-    """Refit on the support of omega_hat with penalty phi * lam there (eq. 3.8).
-    Returns (Omega [p, p] paper form, stats dict, trace or None); the start defaults
-    to omega_hat."""
+                 precision: str = "fp32", trace: bool = False, timing: bool = False, ws=None,
+                 omega_out=None):
+    """Refit on the support of omega_hat with penalty phi * lam there (eq. 3.8), in any
+    precision form.  Returns (Omega [p, p] paper form, stats dict, trace or None); the
+    start defaults to omega_hat."""
     n, p = X.shape
     dev = X.device
     prm = default_params(lam=lam, max_iter=max_iter, tau0=tau0, beta=beta, lipschitz=lipschitz,
-                         tol=tol, power_iters=power_iters, timing=1 if timing else 0)
+                         tol=tol, power_iters=power_iters, timing=1 if timing else 0,
+                         precision=precision)
     if omega_out is None:
         omega_out = torch.empty((p, p), dtype=torch.float32, device=dev)
     omega_out.copy_(omega_hat if omega0 is None else omega0)

@@ -650,6 +650,7 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
     for (int t = 0; t < prm->max_iter; ++t) {
         const int nxt = cur ^ 1;
         GemmArgs ga = grad_args(P, ws, prec, wt[cur], cur, G, P.p_pad, (int)P.p_pad, ls);
+        ga.cmask = mask;  // refit: G = 0 off the support, so the prox keeps those entries 0
         Launch lg = {nullptr, nullptr, t, 0};
         if (timing) { lg.a = pool.get(); lg.b = pool.get(); HIP_TRY(hipEventRecord(lg.a, st)); }
         if (f8)  // MX copy of the current W (blocks along the samples) for the gradient
@@ -668,7 +669,6 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
             a.p = p;
             a.ls = ls;
             a.part = prox_part;
-            a.mask = mask;
             GemmArgs ta = trial_args(P, ws, prec, D, nullptr, nullptr, wt[cur], wt[nxt],
                                      bf ? nxt : -1, ls, 2);
             if (!fused) {
@@ -805,7 +805,7 @@ size_t accord_refit_workspace_bytes(int64_t n, int64_t p, const accord_params* p
         accord_default_params(&d);
         prm = &d;
     }
-    return make_plan(n, p, prm->max_iter, ACCORD_FP32).end_refit;
+    return make_plan(n, p, prm->max_iter, prm->precision).end_refit;
 }
 
 int accord_refit(const float* X, int64_t n, int64_t p, const float* Omega_hat, double phi,
@@ -814,8 +814,6 @@ int accord_refit(const float* X, int64_t n, int64_t p, const float* Omega_hat, d
     g_last_error.clear();
     TRY(check_ptr(Omega_hat, "Omega_hat"));
     if (!(phi >= 0.0 && phi <= 1.0)) return fail(ACCORD_ERR_INVALID_ARG, "phi must lie in [0, 1]");
-    if (prm && prm->precision != ACCORD_FP32)
-        return fail(ACCORD_ERR_UNSUPPORTED, "the refit runs in the FP32 form only");
     return fit_impl(X, n, p, Omega, prm, stats, trace, ws, ws_bytes, stream, Omega_hat, phi);
 }
 

@@ -123,6 +123,8 @@ struct GemmArgs {
     int pred;           // 1: skip if converged; 2: skip if done or converged
     int begin_iter;     // reset the line-search state of a new iteration
     int Mvalid, Nvalid; // extent counted in the norms
+    const uint8_t* cmask; // EPI_GRAD, optional: C entries whose byte (same layout as C)
+                          // is 0 are stored as 0 (the refit's support)
 };
 
 struct ProxArgs {
@@ -140,8 +142,6 @@ struct ProxArgs {
     const LsState* ls;  // if set: tau/lambda from here; skip if done or converged
     double* part;       // [gridDim.x][kPartCols]
     int reduce_only;    // 1: no writes, statistics of om itself
-    const uint8_t* mask;// optional support (same layout, one byte per entry): an
-                        // off-diagonal entry whose byte is 0 takes an infinite penalty
 };
 
 // acceptance-test arguments of one problem of the batched form

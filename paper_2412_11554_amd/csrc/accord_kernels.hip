@@ -304,6 +304,19 @@ __device__ inline void store_frag(const GemmArgs& g, f4 v, int m, int n, double 
     const int64_t off = (int64_t)n * g.ldc + m;
     const bool vec = g.vec_store && m + 3 < g.M;
     v = v * g.alpha;  // EPI_GRAD: 1/n; EPI_TRIAL: 1 (or the adjoint's -tau/n)
+    if (EPI == EPI_GRAD && g.cmask) {  // refit: G is zero off the support
+        uint32_t m4;
+        if (vec) {
+            m4 = *(const uint32_t*)(g.cmask + off);
+        } else {
+            m4 = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                m4 |= (m + r < g.M ? (uint32_t)g.cmask[off + r] : 0u) << (8 * r);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = ((m4 >> (8 * r)) & 0xffu) ? v[r] : 0.f;
+    }
     if (EPI != EPI_GRAD) {
         f4 w = f4{0.f, 0.f, 0.f, 0.f};
         if (g.Wprev) {
@@ -806,11 +819,9 @@ __device__ __forceinline__ void prox_run(const ProxArgs& a) {
     int64_t q = q_begin + threadIdx.x;
     int64_t e = q << 2;
     int64_t col = e / a.ld, row = e - col * a.ld;
-    const uint32_t* m4p = (const uint32_t*)a.mask;
     for (; q < q_end; q += kThreads) {
         const f4 o = om4[q];
         const f4 gv = a.reduce_only ? f4{0.f, 0.f, 0.f, 0.f} : g4[q];
-        const uint32_t m4 = m4p ? m4p[q] : 0x01010101u;
         f4 nw, dv;
         uint16_t h[4], l[4];
 #pragma unroll
@@ -822,7 +833,6 @@ __device__ __forceinline__ void prox_run(const ProxArgs& a) {
             }
             const bool diag = (r == c);
             nw[u] = a.reduce_only ? o[u] : prox_one(o[u], gv[u], diag, tau, lam, tau_f, thr_f);
-            if (!diag && ((m4 >> (8 * u)) & 0xffu) == 0u) nw[u] = 0.f;  // off the support
             dv[u] = delta_repr<DOUT>(nw[u] - o[u], h[u], l[u]);
             prox_account(acc, dv[u], gv[u], nw[u], diag, r < a.p, a.reduce_only);
         }
@@ -851,7 +861,6 @@ __device__ __forceinline__ void prox_run(const ProxArgs& a) {
         const float gv = a.reduce_only ? 0.f : a.g[ee];
         const bool diag = (r == c);
         float nw = a.reduce_only ? o : prox_one(o, gv, diag, tau, lam, tau_f, thr_f);
-        if (!diag && a.mask && a.mask[ee] == 0) nw = 0.f;
         uint16_t h, l;
         const float dv = delta_repr<DOUT>(nw - o, h, l);
         prox_account(acc, dv, gv, nw, diag, r < a.p, a.reduce_only);

@@ -202,8 +202,13 @@ def test_refit_validation(L):
     assert call(om_hat=FAKE + 4) == 1
     assert call(phi=-0.1) == 1 and call(phi=1.5) == 1 and call(phi=float("nan")) == 1
     assert call(X=None) == 1
-    assert call(prm=accord.default_params(lam=0.1, precision="bf16x3")) == 5
     assert call(ws_bytes=accord.accord_workspace_bytes(10, 12, prm)) == 4  # fit size: too small
+    # every precision form runs the refit; its workspace follows the form's layout
+    for prec in ("bf16x1", "bf16x3", "fp8"):
+        q = accord.default_params(lam=0.1, max_iter=3, precision=prec)
+        need_q = accord.accord_refit_workspace_bytes(10, 12, q)
+        assert need_q > accord.accord_workspace_bytes(10, 12, q) > 0
+        assert call(prm=q, ws_bytes=need_q - 1) == 4
     assert L.accord_last_error()
 
 
