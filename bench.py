@@ -98,12 +98,12 @@ def kernel_report(stats, form, n, p, workload_ok_for_traffic):
     algorithmic rate and the roofline it is held to.
 
     gradient  G = X^T W / n: 2 n p^2 flops, MFMA-bound.
-    trial     fp32: the trial GEMM (+ its split-K reduce), 2 n p^2 flops, MFMA-bound.
-              bf16 forms: the fused prox + trial GEMM (+ reduce), which streams Omega, G
-              in and Omega+ out: 12 p^2 algorithmic bytes against HBM, next to its
-              executed MFMA flops; the bound is the larger of the two lower bounds.
-    prox      fp32 form only (fused into the trial otherwise): 16 p^2 bytes
-              (read Omega, G; write Omega+, Delta), HBM-bound."""
+    trial     the fused prox + trial GEMM (+ its split-K reduce), which streams Omega, G
+              in and Omega+ out (12 p^2 algorithmic bytes against HBM) and executes
+              2 n p^2 flops per MFMA pass; the bound is the larger of the two lower
+              bounds (MFMA for fp32 at these sizes, HBM for the bf16 and fp8 forms).
+    prox      separate prox launches (none in the fit of any form since the FP32 form
+              fused its prox too): 16 p^2 bytes (read Omega, G; write Omega+, Delta)."""
     flops = 2.0 * n * p * p
     peak = PEAK_TFLOPS[form]
     traffic = _traffic_table() if workload_ok_for_traffic else {}
@@ -127,27 +127,23 @@ def kernel_report(stats, form, n, p, workload_ok_for_traffic):
     ms, cnt, avg = group("trial_gemm")
     if avg:
         a = flops / (avg * 1e-3) / 1e12
-        if form == "fp32":
-            names = ["k_gemm_f32<2>", "k_splitk_reduce"]
-            d = {"what": "W+ = W + X Delta (+ norms)", "bound": "mfma", "achieved": a,
-                 "peak": peak, "unit": "TFLOP/s", "frac": a / peak}
+        names = (["k_trial_fused32<2>", "k_splitk_reduce"] if form == "fp32" else
+                 ["k_trial_fused8<2>", "k_splitk_reduce_f"] if form == "fp8" else
+                 [f"k_trial_fused<{PASSES[form]}, 2>", "k_splitk_reduce_f"])
+        alg = 12.0 * p * p
+        gbs = alg / (avg * 1e-3) / 1e9
+        t_hbm = alg / (PEAK_HBM_GBS * 1e9)
+        t_mfma = flops * PASSES[form] / (peak * 1e12)
+        d = {"what": "fused prox (eq. 3.5) + W+ = W + X Delta (+ norms)",
+             "algorithmic_bytes": alg,
+             "mfma": {"achieved": a * PASSES[form], "peak": peak, "unit": "TFLOP/s",
+                      "frac": a * PASSES[form] / peak, "useful_tflops": a}}
+        if t_hbm >= t_mfma:
+            d.update({"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                      "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS})
         else:
-            names = (["k_trial_fused8<2>", "k_splitk_reduce_f"] if form == "fp8" else
-                     [f"k_trial_fused<{PASSES[form]}, 2>", "k_splitk_reduce_f"])
-            alg = 12.0 * p * p
-            gbs = alg / (avg * 1e-3) / 1e9
-            t_hbm = alg / (PEAK_HBM_GBS * 1e9)
-            t_mfma = flops * PASSES[form] / (peak * 1e12)
-            d = {"what": "fused prox (eq. 3.5) + W+ = W + X Delta (+ norms)",
-                 "algorithmic_bytes": alg,
-                 "mfma": {"achieved": a * PASSES[form], "peak": peak, "unit": "TFLOP/s",
-                          "frac": a * PASSES[form] / peak, "useful_tflops": a}}
-            if t_hbm >= t_mfma:
-                d.update({"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
-                          "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS})
-            else:
-                d.update({"bound": "mfma", "achieved": a * PASSES[form], "peak": peak,
-                          "unit": "TFLOP/s", "frac": a * PASSES[form] / peak})
+            d.update({"bound": "mfma", "achieved": a * PASSES[form], "peak": peak,
+                      "unit": "TFLOP/s", "frac": a * PASSES[form] / peak})
         d.update({"kernels": names, "launches": cnt, "avg_ms": avg, "total_ms": ms})
         out["trial_gemm"] = d
     ms, cnt, avg = group("prox")
@@ -358,7 +354,7 @@ def run_batch(args):
         "trials_per_iter": float(trials[:, :iters].mean()),
         "launch": "two captured HIP graphs (one sweep of each parity) replayed per sweep",
         "eager_ms_per_step": eager_s * 1e3,
-        "roofline": {"bound": "mfma", "kernel": "whole fit (batched FP32 GEMMs, prox, tests)",
+        "roofline": {"bound": "mfma", "kernel": "whole fit (batched FP32 gradient and fused prox + trial GEMMs, tests)",
                      "achieved": tflops, "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
                      "frac": tflops / PEAK_TFLOPS["fp32"], "traffic": None},
     }

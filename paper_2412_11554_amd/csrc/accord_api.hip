@@ -76,7 +76,8 @@ struct Plan {
     // products and the FP32 form) and, for the bf16 forms, the fused prox + trial
     // kernel's geometry
     Geo t32, tp;
-    int fused;      // bf16 and FP8 forms: the prox runs inside the trial kernel
+    int fused;      // bf16 and FP8 forms: the fused trial kernel's 256 x 128 geometry
+                    // (the FP32 form fuses its prox into the 128 x 128 FP32 tile)
     int prox_rows;  // FP64 prox partial rows left per trial
     int nprox;
     size_t off_ls, off_prox_part, off_norm_part, off_pow_u, off_pow_w, off_pow_pu, off_pow_pw,
@@ -127,7 +128,9 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
         P.tp.splits = choose_splits(P.tp.tiles(), (int)(P.p_pad / kPad), kWSlots);
     }
     P.nprox = prox_blocks(p * P.p_pad);
-    P.prox_rows = P.fused ? P.tp.tilesN * P.tp.splits : P.nprox;
+    // every form's fit runs the prox inside its trial kernel: one row of prox sums per
+    // (column block, split)
+    P.prox_rows = P.fused ? P.tp.tilesN * P.tp.splits : P.t32.tilesN * P.t32.splits;
     const bool bf = is_bf16(prec);
     const bool f8 = prec == PREC_FP8;
     const int ttiles = std::max(norm_rows(P.t32, PREC_FP32), norm_rows(P.tp, prec));
@@ -579,7 +582,6 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
     const bool bf = is_bf16(prec);
     const bool f8 = prec == PREC_FP8;
     const bool fused = P.fused != 0;
-    float* D = fused ? nullptr : at<float>(ws, P.off_d);
     double* prox_part = at<double>(ws, P.off_prox_part);
     double* norm_part = at<double>(ws, P.off_norm_part);
     int32_t* trials_log = at<int32_t>(ws, P.off_trials);
@@ -663,26 +665,19 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
             a.om = om[cur];
             a.g = G;
             a.om_new = om[nxt];
-            a.d = D;
             a.total = total;
             a.ld = P.p_pad;
             a.p = p;
             a.ls = ls;
             a.part = prox_part;
-            GemmArgs ta = trial_args(P, ws, prec, D, nullptr, nullptr, wt[cur], wt[nxt],
+            GemmArgs ta = trial_args(P, ws, prec, nullptr, nullptr, nullptr, wt[cur], wt[nxt],
                                      bf ? nxt : -1, ls, 2);
-            if (!fused) {
-                Launch lp = {nullptr, nullptr, t, k};
-                if (timing) { lp.a = pool.get(); lp.b = pool.get(); HIP_TRY(hipEventRecord(lp.a, st)); }
-                launch_prox(a, P.nprox, st);
-                if (timing) { HIP_TRY(hipEventRecord(lp.b, st)); ev_prox.push_back(lp); }
-            }
             Launch lt = {nullptr, nullptr, t, k};
             if (timing) { lt.a = pool.get(); lt.b = pool.get(); HIP_TRY(hipEventRecord(lt.a, st)); }
             if (fused)
                 launch_trial_fused(ta, a, prec, st);
             else
-                enqueue_trial(ta, prec, st);
+                launch_trial_fused32(ta, a, st);
             if (timing) { HIP_TRY(hipEventRecord(lt.b, st)); ev_trial.push_back(lt); }
             launch_finalize(ls, prox_part, P.prox_rows, norm_part, ttiles, trace, trials_log,
                             mbox_dev, st);
@@ -873,12 +868,12 @@ namespace {
 
 struct BatchPlan {
     int64_t p, p_pad, p_c, nsub, nlam, nprob;
-    int max_iter, tpp, nprox, max_tiles_trial, tiles_grad;
+    int max_iter, tpp, nprox, part_rows, max_tiles_trial, tiles_grad;
     std::vector<int64_t> n, n_pad, row_off, norm_off;
     std::vector<int> tilesM;
     size_t off_ls, off_lam, off_inv_n, off_L, off_args_w0, off_args_grad, off_args_trial,
-        off_prox_init, off_prox_args, off_fin, off_prox_part, off_norm_part, off_trials,
-        off_pow_u, off_pow_w, off_pow_pu, off_pow_pw, off_om[2], off_g, off_d, end;
+        off_prox_init, off_px_trial, off_fin_init, off_fin, off_prox_part, off_norm_part,
+        off_trials, off_pow_u, off_pow_w, off_pow_pu, off_pow_pw, off_om[2], off_g, end;
     std::vector<size_t> off_xp, off_xt, off_wt[2];
 };
 
@@ -896,6 +891,9 @@ int make_batch_plan(const int64_t* n, int64_t nsub, int64_t p, int64_t nlam, int
     B.max_iter = max_iter;
     B.tpp = (int)(B.p_c / kBN);
     B.nprox = kBatchProxBlocks;
+    // prox sum rows per problem: the set-up statistics pass leaves nprox, every trial one
+    // per column tile
+    B.part_rows = std::max(B.nprox, B.tpp);
     B.tiles_grad = (int)(cdiv(B.p_pad, kBM) * nlam * B.tpp);
     B.max_tiles_trial = 0;
     int64_t rows = 0, nmax = 0, norm_rows_total = 0;
@@ -921,9 +919,10 @@ int make_batch_plan(const int64_t* n, int64_t nsub, int64_t p, int64_t nlam, int
     B.off_args_grad = bump(cur, (size_t)2 * nsub * sizeof(GemmArgs));
     B.off_args_trial = bump(cur, (size_t)2 * nsub * sizeof(GemmArgs));
     B.off_prox_init = bump(cur, (size_t)np * sizeof(ProxArgs));
-    B.off_prox_args = bump(cur, (size_t)2 * np * sizeof(ProxArgs));
+    B.off_px_trial = bump(cur, (size_t)2 * nsub * sizeof(ProxArgs));
+    B.off_fin_init = bump(cur, (size_t)np * sizeof(FinArgs));
     B.off_fin = bump(cur, (size_t)np * sizeof(FinArgs));
-    B.off_prox_part = bump(cur, (size_t)np * B.nprox * kPartCols * sizeof(double));
+    B.off_prox_part = bump(cur, (size_t)np * B.part_rows * kPartCols * sizeof(double));
     B.off_norm_part = bump(cur, (size_t)norm_rows_total * kNormCols * sizeof(double));
     B.off_trials = bump(cur, (size_t)np * std::max(max_iter, 1) * sizeof(int32_t));
     const int64_t nmax_pad = round_up(nmax, kPad);
@@ -941,8 +940,7 @@ int make_batch_plan(const int64_t* n, int64_t nsub, int64_t p, int64_t nlam, int
     const size_t mat = (size_t)(np * B.p_c * B.p_pad) * sizeof(float);
     B.off_om[0] = bump(cur, mat);
     B.off_om[1] = bump(cur, mat);
-    B.off_g = bump(cur, mat);
-    B.off_d = bump(cur, mat);
+    B.off_g = bump(cur, mat);  // Delta never reaches HBM: the trial fuses the prox
     B.end = cur;
     return ACCORD_OK;
 }
@@ -1008,7 +1006,6 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
     LsState* ls = at<LsState>(ws, B.off_ls);
     float* om[2] = {at<float>(ws, B.off_om[0]), at<float>(ws, B.off_om[1])};
     float* G = at<float>(ws, B.off_g);
-    float* D = at<float>(ws, B.off_d);
     double* prox_part = at<double>(ws, B.off_prox_part);
     double* norm_part = at<double>(ws, B.off_norm_part);
     int32_t* trials_log = at<int32_t>(ws, B.off_trials);
@@ -1020,8 +1017,8 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
         if (lipschitz) h_L[b] = lipschitz[b];
     }
     std::vector<GemmArgs> a_w0(nsub), a_grad(2 * nsub), a_trial(2 * nsub);
-    std::vector<ProxArgs> a_prox_init(np), a_prox(2 * np);
-    std::vector<FinArgs> a_fin(np);
+    std::vector<ProxArgs> a_prox_init(np), a_px(2 * nsub);
+    std::vector<FinArgs> a_fin_init(np), a_fin(np);
     const int64_t pstep = 4 * (int64_t)kThreads;
     for (int64_t b = 0; b < nsub; ++b) {
         const int64_t k0 = b * nlam;
@@ -1034,7 +1031,7 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
             const int cur = par == 2 ? 0 : par, nxt = par == 2 ? 0 : par ^ 1;
             t.A = xp;
             t.lda = B.p_pad;
-            t.B = par == 2 ? om[0] + k0 * mat : D + k0 * mat;
+            t.B = par == 2 ? om[0] + k0 * mat : nullptr;  // trials produce Delta in place
             t.ldb = B.p_pad;
             t.M = (int)B.n_pad[b];
             t.N = (int)(nlam * B.p_c);
@@ -1056,6 +1053,19 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
                 a_w0[b] = t;
             else
                 a_trial[par * nsub + b] = t;
+        }
+        for (int par = 0; par < 2; ++par) {
+            // the prox of the fused trial: the group's Omega, G and Omega+ (its problems'
+            // columns packed like the trial product's N), per-problem state from ls + k0
+            ProxArgs q = {};
+            q.om = om[par] + k0 * mat;
+            q.g = G + k0 * mat;
+            q.om_new = om[par ^ 1] + k0 * mat;
+            q.ld = B.p_pad;
+            q.p = p;
+            q.ls = ls + k0;
+            q.part = prox_part + k0 * B.part_rows * kPartCols;
+            a_px[par * nsub + b] = q;
         }
         for (int par = 0; par < 2; ++par) {
             GemmArgs g = {};
@@ -1087,27 +1097,20 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
             a.p = p;
             a.step_col = pstep / a.ld;
             a.step_row = pstep - a.step_col * a.ld;
-            a.part = prox_part + k * B.nprox * kPartCols;
+            a.part = prox_part + k * B.part_rows * kPartCols;
             ProxArgs r = a;
             r.om = om[0] + k * mat;
             r.reduce_only = 1;
             a_prox_init[k] = r;
-            for (int par = 0; par < 2; ++par) {
-                ProxArgs q = a;
-                q.om = om[par] + k * mat;
-                q.g = G + k * mat;
-                q.om_new = om[par ^ 1] + k * mat;
-                q.d = D + k * mat;
-                q.ls = ls + k;
-                a_prox[par * np + k] = q;
-            }
             FinArgs f = {};
             f.ls = ls + k;
-            f.prox_part = prox_part + k * B.nprox * kPartCols;
-            f.nprox = B.nprox;
+            f.prox_part = prox_part + k * B.part_rows * kPartCols;
+            f.nprox = B.nprox;  // the set-up statistics pass
             f.ntiles = B.tilesM[b] * B.tpp;
             f.norm_part = norm_part + (B.norm_off[b] + l * (int64_t)f.ntiles) * kNormCols;
             f.trials_log = trials_log + k * std::max(B.max_iter, 1);
+            a_fin_init[k] = f;
+            f.nprox = B.tpp;    // a trial: one row per column tile of the problem
             a_fin[k] = f;
         }
     }
@@ -1115,13 +1118,15 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
     GemmArgs* d_grad = at<GemmArgs>(ws, B.off_args_grad);
     GemmArgs* d_trial = at<GemmArgs>(ws, B.off_args_trial);
     ProxArgs* d_prox_init = at<ProxArgs>(ws, B.off_prox_init);
-    ProxArgs* d_prox = at<ProxArgs>(ws, B.off_prox_args);
+    ProxArgs* d_px = at<ProxArgs>(ws, B.off_px_trial);
+    FinArgs* d_fin_init = at<FinArgs>(ws, B.off_fin_init);
     FinArgs* d_fin = at<FinArgs>(ws, B.off_fin);
     HIP_TRY(hipMemcpyAsync(d_w0, a_w0.data(), a_w0.size() * sizeof(GemmArgs), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_grad, a_grad.data(), a_grad.size() * sizeof(GemmArgs), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_trial, a_trial.data(), a_trial.size() * sizeof(GemmArgs), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_prox_init, a_prox_init.data(), a_prox_init.size() * sizeof(ProxArgs), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(d_prox, a_prox.data(), a_prox.size() * sizeof(ProxArgs), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_px, a_px.data(), a_px.size() * sizeof(ProxArgs), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_fin_init, a_fin_init.data(), a_fin_init.size() * sizeof(FinArgs), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_fin, a_fin.data(), a_fin.size() * sizeof(FinArgs), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(at<double>(ws, B.off_lam), lambda, nlam * sizeof(double), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(at<double>(ws, B.off_inv_n), h_inv_n.data(), nsub * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1131,10 +1136,10 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
     launch_init_state_batch(ls, (int)np, (int)nlam, at<double>(ws, B.off_lam),
                             at<double>(ws, B.off_inv_n), at<double>(ws, B.off_L), prm->tau0,
                             prm->beta, prm->tol, prm->max_iter, st, prm->warm_tau);
-    // padding columns of every problem's Omega and Delta must read as zero
+    // padding columns of every problem's Omega must read as zero (the trials never write
+    // them, and the gradient leaves zeros in those of G)
     HIP_TRY(hipMemsetAsync(om[0], 0, (size_t)(np * mat) * sizeof(float), st));
     HIP_TRY(hipMemsetAsync(om[1], 0, (size_t)(np * mat) * sizeof(float), st));
-    HIP_TRY(hipMemsetAsync(D, 0, (size_t)(np * mat) * sizeof(float), st));
     for (int64_t b = 0; b < nsub; ++b) {
         const int64_t k0 = b * nlam;
         launch_pad_x(X + B.row_off[b] * p, B.n[b], p, at<float>(ws, B.off_xp[b]), B.p_pad,
@@ -1151,7 +1156,7 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
         launch_copy_cols(Omega + k * p * p, p, om[0] + k * mat, B.p_pad, p, B.p_pad, ls + k, st);
     launch_gemm_f32_batch(d_w0, (int)nsub, B.max_tiles_trial, B.tpp, EPI_TRIAL, st);
     launch_prox_batch(d_prox_init, (int)np, B.nprox, st);
-    launch_fit_init_batch(d_fin, (int)np, st);
+    launch_fit_init_batch(d_fin_init, (int)np, st);
     HIP_TRY(hipGetLastError());
     std::vector<LsState> host((size_t)np);
     HIP_TRY(hipMemcpyAsync(host.data(), ls, np * sizeof(LsState), hipMemcpyDeviceToHost, st));
@@ -1179,9 +1184,8 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
     auto enqueue_sweep = [&](int par) {
         launch_gemm_f32_batch(d_grad + par * nsub, (int)nsub, B.tiles_grad, B.tpp, EPI_GRAD, st);
         for (int k = 0; k < ntr; ++k) {
-            launch_prox_batch(d_prox + par * np, (int)np, B.nprox, st);
-            launch_gemm_f32_batch(d_trial + par * nsub, (int)nsub, B.max_tiles_trial, B.tpp,
-                                  EPI_TRIAL, st);
+            launch_trial_fused32_batch(d_trial + par * nsub, d_px + par * nsub, (int)nsub,
+                                       B.max_tiles_trial, B.tpp, B.part_rows, st);
             launch_finalize_batch(d_fin, (int)np, st);
         }
     };

@@ -181,6 +181,7 @@ void launch_quant_w8(const float* Wt, int64_t total, uint8_t* w8, uint8_t* w8s, 
 void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st);
 void launch_splitk_reduce(const GemmArgs& a, hipStream_t st);
 void launch_trial_fused(const GemmArgs& a, const ProxArgs& px, int prec, hipStream_t st);
+void launch_trial_fused32(const GemmArgs& a, const ProxArgs& px, hipStream_t st);
 int prox_blocks(int64_t total);
 void launch_prox(ProxArgs a, int nblocks, hipStream_t st);
 void launch_finalize(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
@@ -216,6 +217,8 @@ void launch_sub_inv_diag(float* obar, int64_t ld_obar, const float* om, int64_t 
 void launch_gemm_f32_batch(const GemmArgs* batch, int ngroups, int max_tiles, int tpp, int epi,
                            hipStream_t st);
 void launch_prox_batch(const ProxArgs* batch, int nprob, int nblocks, hipStream_t st);
+void launch_trial_fused32_batch(const GemmArgs* gb, const ProxArgs* pb, int ngroups,
+                                int max_tiles, int tpp, int nprox_rows, hipStream_t st);
 void launch_finalize_batch(const FinArgs* batch, int nprob, hipStream_t st);
 void launch_fit_init_batch(const FinArgs* batch, int nprob, hipStream_t st);
 void launch_init_state_batch(LsState* ls, int nprob, int nlam, const double* lam,

@@ -890,6 +890,223 @@ __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
     prox_run<DOUT>(a);
 }
 
+// ---------------------------------------------------------------------------
+// Fused trial kernel of the FP32 form: prox (eq. 3.5) + trial product W+ = W + X Delta.
+//
+// The FP32 GEMM tile (128 x 128, 4 waves of 64 x 64 on v_mfma_f32_16x16x4f32, two
+// workgroups per CU) with its B operand produced in place: each K step loads 32 rows
+// of the tile's 128 columns of Omega and G, applies the prox in registers and writes
+// Delta = Omega+ - Omega (FP32) into the LDS stage.  The workgroup with tile_m 0 owns
+// the column block: it stores Omega+ and keeps the line-search sums (FP32 over a
+// thread's 16 entries of a step, FP64 beyond; one row per (tile_n, split) of
+// px.part).  Delta never goes through HBM and the separate prox pass disappears.
+// Off-diagonal entries take the FP32 soft threshold without a branch; the diagonal
+// entries a column can hold (in 8 of its K steps) are redone with the FP64 root under
+// a wave-uniform branch.  Rows past p are zero in Omega and G, so they produce zeros.
+//
+// Column j of the tile belongs to the problem whose columns start at jbase; it is a
+// column of that problem when j - jbase < p.  Loads read column min(j, ncols - 1) of
+// the buffers: in the single fit the buffers hold exactly p columns (ncols = p) and the
+// products of the columns past p are never stored; in the batched form every
+// problem's columns are padded to a multiple of 128 with zero columns, which produce
+// Delta = 0 and W+ = W there.  Only columns of the problem store Omega+ and count.
+// ---------------------------------------------------------------------------
+template <int EPI>
+__device__ __forceinline__ void trial_fused32_tile(const GemmArgs& g, const ProxArgs& px,
+                                                   int tile_m, int tile_n, int split, int jbase,
+                                                   int ncols, double tau, double lam,
+                                                   double* part_row, double* nrm) {
+    __shared__ __attribute__((aligned(16))) float sA[2][kBM * kLDK32];
+    __shared__ __attribute__((aligned(16))) float sB[2][kBN * kLDK32];
+    const bool owner = tile_m == 0;
+    const float tau_f = (float)tau, thr_f = (float)(tau * lam);
+    const int m0 = tile_m * kBM, n0 = tile_n * kBN;
+    const int ksteps = g.K / kBK32;
+    const int s_begin = (int)((int64_t)ksteps * split / g.splits);
+    const int s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lrow = tid >> 3, lcol = (tid & 7) * 4;
+    const float* pa[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int ra = m0 + lrow + 32 * i;
+        ra = ra < g.M ? ra : g.M - 1;  // rows past the edge load a valid row; never stored
+        pa[i] = g.A + (int64_t)ra * g.lda + lcol;
+    }
+    // Omega / G / Omega+: per-workgroup base plus 32-bit byte offsets (p <= 2^20, so a
+    // 128-column block spans less than 2^31 bytes)
+    const char* b_om = (const char*)(px.om + (int64_t)n0 * px.ld);
+    const char* b_g = (const char*)(px.g + (int64_t)n0 * px.ld);
+    char* b_on = (char*)(px.om_new + (int64_t)n0 * px.ld);
+    uint32_t ob[4];
+    int jcol[4];
+    bool jvalid[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = n0 + lrow + 32 * i;
+        jvalid[i] = j - jbase < px.p;
+        jcol[i] = j - jbase;  // column within the problem: the diagonal is row jcol
+        const int jc = j < ncols ? j : ncols - 1;
+        ob[i] = (uint32_t)(((int64_t)(jc - n0) * px.ld + lcol) * 4);
+    }
+    f4 va[4], vo[4], vg[4];
+    f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    ProxAcc pacc;
+
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int r16 = lane & 15, g4 = (lane >> 4) * 4;
+
+#define F32_LOAD(step)                                                                    \
+    do {                                                                                  \
+        const int64_t ka_ = (int64_t)(step) * kBK32;                                      \
+        const uint32_t ko_ = (uint32_t)(step) * (kBK32 * 4);                              \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                   \
+            va[i] = *(const f4*)(pa[i] + ka_);                                            \
+            vo[i] = *(const f4*)(b_om + (ob[i] + ko_));                                   \
+            vg[i] = *(const f4*)(b_g + (ob[i] + ko_));                                    \
+        }                                                                                 \
+    } while (0)
+
+    // prox of the staged step into LDS stage `buf`; the owner stores Omega+ and counts
+#define F32_PRODUCE(buf, step)                                                            \
+    do {                                                                                  \
+        f4 nw_[4];                                                                        \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i)                                     \
+            _Pragma("unroll") for (int u = 0; u < 4; ++u) {                               \
+                const float a_ = fmaf(-tau_f, vg[i][u], vo[i][u]);                        \
+                const float t_ = fabsf(a_) - thr_f;                                       \
+                nw_[i][u] = t_ > 0.f ? copysignf(t_, a_) : 0.f;                           \
+            }                                                                             \
+        const int k0_ = (step) * kBK32 + lcol;                                            \
+        bool hd_[4];                                                                      \
+        bool any_ = false;                                                                \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                   \
+            hd_[i] = jvalid[i] && (unsigned)(jcol[i] - k0_) < 4u;                         \
+            any_ = any_ || hd_[i];                                                        \
+        }                                                                                 \
+        double logd_ = 0.0, nzd_ = 0.0;                                                   \
+        if (__builtin_amdgcn_ballot_w64(any_)) {                                          \
+            _Pragma("unroll") for (int i = 0; i < 4; ++i) {                               \
+                if (hd_[i]) {                                                             \
+                    const int du_ = jcol[i] - k0_;                                        \
+                    const float od_ = du_ == 0 ? vo[i][0] : du_ == 1 ? vo[i][1]           \
+                                    : du_ == 2 ? vo[i][2] : vo[i][3];                     \
+                    const float gd_ = du_ == 0 ? vg[i][0] : du_ == 1 ? vg[i][1]           \
+                                    : du_ == 2 ? vg[i][2] : vg[i][3];                     \
+                    const float wd_ = prox_one(od_, gd_, true, tau, lam, tau_f, thr_f);   \
+                    _Pragma("unroll") for (int u = 0; u < 4; ++u)                         \
+                        nw_[i][u] = u == du_ ? wd_ : nw_[i][u];                           \
+                    logd_ += wd_ > 0.f ? log((double)wd_) : -INFINITY;                    \
+                    nzd_ += wd_ != 0.f ? 1.0 : 0.0;                                       \
+                }                                                                         \
+            }                                                                             \
+        }                                                                                 \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                   \
+            *(f4*)&sA[(buf)][(lrow + 32 * i) * kLDK32 + lcol] = va[i];                    \
+            *(f4*)&sB[(buf)][(lrow + 32 * i) * kLDK32 + lcol] = nw_[i] - vo[i];           \
+        }                                                                                 \
+        if (owner) {                                                                      \
+            const uint32_t ko_ = (uint32_t)(step) * (kBK32 * 4);                          \
+            float sd2_ = 0.f, sdg_ = 0.f, sl1_ = 0.f, sfr_ = 0.f, snz_ = 0.f;            \
+            _Pragma("unroll") for (int i = 0; i < 4; ++i) {                               \
+                if (jvalid[i]) *(f4*)(b_on + (ob[i] + ko_)) = nw_[i];                     \
+                const float lv_ = jvalid[i] ? 1.f : 0.f;                                  \
+                _Pragma("unroll") for (int u = 0; u < 4; ++u) {                           \
+                    const float dv_ = (nw_[i][u] - vo[i][u]) * lv_;                       \
+                    const float nv_ = nw_[i][u] * lv_;                                    \
+                    sd2_ = fmaf(dv_, dv_, sd2_);                                          \
+                    sdg_ = fmaf(dv_, vg[i][u], sdg_);                                     \
+                    sl1_ += fabsf(nv_);                                                   \
+                    sfr_ = fmaf(nv_, nv_, sfr_);                                          \
+                    snz_ += nv_ != 0.f ? 1.f : 0.f;                                       \
+                }                                                                         \
+            }                                                                             \
+            pacc.d2 += (double)sd2_;                                                      \
+            pacc.dg += (double)sdg_;                                                      \
+            pacc.l1 += (double)sl1_;                                                      \
+            pacc.fro += (double)sfr_;                                                     \
+            pacc.nnz += (double)snz_ - nzd_;                                              \
+            pacc.logd += logd_;                                                           \
+        }                                                                                 \
+    } while (0)
+
+    if (s_begin < s_end) {
+        F32_LOAD(s_begin);
+        F32_PRODUCE(0, s_begin);
+        __syncthreads();
+        int cur = 0;
+        for (int s = s_begin; s < s_end; ++s) {
+            const bool more = s + 1 < s_end;
+            if (more) F32_LOAD(s + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            const float* a_base = &sA[cur][(wm + r16) * kLDK32 + g4];
+            const float* b_base = &sB[cur][(wn + r16) * kLDK32 + g4];
+#pragma unroll
+            for (int kk = 0; kk < kBK32; kk += 16) {
+                f4 af[4], bf[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) af[i] = *(const f4*)(a_base + i * 16 * kLDK32 + kk);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bf[j] = *(const f4*)(b_base + j * 16 * kLDK32 + kk);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][q], bf[j][q],
+                                                                             acc[i][j], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (more) F32_PRODUCE(cur ^ 1, s + 1);
+            __syncthreads();
+            cur ^= 1;
+        }
+    }
+#undef F32_LOAD
+#undef F32_PRODUCE
+    __syncthreads();
+    double* red = (double*)&sA[0][0];  // LDS is free after the K loop
+    if (owner) {
+        double v[6] = {pacc.d2, pacc.dg, pacc.l1, pacc.logd, pacc.nnz, pacc.fro};
+        block_sum_in<6>(v, red);
+        if (tid == 0) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) part_row[k] = v[k];
+            part_row[6] = 0.0;
+            part_row[7] = 0.0;
+        }
+        __syncthreads();
+    }
+    gemm_epilogue<EPI>(g, acc, tile_m, tile_n, split, red, nrm);
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(kThreads, 2) k_trial_fused32(GemmArgs g, ProxArgs px) {
+    if (gemm_skip(g)) return;
+    int tile_m, tile_n, split;
+    decode_tile(g, tile_m, tile_n, split);
+    trial_fused32_tile<EPI>(g, px, tile_m, tile_n, split, 0, (int)px.p, px.ls->tau,
+                            px.ls->lambda,
+                            px.part + ((int64_t)tile_n * g.splits + split) * kPartCols,
+                            g.norm_part + (int64_t)(tile_m + tile_n * g.tilesM) * kNormCols);
+}
+
+void launch_trial_fused32(const GemmArgs& a, const ProxArgs& px, hipStream_t st) {
+    const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
+    if (a.splits > 1) {
+        k_trial_fused32<EPI_PARTIAL><<<blocks, kThreads, 0, st>>>(a, px);
+        launch_splitk_reduce(a, st);
+    } else {
+        k_trial_fused32<EPI_TRIAL><<<blocks, kThreads, 0, st>>>(a, px);
+    }
+}
+
 // B-operand producer of k_trial_fused for stage `buf` holding K step `step`, written
 // without branches so that it shares one basic block with the MFMAs of the previous
 // stage and the scheduler can interleave the two: prox of the 2 x 4 staged Omega / G
@@ -2131,6 +2348,38 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32_batch(const GemmArgs* 
     gemm_f32_tile<EPI>(g, tile_m, tile_n, 0, nrm);
 }
 
+// Batched fused prox + trial product (FP32 tile of k_trial_fused32): group blockIdx.y,
+// whose problems' columns are packed along N (tpp tiles each, no split), same tile
+// order as k_gemm_f32_batch.  Each tile reads its problem's state (skipped once that
+// problem accepted or stopped), step and penalty, and leaves its prox sums in row
+// tile_n - prob * tpp of the problem's block of nprox_rows rows.
+__global__ void __launch_bounds__(kThreads, 2) k_trial_fused32_batch(
+    const GemmArgs* __restrict__ gb, const ProxArgs* __restrict__ pb, int tpp, int nprox_rows) {
+    const GemmArgs g = gb[blockIdx.y];
+    const ProxArgs px = pb[blockIdx.y];
+    const int tiles = g.tilesM * g.tilesN;
+    const int logical = blockIdx.x;
+    if (logical >= tiles) return;
+    constexpr int GM = 8;
+    const int per_group = GM * g.tilesN;
+    const int group = logical / per_group;
+    const int first_m = group * GM;
+    const int gsize = (g.tilesM - first_m) < GM ? (g.tilesM - first_m) : GM;
+    const int in_group = logical - group * per_group;
+    const int tile_m = first_m + in_group % gsize;
+    const int tile_n = in_group / gsize;
+    const int prob = tile_n / tpp;
+    const LsState* ls = px.ls + prob;
+    if (g.pred >= 1 && ls->converged) return;
+    if (g.pred >= 2 && ls->done) return;
+    const int tn = tile_n - prob * tpp;
+    double* nrm = g.norm_part +
+                  ((int64_t)prob * g.tilesM * tpp + tile_m + (int64_t)tn * g.tilesM) * kNormCols;
+    double* part_row = px.part + ((int64_t)prob * nprox_rows + tn) * kPartCols;
+    trial_fused32_tile<EPI_TRIAL>(g, px, tile_m, tile_n, 0, prob * tpp * kBN, g.N, ls->tau,
+                                  ls->lambda, part_row, nrm);
+}
+
 template <int DOUT>
 __global__ void __launch_bounds__(kThreads) k_prox_batch(const ProxArgs* __restrict__ batch) {
     const ProxArgs a = batch[blockIdx.y];
@@ -2188,6 +2437,12 @@ void launch_gemm_f32_batch(const GemmArgs* batch, int ngroups, int max_tiles, in
         k_gemm_f32_batch<EPI_GRAD><<<grid, kThreads, 0, st>>>(batch, tpp);
     else
         k_gemm_f32_batch<EPI_TRIAL><<<grid, kThreads, 0, st>>>(batch, tpp);
+}
+
+void launch_trial_fused32_batch(const GemmArgs* gb, const ProxArgs* pb, int ngroups,
+                                int max_tiles, int tpp, int nprox_rows, hipStream_t st) {
+    dim3 grid((unsigned)max_tiles, (unsigned)ngroups);
+    k_trial_fused32_batch<<<grid, kThreads, 0, st>>>(gb, pb, tpp, nprox_rows);
 }
 
 void launch_prox_batch(const ProxArgs* batch, int nprob, int nblocks, hipStream_t st) {
