@@ -679,7 +679,12 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16w(GemmArgs g) {
 
 // Fixed-order sum of the split-K partial tiles, then the trial epilogue.
 // One workgroup per tile; thread t owns the same accumulator slots it had in the
-// GEMM kernel, so (m, n) follow from (t, i, j) exactly as there.
+// GEMM kernel, so (m, n) follow from (t, i, j) exactly as there.  S > 0 is the split
+// count at compile time: every thread then issues the loads of all its 16 fragments
+// of a split together, instead of one fragment's loads per memory round trip (S = 0
+// takes the count from g.splits).  Each sum runs over s = 0, 1, ... in order and the
+// norms over the fragments in order, so every S gives the same bits.
+template <int S>
 __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
     if (g.ls) {
         if (g.pred >= 1 && g.ls->converged) return;
@@ -692,15 +697,30 @@ __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
     const int n0 = tile_n * kBN + (wave & 1) * 64 + (lane & 15);
     const int64_t tiles = (int64_t)g.tilesM * g.tilesN;
     double nv[2] = {0.0, 0.0};
-#pragma unroll 1
-    for (int idx = 0; idx < 16; ++idx) {
-        const int i = idx >> 2, j = idx & 3;
-        f4 v = f4{0.f, 0.f, 0.f, 0.f};
-        for (int s = 0; s < g.splits; ++s) {
+    if (S > 0) {
+        f4 v[16];
+#pragma unroll
+        for (int idx = 0; idx < 16; ++idx) v[idx] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
             const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kBM * kBN));
-            v += P[idx * kThreads + tid];
+#pragma unroll
+            for (int idx = 0; idx < 16; ++idx) v[idx] += P[idx * kThreads + tid];
         }
-        store_frag<EPI_TRIAL>(g, v, m0 + 16 * i, n0 + 16 * j, nv);
+#pragma unroll
+        for (int idx = 0; idx < 16; ++idx)
+            store_frag<EPI_TRIAL>(g, v[idx], m0 + 16 * (idx >> 2), n0 + 16 * (idx & 3), nv);
+    } else {
+#pragma unroll 1
+        for (int idx = 0; idx < 16; ++idx) {
+            const int i = idx >> 2, j = idx & 3;
+            f4 v = f4{0.f, 0.f, 0.f, 0.f};
+            for (int s = 0; s < g.splits; ++s) {
+                const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kBM * kBN));
+                v += P[idx * kThreads + tid];
+            }
+            store_frag<EPI_TRIAL>(g, v, m0 + 16 * i, n0 + 16 * j, nv);
+        }
     }
     block_sum<2>(nv);
     if (tid == 0) {
@@ -736,7 +756,12 @@ void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st) {
 
 void launch_splitk_reduce(const GemmArgs& a, hipStream_t st) {
     const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN);
-    k_splitk_reduce<<<blocks, kThreads, 0, st>>>(a);
+    switch (a.splits) {
+        case 2: k_splitk_reduce<2><<<blocks, kThreads, 0, st>>>(a); break;
+        case 3: k_splitk_reduce<3><<<blocks, kThreads, 0, st>>>(a); break;
+        case 4: k_splitk_reduce<4><<<blocks, kThreads, 0, st>>>(a); break;
+        default: k_splitk_reduce<0><<<blocks, kThreads, 0, st>>>(a); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1433,6 +1458,9 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
 
 // Split-K reduction for the fused tiles (same thread -> fragment map as
 // k_trial_fused); kFReduceParts workgroups per tile, norm row = part * tiles + tile.
+// S > 0: the split count at compile time, so that a thread's loads of one split are
+// issued together (as in k_splitk_reduce; same order of every sum for every S).
+template <int S>
 __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_f(GemmArgs g) {
     if (g.ls) {
         if (g.pred >= 1 && g.ls->converged) return;
@@ -1446,21 +1474,49 @@ __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_f(GemmArgs g) {
     const int nw = tile_n * kFBN + (wave & 1) * 64 + (lane & 31);
     constexpr int PER = 16 / kFReduceParts;
     double nv[2] = {0.0, 0.0};
-#pragma unroll 1
-    for (int idx = part * PER; idx < (part + 1) * PER; ++idx) {
-        const int i = idx >> 3, j = (idx >> 2) & 1, q = idx & 3;
-        f4 v = f4{0.f, 0.f, 0.f, 0.f};
-        for (int s = 0; s < g.splits; ++s) {
+    if (S > 0) {
+        f4 v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) v[u] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
             const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kFBM * kFBN));
-            v += P[idx * kWThreads + tid];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) v[u] += P[(part * PER + u) * kWThreads + tid];
         }
-        store_frag<EPI_TRIAL>(g, v, mw + 32 * i + 8 * q, nw + 32 * j, nv);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = part * PER + u;
+            const int i = idx >> 3, j = (idx >> 2) & 1, q = idx & 3;
+            store_frag<EPI_TRIAL>(g, v[u], mw + 32 * i + 8 * q, nw + 32 * j, nv);
+        }
+    } else {
+#pragma unroll 1
+        for (int idx = part * PER; idx < (part + 1) * PER; ++idx) {
+            const int i = idx >> 3, j = (idx >> 2) & 1, q = idx & 3;
+            f4 v = f4{0.f, 0.f, 0.f, 0.f};
+            for (int s = 0; s < g.splits; ++s) {
+                const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kFBM * kFBN));
+                v += P[idx * kWThreads + tid];
+            }
+            store_frag<EPI_TRIAL>(g, v, mw + 32 * i + 8 * q, nw + 32 * j, nv);
+        }
     }
     block_sum<2, kWThreads / 64>(nv);
     if (tid == 0) {
         const int64_t row = (int64_t)part * tiles + tile;
         g.norm_part[row * kNormCols + 0] = nv[0];
         g.norm_part[row * kNormCols + 1] = nv[1];
+    }
+}
+
+void launch_splitk_reduce_f(const GemmArgs& a, hipStream_t st) {
+    const unsigned blocks = (unsigned)(a.tilesM * a.tilesN * kFReduceParts);
+    switch (a.splits) {
+        case 2: k_splitk_reduce_f<2><<<blocks, kWThreads, 0, st>>>(a); break;
+        case 3: k_splitk_reduce_f<3><<<blocks, kWThreads, 0, st>>>(a); break;
+        case 4: k_splitk_reduce_f<4><<<blocks, kWThreads, 0, st>>>(a); break;
+        default: k_splitk_reduce_f<0><<<blocks, kWThreads, 0, st>>>(a); break;
     }
 }
 
@@ -1475,7 +1531,7 @@ void launch_trial_fused(const GemmArgs& a, const ProxArgs& px, int prec, hipStre
             k_trial_fused<3, EPI_PARTIAL><<<blocks, kWThreads, 0, st>>>(a, px);
         else
             k_trial_fused<1, EPI_PARTIAL><<<blocks, kWThreads, 0, st>>>(a, px);
-        k_splitk_reduce_f<<<(unsigned)(a.tilesM * a.tilesN * kFReduceParts), kWThreads, 0, st>>>(a);
+        launch_splitk_reduce_f(a, st);
     } else {
         if (prec == PREC_BF16X3)
             k_trial_fused<3, EPI_TRIAL><<<blocks, kWThreads, 0, st>>>(a, px);
@@ -2004,7 +2060,7 @@ void launch_trial_fused8(const GemmArgs& a, const ProxArgs& px, hipStream_t st) 
     const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
     if (a.splits > 1) {
         k_trial_fused8<EPI_PARTIAL><<<blocks, kWThreads, 0, st>>>(a, px);
-        k_splitk_reduce_f<<<(unsigned)(a.tilesM * a.tilesN * kFReduceParts), kWThreads, 0, st>>>(a);
+        launch_splitk_reduce_f(a, st);
     } else {
         k_trial_fused8<EPI_TRIAL><<<blocks, kWThreads, 0, st>>>(a, px);
     }
