@@ -102,8 +102,9 @@ def kernel_report(stats, form, n, p, workload_ok_for_traffic):
               in and Omega+ out (12 p^2 algorithmic bytes against HBM) and executes
               2 n p^2 flops per MFMA pass; the bound is the larger of the two lower
               bounds (MFMA for fp32 at these sizes, HBM for the bf16 and fp8 forms).
-    prox      separate prox launches (none in the fit of any form since the FP32 form
-              fused its prox too): 16 p^2 bytes (read Omega, G; write Omega+, Delta)."""
+    prox      separate prox launches (the FP32 form with more than 4 row tiles of 128
+              samples, whose trial is then the plain FP32 GEMM): 16 p^2 bytes (read Omega,
+              G; write Omega+, Delta)."""
     flops = 2.0 * n * p * p
     peak = PEAK_TFLOPS[form]
     traffic = _traffic_table() if workload_ok_for_traffic else {}
@@ -127,14 +128,17 @@ def kernel_report(stats, form, n, p, workload_ok_for_traffic):
     ms, cnt, avg = group("trial_gemm")
     if avg:
         a = flops / (avg * 1e-3) / 1e12
-        names = (["k_trial_fused32<2>", "k_splitk_reduce"] if form == "fp32" else
+        sep = group("prox")[1] > 0  # FP32 with a separate prox pass: plain trial GEMM
+        names = ((["k_gemm_f32<2>" if sep else "k_trial_fused32<2>", "k_splitk_reduce"])
+                 if form == "fp32" else
                  ["k_trial_fused8<2>", "k_splitk_reduce_f"] if form == "fp8" else
                  [f"k_trial_fused<{PASSES[form]}, 2>", "k_splitk_reduce_f"])
         alg = 12.0 * p * p
         gbs = alg / (avg * 1e-3) / 1e9
         t_hbm = alg / (PEAK_HBM_GBS * 1e9)
         t_mfma = flops * PASSES[form] / (peak * 1e12)
-        d = {"what": "fused prox (eq. 3.5) + W+ = W + X Delta (+ norms)",
+        d = {"what": "W+ = W + X Delta (+ norms)" if sep else
+                     "fused prox (eq. 3.5) + W+ = W + X Delta (+ norms)",
              "algorithmic_bytes": alg,
              "mfma": {"achieved": a * PASSES[form], "peak": peak, "unit": "TFLOP/s",
                       "frac": a * PASSES[form] / peak, "useful_tflops": a}}
@@ -154,8 +158,15 @@ def kernel_report(stats, form, n, p, workload_ok_for_traffic):
                        "launches": cnt, "avg_ms": avg, "total_ms": ms, "bound": "hbm",
                        "algorithmic_bytes": alg, "achieved": a, "peak": PEAK_HBM_GBS,
                        "unit": "GB/s", "frac": a / PEAK_HBM_GBS}
+    def measured(k):
+        # exact name, else the one instantiation of a kernel templated on the split count
+        if f"void {k}" in traffic or k in traffic:
+            return traffic.get(f"void {k}", traffic.get(k))
+        inst = [v for name, v in traffic.items() if name.startswith(f"void {k}<")]
+        return inst[0] if len(inst) == 1 else None
+
     for d in out.values():
-        got = [traffic.get(f"void {k}", traffic.get(k)) for k in d["kernels"]]
+        got = [measured(k) for k in d["kernels"]]
         d["traffic"] = sum(got) if got and all(g is not None for g in got) else None
     return out
 

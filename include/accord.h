@@ -143,8 +143,13 @@ typedef struct {
     double lipschitz;       /* L used for the step floor */
     /* per-kernel device time (params.timing == 1; executed launches only) */
     double grad_gemm_ms;    int32_t grad_gemm_launches;   /* G = X^T W / n          */
-    double trial_gemm_ms;   int32_t trial_gemm_launches;  /* W+ = W + X Delta       */
-    double prox_ms;         int32_t prox_launches;        /* fused prox + reductions */
+    double trial_gemm_ms;   int32_t trial_gemm_launches;  /* W+ = W + X Delta, with the
+                                                             prox (eq. 3.5) inside except
+                                                             as below                  */
+    double prox_ms;         int32_t prox_launches;        /* separate prox pass: only the
+                                                             FP32 form with n > 512 (more
+                                                             than 4 row tiles of 128
+                                                             samples); 0 launches else */
     double total_ms;        /* event time of the whole fit on the stream */
     double log_det_d;       /* sum_j log Omega_jj at the result (log det of the diagonal) */
     double l1;              /* ||Omega||_1 at the result (all entries) */

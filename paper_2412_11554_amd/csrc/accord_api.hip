@@ -77,7 +77,8 @@ struct Plan {
     // kernel's geometry
     Geo t32, tp;
     int fused;      // bf16 and FP8 forms: the fused trial kernel's 256 x 128 geometry
-                    // (the FP32 form fuses its prox into the 128 x 128 FP32 tile)
+    int fused32;    // FP32 form: prox fused into the 128 x 128 FP32 trial tile (else a
+                    // separate prox pass writes Delta for the plain FP32 GEMM)
     int prox_rows;  // FP64 prox partial rows left per trial
     int nprox;
     size_t off_ls, off_prox_part, off_norm_part, off_pow_u, off_pow_w, off_pow_pu, off_pow_pw,
@@ -130,7 +131,13 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     P.nprox = prox_blocks(p * P.p_pad);
     // every form's fit runs the prox inside its trial kernel: one row of prox sums per
     // (column block, split)
-    P.prox_rows = P.fused ? P.tp.tilesN * P.tp.splits : P.t32.tilesN * P.t32.splits;
+    // The FP32 fused kernel recomputes the prox in each of the tilesM row tiles of a
+    // column block, while it saves one 16 B-per-entry prox pass.  Measured: faster at
+    // n = 500 (4 row tiles: 300 us against 287 + 77 us at p = 5000), slower at n = 1000
+    // (8 row tiles: 218 ms against 152 + 33 ms at p = 1e5).  So it runs up to 4 row tiles.
+    P.fused32 = !P.fused && P.t32.tilesM <= 4;
+    P.prox_rows = P.fused ? P.tp.tilesN * P.tp.splits
+                          : (P.fused32 ? P.t32.tilesN * P.t32.splits : P.nprox);
     const bool bf = is_bf16(prec);
     const bool f8 = prec == PREC_FP8;
     const int ttiles = std::max(norm_rows(P.t32, PREC_FP32), norm_rows(P.tp, prec));
@@ -582,6 +589,7 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
     const bool bf = is_bf16(prec);
     const bool f8 = prec == PREC_FP8;
     const bool fused = P.fused != 0;
+    float* D = (fused || P.fused32) ? nullptr : at<float>(ws, P.off_d);
     double* prox_part = at<double>(ws, P.off_prox_part);
     double* norm_part = at<double>(ws, P.off_norm_part);
     int32_t* trials_log = at<int32_t>(ws, P.off_trials);
@@ -665,19 +673,28 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
             a.om = om[cur];
             a.g = G;
             a.om_new = om[nxt];
+            a.d = D;
             a.total = total;
             a.ld = P.p_pad;
             a.p = p;
             a.ls = ls;
             a.part = prox_part;
-            GemmArgs ta = trial_args(P, ws, prec, nullptr, nullptr, nullptr, wt[cur], wt[nxt],
+            GemmArgs ta = trial_args(P, ws, prec, D, nullptr, nullptr, wt[cur], wt[nxt],
                                      bf ? nxt : -1, ls, 2);
+            if (D) {  // FP32 form with many row tiles: prox pass, then the plain product
+                Launch lp = {nullptr, nullptr, t, k};
+                if (timing) { lp.a = pool.get(); lp.b = pool.get(); HIP_TRY(hipEventRecord(lp.a, st)); }
+                launch_prox(a, P.nprox, st);
+                if (timing) { HIP_TRY(hipEventRecord(lp.b, st)); ev_prox.push_back(lp); }
+            }
             Launch lt = {nullptr, nullptr, t, k};
             if (timing) { lt.a = pool.get(); lt.b = pool.get(); HIP_TRY(hipEventRecord(lt.a, st)); }
             if (fused)
                 launch_trial_fused(ta, a, prec, st);
-            else
+            else if (P.fused32)
                 launch_trial_fused32(ta, a, st);
+            else
+                enqueue_trial(ta, prec, st);
             if (timing) { HIP_TRY(hipEventRecord(lt.b, st)); ev_trial.push_back(lt); }
             launch_finalize(ls, prox_part, P.prox_rows, norm_part, ttiles, trace, trials_log,
                             mbox_dev, st);

@@ -27,9 +27,11 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));  // 16-byte staging
 
 // Streaming accesses (nontemporal hint) for data touched once per launch: Omega+ from
 // the trial kernels (read again only by the next iteration's trials, after the
-// gradient has streamed G) and the split-K partial tiles (written once, read once).
-// Measured at n = 500, p = 5000: the BF16x3 trial group drops from 147 to 136 us; the
-// same hint on W+ or G made their consumers slower, so those stay ordinary stores.
+// gradient has streamed G) and the trial kernels' split-K partial tiles (written once,
+// read once by the reduce).  Measured at n = 500, p = 5000: the BF16x3 trial group
+// drops from 147 to 136 us.  The same hint on W+, G, the Omega / G loads or the plain
+// FP32 GEMM's partials (the differentiation form's) made things slower, so those stay
+// ordinary accesses.
 __device__ __forceinline__ void st_stream(f4 v, f4* p) { __builtin_nontemporal_store(v, p); }
 __device__ __forceinline__ f4 ld_stream(const f4* p) { return __builtin_nontemporal_load(p); }
 
@@ -373,7 +375,9 @@ __device__ inline void store_frag(const GemmArgs& g, f4 v, int m, int n, double 
 }
 
 // Epilogue shared by all GEMM kernels (thread t owns fragments (i, j) of its wave).
-template <int EPI>
+// STREAM: partial tiles written with the streaming hint (the fused FP32 trial; the
+// plain GEMM's partials, e.g. the differentiation form's, stay ordinary stores).
+template <int EPI, bool STREAM = false>
 __device__ inline void gemm_epilogue(const GemmArgs& g, f4 (&acc)[4][4], int tile_m, int tile_n,
                                      int split, double* red_lds, double* nrm) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -383,7 +387,12 @@ __device__ inline void gemm_epilogue(const GemmArgs& g, f4 (&acc)[4][4], int til
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) st_stream(acc[i][j], &P[(i * 4 + j) * kThreads + tid]);
+            for (int j = 0; j < 4; ++j) {
+                if (STREAM)
+                    st_stream(acc[i][j], &P[(i * 4 + j) * kThreads + tid]);
+                else
+                    P[(i * 4 + j) * kThreads + tid] = acc[i][j];
+            }
         return;
     }
     const int m0 = tile_m * kBM + (wave >> 1) * 64 + (lane >> 4) * 4;
@@ -691,8 +700,9 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16w(GemmArgs g) {
 // count at compile time: every thread then issues the loads of all its 16 fragments
 // of a split together, instead of one fragment's loads per memory round trip (S = 0
 // takes the count from g.splits).  Each sum runs over s = 0, 1, ... in order and the
-// norms over the fragments in order, so every S gives the same bits.
-template <int S>
+// norms over the fragments in order, so every S gives the same bits.  STREAM: the
+// partials are read with the streaming hint (those of the fused FP32 trial).
+template <int S, bool STREAM>
 __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
     if (g.ls) {
         if (g.pred >= 1 && g.ls->converged) return;
@@ -713,7 +723,8 @@ __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
         for (int s = 0; s < S; ++s) {
             const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kBM * kBN));
 #pragma unroll
-            for (int idx = 0; idx < 16; ++idx) v[idx] += ld_stream(&P[idx * kThreads + tid]);
+            for (int idx = 0; idx < 16; ++idx)
+                v[idx] += STREAM ? ld_stream(&P[idx * kThreads + tid]) : P[idx * kThreads + tid];
         }
 #pragma unroll
         for (int idx = 0; idx < 16; ++idx)
@@ -725,7 +736,7 @@ __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
             f4 v = f4{0.f, 0.f, 0.f, 0.f};
             for (int s = 0; s < g.splits; ++s) {
                 const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kBM * kBN));
-                v += ld_stream(&P[idx * kThreads + tid]);
+                v += STREAM ? ld_stream(&P[idx * kThreads + tid]) : P[idx * kThreads + tid];
             }
             store_frag<EPI_TRIAL>(g, v, m0 + 16 * i, n0 + 16 * j, nv);
         }
@@ -762,14 +773,19 @@ void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st) {
         k_gemm_f32<EPI_PARTIAL><<<blocks, kThreads, 0, st>>>(a);
 }
 
-void launch_splitk_reduce(const GemmArgs& a, hipStream_t st) {
+template <bool STREAM>
+void launch_splitk_reduce_t(const GemmArgs& a, hipStream_t st) {
     const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN);
     switch (a.splits) {
-        case 2: k_splitk_reduce<2><<<blocks, kThreads, 0, st>>>(a); break;
-        case 3: k_splitk_reduce<3><<<blocks, kThreads, 0, st>>>(a); break;
-        case 4: k_splitk_reduce<4><<<blocks, kThreads, 0, st>>>(a); break;
-        default: k_splitk_reduce<0><<<blocks, kThreads, 0, st>>>(a); break;
+        case 2: k_splitk_reduce<2, STREAM><<<blocks, kThreads, 0, st>>>(a); break;
+        case 3: k_splitk_reduce<3, STREAM><<<blocks, kThreads, 0, st>>>(a); break;
+        case 4: k_splitk_reduce<4, STREAM><<<blocks, kThreads, 0, st>>>(a); break;
+        default: k_splitk_reduce<0, STREAM><<<blocks, kThreads, 0, st>>>(a); break;
     }
+}
+
+void launch_splitk_reduce(const GemmArgs& a, hipStream_t st) {
+    launch_splitk_reduce_t<false>(a, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1116,7 +1132,7 @@ __device__ __forceinline__ void trial_fused32_tile(const GemmArgs& g, const Prox
         }
         __syncthreads();
     }
-    gemm_epilogue<EPI>(g, acc, tile_m, tile_n, split, red, nrm);
+    gemm_epilogue<EPI, true>(g, acc, tile_m, tile_n, split, red, nrm);
 }
 
 template <int EPI>
@@ -1134,7 +1150,7 @@ void launch_trial_fused32(const GemmArgs& a, const ProxArgs& px, hipStream_t st)
     const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
     if (a.splits > 1) {
         k_trial_fused32<EPI_PARTIAL><<<blocks, kThreads, 0, st>>>(a, px);
-        launch_splitk_reduce(a, st);
+        launch_splitk_reduce_t<true>(a, st);
     } else {
         k_trial_fused32<EPI_TRIAL><<<blocks, kThreads, 0, st>>>(a, px);
     }

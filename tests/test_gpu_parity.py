@@ -232,8 +232,12 @@ def test_fit_benchmark_shape_sampled_columns(gpu_lib, dev):
     assert np.all(tr[1:, 4] >= 1)
 
 
+# n <= 512 runs the FP32 trial with the prox fused into it (at most 4 row tiles of 128
+# samples); n = 600 (5 row tiles) and 1100 take the separate prox pass and the plain
+# FP32 product
 @pytest.mark.parametrize("n,p,lam,iters", [(33, 97, 0.1, 40), (3, 1, 0.2, 10), (1, 2, 0.1, 5),
-                                           (130, 129, 0.05, 25)])
+                                           (130, 129, 0.05, 25), (600, 257, 0.1, 30),
+                                           (1100, 70, 0.1, 20)])
 def test_fit_ragged_shapes(gpu_lib, dev, n, p, lam, iters):
     print(f"fit n={n} p={p}", flush=True)
     rng = np.random.default_rng(n * 1000 + p)
@@ -244,6 +248,17 @@ def test_fit_ragged_shapes(gpu_lib, dev, n, p, lam, iters):
     assert stats["iters"] == iters
     rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
     assert rel <= 1e-4, rel
+
+
+def test_fp32_trial_path_by_row_tiles(gpu_lib, dev):
+    """The FP32 form fuses its prox into the trial product up to 4 row tiles of 128
+    samples and launches a separate prox pass beyond (the launch counts say which)."""
+    rng = np.random.default_rng(7)
+    for n, fused in ((512, True), (513, False)):
+        x = rng.normal(size=(n, 40)).astype(np.float32)
+        _, st, _ = gpu_lib.accord_fit(_t(x, dev), 0.1, 5, timing=True)
+        assert st["iters"] == 5 and st["trial_gemm_launches"] >= 5
+        assert (st["prox_launches"] == 0) == fused, (n, st["prox_launches"])
 
 
 def test_fit_fixed_step_and_start_point(gpu_lib, dev):
