@@ -1480,50 +1480,84 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
     }
 }
 
-// Split-K reduction for the fused tiles (same thread -> fragment map as
-// k_trial_fused); kFReduceParts workgroups per tile, norm row = part * tiles + tile.
-// S > 0: the split count at compile time, so that a thread's loads of one split are
-// issued together (as in k_splitk_reduce; same order of every sum for every S).
+// Split-K reduction for the fused tiles; kFReduceParts (2) workgroups per tile, part
+// p owning the rows 64 c + 32 p .. + 31 (c = 0..3) of the tile, norm row =
+// part * tiles + tile.  S > 0: the split count at compile time, so that a thread's
+// loads of one split are issued together (S = 0 takes it from g.splits).
+// The partial fragments are summed in the GEMM's thread -> fragment map (coalesced
+// reads, each sum over s = 0, 1, ... in order), then turned through LDS so that the
+// epilogue walks W column by column: 8 lanes cover 32 consecutive samples of a column,
+// so W, W+ and its bf16 split move in whole 128-byte lines.
 template <int S>
 __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_f(GemmArgs g) {
+    static_assert(kFReduceParts == 2, "part p owns fragment row block i = p");
     if (g.ls) {
         if (g.pred >= 1 && g.ls->converged) return;
         if (g.pred >= 2 && g.ls->done) return;
     }
+    constexpr int LDR = 132;  // LDS floats per column (128 rows + 4: 16 lanes hit 64 banks)
+    __shared__ __attribute__((aligned(16))) float sT[kFBN * LDR];
     const int tiles = g.tilesM * g.tilesN;
     const int tile = blockIdx.x % tiles, part = blockIdx.x / tiles;
     const int tile_m = tile % g.tilesM, tile_n = tile / g.tilesM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int mw = tile_m * kFBM + (wave >> 1) * 64 + 4 * (lane >> 5);
-    const int nw = tile_n * kFBN + (wave & 1) * 64 + (lane & 31);
     constexpr int PER = 16 / kFReduceParts;
-    double nv[2] = {0.0, 0.0};
-    if (S > 0) {
-        f4 v[PER];
+    f4 v[PER];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) v[u] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < PER; ++u) v[u] = f4{0.f, 0.f, 0.f, 0.f};
+    if (S > 0) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kFBM * kFBN));
 #pragma unroll
             for (int u = 0; u < PER; ++u) v[u] += ld_stream(&P[(part * PER + u) * kWThreads + tid]);
         }
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int idx = part * PER + u;
-            const int i = idx >> 3, j = (idx >> 2) & 1, q = idx & 3;
-            store_frag<EPI_TRIAL>(g, v[u], mw + 32 * i + 8 * q, nw + 32 * j, nv);
-        }
     } else {
-#pragma unroll 1
-        for (int idx = part * PER; idx < (part + 1) * PER; ++idx) {
-            const int i = idx >> 3, j = (idx >> 2) & 1, q = idx & 3;
-            f4 v = f4{0.f, 0.f, 0.f, 0.f};
-            for (int s = 0; s < g.splits; ++s) {
-                const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kFBM * kFBN));
-                v += ld_stream(&P[idx * kWThreads + tid]);
+        for (int s = 0; s < g.splits; ++s) {
+            const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kFBM * kFBN));
+#pragma unroll
+            for (int u = 0; u < PER; ++u) v[u] += ld_stream(&P[(part * PER + u) * kWThreads + tid]);
+        }
+    }
+    // fragment (i = part, j, q) of this thread: rows 32 part + 8 q + 4 (lane / 32) .. + 3 of
+    // the wave's 64-row block, column (wave & 1) 64 + lane % 32 + 32 j
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int j = (u >> 2) & 1, q = u & 3;
+        const int rl = (wave >> 1) * 32 + 8 * q + 4 * (lane >> 5);
+        const int cl = (wave & 1) * 64 + (lane & 31) + 32 * j;
+        *(f4*)&sT[cl * LDR + rl] = v[u];
+    }
+    __syncthreads();
+    double nv[2] = {0.0, 0.0};
+    constexpr int ITEMS = kFBN * 32 / kWThreads;  // f4 per thread: 128 columns x 32 quads
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int e = tid + kWThreads * k;
+        const int cl = e >> 5, rl = (e & 31) * 4;
+        const int m = tile_m * kFBM + (rl >> 5) * 64 + 32 * part + (rl & 31);
+        const int n = tile_n * kFBN + cl;
+        if (n >= g.N || m >= g.M) continue;
+        const f4 d = *(const f4*)&sT[cl * LDR + rl] * g.alpha;  // alpha = 1 in the trials
+        const int64_t off = (int64_t)n * g.ldc + m;  // ldc % 4 == 0: 16-byte aligned quads
+        const f4 w = g.Wprev ? *(const f4*)(g.Wprev + off) : f4{0.f, 0.f, 0.f, 0.f};
+        const f4 out = w + d;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (m + r < g.Mvalid && n < g.Nvalid) {
+                nv[0] += (double)d[r] * (double)d[r];
+                nv[1] += (double)out[r] * (double)out[r];
             }
-            store_frag<EPI_TRIAL>(g, v, mw + 32 * i + 8 * q, nw + 32 * j, nv);
+        }
+        *(f4*)(g.C + off) = out;
+        if (g.Ch) {
+            uint16_t h[4], l[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) split_bf16(out[r], h[r], l[r]);
+            *(uint2*)(g.Ch + off) = make_uint2(h[0] | ((uint32_t)h[1] << 16),
+                                               h[2] | ((uint32_t)h[3] << 16));
+            *(uint2*)(g.Cl + off) = make_uint2(l[0] | ((uint32_t)l[1] << 16),
+                                               l[2] | ((uint32_t)l[3] << 16));
         }
     }
     block_sum<2, kWThreads / 64>(nv);
