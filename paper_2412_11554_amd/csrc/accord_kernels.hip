@@ -694,52 +694,54 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16w(GemmArgs g) {
     }
 }
 
-// Fixed-order sum of the split-K partial tiles, then the trial epilogue.
-// One workgroup per tile; thread t owns the same accumulator slots it had in the
-// GEMM kernel, so (m, n) follow from (t, i, j) exactly as there.  S > 0 is the split
-// count at compile time: every thread then issues the loads of all its 16 fragments
-// of a split together, instead of one fragment's loads per memory round trip (S = 0
-// takes the count from g.splits).  Each sum runs over s = 0, 1, ... in order and the
-// norms over the fragments in order, so every S gives the same bits.  STREAM: the
-// partials are read with the streaming hint (those of the fused FP32 trial).
+// Fixed-order sum of the split-K partial tiles, then the trial epilogue.  One
+// workgroup per tile.  Thread t first sums the 16 fragments it owned in the GEMM
+// kernel (coalesced reads of the partials; each sum over s = 0, 1, ... in order), then
+// the tile is turned through LDS so that the epilogue walks W column by column: a
+// wave covers two columns of 128 samples, so W, W+ (and its bf16 split) move in whole
+// lines.  S > 0 is the split count at compile time, so that a thread's loads of one
+// split are issued together (S = 0 takes it from g.splits).  STREAM: the partials are
+// read with the streaming hint (those of the fused FP32 trial).
 template <int S, bool STREAM>
 __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
     if (g.ls) {
         if (g.pred >= 1 && g.ls->converged) return;
         if (g.pred >= 2 && g.ls->done) return;
     }
+    constexpr int LDR = kBM + 4;  // LDS floats per column (16 lanes of a quad write hit 64 banks)
+    __shared__ __attribute__((aligned(16))) float sT[kBN * LDR];
     const int tile = blockIdx.x;
     const int tile_m = tile % g.tilesM, tile_n = tile / g.tilesM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = tile_m * kBM + (wave >> 1) * 64 + (lane >> 4) * 4;
-    const int n0 = tile_n * kBN + (wave & 1) * 64 + (lane & 15);
     const int64_t tiles = (int64_t)g.tilesM * g.tilesN;
-    double nv[2] = {0.0, 0.0};
-    if (S > 0) {
-        f4 v[16];
+    f4 v[16];
 #pragma unroll
-        for (int idx = 0; idx < 16; ++idx) v[idx] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kBM * kBN));
-#pragma unroll
-            for (int idx = 0; idx < 16; ++idx)
-                v[idx] += STREAM ? ld_stream(&P[idx * kThreads + tid]) : P[idx * kThreads + tid];
-        }
+    for (int idx = 0; idx < 16; ++idx) v[idx] = f4{0.f, 0.f, 0.f, 0.f};
+    const int nsplit = S > 0 ? S : g.splits;
+    constexpr int kUnroll = S > 0 ? S : 1;
+#pragma unroll kUnroll
+    for (int s = 0; s < nsplit; ++s) {
+        const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kBM * kBN));
 #pragma unroll
         for (int idx = 0; idx < 16; ++idx)
-            store_frag<EPI_TRIAL>(g, v[idx], m0 + 16 * (idx >> 2), n0 + 16 * (idx & 3), nv);
-    } else {
-#pragma unroll 1
-        for (int idx = 0; idx < 16; ++idx) {
-            const int i = idx >> 2, j = idx & 3;
-            f4 v = f4{0.f, 0.f, 0.f, 0.f};
-            for (int s = 0; s < g.splits; ++s) {
-                const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kBM * kBN));
-                v += STREAM ? ld_stream(&P[idx * kThreads + tid]) : P[idx * kThreads + tid];
-            }
-            store_frag<EPI_TRIAL>(g, v, m0 + 16 * i, n0 + 16 * j, nv);
-        }
+            v[idx] += STREAM ? ld_stream(&P[idx * kThreads + tid]) : P[idx * kThreads + tid];
+    }
+    // fragment (i, j) of this thread: rows (wave / 2) 64 + 4 (lane / 16) + 16 i .. + 3,
+    // column (wave & 1) 64 + lane % 16 + 16 j of the tile
+#pragma unroll
+    for (int idx = 0; idx < 16; ++idx) {
+        const int rl = (wave >> 1) * 64 + (lane >> 4) * 4 + 16 * (idx >> 2);
+        const int cl = (wave & 1) * 64 + (lane & 15) + 16 * (idx & 3);
+        *(f4*)&sT[cl * LDR + rl] = v[idx];
+    }
+    __syncthreads();
+    double nv[2] = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < kBN * (kBM / 4) / kThreads; ++k) {
+        const int e = tid + kThreads * k;
+        const int cl = e / (kBM / 4), rl = (e % (kBM / 4)) * 4;
+        store_frag<EPI_TRIAL>(g, *(const f4*)&sT[cl * LDR + rl], tile_m * kBM + rl,
+                              tile_n * kBN + cl, nv);
     }
     block_sum<2>(nv);
     if (tid == 0) {
@@ -780,6 +782,10 @@ void launch_splitk_reduce_t(const GemmArgs& a, hipStream_t st) {
         case 2: k_splitk_reduce<2, STREAM><<<blocks, kThreads, 0, st>>>(a); break;
         case 3: k_splitk_reduce<3, STREAM><<<blocks, kThreads, 0, st>>>(a); break;
         case 4: k_splitk_reduce<4, STREAM><<<blocks, kThreads, 0, st>>>(a); break;
+        case 5: k_splitk_reduce<5, STREAM><<<blocks, kThreads, 0, st>>>(a); break;
+        case 6: k_splitk_reduce<6, STREAM><<<blocks, kThreads, 0, st>>>(a); break;
+        case 7: k_splitk_reduce<7, STREAM><<<blocks, kThreads, 0, st>>>(a); break;
+        case 8: k_splitk_reduce<8, STREAM><<<blocks, kThreads, 0, st>>>(a); break;
         default: k_splitk_reduce<0, STREAM><<<blocks, kThreads, 0, st>>>(a); break;
     }
 }
@@ -1486,8 +1492,8 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
 // loads of one split are issued together (S = 0 takes it from g.splits).
 // The partial fragments are summed in the GEMM's thread -> fragment map (coalesced
 // reads, each sum over s = 0, 1, ... in order), then turned through LDS so that the
-// epilogue walks W column by column: 8 lanes cover 32 consecutive samples of a column,
-// so W, W+ and its bf16 split move in whole 128-byte lines.
+// epilogue (store_frag) walks W column by column: 8 lanes cover 32 consecutive samples
+// of a column, so W, W+ and its bf16 split move in whole 128-byte lines.
 template <int S>
 __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_f(GemmArgs g) {
     static_assert(kFReduceParts == 2, "part p owns fragment row block i = p");
@@ -1537,28 +1543,7 @@ __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_f(GemmArgs g) {
         const int cl = e >> 5, rl = (e & 31) * 4;
         const int m = tile_m * kFBM + (rl >> 5) * 64 + 32 * part + (rl & 31);
         const int n = tile_n * kFBN + cl;
-        if (n >= g.N || m >= g.M) continue;
-        const f4 d = *(const f4*)&sT[cl * LDR + rl] * g.alpha;  // alpha = 1 in the trials
-        const int64_t off = (int64_t)n * g.ldc + m;  // ldc % 4 == 0: 16-byte aligned quads
-        const f4 w = g.Wprev ? *(const f4*)(g.Wprev + off) : f4{0.f, 0.f, 0.f, 0.f};
-        const f4 out = w + d;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (m + r < g.Mvalid && n < g.Nvalid) {
-                nv[0] += (double)d[r] * (double)d[r];
-                nv[1] += (double)out[r] * (double)out[r];
-            }
-        }
-        *(f4*)(g.C + off) = out;
-        if (g.Ch) {
-            uint16_t h[4], l[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) split_bf16(out[r], h[r], l[r]);
-            *(uint2*)(g.Ch + off) = make_uint2(h[0] | ((uint32_t)h[1] << 16),
-                                               h[2] | ((uint32_t)h[3] << 16));
-            *(uint2*)(g.Cl + off) = make_uint2(l[0] | ((uint32_t)l[1] << 16),
-                                               l[2] | ((uint32_t)l[3] << 16));
-        }
+        store_frag<EPI_TRIAL>(g, *(const f4*)&sT[cl * LDR + rl], m, n, nv);
     }
     block_sum<2, kWThreads / 64>(nv);
     if (tid == 0) {
