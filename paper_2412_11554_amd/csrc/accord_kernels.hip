@@ -380,8 +380,18 @@ __device__ inline void store_frag(const GemmArgs& g, f4 v, int m, int n, double 
 }
 
 // Epilogue shared by all GEMM kernels (thread t owns fragments (i, j) of its wave).
-// STREAM: partial tiles written with the streaming hint (the fused FP32 trial; the
-// plain GEMM's partials, e.g. the differentiation form's, stay ordinary stores).
+// Column-walk epilogues turn a wave's 64-column block through LDS 32 rows at a time:
+// kEpiLDR floats per column (32 rows + 4, so that 16 lanes writing a quad of rows each
+// cover all 64 banks), one region of 64 columns per wave.
+constexpr int kEpiLDR = 32 + 4;
+constexpr int kEpiFloats = (kWThreads / 64) * 64 * kEpiLDR;  // the 512-thread GEMMs
+
+// Epilogue of the FP32 tile (4 waves of 64 x 64, 16x16 accumulators).  EPI_GRAD walks
+// the tile column by column through LDS (lds: the tile's idle A stages, at least
+// 4 x 64 x kEpiLDR floats), so that 8 lanes store 32 consecutive rows of a column (a
+// 128-byte line) and G takes the streaming hint.  STREAM: partial tiles
+// written with the streaming hint (the fused FP32 trial; the plain GEMM's partials,
+// e.g. the differentiation form's, stay ordinary stores).
 template <int EPI, bool STREAM = false>
 __device__ inline void gemm_epilogue(const GemmArgs& g, f4 (&acc)[4][4], int tile_m, int tile_n,
                                      int split, double* red_lds, double* nrm) {
@@ -400,19 +410,44 @@ __device__ inline void gemm_epilogue(const GemmArgs& g, f4 (&acc)[4][4], int til
             }
         return;
     }
-    const int m0 = tile_m * kBM + (wave >> 1) * 64 + (lane >> 4) * 4;
-    const int n0 = tile_n * kBN + (wave & 1) * 64 + (lane & 15);
     double nv[2] = {0.0, 0.0};
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) store_frag<EPI>(g, acc[i][j], m0 + 16 * i, n0 + 16 * j, nv);
     if (EPI == EPI_TRIAL) {
+        // the trial products keep the fragment-order stores (the column walk measured no
+        // better for them at n = 1000, p = 1e5)
+        const int m0 = tile_m * kBM + (wave >> 1) * 64 + (lane >> 4) * 4;
+        const int n0 = tile_n * kBN + (wave & 1) * 64 + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                store_frag<EPI>(g, acc[i][j], m0 + 16 * i, n0 + 16 * j, nv);
         block_sum_in<2>(nv, red_lds);  // the tile LDS is free after the K loop
         if (tid == 0) {
             nrm[0] = nv[0];
             nrm[1] = nv[1];
         }
+        return;
+    }
+    const int mw = tile_m * kBM + (wave >> 1) * 64, nw = tile_n * kBN + (wave & 1) * 64;
+    float* sw = (float*)red_lds + wave * (64 * kEpiLDR);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        // fragment (i, j): rows 16 i + 4 (lane / 16) .. + 3, column 16 j + lane % 16
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                *(f4*)&sw[(16 * j + (lane & 15)) * kEpiLDR + 16 * i + (lane >> 4) * 4] =
+                    acc[2 * h + i][j];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = lane + 64 * k;
+            const int c = e >> 3, r = (e & 7) * 4;
+            store_frag<EPI, true>(g, *(const f4*)&sw[c * kEpiLDR + r], mw + 32 * h + r, nw + c,
+                                  nv);
+        }
+        __syncthreads();
     }
 }
 
@@ -508,6 +543,8 @@ __device__ __forceinline__ void gemm_f32_tile(const GemmArgs& g, int tile_m, int
         }
     }
     __syncthreads();
+    static_assert(sizeof(sA) >= (size_t)(kThreads / 64) * 64 * kEpiLDR * sizeof(float),
+                  "the epilogue's LDS regions live in sA");
     gemm_epilogue<EPI>(g, acc, tile_m, tile_n, split, (double*)&sA[0][0], nrm);
 }
 
@@ -540,9 +577,6 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 // measured at n = 500, p = 5000, the BF16x3 trials that read G next drop from 136 to
 // 130 us and the gradient from 115 to 114 us (with partial lines the hint cost the
 // gradient 50 us).
-constexpr int kEpiLDR = 32 + 4;
-constexpr int kEpiFloats = (kWThreads / 64) * 64 * kEpiLDR;
-
 template <int EPI>
 __device__ __forceinline__ void grad_epilogue_cols(const GemmArgs& g, const f16v (&acc)[4][2],
                                                    float* sT, int m0w, int n0w,
@@ -1186,6 +1220,8 @@ __device__ __forceinline__ void trial_fused32_tile(const GemmArgs& g, const Prox
         }
         __syncthreads();
     }
+    static_assert(sizeof(sA) >= (size_t)(kThreads / 64) * 64 * kEpiLDR * sizeof(float),
+                  "the epilogue's LDS regions live in sA");
     gemm_epilogue<EPI, true>(g, acc, tile_m, tile_n, split, red, nrm);
 }
 
