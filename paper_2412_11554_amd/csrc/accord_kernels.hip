@@ -310,22 +310,30 @@ __device__ inline bool gemm_skip(const GemmArgs& g) {
 // With Ch/Cl set, the bf16 hi/lo split of the stored value is written as well.
 // NT: the FP32 value goes out with the streaming hint (the bf16 gradient's G, written
 // in whole 128-byte lines by its column-walk epilogue and read once by the next trials).
+// Support bytes of rows m..m+3 of column n (the refit's G mask; all ones without one).
+__device__ inline uint32_t load_mask4(const GemmArgs& g, int m, int n) {
+    if (!g.cmask || n >= g.N || m >= g.M) return 0x01010101u;
+    const int64_t off = (int64_t)n * g.ldc + m;
+    if (g.vec_store && m + 3 < g.M) return *(const uint32_t*)(g.cmask + off);
+    uint32_t m4 = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) m4 |= (m + r < g.M ? (uint32_t)g.cmask[off + r] : 0u) << (8 * r);
+    return m4;
+}
+
+// m4: the support bytes of the quad, when the caller loaded them ahead of its stores
+// (kNoMask4: load them here).
+constexpr uint64_t kNoMask4 = ~0ull;
+
 template <int EPI, bool NT = false>
-__device__ inline void store_frag(const GemmArgs& g, f4 v, int m, int n, double (&nv)[2]) {
+__device__ inline void store_frag(const GemmArgs& g, f4 v, int m, int n, double (&nv)[2],
+                                  uint64_t m4pre = kNoMask4) {
     if (n >= g.N || m >= g.M) return;
     const int64_t off = (int64_t)n * g.ldc + m;
     const bool vec = g.vec_store && m + 3 < g.M;
     v = v * g.alpha;  // EPI_GRAD: 1/n; EPI_TRIAL: 1 (or the adjoint's -tau/n)
     if (EPI == EPI_GRAD && g.cmask) {  // refit: G is zero off the support
-        uint32_t m4;
-        if (vec) {
-            m4 = *(const uint32_t*)(g.cmask + off);
-        } else {
-            m4 = 0;
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                m4 |= (m + r < g.M ? (uint32_t)g.cmask[off + r] : 0u) << (8 * r);
-        }
+        const uint32_t m4 = m4pre != kNoMask4 ? (uint32_t)m4pre : load_mask4(g, m, n);
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = ((m4 >> (8 * r)) & 0xffu) ? v[r] : 0.f;
     }
@@ -439,13 +447,21 @@ __device__ inline void gemm_epilogue(const GemmArgs& g, f4 (&acc)[4][4], int til
             for (int j = 0; j < 4; ++j)
                 *(f4*)&sw[(16 * j + (lane & 15)) * kEpiLDR + 16 * i + (lane >> 4) * 4] =
                     acc[2 * h + i][j];
+        // the refit's support bytes are loaded before any store (a byte load may alias G,
+        // so the compiler would not move it above the stores itself)
+        uint32_t m4[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = lane + 64 * k;
+            m4[k] = load_mask4(g, mw + 32 * h + (e & 7) * 4, nw + (e >> 3));
+        }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int e = lane + 64 * k;
             const int c = e >> 3, r = (e & 7) * 4;
             store_frag<EPI, true>(g, *(const f4*)&sw[c * kEpiLDR + r], mw + 32 * h + r, nw + c,
-                                  nv);
+                                  nv, m4[k]);
         }
         __syncthreads();
     }
@@ -592,13 +608,20 @@ __device__ __forceinline__ void grad_epilogue_cols(const GemmArgs& g, const f16v
                 *(f4*)&sw[((lane & 31) + 32 * j) * kEpiLDR + 8 * q + 4 * (lane >> 5)] =
                     f4{acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2],
                        acc[i][j][4 * q + 3]};
+        // the refit's support bytes are loaded before any store (see gemm_epilogue)
+        uint32_t m4[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = lane + 64 * k;
+            m4[k] = load_mask4(g, m0w + 32 * i + (e & 7) * 4, n0w + (e >> 3));
+        }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int e = lane + 64 * k;
             const int c = e >> 3, r = (e & 7) * 4;
             store_frag<EPI, true>(g, *(const f4*)&sw[c * kEpiLDR + r], m0w + 32 * i + r,
-                                  n0w + c, nv);
+                                  n0w + c, nv, m4[k]);
         }
         __syncthreads();
     }
