@@ -261,6 +261,47 @@ def test_fp32_trial_path_by_row_tiles(gpu_lib, dev):
         assert (st["prox_launches"] == 0) == fused, (n, st["prox_launches"])
 
 
+def _plan_splits(tiles, ksteps64, slots):
+    """The library's split-K rule (minimise rounds of resident workgroups per split, keep
+    at least two K steps of 64 per split); used here only to say which reduce runs."""
+    best, best_cost = 1, -(-tiles // slots)
+    for s in range(2, 9):
+        if ksteps64 // s < 2:
+            break
+        cost = -(-(tiles * s) // slots) / s
+        if cost < best_cost * 0.9:
+            best, best_cost = s, cost
+    return best
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("n,p", [(512, 8192), (512, 4096), (300, 3000), (64, 1024)])
+def test_fit_split_k_counts(gpu_lib, dev, prec, n, p):
+    """Split-K trial products with 2, 4, 5 or 7, and 8 splits (the reduces are compiled
+    per split count up to 4 for the low-precision forms and up to 8 for FP32; beyond,
+    a loop over the splits): sampled columns against the oracle replaying the steps."""
+    cd = lambda a, b: -(-a // b)
+    n_pad, p_pad = cd(n, 64) * 64, cd(p, 64) * 64
+    if prec == "fp32":
+        splits = _plan_splits(cd(n_pad, 128) * cd(p, 128), p_pad // 64, 512)
+    else:
+        splits = _plan_splits(cd(n_pad, 256) * cd(p, 128), p_pad // 64, 256)
+    print(f"{prec} n={n} p={p}: {splits} splits", flush=True)
+    assert splits > 1
+    rng = np.random.default_rng(n + p)
+    x32 = rng.normal(size=(n, p)).astype(np.float32)
+    x32 -= x32.mean(axis=0, keepdims=True)
+    om, st, tr = gpu_lib.accord_fit(_t(x32, dev), 0.1, 6, trace=True, precision=prec)
+    taus = tr.cpu().numpy()[1:, 3]
+    cols = np.array([0, 1, p // 2, p - 1])
+    ref = oracle.fit_fbs(x32.astype(np.float64), 0.1, len(taus), L=st["lipschitz"],
+                         tau_replay=taus, columns=cols)
+    got = om.cpu().numpy()[cols, :].astype(np.float64).T
+    rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
+    assert st["iters"] == 6
+    assert rel <= 1e-4, rel
+
+
 def test_fit_fixed_step_and_start_point(gpu_lib, dev):
     import torch
     w = datagen.small_random_problem(60, 90, seed=3)
