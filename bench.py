@@ -2,7 +2,7 @@
 
 One step = one complete accord_fit (Alg. 1) on the block power-law workload
 n = 500, p = 5000 (10 Barabasi-Albert(m=1) blocks of 500, lambda = 0.05,
-500 iterations, L estimated on the device by power iteration).  X is resident in
+500 iterations, L estimated on the device by the Lanczos iteration).  X is resident in
 HBM before the timed region.  `value` = prox-grad iterations per second of the
 headline form over the K timed steps.  --workload ba100k runs the same harness at
 n = 1000, p = 1e5 (200 blocks, lambda = 0.03, 300 iterations; --iters shortens it).
@@ -469,7 +469,7 @@ def run_diff(args):
 def run_refit(args):
     """The steps around the solver at n = 500, p = 5000: one step = the refit of
     eq. 3.8 (Alg. 1 with the gradient zeroed off the support, 200 iterations, from a
-    synthetic first-stage estimate on the true graph's support, L by power iteration)
+    synthetic first-stage estimate on the true graph's support, L by the Lanczos iteration)
     followed by the reparametrisation (Theta and the partial correlations).  Each form
     of --forms is timed; the first is the headline.
     value = refit iterations per second, the reparametrisation's time included."""
@@ -705,7 +705,7 @@ def main():
                                f"{iters} iterations",
                    "n": n, "p": p, "lambda": w.lam, "iters_per_step": iters,
                    "form": forms[0],
-                   "lipschitz": "device power iteration, 400 steps"},
+                   "lipschitz": "device Lanczos estimate, 64 steps"},
         "xtw_tflops": ks.get("grad_gemm", {}).get("achieved"),
         "roofline": roofline,
         "forms": results,

@@ -103,14 +103,18 @@ typedef struct {
     double tau0;        /* initial step of EVERY iteration (Alg. 1), > 0; typical 1 */
     double beta;        /* backtracking factor in (0, 1]; 1 = fixed step tau0, no test */
     double lipschitz;   /* L = sigma_max(X^T X / n) (Sec. 3.2); 0 = estimate on the device
-                           by power iteration.  The step floor of Alg. 1 is tau <= 1/L. */
+                           by the Lanczos iteration (the largest eigenvalue of the Lanczos
+                           tridiagonal, converged to FP64 level for the default step count
+                           on the benchmark data).  The step floor of Alg. 1 is tau <= 1/L. */
     double tol;         /* 0 = run exactly max_iter iterations; > 0 = also stop once
                            ||Delta||_F <= tol * max(1, ||Omega_{t+1}||_F) */
     int32_t max_iter;   /* iterations, >= 0 */
     int32_t precision;  /* accord_precision */
     int32_t check_every;/* kept for compatibility (>= 1 when tol > 0): the host now learns the
                            device's stop flag after every trial, so it is not used */
-    int32_t power_iters;/* power-iteration steps when lipschitz == 0 (0 = 400) */
+    int32_t power_iters;/* Lanczos steps of the L estimate when lipschitz == 0 (0 = 64; at
+                           most 256, larger values are taken as 256; fewer steps are run
+                           when the Krylov space stops growing) */
     int32_t timing;     /* 1 = time every kernel launch with HIP events (fills the *_ms fields) */
     int32_t warm_tau;   /* 0 = every iteration's first trial is tau0 (Alg. 1).  1 = a variant
                            that departs from Alg. 1: after the first iteration, the first
@@ -156,7 +160,7 @@ typedef struct {
 } accord_stats;
 
 /* Fills `prm` with defaults: lambda 0.1, tau0 1, beta 0.5, lipschitz 0 (estimate),
- * tol 0, max_iter 100, FP32, check_every 10, power_iters 400, timing 0, warm_tau 0,
+ * tol 0, max_iter 100, FP32, check_every 10, power_iters 64, timing 0, warm_tau 0,
  * graph 0, refresh_every 0. */
 void accord_default_params(accord_params* prm);
 
@@ -219,7 +223,7 @@ int accord_fit(const float* X, int64_t n, int64_t p, float* Omega, const accord_
  *          last iterates.
  *   prm: tau0, beta, tol, max_iter, power_iters as in accord_fit; prm->lambda is
  *        not used; precision must be ACCORD_FP32 (else ACCORD_ERR_UNSUPPORTED).
- *   lipschitz: host double[nsub] (L of each data set) or NULL (power iteration).
+ *   lipschitz: host double[nsub] (L of each data set) or NULL (Lanczos estimate).
  *   stats: host accord_batch_stats[nsub*nlam] or NULL.
  *   trials: device int32[nsub*nlam*max_iter] or NULL: the trials each iteration
  *           used (the accepted step of iteration t of problem k is

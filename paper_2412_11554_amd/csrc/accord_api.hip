@@ -81,7 +81,7 @@ struct Plan {
                     // separate prox pass writes Delta for the plain FP32 GEMM)
     int prox_rows;  // FP64 prox partial rows left per trial
     int nprox;
-    size_t off_ls, off_prox_part, off_norm_part, off_pow_u, off_pow_w, off_pow_pu, off_pow_pw,
+    size_t off_ls, off_prox_part, off_norm_part, off_lz,
         off_trials, off_xp, off_xt, off_xsplit[4], off_x8, off_x8s, off_xt8, off_xt8s, off_wt0,
         off_wt1, off_wsplit[4], off_w8, off_w8s, off_split,
         off_om0, end_grad, off_g, off_d, off_om1, end_fit;
@@ -158,10 +158,7 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
                                     sizeof(double));
     P.end_prox = cur;
     P.off_norm_part = bump(cur, (size_t)ttiles * kNormCols * sizeof(double));
-    P.off_pow_u = bump(cur, (size_t)P.n_pad * sizeof(double));
-    P.off_pow_w = bump(cur, (size_t)P.p_pad * sizeof(double));
-    P.off_pow_pu = bump(cur, (size_t)n * sizeof(double));
-    P.off_pow_pw = bump(cur, (size_t)cdiv(p, kThreads / 64) * sizeof(double));
+    P.off_lz = bump(cur, lz_buf_bytes(P.n_pad, P.p_pad));
     P.off_trials = bump(cur, (size_t)(max_iter > 0 ? max_iter : 1) * sizeof(int32_t));
     P.off_xp = bump(cur, xn * sizeof(float));
     P.off_xt = bump(cur, xn * sizeof(float));
@@ -429,7 +426,7 @@ void accord_default_params(accord_params* prm) {
     prm->max_iter = 100;
     prm->precision = ACCORD_FP32;
     prm->check_every = 10;
-    prm->power_iters = 400;
+    prm->power_iters = kLzDefaultSteps;
     prm->timing = 0;
 }
 
@@ -614,10 +611,9 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
         launch_quant_x8(X, n, p, P.p_pad, P.n_pad, q, st);
     }
     if (prm->lipschitz <= 0.0) {
-        launch_power_iteration(xp, P.p_pad, xt, P.n_pad, n, p, at<double>(ws, P.off_pow_w),
-                               at<double>(ws, P.off_pow_u), at<double>(ws, P.off_pow_pu),
-                               at<double>(ws, P.off_pow_pw),
-                               prm->power_iters > 0 ? prm->power_iters : 400, ls, st);
+        launch_lipschitz(xp, P.p_pad, xt, P.n_pad, n, p,
+                         lz_buf(at<char>(ws, P.off_lz), P.n_pad, P.p_pad),
+                         prm->power_iters > 0 ? prm->power_iters : kLzDefaultSteps, ls, st);
     }
     // W0 = X Omega0 in FP32 (once), plus its bf16 split for the first gradient
     enqueue_trial(trial_args(P, ws, PREC_FP32, om[0], nullptr, nullptr, nullptr, wt[0],
@@ -890,7 +886,8 @@ struct BatchPlan {
     std::vector<int> tilesM;
     size_t off_ls, off_lam, off_inv_n, off_L, off_args_w0, off_args_grad, off_args_trial,
         off_prox_init, off_px_trial, off_fin_init, off_fin, off_prox_part, off_norm_part,
-        off_trials, off_pow_u, off_pow_w, off_pow_pu, off_pow_pw, off_om[2], off_g, end;
+        off_trials, off_lz, off_om[2], off_g, end;
+    int64_t lz_npad;  // sample extent of the Lanczos buffers (the largest n_pad)
     std::vector<size_t> off_xp, off_xt, off_wt[2];
 };
 
@@ -943,10 +940,8 @@ int make_batch_plan(const int64_t* n, int64_t nsub, int64_t p, int64_t nlam, int
     B.off_norm_part = bump(cur, (size_t)norm_rows_total * kNormCols * sizeof(double));
     B.off_trials = bump(cur, (size_t)np * std::max(max_iter, 1) * sizeof(int32_t));
     const int64_t nmax_pad = round_up(nmax, kPad);
-    B.off_pow_u = bump(cur, (size_t)nmax_pad * sizeof(double));
-    B.off_pow_w = bump(cur, (size_t)B.p_pad * sizeof(double));
-    B.off_pow_pu = bump(cur, (size_t)nmax * sizeof(double));
-    B.off_pow_pw = bump(cur, (size_t)cdiv(p, kThreads / 64) * sizeof(double));
+    B.lz_npad = nmax_pad;
+    B.off_lz = bump(cur, lz_buf_bytes(nmax_pad, B.p_pad));
     for (int64_t b = 0; b < nsub; ++b) {
         const size_t xn = (size_t)(B.n_pad[b] * B.p_pad);
         B.off_xp.push_back(bump(cur, xn * sizeof(float)));
@@ -1162,11 +1157,10 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
         launch_pad_x(X + B.row_off[b] * p, B.n[b], p, at<float>(ws, B.off_xp[b]), B.p_pad,
                      at<float>(ws, B.off_xt[b]), B.n_pad[b], XSplit{}, ls + k0, st);
         if (!lipschitz)
-            launch_power_iteration(at<float>(ws, B.off_xp[b]), B.p_pad, at<float>(ws, B.off_xt[b]),
-                                   B.n_pad[b], B.n[b], p, at<double>(ws, B.off_pow_w),
-                                   at<double>(ws, B.off_pow_u), at<double>(ws, B.off_pow_pu),
-                                   at<double>(ws, B.off_pow_pw),
-                                   prm->power_iters > 0 ? prm->power_iters : 400, ls + k0, st);
+            launch_lipschitz(at<float>(ws, B.off_xp[b]), B.p_pad, at<float>(ws, B.off_xt[b]),
+                             B.n_pad[b], B.n[b], p, lz_buf(at<char>(ws, B.off_lz), B.lz_npad, B.p_pad),
+                             prm->power_iters > 0 ? prm->power_iters : kLzDefaultSteps, ls + k0,
+                             st);
     }
     if (!lipschitz) launch_share_L_batch(ls, (int)np, (int)nlam, st);
     for (int64_t k = 0; k < np; ++k)

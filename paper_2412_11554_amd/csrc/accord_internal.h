@@ -194,9 +194,20 @@ void launch_combine_objective(const double* prox_part, int nprox, const double* 
                               int ntiles, double lambda, double inv_n, double* out, hipStream_t st);
 void launch_transpose_w(const float* Wt, int64_t ldt, int64_t n, int64_t p, float* W,
                         hipStream_t st);
-void launch_power_iteration(const float* Xp, int64_t p_pad, const float* Xt, int64_t n_pad,
-                            int64_t n, int64_t p, double* w, double* u, double* part_u,
-                            double* part_w, int steps, LsState* ls, hipStream_t st);
+// Lanczos estimate of L (buffers carved by lz_buf from lz_buf_bytes bytes)
+constexpr int kLzMaxSteps = 256;   // cap on the Lanczos steps
+constexpr int kLzDefaultSteps = 64;
+constexpr int kLzMaxBlocks = 1024; // cap on the elementwise kernels' workgroups
+struct LzBuf {
+    double *q0, *q1, *r, *w, *u;   // q_{k-1}, q_k, residual, S q_k (p_pad), X q_k (n_pad)
+    double *pa, *pb;               // partials of alpha and ||r||^2
+    double *alpha, *beta;          // the tridiagonal (kLzMaxSteps each)
+    int* stop;                     // 0, or the number of valid steps after a breakdown
+};
+size_t lz_buf_bytes(int64_t n_pad, int64_t p_pad);
+LzBuf lz_buf(void* base, int64_t n_pad, int64_t p_pad);
+void launch_lipschitz(const float* Xp, int64_t p_pad, const float* Xt, int64_t n_pad, int64_t n,
+                      int64_t p, const LzBuf& buf, int steps, LsState* ls, hipStream_t st);
 
 // steps around the solver: support mask of a refit, reparametrisation
 void launch_support_mask(const float* om_hat, int64_t p, int64_t p_pad, uint8_t* mask,

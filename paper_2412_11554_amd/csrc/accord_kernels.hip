@@ -11,7 +11,7 @@
 //   k_splitk_reduce fixed-order sum of split-K partial tiles + trial epilogue
 //   k_prox         fused closed-form prox (eq. 3.5) + FP64 line-search partial sums
 //   k_finalize     FP64 acceptance test of Alg. 1, step update, iteration record
-//   k_pow_*        power iteration for L = sigma_max(X^T X / n) (Sec. 3.2)
+//   k_lz_*         Lanczos estimate of L = sigma_max(X^T X / n) (Sec. 3.2)
 //   copies / transposes into the padded operand layouts
 //
 // All cross-workgroup reductions are two-stage (per-workgroup partials, then one
@@ -2403,97 +2403,200 @@ void launch_combine_objective(const double* prox_part, int nprox, const double* 
 }
 
 // ---------------------------------------------------------------------------
-// Power iteration for L = sigma_max(X^T X / n):  v <- X^T (X v) / ||X^T (X v)||.
-// The Rayleigh quotient ||X v||^2 / n of the last unit vector is L's estimate
-// (it approaches sigma_max from below; the error shrinks like (l2/l1)^(2k)).
-// FP64 vectors, FP32 data.
+// L = sigma_max(S), S = X^T X / n (Sec. 3.2), by the Lanczos iteration on S:
+//   q_1 = fixed sign vector / sqrt(p),  w = S q_k,  alpha_k = q_k^T w,
+//   r = w - alpha_k q_k - beta_{k-1} q_{k-1},  beta_k = ||r||,  q_{k+1} = r / beta_k,
+// and L = the largest eigenvalue of the tridiagonal matrix T_m (diagonal alpha,
+// off-diagonal beta), found by Sturm-count bisection.  Its largest eigenvalue
+// approaches sigma_max from below much faster than the power iteration's Rayleigh
+// quotient when the top of the spectrum is crowded (at n = 500, p = 5000, power-law
+// blocks: machine precision after 48 steps, against 2e-11 left after 400 power steps).
+// The iteration stops early when beta_k vanishes (the Krylov space is invariant, e.g.
+// p = 1 or rank-one X).  FP64 vectors, FP32 data; one step is four launches: u = X q
+// (one workgroup per sample), w = X^T u / n with the partials of alpha (one wave per
+// variable), r with the partials of ||r||^2, and q <- r / beta.  Every workgroup sums a
+// set of partials itself, in the same fixed order, so all see the same alpha / beta.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_pow_start(double* w, int64_t p) {
-    for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < p;
+struct LzArgs {
+    const float* Xp;   // n x p_pad, row-major (padded X)
+    int64_t ldp;
+    const float* Xt;   // p x n_pad, row-major (padded X^T)
+    int64_t ldt;
+    int64_t n, p;
+    LzBuf b;
+    int nbw;           // workgroups of the w kernel (kThreads / 64 variables each)
+    int nbr;           // workgroups of the elementwise kernels
+};
+
+__global__ void __launch_bounds__(kThreads) k_lz_start(LzArgs a) {
+    for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < a.p;
          k += (int64_t)gridDim.x * kThreads) {
-        // fixed pseudo-random signs (integer hash); ||w|| = sqrt(p)
+        // fixed pseudo-random signs (integer hash), scaled to a unit vector
         uint32_t h = (uint32_t)k * 2654435761u;
         h ^= h >> 15;
         h *= 2246822519u;
         h ^= h >> 13;
-        w[k] = (h & 1u) ? 1.0 : -1.0;
+        a.b.q1[k] = ((h & 1u) ? 1.0 : -1.0) / sqrt((double)a.p);
+        a.b.q0[k] = 0.0;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.b.stop = 0;
 }
 
-// u = X (w / ||w||): one workgroup per sample row (n rows are too few to fill the
-// chip with one wave each).  ||w||^2 is summed from the previous step's partials by
-// every workgroup in the same fixed order (or is p at step 0).
-__global__ void __launch_bounds__(kThreads) k_pow_xv(const float* __restrict__ Xp,
-                                                     int64_t ldx, int64_t n, int64_t p,
-                                                     const double* __restrict__ w,
-                                                     const double* __restrict__ part_w, int nbw,
-                                                     double* __restrict__ u,
-                                                     double* __restrict__ part_u) {
-    double ww[1];
-    if (part_w) {
-        sum_partials<1>(part_w, nbw, 1, ww);
-    } else if (threadIdx.x == 0) {
-        ww[0] = (double)p;
-    }
-    __shared__ double s_scale;
-    if (threadIdx.x == 0) s_scale = ww[0] > 0.0 ? 1.0 / sqrt(ww[0]) : 0.0;
-    __syncthreads();
-    const double scale = s_scale;
+// u = X q_k: one workgroup per sample row
+__global__ void __launch_bounds__(kThreads) k_lz_xq(LzArgs a) {
+    if (*a.b.stop) return;
     const int64_t i = blockIdx.x;
-    const float* row = Xp + i * ldx;
+    const float* row = a.Xp + i * a.ldp;
     double v[1] = {0.0};
-    for (int64_t k = threadIdx.x; k < p; k += kThreads) v[0] += (double)row[k] * w[k];
+    for (int64_t k = threadIdx.x; k < a.p; k += kThreads) v[0] += (double)row[k] * a.b.q1[k];
     block_sum<1>(v);
-    if (threadIdx.x == 0) {
-        const double ui = v[0] * scale;
-        u[i] = ui;
-        part_u[i] = ui * ui;
-    }
+    if (threadIdx.x == 0) a.b.u[i] = v[0];
 }
 
-// w = X^T u: one wave per variable row of Xt
-__global__ void __launch_bounds__(kThreads) k_pow_xtu(const float* __restrict__ Xt,
-                                                      int64_t ldt, int64_t p, int64_t n,
-                                                      const double* __restrict__ u,
-                                                      double* __restrict__ w,
-                                                      double* __restrict__ part_w) {
+// w = X^T u / n (one wave per variable) and the partials of alpha_k = q_k^T w
+__global__ void __launch_bounds__(kThreads) k_lz_xtu(LzArgs a) {
+    if (*a.b.stop) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t j = (int64_t)blockIdx.x * (kThreads / 64) + wave;
     double s = 0.0;
-    if (j < p) {
-        const float* row = Xt + j * ldt;
-        for (int64_t k = lane; k < n; k += 64) s += (double)row[k] * u[k];
-        s = wave_sum(s);
-        if (lane == 0) w[j] = s;
+    if (j < a.p) {
+        const float* row = a.Xt + j * a.ldt;
+        for (int64_t k = lane; k < a.n; k += 64) s += (double)row[k] * a.b.u[k];
+        s = wave_sum(s) / (double)a.n;
+        if (lane == 0) a.b.w[j] = s;
     }
-    double v[1] = {(j < p && lane == 0) ? s * s : 0.0};
+    double v[1] = {(j < a.p && lane == 0) ? s * a.b.q1[j] : 0.0};
     block_sum<1>(v);
-    if (threadIdx.x == 0) part_w[blockIdx.x] = v[0];
+    if (threadIdx.x == 0) a.b.pa[blockIdx.x] = v[0];
 }
 
-// L = ||X v||^2 / n for the last unit vector v (its Rayleigh quotient)
-__global__ void __launch_bounds__(kThreads) k_pow_finish(const double* part_u, int nbu,
-                                                         LsState* ls) {
-    double vu[1];
-    sum_partials<1>(part_u, nbu, 1, vu);
-    if (threadIdx.x != 0) return;
-    ls->L = vu[0] * ls->inv_n;
-    ls->inv_L = ls->L > 0.0 ? 1.0 / ls->L : 0.0;
-}
-
-void launch_power_iteration(const float* Xp, int64_t p_pad, const float* Xt, int64_t n_pad,
-                            int64_t n, int64_t p, double* w, double* u, double* part_u,
-                            double* part_w, int steps, LsState* ls, hipStream_t st) {
-    const int nbu = (int)n;  // one workgroup (and one partial) per sample row
-    const int nbw = (int)cdiv(p, kThreads / 64);
-    const int64_t sb = cdiv(p, kThreads);
-    k_pow_start<<<(unsigned)(sb < 1024 ? sb : 1024), kThreads, 0, st>>>(w, p);
-    for (int s = 0; s < steps; ++s) {
-        k_pow_xv<<<nbu, kThreads, 0, st>>>(Xp, p_pad, n, p, w, s == 0 ? nullptr : part_w, nbw,
-                                           u, part_u);
-        if (s + 1 < steps) k_pow_xtu<<<nbw, kThreads, 0, st>>>(Xt, n_pad, p, n, u, w, part_w);
+// alpha_k, r = w - alpha_k q_k - beta_{k-1} q_{k-1} and the partials of ||r||^2
+__global__ void __launch_bounds__(kThreads) k_lz_resid(LzArgs a, int k) {
+    if (*a.b.stop) return;
+    double al[1];
+    sum_partials<1>(a.b.pa, a.nbw, 1, al);
+    __shared__ double s_al;
+    if (threadIdx.x == 0) s_al = al[0];
+    __syncthreads();
+    const double alpha = s_al, beta = k > 0 ? a.b.beta[k - 1] : 0.0;
+    double v[1] = {0.0};
+    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < a.p;
+         j += (int64_t)gridDim.x * kThreads) {
+        const double r = a.b.w[j] - alpha * a.b.q1[j] - beta * a.b.q0[j];
+        a.b.r[j] = r;
+        v[0] += r * r;
     }
-    k_pow_finish<<<1, kThreads, 0, st>>>(part_u, nbu, ls);
+    block_sum<1>(v);
+    if (threadIdx.x == 0) {
+        a.b.pb[blockIdx.x] = v[0];
+        if (blockIdx.x == 0) a.b.alpha[k] = alpha;
+    }
+}
+
+// beta_k = ||r||; q_{k-1} <- q_k, q_k <- r / beta_k; stop (k + 1 valid steps) when beta_k
+// vanishes against alpha_k + beta_{k-1}
+__global__ void __launch_bounds__(kThreads) k_lz_next(LzArgs a, int k) {
+    if (*a.b.stop) return;
+    double bb[1];
+    sum_partials<1>(a.b.pb, a.nbr, 1, bb);
+    __shared__ double s_b;
+    if (threadIdx.x == 0) s_b = sqrt(bb[0]);
+    __syncthreads();
+    const double beta = s_b;
+    const double scale = fabs(a.b.alpha[k]) + (k > 0 ? a.b.beta[k - 1] : 0.0);
+    if (!(beta > 1e-13 * scale)) {  // also for beta = 0 and non-finite values
+        if (blockIdx.x == 0 && threadIdx.x == 0) *a.b.stop = k + 1;
+        return;
+    }
+    const double inv = 1.0 / beta;
+    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < a.p;
+         j += (int64_t)gridDim.x * kThreads) {
+        a.b.q0[j] = a.b.q1[j];
+        a.b.q1[j] = a.b.r[j] * inv;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.b.beta[k] = beta;
+}
+
+// Number of eigenvalues of the tridiagonal (alpha, beta) below x (Sturm sequence).
+__device__ inline int sturm_below(const double* al, const double* be, int m, double x) {
+    int cnt = 0;
+    double d = al[0] - x;
+    for (int i = 0;; ++i) {
+        if (d == 0.0) d = -1e-300;  // x on an eigenvalue of the leading block: count it below
+        cnt += d < 0.0 ? 1 : 0;
+        if (i + 1 == m) break;
+        d = al[i + 1] - x - be[i] * be[i] / d;
+    }
+    return cnt;
+}
+
+// L = the largest eigenvalue of T_m by bisection on the Gershgorin interval
+__global__ void k_lz_finish(LzArgs a, int steps, LsState* ls) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int m = *a.b.stop > 0 ? *a.b.stop : steps;
+    const double* al = a.b.alpha;
+    const double* be = a.b.beta;
+    double lo = 0.0, hi = 0.0;
+    for (int i = 0; i < m; ++i) {
+        const double rad = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i + 1 < m ? fabs(be[i]) : 0.0);
+        lo = i == 0 ? al[i] - rad : fmin(lo, al[i] - rad);
+        hi = i == 0 ? al[i] + rad : fmax(hi, al[i] + rad);
+    }
+    for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_below(al, be, m, mid) == m) hi = mid;  // every eigenvalue lies below mid
+        else lo = mid;
+    }
+    const double L = isfinite(lo) ? 0.5 * (lo + hi) : lo;
+    ls->L = L;
+    ls->inv_L = L > 0.0 ? 1.0 / L : 0.0;
+}
+
+size_t lz_buf_bytes(int64_t n_pad, int64_t p_pad) {
+    const int64_t nbw = cdiv(p_pad, kThreads / 64);
+    return (size_t)(4 * p_pad + n_pad + nbw + kLzMaxBlocks + 2 * kLzMaxSteps + 2) * sizeof(double);
+}
+
+LzBuf lz_buf(void* base, int64_t n_pad, int64_t p_pad) {
+    double* d = (double*)base;
+    const int64_t nbw = cdiv(p_pad, kThreads / 64);
+    LzBuf b;
+    b.q0 = d;
+    b.q1 = b.q0 + p_pad;
+    b.r = b.q1 + p_pad;
+    b.w = b.r + p_pad;
+    b.u = b.w + p_pad;
+    b.pa = b.u + n_pad;
+    b.pb = b.pa + nbw;
+    b.alpha = b.pb + kLzMaxBlocks;
+    b.beta = b.alpha + kLzMaxSteps;
+    b.stop = (int*)(b.beta + kLzMaxSteps);
+    return b;
+}
+
+void launch_lipschitz(const float* Xp, int64_t p_pad, const float* Xt, int64_t n_pad, int64_t n,
+                      int64_t p, const LzBuf& buf, int steps, LsState* ls, hipStream_t st) {
+    if (steps > kLzMaxSteps) steps = kLzMaxSteps;
+    LzArgs a;
+    a.Xp = Xp;
+    a.ldp = p_pad;
+    a.Xt = Xt;
+    a.ldt = n_pad;
+    a.n = n;
+    a.p = p;
+    a.b = buf;
+    a.nbw = (int)cdiv(p, kThreads / 64);
+    const int64_t nr = cdiv(p, kThreads);
+    a.nbr = (int)(nr < kLzMaxBlocks ? nr : kLzMaxBlocks);
+    k_lz_start<<<(unsigned)a.nbr, kThreads, 0, st>>>(a);
+    for (int k = 0; k < steps; ++k) {
+        k_lz_xq<<<(unsigned)n, kThreads, 0, st>>>(a);
+        k_lz_xtu<<<(unsigned)a.nbw, kThreads, 0, st>>>(a);
+        k_lz_resid<<<(unsigned)a.nbr, kThreads, 0, st>>>(a, k);
+        k_lz_next<<<(unsigned)a.nbr, kThreads, 0, st>>>(a, k);
+    }
+    k_lz_finish<<<1, 64, 0, st>>>(a, steps, ls);
 }
 
 }  // namespace accord
@@ -2596,7 +2699,7 @@ __global__ void __launch_bounds__(kThreads) k_fit_init_batch(const FinArgs* __re
 }
 
 // Line-search state of every problem k = b * nlam + l: lambda[l], 1/n_b, and L_b
-// (0 = taken later from the power iteration of group b).
+// (0 = taken later from the Lanczos estimate of group b).
 __global__ void k_init_state_batch(LsState* ls, int nprob, int nlam, const double* lam,
                                    const double* inv_n, const double* L, double tau0,
                                    double beta, double tol, int max_iter, int warm_tau) {

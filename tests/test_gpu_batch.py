@@ -58,7 +58,8 @@ def test_batch_small_all_problems(gpu_lib):
 
 @pytest.mark.parametrize("p,ns", [(150, [1, 33, 65]), (130, [64, 65])])
 def test_batch_ragged(gpu_lib, p, ns):
-    """p not a multiple of the 128-column tile, tiny and ragged n, power iteration."""
+    """p not a multiple of the 128-column tile, tiny and ragged n (n = 1: rank one), L by
+    the device's Lanczos estimate (the step count asked for is capped at 256)."""
     rng = np.random.default_rng(p)
     xs = [rng.normal(size=(n, p)).astype(np.float32) for n in ns]
     w = datagen.BatchWorkload("ragged", p, xs, np.array([0.08, 0.2, 0.5]), 12)
@@ -90,7 +91,7 @@ def test_batch_stop_rule_per_problem(gpu_lib):
 
 def test_batch_full_size_sampled(gpu_lib):
     """16 bootstrap subsamples (n in 100..400) x 32 penalties in [0.02, 0.5] at
-    p = 2000, 300 iterations, L by power iteration: sampled problems and columns
+    p = 2000, 300 iterations, L by the Lanczos estimate: sampled problems and columns
     against the oracle replaying their steps."""
     w = datagen.workload("batch")
     print(f"batch: {len(w.xs)} x {len(w.lams)} problems, p={w.p}, {w.iters} iterations",

@@ -82,7 +82,7 @@ def _check_sampled(c2, form, om, st, tr):
     # steps are tau0 * beta^k
     k = np.log2(taus)
     assert np.allclose(k, np.round(k)) and np.all(taus <= 1.0)
-    # device power iteration: a lower bound (Rayleigh quotient) close to the top eigenvalue
+    # device Lanczos estimate: the largest Ritz value, a lower bound up to rounding
     assert st["lipschitz"] <= c2["L"] * (1 + 1e-6)
     assert abs(st["lipschitz"] - c2["L"]) <= 5e-3 * c2["L"]
     f = trace[:, 0]

@@ -210,7 +210,7 @@ def test_fit_small_workload_parity(gpu_lib, dev, name):
 
 
 def test_fit_benchmark_shape_sampled_columns(gpu_lib, dev):
-    """n=500, p=5000 block power-law workload, 500 iterations, L by power iteration
+    """n=500, p=5000 block power-law workload, 500 iterations, L by the Lanczos estimate
     (the benchmarked configuration); the oracle replays the GPU's steps on sampled
     columns (columns evolve independently once the steps are fixed)."""
     import torch
@@ -259,6 +259,29 @@ def test_fp32_trial_path_by_row_tiles(gpu_lib, dev):
         _, st, _ = gpu_lib.accord_fit(_t(x, dev), 0.1, 5, timing=True)
         assert st["iters"] == 5 and st["trial_gemm_launches"] >= 5
         assert (st["prox_launches"] == 0) == fused, (n, st["prox_launches"])
+
+
+@pytest.mark.parametrize("n,p", [(1, 7), (5, 1), (3, 2), (100, 200), (600, 100), (40, 1000)])
+def test_lipschitz_lanczos(gpu_lib, dev, n, p):
+    """The device's L (largest Ritz value of 64 Lanczos steps, fewer when the Krylov space
+    stops growing) against sigma_max(X)^2 / n from a dense SVD: within 1e-10, and above
+    it by rounding at most."""
+    rng = np.random.default_rng(n * 7 + p)
+    x32 = rng.normal(size=(n, p)).astype(np.float32)
+    _, st, _ = gpu_lib.accord_fit(_t(x32, dev), 0.1, 1)
+    L = oracle.lipschitz(x32.astype(np.float64))
+    print(f"n={n} p={p}: L {st['lipschitz']:.15g} vs {L:.15g}", flush=True)
+    assert abs(st["lipschitz"] - L) <= 1e-10 * L
+    assert st["lipschitz"] <= L * (1 + 1e-12)
+
+
+def test_lipschitz_benchmark_data(gpu_lib, dev):
+    """n = 500, p = 5000 power-law data, where the top of the spectrum is crowded (400
+    power steps still leave 2e-11): the Lanczos estimate within 1e-12."""
+    w = datagen.workload("ba5000")
+    _, st, _ = gpu_lib.accord_fit(_t(w.X, dev), w.lam, 1)
+    L = oracle.lipschitz(w.X.astype(np.float64))
+    assert abs(st["lipschitz"] - L) <= 1e-12 * L, (st["lipschitz"], L)
 
 
 def _plan_splits(tiles, ksteps64, slots):

@@ -111,7 +111,7 @@ def test_refit_converges_to_restricted_optimum(gpu_lib, prec):
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_refit_full_size_sampled(gpu_lib, prec):
     """n = 500, p = 5000 power-law data, a synthetic first-stage estimate on the true
-    graph (block-diagonal support), phi = 0.5, 200 iterations, L by power iteration:
+    graph (block-diagonal support), phi = 0.5, 200 iterations, L by the Lanczos estimate:
     sampled columns against the oracle replaying the steps; the support holds
     everywhere."""
     d = datagen.refit_workload()
