@@ -61,6 +61,7 @@ def test_default_params(L):
     assert prm.lambda_ == 0.1 and prm.tau0 == 1.0 and prm.beta == 0.5
     assert prm.lipschitz == 0.0 and prm.max_iter == 100 and prm.check_every == 10
     assert prm.warm_tau == 0 and prm.graph == 0 and prm.refresh_every == 0
+    assert prm.power_iters == 64  # Lanczos steps of the L estimate
 
 
 def test_status_strings(L):
