@@ -26,7 +26,8 @@
  * Ownership.  The caller owns every buffer, including the workspace `ws`
  * (device, 256-byte aligned, at least accord_workspace_bytes() bytes).  The
  * library allocates no device memory and frees nothing; its only global state
- * is a thread-local last-error string.  Calls with distinct workspaces are
+ * is a thread-local last-error string, the pinned host mailbox of the fit loop, and
+ * (with params.timing) a thread-local cache of HIP events that later calls reuse.  Calls with distinct workspaces are
  * independent; calls sharing a workspace must be stream-ordered.
  *
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = default stream).

@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -395,19 +396,26 @@ Posted read_mailbox(const Mailbox* mb) {
 }
 
 // HIP event pool for per-kernel timing
+// HIP events for params.timing.  A fit records two per launch group (thousands per
+// fit); creating and destroying them per call cost milliseconds of host time between
+// the launches, so they are kept per thread and device and reused by later calls (a
+// call is synchronous: its events have completed and been read before it returns).
 struct EventPool {
-    std::vector<hipEvent_t> ev;
+    std::vector<hipEvent_t>* ev = nullptr;
     size_t used = 0;
+    EventPool() {
+        static thread_local std::map<int, std::vector<hipEvent_t>> cache;
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        ev = &cache[dev];
+    }
     hipEvent_t get() {
-        if (used == ev.size()) {
+        if (used == ev->size()) {
             hipEvent_t e;
             if (hipEventCreate(&e) != hipSuccess) return nullptr;
-            ev.push_back(e);
+            ev->push_back(e);
         }
-        return ev[used++];
-    }
-    ~EventPool() {
-        for (auto e : ev) (void)hipEventDestroy(e);
+        return (*ev)[used++];
     }
 };
 
