@@ -116,7 +116,10 @@ typedef struct {
     int32_t power_iters;/* Lanczos steps of the L estimate when lipschitz == 0 (0 = 64; at
                            most 256, larger values are taken as 256; fewer steps are run
                            when the Krylov space stops growing) */
-    int32_t timing;     /* 1 = time every kernel launch with HIP events (fills the *_ms fields) */
+    int32_t timing;     /* 0 = off; k >= 1 = bracket the launch groups of every k-th iteration
+                           with HIP events (fills the *_ms fields: sums and counts over those
+                           iterations, whose means estimate every launch's).  Each event costs a
+                           few microseconds of GPU time, so k = 1 slows the fit measurably */
     int32_t warm_tau;   /* 0 = every iteration's first trial is tau0 (Alg. 1).  1 = a variant
                            that departs from Alg. 1: after the first iteration, the first
                            trial is min(tau0, tau_{t-1} / beta) (one step above the last
@@ -146,7 +149,8 @@ typedef struct {
     double tau_last;        /* accepted step of the last iteration */
     double delta_fro;       /* ||Delta||_F of the last iteration */
     double lipschitz;       /* L used for the step floor */
-    /* per-kernel device time (params.timing == 1; executed launches only) */
+    /* per-kernel device time (params.timing >= 1; executed launches of the sampled
+       iterations only; total_ms covers the whole fit) */
     double grad_gemm_ms;    int32_t grad_gemm_launches;   /* G = X^T W / n          */
     double trial_gemm_ms;   int32_t trial_gemm_launches;  /* W+ = W + X Delta, with the
                                                              prox (eq. 3.5) inside except

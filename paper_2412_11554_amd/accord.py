@@ -235,7 +235,7 @@ def accord_objective(X: torch.Tensor, Omega: torch.Tensor, lam: float, *, out=No
 def accord_fit(X: torch.Tensor, lam: float, max_iter: int, *, omega0: torch.Tensor | None = None,
                tau0: float = 1.0, beta: float = 0.5, lipschitz: float = 0.0, tol: float = 0.0,
                check_every: int = 10, power_iters: int = 0, precision: str = "fp32",
-               trace: bool = False, timing: bool = False, warm_tau: bool = False,
+               trace: bool = False, timing: int = 0, warm_tau: bool = False,
                refresh_every: int = 0, ws=None, omega_out=None):
     """ACCORD-FBS (Alg. 1).  Returns (Omega [p, p] paper form, stats dict, trace or None).
     omega0 defaults to the identity.  warm_tau selects the warm-started step variant."""
@@ -243,7 +243,7 @@ def accord_fit(X: torch.Tensor, lam: float, max_iter: int, *, omega0: torch.Tens
     dev = X.device
     prm = default_params(lam=lam, max_iter=max_iter, tau0=tau0, beta=beta, lipschitz=lipschitz,
                          tol=tol, check_every=check_every, power_iters=power_iters,
-                         precision=precision, timing=1 if timing else 0,
+                         precision=precision, timing=int(timing),
                          warm_tau=1 if warm_tau else 0, refresh_every=refresh_every)
     if omega_out is None:
         omega_out = torch.empty((p, p), dtype=torch.float32, device=dev)
@@ -400,7 +400,7 @@ def accord_refit_workspace_bytes(n: int, p: int, params: accord_params | None = 
 def accord_refit(X: torch.Tensor, omega_hat: torch.Tensor, lam: float, phi: float, max_iter: int,
                  *, omega0: torch.Tensor | None = None, tau0: float = 1.0, beta: float = 0.5,
                  lipschitz: float = 0.0, tol: float = 0.0, power_iters: int = 0,
-                 precision: str = "fp32", trace: bool = False, timing: bool = False, ws=None,
+                 precision: str = "fp32", trace: bool = False, timing: int = 0, ws=None,
                  omega_out=None):
     """Refit on the support of omega_hat with penalty phi * lam there (eq. 3.8), in any
     precision form.  Returns (Omega [p, p] paper form, stats dict, trace or None); the
@@ -408,7 +408,7 @@ def accord_refit(X: torch.Tensor, omega_hat: torch.Tensor, lam: float, phi: floa
     n, p = X.shape
     dev = X.device
     prm = default_params(lam=lam, max_iter=max_iter, tau0=tau0, beta=beta, lipschitz=lipschitz,
-                         tol=tol, power_iters=power_iters, timing=1 if timing else 0,
+                         tol=tol, power_iters=power_iters, timing=int(timing),
                          precision=precision)
     if omega_out is None:
         omega_out = torch.empty((p, p), dtype=torch.float32, device=dev)

@@ -344,6 +344,7 @@ int check_params(const accord_params* prm) {
     if (prm->tol > 0.0 && prm->check_every < 1)
         return fail(ACCORD_ERR_INVALID_ARG, "check_every must be >= 1 when tol > 0");
     if (prm->power_iters < 0) return fail(ACCORD_ERR_INVALID_ARG, "power_iters must be >= 0");
+    if (prm->timing < 0) return fail(ACCORD_ERR_INVALID_ARG, "timing must be >= 0");
     if (prm->warm_tau != 0 && prm->warm_tau != 1)
         return fail(ACCORD_ERR_INVALID_ARG, "warm_tau must be 0 or 1");
     if (prm->graph != 0 && prm->graph != 1)
@@ -576,6 +577,10 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
     const double lambda = support_src ? phi * prm->lambda : prm->lambda;
     hipStream_t st = (hipStream_t)stream;
     const bool timing = prm->timing != 0;
+    // every timing-th iteration's launch groups are bracketed by events: an event in the
+    // stream costs a few microseconds of GPU time, so sparse sampling keeps the timed fit
+    // close to an untimed one
+    const int tstride = prm->timing > 0 ? prm->timing : 1;
     EventPool pool;
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     if (timing) {
@@ -663,15 +668,16 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
     int base = 0;  // trials finalised before the current iteration
     for (int t = 0; t < prm->max_iter; ++t) {
         const int nxt = cur ^ 1;
+        const bool tim = timing && t % tstride == 0;
         GemmArgs ga = grad_args(P, ws, prec, wt[cur], cur, G, P.p_pad, (int)P.p_pad, ls);
         ga.cmask = mask;  // refit: G = 0 off the support, so the prox keeps those entries 0
         Launch lg = {nullptr, nullptr, t, 0};
-        if (timing) { lg.a = pool.get(); lg.b = pool.get(); HIP_TRY(hipEventRecord(lg.a, st)); }
+        if (tim) { lg.a = pool.get(); lg.b = pool.get(); HIP_TRY(hipEventRecord(lg.a, st)); }
         if (f8)  // MX copy of the current W (blocks along the samples) for the gradient
             launch_quant_w8(wt[cur], p * P.n_pad, at<uint8_t>(ws, P.off_w8),
                             at<uint8_t>(ws, P.off_w8s), ls, st);
         launch_gemm(ga, EPI_GRAD, prec, st);
-        if (timing) { HIP_TRY(hipEventRecord(lg.b, st)); ev_grad.push_back(lg); }
+        if (tim) { HIP_TRY(hipEventRecord(lg.b, st)); ev_grad.push_back(lg); }
         auto enqueue_trial_k = [&](int k) -> int {
             ProxArgs a = {};
             a.om = om[cur];
@@ -687,19 +693,19 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
                                      bf ? nxt : -1, ls, 2);
             if (D) {  // FP32 form with many row tiles: prox pass, then the plain product
                 Launch lp = {nullptr, nullptr, t, k};
-                if (timing) { lp.a = pool.get(); lp.b = pool.get(); HIP_TRY(hipEventRecord(lp.a, st)); }
+                if (tim) { lp.a = pool.get(); lp.b = pool.get(); HIP_TRY(hipEventRecord(lp.a, st)); }
                 launch_prox(a, P.nprox, st);
-                if (timing) { HIP_TRY(hipEventRecord(lp.b, st)); ev_prox.push_back(lp); }
+                if (tim) { HIP_TRY(hipEventRecord(lp.b, st)); ev_prox.push_back(lp); }
             }
             Launch lt = {nullptr, nullptr, t, k};
-            if (timing) { lt.a = pool.get(); lt.b = pool.get(); HIP_TRY(hipEventRecord(lt.a, st)); }
+            if (tim) { lt.a = pool.get(); lt.b = pool.get(); HIP_TRY(hipEventRecord(lt.a, st)); }
             if (fused)
                 launch_trial_fused(ta, a, prec, st);
             else if (P.fused32)
                 launch_trial_fused32(ta, a, st);
             else
                 enqueue_trial(ta, prec, st);
-            if (timing) { HIP_TRY(hipEventRecord(lt.b, st)); ev_trial.push_back(lt); }
+            if (tim) { HIP_TRY(hipEventRecord(lt.b, st)); ev_trial.push_back(lt); }
             launch_finalize(ls, prox_part, P.prox_rows, norm_part, ttiles, trace, trials_log,
                             mbox_dev, st);
             HIP_TRY(hipGetLastError());

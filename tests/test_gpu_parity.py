@@ -284,6 +284,18 @@ def test_lipschitz_benchmark_data(gpu_lib, dev):
     assert abs(st["lipschitz"] - L) <= 1e-12 * L, (st["lipschitz"], L)
 
 
+def test_fit_sampled_timing(gpu_lib, dev):
+    """params.timing = k brackets the launch groups of every k-th iteration: 20 iterations
+    with k = 4 time the gradients of iterations 0, 4, .., 16; k = 0 times nothing."""
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(60, 90)).astype(np.float32)
+    _, st, _ = gpu_lib.accord_fit(_t(x, dev), 0.1, 20, timing=4)
+    assert st["iters"] == 20 and st["grad_gemm_launches"] == 5
+    assert 5 <= st["trial_gemm_launches"] <= st["trials"] and st["total_ms"] > 0
+    _, st0, _ = gpu_lib.accord_fit(_t(x, dev), 0.1, 20)
+    assert st0["grad_gemm_launches"] == 0 and st0["trial_gemm_launches"] == 0
+
+
 def _plan_splits(tiles, ksteps64, slots):
     """The library's split-K rule (minimise rounds of resident workgroups per split, keep
     at least two K steps of 64 per split); used here only to say which reduce runs."""
