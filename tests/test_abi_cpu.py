@@ -93,15 +93,18 @@ FAKE = 1 << 20  # a 16-byte aligned non-null address; validation fails before an
     (dict(max_iter=-1), 1), (dict(precision=7), 5), (dict(tol=1e-6, check_every=0), 1),
     (dict(lipschitz=-2.0), 1), (dict(lam=float("nan")), 1),
     (dict(p=(1 << 20) + 1), 1), (dict(n=(1 << 20) + 1), 1),
+    (dict(timing=-1), 1), (dict(power_iters=-1), 1),
 ])
 def test_fit_validation(L, kw, status):
     args = dict(X=FAKE, n=10, p=12, Omega=FAKE, ws=FAKE, ws_bytes=1 << 40, lam=0.1, tau0=1.0,
-                beta=0.5, max_iter=3, precision=0, tol=0.0, check_every=10, lipschitz=0.0)
+                beta=0.5, max_iter=3, precision=0, tol=0.0, check_every=10, lipschitz=0.0,
+                timing=0, power_iters=0)
     args.update(kw)
     prm = accord.default_params(lam=args["lam"], tau0=args["tau0"], beta=args["beta"],
                                 max_iter=args["max_iter"], precision=args["precision"],
                                 tol=args["tol"], check_every=args["check_every"],
-                                lipschitz=args["lipschitz"])
+                                lipschitz=args["lipschitz"], timing=args["timing"],
+                                power_iters=args["power_iters"])
     st = accord.accord_stats()
     r = L.accord_fit(args["X"], args["n"], args["p"], args["Omega"], ctypes.byref(prm),
                      ctypes.byref(st), None, args["ws"], args["ws_bytes"], None)
@@ -277,3 +280,10 @@ def test_variant_params_validation(L, field, value):
     r = L.accord_fit(FAKE, 10, 12, FAKE, ctypes.byref(prm), ctypes.byref(st), None, FAKE, 1 << 40,
                      None)
     assert r == 1 and field.encode() in L.accord_last_error()
+
+
+def test_bench_timing_stride():
+    """The benchmark samples about 64 iterations of a timed fit (every k-th one)."""
+    import bench
+    assert bench.timing_stride(500) == 7 and bench.timing_stride(200) == 3
+    assert bench.timing_stride(10) == 1 and bench.timing_stride(0) == 1
