@@ -396,11 +396,10 @@ Posted read_mailbox(const Mailbox* mb) {
             (w >> 63) != 0};
 }
 
-// HIP event pool for per-kernel timing
-// HIP events for params.timing.  A fit records two per launch group (thousands per
-// fit); creating and destroying them per call cost milliseconds of host time between
-// the launches, so they are kept per thread and device and reused by later calls (a
-// call is synchronous: its events have completed and been read before it returns).
+// HIP events for params.timing.  A fit records two per sampled launch group (thousands
+// per fit with timing = 1); rather than creating and destroying them in every call,
+// they are kept per thread and device and reused by later calls (a call is
+// synchronous: its events have completed and been read before it returns).
 struct EventPool {
     std::vector<hipEvent_t>* ev = nullptr;
     size_t used = 0;
