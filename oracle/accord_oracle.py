@@ -139,6 +139,23 @@ def line_search_test(x, om, om_new, g_at_om, g_cur, tau):
     return canonical, literal, xd2_over_n, d2
 
 
+def identity_columns(p, cols):
+    """Columns ``cols`` of the p x p identity, built without forming the identity."""
+    cols = np.asarray(cols)
+    out = np.zeros((p, len(cols)))
+    out[cols, np.arange(len(cols))] = 1.0
+    return out
+
+
+def x_times(x, om):
+    """X @ om.  When om is mostly zeros (the iterates of a penalised fit), the product
+    runs over its nonzero entries only (scipy.sparse); the value is the same product."""
+    if om.size >= 1 << 20 and np.count_nonzero(om) < 0.25 * om.size:
+        from scipy import sparse
+        return np.asarray(x @ sparse.csc_matrix(om))
+    return x @ om
+
+
 @dataclass
 class FitResult:
     omega: np.ndarray                   # final iterate (column form)
@@ -155,7 +172,7 @@ class FitResult:
 
 
 def fit_fbs(x, lam, iters, omega0=None, tau0=1.0, beta=0.5, L=None, tol=0.0,
-            tau_replay=None, columns=None, warm_tau=False):
+            tau_replay=None, columns=None, warm_tau=False, record=True):
     """ACCORD-FBS (Alg. 1) in float64.
 
     For t = 0, 1, ...: compute G = grad g(Om_t) once (it does not depend on tau);
@@ -174,7 +191,13 @@ def fit_fbs(x, lam, iters, omega0=None, tau0=1.0, beta=0.5, L=None, tol=0.0,
     warm_tau: a variant that departs from Alg. 1 (which restarts every iteration at
       tau0): after the first iteration the trials start at min(tau0, tau_{t-1} / beta).
       The acceptance test and the floor are unchanged.
+    record: with tau_replay, False skips what a replay does not need -- the objective
+      values and the acceptance test of each (already decided) step -- so a long replay
+      on many columns costs the two products of the gradient per iteration; the
+      iterates are the same (f, g and literal_agree stay empty).
     """
+    if not record and tau_replay is None:
+        raise ValueError("record=False needs tau_replay (the line search needs the sums)")
     x = _f64(x)
     n, p = x.shape
     if L is None:
@@ -183,7 +206,7 @@ def fit_fbs(x, lam, iters, omega0=None, tau0=1.0, beta=0.5, L=None, tol=0.0,
         if tau_replay is None:
             raise ValueError("columns= needs tau_replay (the shared step couples columns)")
         cols = np.asarray(columns)
-        om = (np.eye(p)[:, cols] if omega0 is None else _f64(omega0)[:, cols].copy())
+        om = identity_columns(p, cols) if omega0 is None else _f64(omega0)[:, cols].copy()
         # diagonal positions of the selected columns inside the p x |J| block
         diag_rows = cols
     else:
@@ -207,6 +230,23 @@ def fit_fbs(x, lam, iters, omega0=None, tau0=1.0, beta=0.5, L=None, tol=0.0,
         return g, g + h
 
     res = FitResult(omega=om, iters=0, lipschitz=L)
+    if not record:
+        xt = np.ascontiguousarray(x.T)
+        for t in range(iters):
+            tau = float(tau_replay[t])
+            G = xt @ x_times(x, om) / n
+            om_new = _prox_cols(om, G, tau)
+            d2 = float(np.sum((om_new - om) ** 2))
+            res.tau.append(tau)
+            res.trials.append(1)
+            res.delta_fro.append(np.sqrt(d2))
+            om = om_new
+            res.iters = t + 1
+            if tol > 0 and np.sqrt(d2) <= tol * max(1.0, float(np.linalg.norm(om))):
+                res.converged = True
+                break
+        res.omega = om
+        return res
     g_cur, f_cur = _obj(om)
     res.g.append(g_cur)
     res.f.append(f_cur)

@@ -47,7 +47,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .accord_oracle import FitResult, diag_root, soft_threshold
+from .accord_oracle import FitResult, diag_root, identity_columns, soft_threshold
 
 E4M3_MAX = 448.0
 MX_BLOCK = 32
@@ -127,7 +127,7 @@ def fit_fbs_mx(x, lam, tau_replay, omega0=None, columns=None, quant=mx_quantize)
     n, p = x.shape
     if columns is not None:
         cols = np.asarray(columns)
-        om = np.eye(p)[:, cols] if omega0 is None else np.asarray(omega0, np.float64)[:, cols].copy()
+        om = identity_columns(p, cols) if omega0 is None else np.asarray(omega0, np.float64)[:, cols].copy()
         diag_rows = cols
     else:
         om = np.eye(p) if omega0 is None else np.asarray(omega0, np.float64).copy()

@@ -118,3 +118,95 @@ def test_fit_fbs_mx_column_subset_replay():
     plain = oracle.fit_fbs(x, lam, 8, tau_replay=taus)
     rel = np.linalg.norm(full.omega - plain.omega) / np.linalg.norm(plain.omega)
     assert 1e-5 < rel < 0.1
+
+
+def _mx_loops(v, blocks_along_rows):
+    """MX rounding written out block by block: for every column (blocks_along_rows) or
+    every row, each run of 32 consecutive entries gets the scale 2^s of its own
+    maximum and its entries are rounded to E4M3 times that scale."""
+    v = np.asarray(v, dtype=np.float64)
+    out = np.empty_like(v)
+    rows, cols = v.shape
+    if blocks_along_rows:
+        for j in range(cols):
+            for b0 in range(0, rows, 32):
+                blk = v[b0:b0 + 32, j]
+                s = 2.0 ** mx.mx_scale_exp(np.max(np.abs(blk)))
+                out[b0:b0 + 32, j] = mx.e4m3_round(blk / s) * s
+    else:
+        for i in range(rows):
+            for b0 in range(0, cols, 32):
+                blk = v[i, b0:b0 + 32]
+                s = 2.0 ** mx.mx_scale_exp(np.max(np.abs(blk)))
+                out[i, b0:b0 + 32] = mx.e4m3_round(blk / s) * s
+    return out
+
+
+def _one_mx_step_by_hand(x, lam, tau, cols):
+    """One MX step from the identity, with every operand blocked along the index its
+    product sums over: X^T W sums over samples (X per feature, W per column, runs of
+    32 samples); X Delta sums over features (X per sample row, Delta per column, runs
+    of 32 features)."""
+    n, p = x.shape
+    om = np.zeros((p, len(cols)))
+    om[cols, np.arange(len(cols))] = 1.0
+    w = x @ om
+    g = _mx_loops(x, True).T @ _mx_loops(w, True) / n
+    a = om - tau * g
+    new = np.sign(a) * np.maximum(np.abs(a) - tau * lam, 0.0)
+    jj = np.arange(len(cols))
+    b = a[cols, jj] - tau * lam
+    new[cols, jj] = (b + np.sqrt(b * b + 4 * tau)) / 2
+    w_new = w + _mx_loops(x, False) @ _mx_loops(new - om, True)
+    return new, w_new
+
+
+def _axis_probe_data():
+    """64 samples x 96 features with a few outliers 2^12 - 2^14 times the other
+    entries.  E4M3 keeps 3 mantissa bits in every normal binade, so a block's scale
+    matters only for entries that fall below the normal range relative to the block
+    maximum: here the ordinary entries of an outlier's 32-run become subnormal or zero,
+    and that run is a different set of entries along the row than along the column."""
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=(64, 96))
+    x[3, 40] = 3.0e4
+    x[50, 5] = -1.2e4
+    x[20, 70] = 6.0e4
+    return x
+
+
+def test_fit_fbs_mx_x_blocks_follow_each_contraction():
+    """X enters X^T W blocked along the samples and X Delta blocked along the
+    features; the oracle's one MX step equals the step written out block by block."""
+    x = _axis_probe_data()
+    cols = np.array([5, 33, 40, 70, 90])
+    lam, tau = 0.05, 0.02
+    want_om, want_w = _one_mx_step_by_hand(x, lam, tau, cols)
+    got = mx.fit_fbs_mx(x, lam, [tau], columns=cols)
+    assert np.max(np.abs(got.omega - want_om)) <= 1e-13 * np.max(np.abs(want_om))
+    assert np.max(np.abs(got.extra["w"] - want_w)) <= 1e-13 * np.max(np.abs(want_w))
+
+
+@pytest.mark.parametrize("which", ["grad", "trial", "both"])
+def test_mutation_swapped_x_axis_breaks_the_block_pin(which):
+    """Planting the wrong blocking axis for X (in the gradient's X^T, the trial's X, or
+    both) changes the step away from the block-by-block computation."""
+    x = _axis_probe_data()
+    n, p = x.shape
+    cols = np.array([5, 33, 40, 70, 90])
+    lam, tau = 0.05, 0.02
+    want_om, want_w = _one_mx_step_by_hand(x, lam, tau, cols)
+
+    def swapped(v, axis):
+        v = np.asarray(v)
+        if v.shape == (n, p) and (which == "both" or (which == "grad") == (axis == 0)):
+            axis = 1 - axis
+        return mx.mx_quantize(v, axis)
+
+    got = mx.fit_fbs_mx(x, lam, [tau], columns=cols, quant=swapped)
+    bad_om = np.max(np.abs(got.omega - want_om)) > 1e-6 * np.max(np.abs(want_om))
+    bad_w = np.max(np.abs(got.extra["w"] - want_w)) > 1e-6 * np.max(np.abs(want_w))
+    if which == "trial":
+        assert bad_w           # the trial's X only enters W
+    else:
+        assert bad_om and bad_w

@@ -294,6 +294,35 @@ def test_p12_column_subset_replay():
     assert np.allclose(sub.omega, r.omega[:, cols], atol=1e-13)
 
 
+
+def test_p12_lean_replay_is_the_same_replay():
+    """record=False (no objective or test bookkeeping, products over the nonzeros of
+    the iterate) follows the same iterates as the recorded replay, on the full matrix
+    and on a column subset large enough for the sparse product."""
+    x = _problem(30, 40, 12)
+    r = oracle.fit_fbs(x, 0.1, 40)
+    lean = oracle.fit_fbs(x, 0.1, 40, tau_replay=r.tau, record=False)
+    assert np.allclose(lean.omega, r.omega, atol=1e-13)
+    assert np.allclose(lean.delta_fro, r.delta_fro, rtol=1e-12, atol=1e-15)
+    # p = 2048, 512 columns: 2^20 entries, so the left product runs on the nonzeros
+    xb = _problem(64, 2048, 13)
+    taus = [0.02, 0.04, 0.02, 0.01, 0.02]
+    cols = np.r_[0:256, 1792:2048]
+    full = oracle.fit_fbs(xb, 0.3, 5, tau_replay=taus, columns=cols)
+    lean = oracle.fit_fbs(xb, 0.3, 5, tau_replay=taus, columns=cols, record=False)
+    assert np.count_nonzero(lean.omega) < 0.25 * lean.omega.size
+    assert np.allclose(lean.omega, full.omega, atol=1e-13)
+    with pytest.raises(ValueError):
+        oracle.fit_fbs(xb, 0.2, 5, record=False)
+
+
+def test_x_times_is_the_product():
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(20, 1024))
+    om = np.where(rng.random((1024, 1024)) < 0.01, rng.normal(size=(1024, 1024)), 0.0)
+    assert np.allclose(ao.x_times(x, om), x @ om, rtol=1e-13, atol=1e-13)
+    assert np.array_equal(ao.identity_columns(7, [0, 6, 3]), np.eye(7)[:, [0, 6, 3]])
+
 # ---------------------------------------------------------------- mutations
 def test_mutation_transposed_gradient_breaks_p4(monkeypatch):
     """A transposed operand in the smooth part (row form gradient on the column
