@@ -1,11 +1,19 @@
 """Benchmark of the ACCORD-FBS hot path on one MI355X.
 
-One step = one complete accord_fit (Alg. 1) on the block power-law workload
-n = 500, p = 5000 (10 Barabasi-Albert(m=1) blocks of 500, lambda = 0.05,
-500 iterations, L estimated on the device by the Lanczos iteration).  X is resident in
-HBM before the timed region.  `value` = prox-grad iterations per second of the
-headline form over the K timed steps.  --workload ba100k runs the same harness at
-n = 1000, p = 1e5 (200 blocks, lambda = 0.03, 300 iterations; --iters shortens it).
+Default workload (ba100k): the block power-law problem n = 1000, p = 1e5 (200
+Barabasi-Albert(m=1) blocks of 500, lambda = 0.03), whose fit runs 300 iterations of
+Alg. 1.  One step = one accord_fit call of 12 iterations that continues from the
+previous step's iterate (Omega in/out; L from the first call's Lanczos estimate is
+passed to the later ones), so warm-up + timed steps walk the fit's iterations in
+order: 5 + 20 steps are its 300 iterations.  Each call's set-up (operand casts,
+W0 = X Omega in FP32, f(Omega)) is inside the timed region.  X is resident in HBM
+before the timed region.  `value` = prox-grad iterations per second of the headline
+form over the K timed steps.  The other forms run 1 warm-up + --beside-steps timed
+steps from the identity.
+
+--workload ba5000: n = 500, p = 5000 (10 blocks, lambda = 0.05); one step = one
+complete 500-iteration fit, every form over the same steps, plus the warm-started step
+variant and the time to the estimate (stop rule) of each form.
 
 Forms (the contraction arithmetic; prox, test and sums are the same in all):
   bf16x3  bf16 MFMA on hi/lo splits, three passes (meets the FP32 error bar); headline
@@ -23,9 +31,11 @@ Also reported per form:
                 against the FP64 oracle replaying the form's step sizes (the MX-FP8
                 oracle for fp8) (untimed)
   error_vs_estimate  the same columns against the oracle's estimate (the minimiser)
-and once: cpu_baseline, the FP64 oracle timed on this host on a bounded sample, and
-time_to_error: wall time of fp32, bf16x3 and two-phase (bf16x1 or fp8, then bf16x3)
-runs from the identity to the stop rule, with their error against the estimate.
+and once: cpu_baseline, the FP64 oracle timed on this host on a bounded sample (at
+p = 1e5: replaying the headline's first steps on columns 0..4999, scaled to the whole
+problem), and (ba5000) time_to_error: wall time of fp32, bf16x3 and two-phase (bf16x1
+or fp8, then bf16x3) runs from the identity to the stop rule, with their error against
+the estimate.
 """
 from __future__ import annotations
 
@@ -50,6 +60,34 @@ METRIC = "prox-grad iters/sec + X^T(XΩ) MFMA TFLOP/s, mixed vs FP32 at matched 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline_columns(w, taus, L, ncols=5000, budget_s=20.0):
+    """The FP64 oracle on a bounded sample of a problem too large for a host-side full
+    iterate (p x p FP64 is 80 GB at p = 1e5): it replays the GPU's first steps on columns
+    0..ncols-1 (with the steps fixed the columns evolve independently, so this is what the
+    full run does on those columns), and the rate is scaled by ncols / p to the whole
+    problem.  The replay runs one trial per iteration; the full search would add the
+    rejected trials' products, so the value is an upper bound on the oracle's rate."""
+    import oracle
+
+    x = w.X.astype(np.float64)
+    cols = np.arange(min(ncols, w.p))
+    t0 = time.perf_counter()
+    oracle.fit_fbs(x, w.lam, 1, L=L, tau_replay=taus, columns=cols, record=False)
+    one = time.perf_counter() - t0
+    k = max(1, min(5, int(budget_s / max(one, 1e-3))))
+    if k > 1:
+        t0 = time.perf_counter()
+        oracle.fit_fbs(x, w.lam, k, L=L, tau_replay=taus, columns=cols, record=False)
+        dt = time.perf_counter() - t0
+    else:
+        dt = one
+    return {"value": k / dt * len(cols) / w.p, "unit": "iters/s", "cores": _threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle replaying the first {k} steps of the headline fit on "
+                      f"columns 0..{len(cols) - 1} of n={w.n}, p={w.p} ({dt:.1f} s); "
+                      f"rate scaled by {len(cols)}/{w.p} to the whole problem"}
 
 
 def cpu_baseline(w, budget_s: float = 15.0):
@@ -78,10 +116,10 @@ def cpu_baseline(w, budget_s: float = 15.0):
                       f"({sum(r.trials)} backtracking trials, {dt:.1f} s, FP64 numpy)"}
 
 
-def _traffic_table():
+def _traffic_table(workload):
     """HBM bytes per launch measured by rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by a plain
     copy's reading), valid only while the kernel source is the one that was profiled."""
-    path = os.path.join(ROOT, "profiles", "traffic_ba5000_bench.md")
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_bench.md")
     src = os.path.join(ROOT, "paper_2412_11554_amd", "csrc", "accord_kernels.hip")
     try:
         line = [l for l in open(path) if l.startswith("traffic-json: ")][-1]
@@ -93,7 +131,7 @@ def _traffic_table():
     return tab["bytes_per_launch"] if tab.get("kernel_sha256_16") == digest else {}
 
 
-def kernel_report(stats, form, n, p, workload_ok_for_traffic):
+def kernel_report(stats, form, n, p, traffic_workload):
     """Per kernel group: mean duration from the library's HIP events, the achieved
     algorithmic rate and the roofline it is held to.
 
@@ -107,7 +145,7 @@ def kernel_report(stats, form, n, p, workload_ok_for_traffic):
               G; write Omega+, Delta)."""
     flops = 2.0 * n * p * p
     peak = PEAK_TFLOPS[form]
-    traffic = _traffic_table() if workload_ok_for_traffic else {}
+    traffic = _traffic_table(traffic_workload) if traffic_workload else {}
     out = {}
 
     def group(key):
@@ -178,25 +216,41 @@ def timing_stride(iters):
     return max(1, iters // 64)
 
 
-def run_form(form, X, w, iters, ws, om, steps, warmup, check, warm_tau=False):
+def run_form(form, X, w, iters, ws, om, steps, warmup, check, warm_tau=False, carry=False,
+             traffic_workload=None):
+    """warmup + steps accord_fit calls of `iters` iterations.  carry=False: every call is a
+    whole fit from the identity.  carry=True: the calls continue one fit (Omega in/out, the
+    first call's L passed on), so the steps walk its iterations in order."""
     import torch
 
     from paper_2412_11554_amd import accord
 
-    def step(timing: bool):
-        return accord.accord_fit(X, w.lam, iters, ws=ws, omega_out=om,
-                                 timing=timing_stride(iters) if timing else 0,
-                                 trace=True, precision=form, warm_tau=warm_tau)
+    state = {"L": 0.0, "started": False, "taus": [], "trials": 0, "iters": 0}
 
-    for _ in range(warmup):
+    def step(timing: bool):
+        om_, st, tr = accord.accord_fit(
+            X, w.lam, iters, ws=ws, omega_out=om,
+            omega0=om if (carry and state["started"]) else None,
+            lipschitz=state["L"], timing=timing_stride(iters) if timing else 0,
+            trace=True, precision=form, warm_tau=warm_tau)
+        taus = tr.cpu().numpy()[1:st["iters"] + 1, 3]
+        if carry:
+            state["L"] = st["lipschitz"]
+            state["started"] = True
+            state["taus"].extend(taus.tolist())
+        else:
+            state["taus"] = taus.tolist()
+        return om_, st, tr
+
+    for i in range(warmup):
         step(False)
+        log(f"[{form}] warmup step {i + 1}/{warmup}")
     torch.cuda.synchronize()
     log(f"[{form}] warmup done")
     t0 = time.perf_counter()
     stats = []
-    trace = None
     for i in range(steps):
-        _, st, trace = step(True)
+        _, st, _ = step(True)
         stats.append(st)
         log(f"[{form}] step {i + 1}/{steps}: {st['iters']} iters, {st['trials']} trials, "
             f"{st['total_ms']:.1f} ms")
@@ -204,14 +258,17 @@ def run_form(form, X, w, iters, ws, om, steps, warmup, check, warm_tau=False):
     elapsed = time.perf_counter() - t0
     res = {"iters_per_s": sum(s["iters"] for s in stats) / elapsed,
            "ms_per_step": elapsed / steps * 1e3,
-           "trials_per_iter": stats[-1]["trials"] / max(1, stats[-1]["iters"]),
-           "kernels": kernel_report(stats, form, w.n, w.p,
-                                    w.p == 5000 and iters == w.iters)}
+           "steps": steps, "warmup": warmup, "iters_per_step": iters,
+           "trials_per_iter": sum(s["trials"] for s in stats) / max(1, sum(s["iters"] for s in stats)),
+           "lipschitz": stats[-1]["lipschitz"], "lz_steps": stats[0]["lz_steps"] if not carry else None,
+           "kernels": kernel_report(stats, form, w.n, w.p, traffic_workload)}
+    if carry:
+        res["iterations_run"] = len(state["taus"])
     if check:
         import oracle
         from oracle import mx_oracle
         cols = sample_cols(w.p)
-        taus = trace.cpu().numpy()[1:, 3]
+        taus = np.asarray(state["taus"], dtype=np.float64)
         x = w.X.astype(np.float64)
         got = om.cpu().numpy()[cols, :].astype(np.float64).T
         if form == "fp8":
@@ -221,17 +278,23 @@ def run_form(form, X, w, iters, ws, om, steps, warmup, check, warm_tau=False):
             what = "MX-FP8 oracle replaying this form's step sizes"
         else:
             ref = oracle.fit_fbs(x, w.lam, len(taus), L=stats[-1]["lipschitz"],
-                                 tau_replay=taus, columns=cols).omega
+                                 tau_replay=taus, columns=cols, record=False).omega
             what = "FP64 oracle replaying this form's step sizes"
         res["error_vs_oracle"] = {
             "rel_fro_sampled_cols": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
-            "cols": cols.tolist(), "reference": what}
+            "iterations": int(len(taus)), "cols": cols.tolist(), "reference": what}
+        log(f"[{form}] error vs oracle after {len(taus)} iterations: "
+            f"{res['error_vs_oracle']['rel_fro_sampled_cols']:.2e}")
         res["_sampled_cols"] = got
+    res["_taus"] = state["taus"]
     return res
 
 
 def sample_cols(p):
-    return np.array([0, 1, 499, p // 2, p - 2, p - 1])
+    if p <= 5000:
+        return np.array([0, 1, 499, p // 2, p - 2, p - 1])
+    # a whole power-law block's first columns, then columns spread over the others
+    return np.unique(np.r_[0:8, 499, 500, p // 7, p // 3, p // 2, 2 * p // 3, p - 2, p - 1])
 
 
 ESTIMATE_ITERS = 6000
@@ -618,12 +681,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--iters", type=int, default=None,
-                    help="iterations per fit (default: the workload's own count)")
-    ap.add_argument("--workload", default="ba5000",
+                    help="iterations per step (ba100k: 12 per call, the fit carried across "
+                         "calls; ba5000: one whole fit of 500)")
+    ap.add_argument("--beside-steps", type=int, default=None,
+                    help="ba100k: timed steps of the forms after the headline (default "
+                         "max(1, steps // 4), after one warm-up step)")
+    ap.add_argument("--workload", default="ba100k",
                     choices=["ba5000", "ba100k", "batch", "diff", "refit"],
-                    help="ba5000: n=500, p=5000, 10 blocks, lambda 0.05, 500 iterations "
-                         "(default); ba100k: n=1000, p=1e5, 200 blocks, lambda 0.03, "
-                         "300 iterations (the precision-form size); batch: 16 bootstrap "
+                    help="ba100k (default): n=1000, p=1e5, 200 blocks, lambda 0.03, the fit's "
+                         "300 iterations as warm-up + timed steps of 12; ba5000: n=500, "
+                         "p=5000, 10 blocks, lambda 0.05, 500 iterations per step; batch: 16 bootstrap "
                          "subsamples x 32 penalties at p=2000, 300 iterations, FP32, in "
                          "one accord_fit_batch call; diff: held-out loss gradient through "
                          "50 unrolled steps, n=300 (+150 held out), p=3000; refit: the "
@@ -651,8 +718,11 @@ def main():
 
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     dev = torch.device("cuda:0")
+    log(f"[setup] generating {args.workload}")
     w = datagen.workload(args.workload)
-    n, p, iters = w.n, w.p, (args.iters or w.iters)
+    carry = args.workload == "ba100k"
+    n, p, iters = w.n, w.p, (args.iters or (12 if carry else w.iters))
+    log(f"[setup] n={n} p={p} lambda={w.lam} iters per step {iters}")
     X = torch.from_numpy(w.X).to(dev)
     need = max(accord.accord_workspace_bytes(n, p, accord.default_params(max_iter=iters,
                                                                           precision=f))
@@ -669,12 +739,26 @@ def main():
         del a, b
 
     results = {}
-    for f in forms:
-        results[f] = run_form(f, X, w, iters, ws, om, args.steps, args.warmup, not args.no_check)
-    # the headline form with the warm-started step variant (not Alg. 1: reported beside it)
-    variant = run_form(forms[0], X, w, iters, ws, om, args.steps, args.warmup, not args.no_check,
-                       warm_tau=True)
-    variant.pop("_sampled_cols", None)
+    variants = {}
+    traffic_wl = args.workload if (iters == (12 if carry else w.iters)) else None
+    for k, f in enumerate(forms):
+        if carry and k > 0:
+            st_, wu_ = args.beside_steps or max(1, args.steps // 4), 1
+        else:
+            st_, wu_ = args.steps, args.warmup
+        results[f] = run_form(f, X, w, iters, ws, om, st_, wu_, not args.no_check, carry=carry,
+                              traffic_workload=traffic_wl)
+        if k == 0 and carry and not args.no_cpu_baseline:
+            # the oracle on a bounded sample, replaying the headline's first steps
+            cpu = cpu_baseline_columns(w, results[f]["_taus"], results[f]["lipschitz"])
+            log(f"[cpu baseline] {cpu['sample']}")
+    if not carry:
+        # the headline form with the warm-started step variant (not Alg. 1: reported beside it)
+        variant = run_form(forms[0], X, w, iters, ws, om, args.steps, args.warmup,
+                           not args.no_check, warm_tau=True)
+        variant.pop("_sampled_cols", None)
+        variant.pop("_taus", None)
+        variants[f"{forms[0]} warm-tau"] = variant
 
     head = results[forms[0]]
     ks = head["kernels"]
@@ -685,8 +769,10 @@ def main():
         roofline = {"kernel": " + ".join(d["kernels"]), "bound": d["bound"],
                     "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
                     "frac": d["frac"], "traffic": d["traffic"]}
-    # the oracle's full p x p FP64 iterate is 80 GB at p = 1e5: host baseline on ba5000 only
-    cpu = None if (args.no_cpu_baseline or w.p > 5000) else cpu_baseline(w)
+    if not carry:
+        cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+    elif args.no_cpu_baseline:
+        cpu = None
     tte = None
     if not args.no_check and w.p <= 5000:
         est = estimate_cols(w)
@@ -696,6 +782,12 @@ def main():
         tte = time_to_error(X, w, ws, om, est)
     for r in results.values():
         r.pop("_sampled_cols", None)
+        r.pop("_taus", None)
+    wl = (f"block power-law ACCORD-FBS fit: n={n}, p={p}, {p // 500} BA(m=1) blocks of 500, "
+          f"lambda={w.lam}, " +
+          (f"iterations 1..{(args.warmup + args.steps) * iters} of the fit ({w.iters} in the "
+           f"configuration) as {args.warmup} warm-up + {args.steps} timed calls of {iters} "
+           f"iterations, each continuing the last" if carry else f"{iters} iterations per step"))
     out = {
         "metric": METRIC,
         "value": head["iters_per_s"],
@@ -709,21 +801,25 @@ def main():
         "vs_baseline": None,
         "dtype": forms[0],
         "data": "synthetic",
-        "config": {"workload": f"block power-law ACCORD-FBS fit: n={n}, p={p}, "
-                               f"{p // 500} BA(m=1) blocks of 500, lambda={w.lam}, "
-                               f"{iters} iterations",
+        "config": {"workload": wl,
                    "n": n, "p": p, "lambda": w.lam, "iters_per_step": iters,
                    "form": forms[0],
-                   "lipschitz": "device Lanczos estimate, 64 steps"},
+                   "lipschitz": "device Lanczos estimate (top Ritz value + residual bound)"},
         "xtw_tflops": ks.get("grad_gemm", {}).get("achieved"),
         "roofline": roofline,
         "forms": results,
-        "variants": {f"{forms[0]} warm-tau": variant},
+        "variants": variants or None,
         "cpu_baseline": cpu,
         "time_to_error": tte,
     }
     if "fp32" in results and forms[0] != "fp32":
         out["speedup_vs_fp32"] = head["iters_per_s"] / results["fp32"]["iters_per_s"]
+        if carry:
+            out["speedup_vs_fp32_note"] = (
+                f"the headline's timed steps cover iterations {args.warmup * iters + 1}.."
+                f"{(args.warmup + args.steps) * iters}; the other forms' cover iterations "
+                f"{iters + 1}..{(1 + results['fp32']['steps']) * iters} of their own fits "
+                f"(trials per iteration are given for each)")
     print(json.dumps(out), flush=True)
 
 

@@ -104,18 +104,19 @@ typedef struct {
     double tau0;        /* initial step of EVERY iteration (Alg. 1), > 0; typical 1 */
     double beta;        /* backtracking factor in (0, 1]; 1 = fixed step tau0, no test */
     double lipschitz;   /* L = sigma_max(X^T X / n) (Sec. 3.2); 0 = estimate on the device
-                           by the Lanczos iteration (the largest eigenvalue of the Lanczos
-                           tridiagonal, converged to FP64 level for the default step count
-                           on the benchmark data).  The step floor of Alg. 1 is tau <= 1/L. */
+                           by the Lanczos iteration: theta + beta_m |s_m|, the top Ritz value
+                           plus its residual bound, so that the estimate errs above sigma_max
+                           and the step floor tau <= 1/L stays on the safe side.  The
+                           iteration stops once the bound is below 1e-12 theta (checked every
+                           8 steps), when the Krylov space stops growing, or at power_iters
+                           steps.  The step floor of Alg. 1 is tau <= 1/L. */
     double tol;         /* 0 = run exactly max_iter iterations; > 0 = also stop once
                            ||Delta||_F <= tol * max(1, ||Omega_{t+1}||_F) */
     int32_t max_iter;   /* iterations, >= 0 */
     int32_t precision;  /* accord_precision */
-    int32_t check_every;/* kept for compatibility (>= 1 when tol > 0): the host now learns the
-                           device's stop flag after every trial, so it is not used */
-    int32_t power_iters;/* Lanczos steps of the L estimate when lipschitz == 0 (0 = 64; at
-                           most 256, larger values are taken as 256; fewer steps are run
-                           when the Krylov space stops growing) */
+    int32_t power_iters;/* cap on the Lanczos steps of the L estimate when lipschitz == 0
+                           (0 = 256; larger values are taken as 256); fewer are run once the
+                           residual bound is met or the Krylov space stops growing */
     int32_t timing;     /* 0 = off; k >= 1 = bracket the launch groups of every k-th iteration
                            with HIP events (fills the *_ms fields: sums and counts over those
                            iterations, whose means estimate every launch's).  Each event costs a
@@ -162,10 +163,11 @@ typedef struct {
     double total_ms;        /* event time of the whole fit on the stream */
     double log_det_d;       /* sum_j log Omega_jj at the result (log det of the diagonal) */
     double l1;              /* ||Omega||_1 at the result (all entries) */
+    int32_t lz_steps;       /* Lanczos steps of the device estimate of L (0 if L was given) */
 } accord_stats;
 
 /* Fills `prm` with defaults: lambda 0.1, tau0 1, beta 0.5, lipschitz 0 (estimate),
- * tol 0, max_iter 100, FP32, check_every 10, power_iters 64, timing 0, warm_tau 0,
+ * tol 0, max_iter 100, FP32, power_iters 256, timing 0, warm_tau 0,
  * graph 0, refresh_every 0. */
 void accord_default_params(accord_params* prm);
 

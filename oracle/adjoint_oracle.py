@@ -23,6 +23,14 @@ Backward (reverse-mode, written out from the chain rule): with Ob = dl/dOm_t+1,
   * A = Om - (tau/n) X^T X Om, so
       Om_t bar = Ab - tau S Ab                          (S symmetric),
       X bar   += -(tau/n) (X Om Ab^T + X Ab Om^T).
+The kink decision |a| > tau lambda is a discrete outcome decided by floating point.
+``adjoint(..., active=...)`` takes it from the caller for every off-diagonal entry
+(one boolean mask per step), so that a comparison with a run whose iterates are
+rounded differently can use that run's decisions: an entry whose |a| lies within
+that run's rounding of tau lambda may sit on the other side of the kink there, and
+its derivative jumps between 0 and 1.  A caller must first check that the two sets of
+decisions differ only inside that rounding band.
+
 Pins: tests/test_oracle_adjoint_pins.py (central finite differences in FP64 on
 lambda and on entries of X, a directional-derivative (dot-product) test, and the
 loss gradient against finite differences).
@@ -73,9 +81,11 @@ def val_loss_grad(xv, om):
     return g
 
 
-def adjoint(x, lam, taus, obar_final, omega0=None, iterates=None):
+def adjoint(x, lam, taus, obar_final, omega0=None, iterates=None, active=None):
     """Reverse pass: returns (Om_0 bar, lambda bar, X bar) for the loss whose
-    gradient at Om_K is ``obar_final``."""
+    gradient at Om_K is ``obar_final``.  active: None, or one p x p boolean mask per
+    step giving the off-diagonal kink decisions |a_t| > tau_t lambda to use instead of
+    this function's own (the diagonal has no kink and ignores it)."""
     x = _f64(x)
     n, p = x.shape
     its = replay_iterates(x, lam, taus, omega0) if iterates is None else iterates
@@ -89,9 +99,9 @@ def adjoint(x, lam, taus, obar_final, omega0=None, iterates=None):
         g = x.T @ (x @ om) / n
         a = om - tau * g
         thr = tau * lam
-        active = np.abs(a) > thr
-        dwda = active.astype(np.float64)
-        dwdl = -tau * np.sign(a) * active
+        act = np.abs(a) > thr if active is None else np.asarray(active[t], dtype=bool)
+        dwda = act.astype(np.float64)
+        dwdl = -tau * np.sign(a) * act
         b = a[jj, jj] - thr
         r = np.sqrt(b * b + 4.0 * tau)
         dd = 0.5 * (1.0 + b / r)
@@ -111,4 +121,19 @@ def unrolled_loss(x, xv, lam, taus, omega0=None):
     return val_loss(xv, replay_iterates(x, lam, taus, omega0)[-1])
 
 
-__all__ = ["replay_iterates", "val_loss", "val_loss_grad", "adjoint", "unrolled_loss"]
+def kink_margins(x, lam, taus, iterates=None):
+    """Per step, the signed distance |a_t| - tau_t lambda of every entry from the kink
+    of the soft threshold (positive: active), with a_t = Om_t - tau_t S Om_t."""
+    x = _f64(x)
+    n = x.shape[0]
+    its = replay_iterates(x, lam, taus) if iterates is None else iterates
+    out = []
+    for t, tau in enumerate(taus):
+        om = its[t]
+        a = om - tau * (x.T @ (x @ om)) / n
+        out.append(np.abs(a) - tau * lam)
+    return out
+
+
+__all__ = ["replay_iterates", "val_loss", "val_loss_grad", "adjoint", "kink_margins",
+           "unrolled_loss"]

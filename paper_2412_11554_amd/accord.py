@@ -35,7 +35,7 @@ class accord_params(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("tau0", ctypes.c_double),
                 ("beta", ctypes.c_double), ("lipschitz", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("precision", ctypes.c_int32),
                 ("power_iters", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("warm_tau", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("refresh_every", ctypes.c_int32)]
@@ -51,7 +51,7 @@ class accord_stats(ctypes.Structure):
                 ("trial_gemm_ms", ctypes.c_double), ("trial_gemm_launches", ctypes.c_int32),
                 ("prox_ms", ctypes.c_double), ("prox_launches", ctypes.c_int32),
                 ("total_ms", ctypes.c_double), ("log_det_d", ctypes.c_double),
-                ("l1", ctypes.c_double)]
+                ("l1", ctypes.c_double), ("lz_steps", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -234,7 +234,7 @@ def accord_objective(X: torch.Tensor, Omega: torch.Tensor, lam: float, *, out=No
 
 def accord_fit(X: torch.Tensor, lam: float, max_iter: int, *, omega0: torch.Tensor | None = None,
                tau0: float = 1.0, beta: float = 0.5, lipschitz: float = 0.0, tol: float = 0.0,
-               check_every: int = 10, power_iters: int = 0, precision: str = "fp32",
+               power_iters: int = 0, precision: str = "fp32",
                trace: bool = False, timing: int = 0, warm_tau: bool = False,
                refresh_every: int = 0, ws=None, omega_out=None):
     """ACCORD-FBS (Alg. 1).  Returns (Omega [p, p] paper form, stats dict, trace or None).
@@ -242,7 +242,7 @@ def accord_fit(X: torch.Tensor, lam: float, max_iter: int, *, omega0: torch.Tens
     n, p = X.shape
     dev = X.device
     prm = default_params(lam=lam, max_iter=max_iter, tau0=tau0, beta=beta, lipschitz=lipschitz,
-                         tol=tol, check_every=check_every, power_iters=power_iters,
+                         tol=tol, power_iters=power_iters,
                          precision=precision, timing=int(timing),
                          warm_tau=1 if warm_tau else 0, refresh_every=refresh_every)
     if omega_out is None:

@@ -341,8 +341,6 @@ int check_params(const accord_params* prm) {
     if (prm->precision != ACCORD_FP32 && prm->precision != ACCORD_BF16X1 &&
         prm->precision != ACCORD_BF16X3 && prm->precision != ACCORD_FP8)
         return fail(ACCORD_ERR_UNSUPPORTED, "precision form %d is not available", prm->precision);
-    if (prm->tol > 0.0 && prm->check_every < 1)
-        return fail(ACCORD_ERR_INVALID_ARG, "check_every must be >= 1 when tol > 0");
     if (prm->power_iters < 0) return fail(ACCORD_ERR_INVALID_ARG, "power_iters must be >= 0");
     if (prm->timing < 0) return fail(ACCORD_ERR_INVALID_ARG, "timing must be >= 0");
     if (prm->warm_tau != 0 && prm->warm_tau != 1)
@@ -433,7 +431,6 @@ void accord_default_params(accord_params* prm) {
     prm->tol = 0.0;
     prm->max_iter = 100;
     prm->precision = ACCORD_FP32;
-    prm->check_every = 10;
     prm->power_iters = kLzDefaultSteps;
     prm->timing = 0;
 }
@@ -777,6 +774,7 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
         stats->lipschitz = host.L;
         stats->log_det_d = host.logd_cur;
         stats->l1 = host.l1_cur;
+        stats->lz_steps = host.lz_steps;
         if (timing) {
             std::vector<int32_t> tl((size_t)(host.iter > 0 ? host.iter : 1), 0);
             if (host.iter > 0)

@@ -56,6 +56,7 @@ struct LsState {
     int32_t max_iter;
     int32_t fixed_step; // beta == 1: the single trial is accepted
     int32_t warm_tau;   // 1: an iteration starts from min(tau0, tau_acc / beta), not tau0
+    int32_t lz_steps;   // Lanczos steps of the device estimate of L (0: L was given)
 };
 
 // Pinned host mailbox: after every executed acceptance test the device posts the
@@ -196,13 +197,17 @@ void launch_transpose_w(const float* Wt, int64_t ldt, int64_t n, int64_t p, floa
                         hipStream_t st);
 // Lanczos estimate of L (buffers carved by lz_buf from lz_buf_bytes bytes)
 constexpr int kLzMaxSteps = 256;   // cap on the Lanczos steps
-constexpr int kLzDefaultSteps = 64;
+constexpr int kLzDefaultSteps = 256;
+constexpr int kLzCheck = 8;         // steps between checks of the Ritz residual bound
+constexpr double kLzRelTol = 1e-12; // stop once beta_m |s_m| <= kLzRelTol * theta
+constexpr int kLzInvariant = 1, kLzConverged = 2;  // why the iteration stopped early
 constexpr int kLzMaxBlocks = 1024; // cap on the elementwise kernels' workgroups
 struct LzBuf {
     double *q0, *q1, *r, *w, *u;   // q_{k-1}, q_k, residual, S q_k (p_pad), X q_k (n_pad)
     double *pa, *pb;               // partials of alpha and ||r||^2
     double *alpha, *beta;          // the tridiagonal (kLzMaxSteps each)
-    int* stop;                     // 0, or the number of valid steps after a breakdown
+    int* stop;                     // [0]: 0, or the valid steps of an early stop;
+                                   // [1]: kLzInvariant or kLzConverged
 };
 size_t lz_buf_bytes(int64_t n_pad, int64_t p_pad);
 LzBuf lz_buf(void* base, int64_t n_pad, int64_t p_pad);

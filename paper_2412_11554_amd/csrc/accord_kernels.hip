@@ -2405,17 +2405,22 @@ void launch_combine_objective(const double* prox_part, int nprox, const double* 
 // ---------------------------------------------------------------------------
 // L = sigma_max(S), S = X^T X / n (Sec. 3.2), by the Lanczos iteration on S:
 //   q_1 = fixed sign vector / sqrt(p),  w = S q_k,  alpha_k = q_k^T w,
-//   r = w - alpha_k q_k - beta_{k-1} q_{k-1},  beta_k = ||r||,  q_{k+1} = r / beta_k,
-// and L = the largest eigenvalue of the tridiagonal matrix T_m (diagonal alpha,
-// off-diagonal beta), found by Sturm-count bisection.  Its largest eigenvalue
-// approaches sigma_max from below much faster than the power iteration's Rayleigh
-// quotient when the top of the spectrum is crowded (at n = 500, p = 5000, power-law
-// blocks: machine precision after 48 steps, against 2e-11 left after 400 power steps).
-// The iteration stops early when beta_k vanishes (the Krylov space is invariant, e.g.
-// p = 1 or rank-one X).  FP64 vectors, FP32 data; one step is four launches: u = X q
-// (one workgroup per sample), w = X^T u / n with the partials of alpha (one wave per
-// variable), r with the partials of ||r||^2, and q <- r / beta.  Every workgroup sums a
-// set of partials itself, in the same fixed order, so all see the same alpha / beta.
+//   r = w - alpha_k q_k - beta_{k-1} q_{k-1},  beta_k = ||r||,  q_{k+1} = r / beta_k.
+// After m steps the tridiagonal T_m (diagonal alpha, off-diagonal beta) has a largest
+// eigenvalue theta (its top Ritz value) with unit eigenvector s, and the Ritz pair
+// (theta, Q_m s) has the residual norm ||S Q_m s - theta Q_m s|| = beta_m |s_m|.  theta
+// approaches sigma_max from below; the estimate is theta + beta_m |s_m|, so that the
+// step floor tau <= 1/L of Alg. 1 errs on the safe side.  Every kLzCheck steps the
+// residual bound is evaluated and the iteration stops once it is below kLzRelTol * theta
+// (at n = 500, p = 5000 after 64 steps; at n = 1000, p = 1e5, where the top of the
+// spectrum is crowded, after about 110).  It also stops when beta_k vanishes (the
+// Krylov space is invariant, e.g. p = 1 or rank-one X: theta is then exact) and at the
+// step cap.  theta comes from Sturm-count multisection on 64 lanes, s from inverse
+// iteration on the positive definite sigma I - T_m with sigma just above theta.
+// FP64 vectors, FP32 data; one step is four launches: u = X q (one workgroup per
+// sample), w = X^T u / n with the partials of alpha (one wave per variable), r with the
+// partials of ||r||^2, and q <- r / beta.  Every workgroup sums a set of partials
+// itself, in the same fixed order, so all see the same alpha / beta.
 // ---------------------------------------------------------------------------
 struct LzArgs {
     const float* Xp;   // n x p_pad, row-major (padded X)
@@ -2439,7 +2444,10 @@ __global__ void __launch_bounds__(kThreads) k_lz_start(LzArgs a) {
         a.b.q1[k] = ((h & 1u) ? 1.0 : -1.0) / sqrt((double)a.p);
         a.b.q0[k] = 0.0;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a.b.stop = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.b.stop[0] = 0;
+        a.b.stop[1] = 0;
+    }
 }
 
 // u = X q_k: one workgroup per sample row
@@ -2505,7 +2513,10 @@ __global__ void __launch_bounds__(kThreads) k_lz_next(LzArgs a, int k) {
     const double beta = s_b;
     const double scale = fabs(a.b.alpha[k]) + (k > 0 ? a.b.beta[k - 1] : 0.0);
     if (!(beta > 1e-13 * scale)) {  // also for beta = 0 and non-finite values
-        if (blockIdx.x == 0 && threadIdx.x == 0) *a.b.stop = k + 1;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            *a.b.stop = k + 1;
+            a.b.stop[1] = kLzInvariant;
+        }
         return;
     }
     const double inv = 1.0 / beta;
@@ -2530,27 +2541,89 @@ __device__ inline int sturm_below(const double* al, const double* be, int m, dou
     return cnt;
 }
 
-// L = the largest eigenvalue of T_m by bisection on the Gershgorin interval
-__global__ void k_lz_finish(LzArgs a, int steps, LsState* ls) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    const int m = *a.b.stop > 0 ? *a.b.stop : steps;
-    const double* al = a.b.alpha;
-    const double* be = a.b.beta;
+// Largest eigenvalue theta of T_m (one wave): the Gershgorin interval is cut into 65
+// parts per round by the Sturm counts of 64 lanes; [lo, hi] keeps the top eigenvalue.
+// Returns hi (>= theta up to the count's rounding) and writes lo.
+__device__ double lz_top_ritz(const double* al, const double* be, int m, double* lo_out) {
+    const int lane = threadIdx.x & 63;
     double lo = 0.0, hi = 0.0;
     for (int i = 0; i < m; ++i) {
         const double rad = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i + 1 < m ? fabs(be[i]) : 0.0);
         lo = i == 0 ? al[i] - rad : fmin(lo, al[i] - rad);
         hi = i == 0 ? al[i] + rad : fmax(hi, al[i] + rad);
     }
-    for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (mid <= lo || mid >= hi) break;
-        if (sturm_below(al, be, m, mid) == m) hi = mid;  // every eigenvalue lies below mid
-        else lo = mid;
+    for (int round = 0; round < 12 && hi > lo; ++round) {
+        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+        // lanes whose point lies above every eigenvalue
+        const uint64_t above = __ballot(sturm_below(al, be, m, x) == m);
+        const int first = above ? __ffsll((unsigned long long)above) - 1 : 64;
+        const double nhi = first < 64 ? __shfl(x, first, 64) : hi;
+        const double nlo = first > 0 ? __shfl(x, first - 1, 64) : lo;
+        if (!(nhi < hi || nlo > lo)) break;  // the points no longer split the interval
+        lo = nlo;
+        hi = nhi;
     }
-    const double L = isfinite(lo) ? 0.5 * (lo + hi) : lo;
+    *lo_out = lo;
+    return hi;
+}
+
+// |s_m| of the unit eigenvector s of T_m for its top eigenvalue: three steps of inverse
+// iteration with sigma I - T_m (sigma above every eigenvalue, so the LDL^T pivots are
+// positive and the tridiagonal solve needs no pivoting).  One thread.
+__device__ double lz_last_component(const double* al, const double* be, int m, double hi) {
+    if (m == 1) return 1.0;
+    const double sigma = hi + 1e-13 * fabs(hi) + 1e-300;
+    double d[kLzMaxSteps], y[kLzMaxSteps];
+    d[0] = sigma - al[0];
+    for (int i = 1; i < m; ++i) d[i] = sigma - al[i] - be[i - 1] * be[i - 1] / d[i - 1];
+    for (int i = 0; i < m; ++i) y[i] = 1.0;
+    double last = 0.0;
+    for (int it = 0; it < 3; ++it) {
+        // (sigma I - T) z = y: forward with L (sub-diagonal -be[i] / d[i]), back with D L^T
+        for (int i = 1; i < m; ++i) y[i] += be[i - 1] / d[i - 1] * y[i - 1];
+        y[m - 1] /= d[m - 1];
+        for (int i = m - 2; i >= 0; --i) y[i] = (y[i] + be[i] * y[i + 1]) / d[i];
+        double nrm = 0.0;
+        for (int i = 0; i < m; ++i) nrm = fmax(nrm, fabs(y[i]));
+        double ss = 0.0;
+        for (int i = 0; i < m; ++i) {
+            y[i] /= nrm;
+            ss += y[i] * y[i];
+        }
+        last = fabs(y[m - 1]) / sqrt(ss);
+    }
+    return last;
+}
+
+// Every kLzCheck steps: stop once the Ritz residual bound is below kLzRelTol * theta.
+__global__ void k_lz_check(LzArgs a, int k) {
+    if (*a.b.stop) return;
+    const int m = k + 1;
+    double lo;
+    const double hi = lz_top_ritz(a.b.alpha, a.b.beta, m, &lo);
+    if (threadIdx.x != 0) return;
+    const double bound = a.b.beta[k] * lz_last_component(a.b.alpha, a.b.beta, m, hi);
+    if (bound <= kLzRelTol * hi) {
+        *a.b.stop = m;
+        a.b.stop[1] = kLzConverged;
+    }
+}
+
+// L = theta + beta_m |s_m| after m valid steps (theta alone when the space is invariant)
+__global__ void k_lz_finish(LzArgs a, int steps, LsState* ls) {
+    if (blockIdx.x != 0) return;
+    const int m = *a.b.stop > 0 ? *a.b.stop : steps;
+    double lo;
+    const double hi = lz_top_ritz(a.b.alpha, a.b.beta, m, &lo);
+    if (threadIdx.x != 0) return;
+    const double theta = 0.5 * (lo + hi);
+    const bool invariant = *a.b.stop > 0 && a.b.stop[1] == kLzInvariant;
+    const double bound = invariant ? 0.0
+                                   : a.b.beta[m - 1] * lz_last_component(a.b.alpha, a.b.beta, m, hi);
+    const double L = isfinite(theta) ? theta + bound : theta;
     ls->L = L;
     ls->inv_L = L > 0.0 ? 1.0 / L : 0.0;
+    ls->lz_steps = m;
 }
 
 size_t lz_buf_bytes(int64_t n_pad, int64_t p_pad) {
@@ -2595,6 +2668,7 @@ void launch_lipschitz(const float* Xp, int64_t p_pad, const float* Xt, int64_t n
         k_lz_xtu<<<(unsigned)a.nbw, kThreads, 0, st>>>(a);
         k_lz_resid<<<(unsigned)a.nbr, kThreads, 0, st>>>(a, k);
         k_lz_next<<<(unsigned)a.nbr, kThreads, 0, st>>>(a, k);
+        if ((k + 1) % kLzCheck == 0 && k + 1 < steps) k_lz_check<<<1, 64, 0, st>>>(a, k);
     }
     k_lz_finish<<<1, 64, 0, st>>>(a, steps, ls);
 }

@@ -40,6 +40,7 @@ def test_struct_layout_matches_header(tmp_path):
         " offsetof(accord_params, timing)); printf(\"%zu %zu\\n\", sizeof(accord_batch_stats),"
         " offsetof(accord_batch_stats, lipschitz)); printf(\"%zu %zu\\n\","
         " offsetof(accord_stats, log_det_d), offsetof(accord_batch_stats, log_det_d));"
+        " printf(\"%zu\\n\", offsetof(accord_stats, lz_steps));"
         " return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -54,14 +55,15 @@ def test_struct_layout_matches_header(tmp_path):
     assert vals[6] == accord.accord_batch_stats.lipschitz.offset
     assert vals[7] == accord.accord_stats.log_det_d.offset
     assert vals[8] == accord.accord_batch_stats.log_det_d.offset
+    assert vals[9] == accord.accord_stats.lz_steps.offset
 
 
 def test_default_params(L):
     prm = accord.default_params()
     assert prm.lambda_ == 0.1 and prm.tau0 == 1.0 and prm.beta == 0.5
-    assert prm.lipschitz == 0.0 and prm.max_iter == 100 and prm.check_every == 10
+    assert prm.lipschitz == 0.0 and prm.max_iter == 100
     assert prm.warm_tau == 0 and prm.graph == 0 and prm.refresh_every == 0
-    assert prm.power_iters == 64  # Lanczos steps of the L estimate
+    assert prm.power_iters == 256  # cap on the Lanczos steps of the L estimate
 
 
 def test_status_strings(L):
@@ -90,19 +92,19 @@ FAKE = 1 << 20  # a 16-byte aligned non-null address; validation fails before an
     (dict(X=None), 1), (dict(n=0), 1), (dict(p=0), 1), (dict(Omega=None), 1),
     (dict(X=FAKE + 4), 1), (dict(ws=None), 4), (dict(ws=FAKE + 16), 4), (dict(ws_bytes=10), 4),
     (dict(lam=-1.0), 1), (dict(tau0=0.0), 1), (dict(beta=0.0), 1), (dict(beta=1.5), 1),
-    (dict(max_iter=-1), 1), (dict(precision=7), 5), (dict(tol=1e-6, check_every=0), 1),
+    (dict(max_iter=-1), 1), (dict(precision=7), 5), (dict(tol=-1e-6), 1),
     (dict(lipschitz=-2.0), 1), (dict(lam=float("nan")), 1),
     (dict(p=(1 << 20) + 1), 1), (dict(n=(1 << 20) + 1), 1),
     (dict(timing=-1), 1), (dict(power_iters=-1), 1),
 ])
 def test_fit_validation(L, kw, status):
     args = dict(X=FAKE, n=10, p=12, Omega=FAKE, ws=FAKE, ws_bytes=1 << 40, lam=0.1, tau0=1.0,
-                beta=0.5, max_iter=3, precision=0, tol=0.0, check_every=10, lipschitz=0.0,
+                beta=0.5, max_iter=3, precision=0, tol=0.0, lipschitz=0.0,
                 timing=0, power_iters=0)
     args.update(kw)
     prm = accord.default_params(lam=args["lam"], tau0=args["tau0"], beta=args["beta"],
                                 max_iter=args["max_iter"], precision=args["precision"],
-                                tol=args["tol"], check_every=args["check_every"],
+                                tol=args["tol"],
                                 lipschitz=args["lipschitz"], timing=args["timing"],
                                 power_iters=args["power_iters"])
     st = accord.accord_stats()

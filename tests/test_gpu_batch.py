@@ -113,6 +113,24 @@ def test_batch_full_size_sampled(gpu_lib):
     assert np.all(nnz[:, 0] > nnz[:, -1])
 
 
+def test_batch_full_size_deterministic(gpu_lib):
+    """The benchmark's 16 x 32 problems at p = 2000, 10 iterations, twice (the second
+    through the captured graphs): the same bits."""
+    import torch
+    w = datagen.workload("batch")
+    X = torch.from_numpy(w.stacked()).cuda()
+    print(f"[determinism] batch {len(w.xs)} x {len(w.lams)} problems, p={w.p}, 10 iterations "
+          "twice", flush=True)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a, sa, ta = gpu_lib.accord_fit_batch(X, w.n, w.lams, 10, trials=True)
+        a, ta = a.clone(), ta.clone()
+        b, sb, tb = gpu_lib.accord_fit_batch(X, w.n, w.lams, 10, trials=True, graph=True)
+        s.synchronize()
+    assert torch.equal(a, b) and torch.equal(ta, tb)
+    assert [d["f"] for d in sa] == [d["f"] for d in sb]
+
+
 def test_batch_errors(gpu_lib):
     import torch
     from paper_2412_11554_amd import accord

@@ -7,15 +7,22 @@ Bars.  The device runs the forward and reverse recursions in FP32 (GEMMs accumul
 in FP32; the diagonal root and the lambda sums in FP64).  The unrolled map is only
 piecewise smooth: an entry whose |a| lies within FP32 rounding of tau lambda may
 take the other side of the soft-threshold kink than in FP64, and its derivative
-jumps between 0 and 1 there.  Over a few steps only a handful of entries come that
-close (counted and printed from the oracle side), and each moves the gradient by
-about one entry's share of it; the short runs must agree to 1e-3 in relative
-Frobenius norm, and the loss to 1e-5.  (All kernels are deterministic, so a run
-that meets the bar meets it every time.)  The full 50-step run at p = 3000 does cross
-such ties: rounding only the oracle's own iterates to FP32 already flips up to 19
-entries per iterate and moves dl/dlambda by 1.7% and dl/dX by 3.6%.  There the
-loss (continuous) keeps the 1e-5 bar, and the gradients are held to 5e-2 (lambda)
-and 0.2 (X, relative Frobenius, with cosine >= 0.99): their ties are not unique.
+jumps between 0 and 1 there.  In the small runs only a handful of entries come that
+close (counted and printed from the oracle side); they must agree to 1e-3 in
+relative Frobenius norm, and the loss to 1e-5.  (All kernels are deterministic, so
+a run that meets the bar meets it every time.)
+
+At the full width (n = 300, p = 3000) such entries are many: already after the first
+two steps about 1.6e4 entries lie within the FP32 error band of the kink, and
+flipping the oracle's decision for only the few within 1e-8 of it moves dl/dX by
+1.4e-3 relative (the gradient is small next to the per-step terms it sums).  So the
+full-size tests compare decisions first: the device's decision for every off-diagonal
+entry and step (|a| > tau lambda exactly when its iterate entry is nonzero) must equal
+the oracle's wherever the oracle's distance to the kink exceeds the FP32 band; the
+oracle's reverse pass then takes the device's decisions (adjoint(..., active=...)),
+and the gradients are held to bars set by FP32 arithmetic alone: 1e-4 for two steps,
+and for the 50-step run 1e-3 (the reverse recursion multiplies by I - tau S, whose norm
+exceeds 1 for the accepted steps, so rounding grows along it).
 """
 import numpy as np
 import pytest
@@ -47,22 +54,69 @@ def _oracle(x32, xv32, lam, taus):
     return loss, lbar, xbar
 
 
-def _near_ties(x32, lam, taus):
-    """Off-diagonal entries (over all steps) whose distance to the kink,
-    | |a| - tau lambda |, is within a probabilistic FP32 error of a:
+def _fp32_bands(x, taus, its):
+    """Per step, a probabilistic FP32 error of a = Omega - tau S Omega, entry by entry:
     4u (|Omega| + tau (sqrt(n) + sqrt(p)) (|X|^T |X| |Omega|) / n)."""
-    x = x32.astype(np.float64)
     n, p = x.shape
     u = 2.0 ** -24
     ax = np.abs(x)
-    count = 0
-    for t, om in enumerate(ad.replay_iterates(x, lam, taus)[:-1]):
-        g = x.T @ (x @ om) / n
-        a = om - taus[t] * g
-        err = 4 * u * (np.abs(om) + taus[t] * (np.sqrt(n) + np.sqrt(p)) * (ax.T @ (ax @ np.abs(om))) / n)
-        off = ~np.eye(p, dtype=bool)
-        count += int(np.sum((np.abs(np.abs(a) - taus[t] * lam) <= err) & off))
-    return count
+    return [4 * u * (np.abs(om) + taus[t] * (np.sqrt(n) + np.sqrt(p)) *
+                     (ax.T @ (ax @ np.abs(om))) / n) for t, om in enumerate(its[:-1])]
+
+
+def _near_ties(x32, lam, taus):
+    """Off-diagonal entries (over all steps) whose distance to the kink,
+    | |a| - tau lambda |, is within the FP32 band of a (_fp32_bands)."""
+    x = x32.astype(np.float64)
+    p = x.shape[1]
+    its = ad.replay_iterates(x, lam, taus)
+    off = ~np.eye(p, dtype=bool)
+    return sum(int(np.sum((np.abs(m) <= b) & off))
+               for m, b in zip(ad.kink_margins(x, lam, taus, its), _fp32_bands(x, taus, its)))
+
+
+def _device_decisions(x32, lam, taus):
+    """The device's kink decision of every entry and step, from its own forward replay:
+    the off-diagonal entry (i, j) of Omega_t+1 is nonzero exactly when |a| > tau lambda.
+    Column form (entry (i, j) = row i of column j), one boolean p x p mask per step."""
+    import torch
+    from paper_2412_11554_amd import accord
+    n, p = x32.shape
+    X = torch.from_numpy(x32).cuda()
+    om = torch.eye(p, dtype=torch.float32, device="cuda")
+    seq = torch.empty((len(taus), p, p), dtype=torch.float32, device="cuda")
+    accord.accord_fbs_replay(X, om, list(taus), lam, seq=seq)
+    nz = (seq != 0).cpu().numpy()
+    del seq
+    return [m.T for m in nz]
+
+
+def _compare_with_device_decisions(x32, xv32, lam, taus, every):
+    """Device gradients against the oracle's reverse pass on the device's kink decisions,
+    after checking those decisions against the oracle's outside the FP32 band."""
+    x, xv = x32.astype(np.float64), xv32.astype(np.float64)
+    p = x.shape[1]
+    its = ad.replay_iterates(x, lam, taus)
+    margins = ad.kink_margins(x, lam, taus, its)
+    bands = _fp32_bands(x, taus, its)
+    dev = _device_decisions(x32, lam, taus)
+    off = ~np.eye(p, dtype=bool)
+    ties = differ = 0
+    for m, b, d in zip(margins, bands, dev):
+        diff = ((m > 0) != d) & off
+        outside = diff & (np.abs(m) > b)
+        assert not outside.any(), (int(outside.sum()), float(np.abs(m[outside]).min()))
+        ties += int(np.sum((np.abs(m) <= b) & off))
+        differ += int(diff.sum())
+    loss, lbar, xbar = _grads(x32, xv32, lam, taus, every)
+    rl = ad.val_loss(xv, its[-1])
+    _, rlbar, rxbar = ad.adjoint(x, lam, taus, ad.val_loss_grad(xv, its[-1]), iterates=its,
+                                 active=dev)
+    rel_x = np.linalg.norm(xbar - rxbar) / np.linalg.norm(rxbar)
+    print(f"{len(taus)} steps: {ties} entries within the FP32 band of the kink, {differ} "
+          f"decided differently by the device (all inside the band); loss {loss:.9g} vs "
+          f"{rl:.9g}; dl/dlambda {lbar:.8g} vs {rlbar:.8g}; dX rel {rel_x:.2e}", flush=True)
+    return loss, lbar, rel_x, rl, rlbar
 
 
 @pytest.mark.parametrize("n,p,nv,K,every", [(40, 14, 25, 12, 5), (33, 97, 20, 9, 4),
@@ -96,21 +150,15 @@ def test_diff_checkpointing_is_exact(gpu_lib):
 
 
 def test_diff_full_width_tight(gpu_lib):
-    """The full-size shapes (n = 300, p = 3000) over the first two steps, where no
-    entry is near a kink: the same kernels and launch geometry at the tight bar."""
+    """The full-size shapes (n = 300, p = 3000) over the first two steps, on the device's
+    kink decisions (checked against the oracle's outside the FP32 band): bars of 1e-4."""
     d = datagen.diff_workload()
     x32, xv32, lam = d["x_train"], d["x_val"], d["lam"]
     taus = [0.25, 0.125]
-    ties = _near_ties(x32, lam, taus)
-    loss, lbar, xbar = _grads(x32, xv32, lam, taus, 2)
-    rl, rlbar, rxbar = _oracle(x32, xv32, lam, taus)
-    rel_x = np.linalg.norm(xbar - rxbar) / np.linalg.norm(rxbar)
-    print(f"two steps: loss {loss:.9g} vs {rl:.9g}; dl/dlambda {lbar:.7g} vs {rlbar:.7g}; "
-          f"dX rel {rel_x:.2e}", flush=True)
+    loss, lbar, rel_x, rl, rlbar = _compare_with_device_decisions(x32, xv32, lam, taus, 2)
     assert loss == pytest.approx(rl, rel=1e-5)
-    assert lbar == pytest.approx(rlbar, rel=5e-2)
-    assert rel_x <= 0.2
-    assert np.sum(xbar * rxbar) >= 0.99 * np.linalg.norm(xbar) * np.linalg.norm(rxbar)
+    assert lbar == pytest.approx(rlbar, rel=1e-4)
+    assert rel_x <= 1e-4
 
 
 def test_diff_full_size(gpu_lib):
@@ -124,12 +172,9 @@ def test_diff_full_size(gpu_lib):
     _, st, tr = accord.accord_fit(X, lam, K, trace=True)
     taus = tr[1:, 3].cpu().numpy()
     print(f"diff: p={d['p']} K={K}, {st['trials']} trials in the recording fit", flush=True)
-    loss, lbar, xbar = _grads(x32, xv32, lam, taus, d["every"])
-    rl, rlbar, rxbar = _oracle(x32, xv32, lam, taus)
-    rel_x = np.linalg.norm(xbar - rxbar) / np.linalg.norm(rxbar)
-    print(f"loss {loss:.8g} vs {rl:.8g}; dl/dlambda {lbar:.6g} vs {rlbar:.6g}; dX rel {rel_x:.2e}",
-          flush=True)
+    del X
+    loss, lbar, rel_x, rl, rlbar = _compare_with_device_decisions(x32, xv32, lam, taus,
+                                                                  d["every"])
     assert loss == pytest.approx(rl, rel=1e-5)
-    assert lbar == pytest.approx(rlbar, rel=5e-2)
-    assert rel_x <= 0.2
-    assert np.sum(xbar * rxbar) >= 0.99 * np.linalg.norm(xbar) * np.linalg.norm(rxbar)
+    assert lbar == pytest.approx(rlbar, rel=1e-3)
+    assert rel_x <= 1e-3

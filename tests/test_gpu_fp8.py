@@ -181,7 +181,7 @@ def test_fp8_then_bf16x3_refinement_reaches_estimate(gpu_lib, dev):
     X = _t(w.X, dev)
     om1, s1, _ = gpu_lib.accord_fit(X, lam, 300, lipschitz=L, precision="fp8")
     om2, s2, _ = gpu_lib.accord_fit(X, lam, 5000, lipschitz=L, precision="bf16x3", omega0=om1,
-                                    tol=1e-5, check_every=20)
+                                    tol=1e-5)
     torch.cuda.synchronize()
     assert s2["converged"] == 1
     ref = oracle.fit_fbs(x, lam, 50000, tol=1e-15).omega

@@ -106,3 +106,38 @@ def test_adjoint_omega0_matches_finite_differences():
               - ad.unrolled_loss(x, xv, lam, taus, om0 - e)) / (2 * h)
         # rounding of the loss (about 10) over 2h limits the difference to ~1e-9
         assert ob0[i, j] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+def test_adjoint_with_given_decisions():
+    """adjoint(active=...) with the oracle's own kink decisions (the signs of
+    kink_margins) is the plain reverse pass, bit for bit; a decision flipped at one
+    entry of the last step changes lambda bar by that entry's term there, since at
+    the last step Ob is the loss gradient itself and the flip touches only that term
+    and what propagates to the earlier steps through Ab."""
+    x, xv, lam, taus = _setup(K=6)
+    its = ad.replay_iterates(x, lam, taus)
+    ob = ad.val_loss_grad(xv, its[-1])
+    ref = ad.adjoint(x, lam, taus, ob, iterates=its)
+    own = [m > 0 for m in ad.kink_margins(x, lam, taus, its)]
+    got = ad.adjoint(x, lam, taus, ob, iterates=its, active=own)
+    assert np.array_equal(got[0], ref[0]) and got[1] == ref[1]
+    assert np.array_equal(got[2], ref[2])
+    # the margins are the distances of a_t from the kink, signed by the decision
+    n = x.shape[0]
+    a0 = its[0] - taus[0] * (x.T @ (x @ its[0])) / n
+    assert np.allclose(ad.kink_margins(x, lam, taus, its)[0], np.abs(a0) - taus[0] * lam)
+    # one flipped decision at the last step: with a one-step reverse pass (K = 1) the
+    # change of lambda bar is exactly that entry's term -tau sign(a) Ob_ij
+    t1 = taus[:1]
+    its1 = its[:2]
+    ob1 = ad.val_loss_grad(xv, its1[-1])
+    m = ad.kink_margins(x, lam, t1, its1)[0]
+    act = m > 0
+    off = ~np.eye(x.shape[1], dtype=bool)
+    i, j = np.argwhere(act & off)[0]
+    flipped = act.copy()
+    flipped[i, j] = False
+    base = ad.adjoint(x, lam, t1, ob1, iterates=its1, active=[act])[1]
+    fl = ad.adjoint(x, lam, t1, ob1, iterates=its1, active=[flipped])[1]
+    a = its1[0] - t1[0] * (x.T @ (x @ its1[0])) / n
+    assert fl - base == pytest.approx(t1[0] * np.sign(a[i, j]) * ob1[i, j], rel=1e-12, abs=1e-15)

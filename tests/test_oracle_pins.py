@@ -297,8 +297,9 @@ def test_p12_column_subset_replay():
 
 def test_p12_lean_replay_is_the_same_replay():
     """record=False (no objective or test bookkeeping, products over the nonzeros of
-    the iterate) follows the same iterates as the recorded replay, on the full matrix
-    and on a column subset large enough for the sparse product."""
+    the iterate, the prox by column chunks on threads) follows the same iterates as the
+    recorded replay: on the full matrix, on a column subset sparse enough for the sparse
+    product, and on a block large enough for the chunked prox."""
     x = _problem(30, 40, 12)
     r = oracle.fit_fbs(x, 0.1, 40)
     lean = oracle.fit_fbs(x, 0.1, 40, tau_replay=r.tau, record=False)
@@ -308,10 +309,19 @@ def test_p12_lean_replay_is_the_same_replay():
     xb = _problem(64, 2048, 13)
     taus = [0.02, 0.04, 0.02, 0.01, 0.02]
     cols = np.r_[0:256, 1792:2048]
-    full = oracle.fit_fbs(xb, 0.3, 5, tau_replay=taus, columns=cols)
-    lean = oracle.fit_fbs(xb, 0.3, 5, tau_replay=taus, columns=cols, record=False)
-    assert np.count_nonzero(lean.omega) < 0.25 * lean.omega.size
+    full = oracle.fit_fbs(xb, 0.5, 5, tau_replay=taus, columns=cols)
+    lean = oracle.fit_fbs(xb, 0.5, 5, tau_replay=taus, columns=cols, record=False)
+    assert np.count_nonzero(lean.omega) < 0.003 * lean.omega.size
     assert np.allclose(lean.omega, full.omega, atol=1e-13)
+    # p = 4096, 1024 columns (2^22 entries, a dense iterate): the chunked prox
+    xc = _problem(32, 4096, 14)
+    cols = np.arange(0, 4096, 4)
+    taus = [0.05, 0.1, 0.05]
+    full = oracle.fit_fbs(xc, 0.2, 3, tau_replay=taus, columns=cols)
+    lean = oracle.fit_fbs(xc, 0.2, 3, tau_replay=taus, columns=cols, record=False)
+    assert np.count_nonzero(lean.omega) > 0.2 * lean.omega.size
+    assert np.array_equal(lean.omega, full.omega)
+    assert np.allclose(lean.delta_fro, full.delta_fro, rtol=1e-12)
     with pytest.raises(ValueError):
         oracle.fit_fbs(xb, 0.2, 5, record=False)
 
