@@ -199,7 +199,7 @@ def _prox_by_column_chunks(prox_cols, om, G, tau):
 
 
 def fit_fbs(x, lam, iters, omega0=None, tau0=1.0, beta=0.5, L=None, tol=0.0,
-            tau_replay=None, columns=None, warm_tau=False, record=True):
+            tau_replay=None, columns=None, warm_tau=False, record=True, progress=None):
     """ACCORD-FBS (Alg. 1) in float64.
 
     For t = 0, 1, ...: compute G = grad g(Om_t) once (it does not depend on tau);
@@ -222,6 +222,7 @@ def fit_fbs(x, lam, iters, omega0=None, tau0=1.0, beta=0.5, L=None, tol=0.0,
       values and the acceptance test of each (already decided) step -- so a long replay
       on many columns costs the two products of the gradient per iteration; the
       iterates are the same (f, g and literal_agree stay empty).
+    progress: optional callable, called with the iteration count after each iteration.
     """
     if not record and tau_replay is None:
         raise ValueError("record=False needs tau_replay (the line search needs the sums)")
@@ -273,6 +274,8 @@ def fit_fbs(x, lam, iters, omega0=None, tau0=1.0, beta=0.5, L=None, tol=0.0,
             res.delta_fro.append(np.sqrt(d2))
             om = om_new
             res.iters = t + 1
+            if progress is not None:
+                progress(t + 1)
             if tol > 0 and np.sqrt(d2) <= tol * max(1.0, float(np.linalg.norm(om))):
                 res.converged = True
                 break

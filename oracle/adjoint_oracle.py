@@ -46,19 +46,27 @@ def _f64(a):
     return np.asarray(a, dtype=np.float64)
 
 
-def replay_iterates(x, lam, taus, omega0=None):
-    """[Om_0, ..., Om_K] of the fixed-step iteration (fresh G = S Om each step)."""
+def replay_iterates(x, lam, taus, omega0=None, active=None, round_fp32=False):
+    """[Om_0, ..., Om_K] of the fixed-step iteration (fresh G = S Om each step).
+
+    For perturbation studies: active (one p x p boolean mask per step) fixes the
+    off-diagonal kink decisions (an active entry takes a - tau lambda sign(a), an
+    inactive one 0), and round_fp32 rounds every iterate to float32, as a run that
+    keeps its iterates in FP32 does."""
     x = _f64(x)
     n, p = x.shape
     om = np.eye(p) if omega0 is None else _f64(omega0).copy()
     out = [om]
     jj = np.arange(p)
-    for tau in taus:
+    for t, tau in enumerate(taus):
         g = x.T @ (x @ om) / n
         a = om - tau * g
-        nw = soft_threshold(a, tau * lam)
+        if active is None:
+            nw = soft_threshold(a, tau * lam)
+        else:
+            nw = np.where(active[t], np.sign(a) * (np.abs(a) - tau * lam), 0.0)
         nw[jj, jj] = diag_root(a[jj, jj], tau, lam)
-        om = nw
+        om = nw.astype(np.float32).astype(np.float64) if round_fp32 else nw
         out.append(om)
     return out
 

@@ -18,11 +18,17 @@ flipping the oracle's decision for only the few within 1e-8 of it moves dl/dX by
 1.4e-3 relative (the gradient is small next to the per-step terms it sums).  So the
 full-size tests compare decisions first: the device's decision for every off-diagonal
 entry and step (|a| > tau lambda exactly when its iterate entry is nonzero) must equal
-the oracle's wherever the oracle's distance to the kink exceeds the FP32 band; the
-oracle's reverse pass then takes the device's decisions (adjoint(..., active=...)),
-and the gradients are held to bars set by FP32 arithmetic alone: 1e-4 for two steps,
-and for the 50-step run 1e-3 (the reverse recursion multiplies by I - tau S, whose norm
-exceeds 1 for the accepted steps, so rounding grows along it).
+the oracle's wherever the oracle's distance to the kink exceeds the FP32 band of a plus
+the difference between the oracle's a and the a of the device's own iterate (over 50
+steps the FP32 iterates drift from the FP64 ones, which moves entries across the kink
+that one step's rounding would not); the oracle's reverse pass then takes the device's
+decisions (adjoint(..., active=...)), and the gradients are held to bars set by FP32 arithmetic alone.  Two steps: 1e-4
+(measured 4e-7).  The 50-step run: the unrolled map is badly conditioned there (its
+steps include tau = 1, where I - tau S expands, and dl/dX is a sum of per-step terms
+about 20 times its own size), so rounding only the oracle's forward iterates to FP32,
+with the decisions held, already moves dl/dX by about 1e-2 and dl/dlambda by 5e-3.
+The test measures that sensitivity on the oracle side and holds the device to three
+times it (plus 1e-4); a reverse pass wrong by a few percent fails.
 """
 import numpy as np
 import pytest
@@ -75,10 +81,10 @@ def _near_ties(x32, lam, taus):
                for m, b in zip(ad.kink_margins(x, lam, taus, its), _fp32_bands(x, taus, its)))
 
 
-def _device_decisions(x32, lam, taus):
-    """The device's kink decision of every entry and step, from its own forward replay:
-    the off-diagonal entry (i, j) of Omega_t+1 is nonzero exactly when |a| > tau lambda.
-    Column form (entry (i, j) = row i of column j), one boolean p x p mask per step."""
+def _device_replay(x32, lam, taus):
+    """The device's forward replay: its iterates Omega_1 .. Omega_K (column form, entry
+    (i, j) = row i of column j) and its kink decision of every entry and step (the
+    off-diagonal entry (i, j) of Omega_t+1 is nonzero exactly when |a| > tau lambda)."""
     import torch
     from paper_2412_11554_amd import accord
     n, p = x32.shape
@@ -86,37 +92,66 @@ def _device_decisions(x32, lam, taus):
     om = torch.eye(p, dtype=torch.float32, device="cuda")
     seq = torch.empty((len(taus), p, p), dtype=torch.float32, device="cuda")
     accord.accord_fbs_replay(X, om, list(taus), lam, seq=seq)
-    nz = (seq != 0).cpu().numpy()
+    its = seq.cpu().numpy()
     del seq
-    return [m.T for m in nz]
+    its = [m.T for m in its]
+    return its, [m != 0 for m in its]
 
 
 def _compare_with_device_decisions(x32, xv32, lam, taus, every):
     """Device gradients against the oracle's reverse pass on the device's kink decisions,
-    after checking those decisions against the oracle's outside the FP32 band."""
+    after checking those decisions against the oracle's: they may differ only where the
+    oracle's distance to the kink is within the FP32 band of a plus the distance between
+    the oracle's a and the a of the device's own iterate (computed in FP64), i.e. where
+    rounding, or the drift of the FP32 iterates over the earlier steps, can put the
+    entry on the other side."""
     x, xv = x32.astype(np.float64), xv32.astype(np.float64)
-    p = x.shape[1]
+    n, p = x.shape
     its = ad.replay_iterates(x, lam, taus)
     margins = ad.kink_margins(x, lam, taus, its)
     bands = _fp32_bands(x, taus, its)
-    dev = _device_decisions(x32, lam, taus)
+    dev_its, dev = _device_replay(x32, lam, taus)
     off = ~np.eye(p, dtype=bool)
     ties = differ = 0
-    for m, b, d in zip(margins, bands, dev):
+    drift_max = 0.0
+    outside_all = []
+    for t, (m, b, d) in enumerate(zip(margins, bands, dev)):
+        om_dev = np.eye(p) if t == 0 else dev_its[t - 1].astype(np.float64)
+        a_dev = om_dev - taus[t] * (x.T @ (x @ om_dev)) / n
+        a_or = its[t] - taus[t] * (x.T @ (x @ its[t])) / n
+        drift = np.abs(a_dev - a_or)
+        drift_max = max(drift_max, float(drift.max()))
+        band = b + drift
         diff = ((m > 0) != d) & off
-        outside = diff & (np.abs(m) > b)
-        assert not outside.any(), (int(outside.sum()), float(np.abs(m[outside]).min()))
-        ties += int(np.sum((np.abs(m) <= b) & off))
+        outside = diff & (np.abs(m) > band)
+        outside_all.append((t, int(outside.sum())))
+        ties += int(np.sum((np.abs(m) <= band) & off))
         differ += int(diff.sum())
+    # the forward iterates themselves agree (the drift above stays small): FP32 bar
+    fwd = np.linalg.norm(dev_its[-1] - its[-1]) / np.linalg.norm(its[-1])
     loss, lbar, xbar = _grads(x32, xv32, lam, taus, every)
     rl = ad.val_loss(xv, its[-1])
     _, rlbar, rxbar = ad.adjoint(x, lam, taus, ad.val_loss_grad(xv, its[-1]), iterates=its,
                                  active=dev)
     rel_x = np.linalg.norm(xbar - rxbar) / np.linalg.norm(rxbar)
-    print(f"{len(taus)} steps: {ties} entries within the FP32 band of the kink, {differ} "
-          f"decided differently by the device (all inside the band); loss {loss:.9g} vs "
-          f"{rl:.9g}; dl/dlambda {lbar:.8g} vs {rlbar:.8g}; dX rel {rel_x:.2e}", flush=True)
-    return loss, lbar, rel_x, rl, rlbar
+    print(f"{len(taus)} steps: {ties} entries within the band of the kink, {differ} decided "
+          f"differently by the device (all inside the band; largest drift of a {drift_max:.1e}, "
+          f"final iterate rel {fwd:.1e}); loss {loss:.9g} vs {rl:.9g}; dl/dlambda {lbar:.8g} "
+          f"vs {rlbar:.8g}; dX rel {rel_x:.2e}", flush=True)
+    assert all(c == 0 for _, c in outside_all), [tc for tc in outside_all if tc[1]]
+    assert fwd <= 1e-4, fwd
+    return loss, lbar, rel_x, rl, rlbar, (x, xv, its, dev, rxbar)
+
+
+def _fp32_forward_sensitivity(x, xv, lam, taus, its, dev, rxbar, rlbar):
+    """How far the oracle's own gradients move when only its forward iterates are rounded
+    to FP32 (the device's kink decisions held in both): relative change of dl/dX and of
+    dl/dlambda.  A run that keeps its iterates in FP32 cannot be expected closer."""
+    its32 = ad.replay_iterates(x, lam, taus, active=dev, round_fp32=True)
+    _, lb32, xb32 = ad.adjoint(x, lam, taus, ad.val_loss_grad(xv, its32[-1]), iterates=its32,
+                               active=dev)
+    return (float(np.linalg.norm(xb32 - rxbar) / np.linalg.norm(rxbar)),
+            float(abs(lb32 - rlbar) / abs(rlbar)))
 
 
 @pytest.mark.parametrize("n,p,nv,K,every", [(40, 14, 25, 12, 5), (33, 97, 20, 9, 4),
@@ -155,7 +190,7 @@ def test_diff_full_width_tight(gpu_lib):
     d = datagen.diff_workload()
     x32, xv32, lam = d["x_train"], d["x_val"], d["lam"]
     taus = [0.25, 0.125]
-    loss, lbar, rel_x, rl, rlbar = _compare_with_device_decisions(x32, xv32, lam, taus, 2)
+    loss, lbar, rel_x, rl, rlbar, _ = _compare_with_device_decisions(x32, xv32, lam, taus, 2)
     assert loss == pytest.approx(rl, rel=1e-5)
     assert lbar == pytest.approx(rlbar, rel=1e-4)
     assert rel_x <= 1e-4
@@ -173,8 +208,13 @@ def test_diff_full_size(gpu_lib):
     taus = tr[1:, 3].cpu().numpy()
     print(f"diff: p={d['p']} K={K}, {st['trials']} trials in the recording fit", flush=True)
     del X
-    loss, lbar, rel_x, rl, rlbar = _compare_with_device_decisions(x32, xv32, lam, taus,
-                                                                  d["every"])
+    loss, lbar, rel_x, rl, rlbar, ctx = _compare_with_device_decisions(x32, xv32, lam, taus,
+                                                                       d["every"])
+    x, xv, its, dev, rxbar = ctx
+    sx, sl = _fp32_forward_sensitivity(x, xv, lam, taus, its, dev, rxbar, rlbar)
+    print(f"FP32 rounding of the oracle's forward iterates alone moves dl/dX by {sx:.2e} and "
+          f"dl/dlambda by {sl:.2e}; the device is off by {rel_x:.2e} and "
+          f"{abs(lbar - rlbar) / abs(rlbar):.2e}", flush=True)
     assert loss == pytest.approx(rl, rel=1e-5)
-    assert lbar == pytest.approx(rlbar, rel=1e-3)
-    assert rel_x <= 1e-3
+    assert abs(lbar - rlbar) <= (3 * sl + 1e-4) * abs(rlbar)
+    assert rel_x <= 3 * sx + 1e-4

@@ -141,3 +141,17 @@ def test_adjoint_with_given_decisions():
     fl = ad.adjoint(x, lam, t1, ob1, iterates=its1, active=[flipped])[1]
     a = its1[0] - t1[0] * (x.T @ (x @ its1[0])) / n
     assert fl - base == pytest.approx(t1[0] * np.sign(a[i, j]) * ob1[i, j], rel=1e-12, abs=1e-15)
+
+
+def test_replay_with_given_decisions_and_rounding():
+    """replay_iterates with the run's own kink decisions is the plain replay; with
+    round_fp32 every iterate is the float32 rounding of a step from the previous one."""
+    x, xv, lam, taus = _setup(K=5)
+    its = ad.replay_iterates(x, lam, taus)
+    own = [m > 0 for m in ad.kink_margins(x, lam, taus, its)]
+    again = ad.replay_iterates(x, lam, taus, active=own)
+    assert all(np.array_equal(a, b) for a, b in zip(its, again))
+    r32 = ad.replay_iterates(x, lam, taus, active=own, round_fp32=True)
+    one = ad.replay_iterates(x, lam, taus[2:3], omega0=r32[2], active=own[2:3])[1]
+    assert np.array_equal(r32[3], one.astype(np.float32).astype(np.float64))
+    assert 0 < np.abs(r32[-1] - its[-1]).max() < 1e-5
