@@ -26,8 +26,11 @@
  * Ownership.  The caller owns every buffer, including the workspace `ws`
  * (device, 256-byte aligned, at least accord_workspace_bytes() bytes).  The
  * library allocates no device memory and frees nothing; its only global state
- * is a thread-local last-error string, the pinned host mailbox of the fit loop, and
- * (with params.timing) a thread-local cache of HIP events that later calls reuse.  Calls with distinct workspaces are
+ * is a thread-local last-error string, the pinned host mailbox of the fit loop (one
+ * hipHostMalloc of 16 bytes per calling thread, allocated on that thread's first
+ * accord_fit and kept until the process ends), (with params.timing) a thread-local
+ * cache of HIP events that later calls reuse, and the static partial-sum array of
+ * accord_prox_noalloc.  Calls with distinct workspaces are
  * independent; calls sharing a workspace must be stream-ordered.
  *
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = default stream).
@@ -194,6 +197,20 @@ int accord_grad(const float* X, int64_t n, int64_t p, const float* Omega,
  * Asynchronous. */
 int accord_prox(const float* Omega, const float* G, int64_t p, double tau, double lambda,
                 float* Omega_out, double* red, void* ws, size_t ws_bytes, void* stream);
+
+/* accord_prox for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same operation,
+ * arguments (without the workspace), errors and kernels as accord_prox, so the same
+ * results bit for bit.  Its FP64 partial sums go to a library-owned device array of
+ * 256 KiB (4096 rows of 8 doubles; every p the library accepts needs at most 4096 rows,
+ * and a larger need is rejected with ACCORD_ERR_INVALID_ARG), one per GPU, held until the
+ * process ends.  The call allocates nothing: the first call on a device looks up the
+ * array's address there.  All calls on one GPU share that array, and each call leaves
+ * its partial sums in it: calls that overlap on one GPU (on different streams, or from
+ * different threads without ordering) race and must be serialised by the caller.
+ * Asynchronous and stream-ordered like accord_prox. */
+int accord_prox_noalloc(const float* Omega, const float* G, int64_t p, double tau,
+                        double lambda, float* Omega_out, double* red, void* stream);
 
 /* Objective of eq. 3.2 at Omega (column form):
  * out (device double[3], written) = { g, h, f } with g = ||X Omega||_F^2/(2n),

@@ -95,6 +95,8 @@ def lib() -> ctypes.CDLL:
         L.accord_workspace_bytes.restype = _sz
         L.accord_grad.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]
         L.accord_prox.argtypes = [_vp, _vp, _i64, _d, _d, _vp, _vp, _vp, _sz, _vp]
+        L.accord_prox_noalloc.argtypes = [_vp, _vp, _i64, _d, _d, _vp, _vp, _vp]
+        L.accord_prox_noalloc.restype = ctypes.c_int
         L.accord_objective.argtypes = [_vp, _i64, _i64, _vp, _d, _vp, _vp, _sz, _vp]
         L.accord_fit.argtypes = [_vp, _i64, _i64, _vp, ctypes.POINTER(accord_params),
                                  ctypes.POINTER(accord_stats), _vp, _vp, _sz, _vp]
@@ -216,6 +218,17 @@ def accord_prox(Omega: torch.Tensor, G: torch.Tensor, tau: float, lam: float, *,
     _check(lib().accord_prox(_dev(Omega, "Omega"), _dev(G, "G"), p, float(tau), float(lam),
                              _dev(out, "Omega_out"), _dev(red, "red", torch.float64),
                              ws.data_ptr(), ws.numel(), _stream(dev)))
+    return out, red
+
+
+def accord_prox_noalloc(Omega: torch.Tensor, G: torch.Tensor, tau: float, lam: float,
+                        out: torch.Tensor, red: torch.Tensor):
+    """accord_prox without a workspace (the library's own scratch array); the caller
+    passes the outputs: out [p, p] float32 and red [6] float64 device tensors."""
+    p = Omega.shape[0]
+    _check(lib().accord_prox_noalloc(_dev(Omega, "Omega"), _dev(G, "G"), p, float(tau),
+                                     float(lam), _dev(out, "Omega_out"),
+                                     _dev(red, "red", torch.float64), _stream(Omega.device)))
     return out, red
 
 

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -460,9 +461,13 @@ const char* accord_status_str(int s) {
 
 const char* accord_last_error(void) { return g_last_error.c_str(); }
 
-int accord_prox(const float* Omega, const float* G, int64_t p, double tau, double lambda,
-                float* Omega_out, double* red, void* ws, size_t ws_bytes, void* stream) {
-    g_last_error.clear();
+}  // extern "C"
+
+namespace {
+
+// arguments of accord_prox and accord_prox_noalloc (everything but the workspace)
+int check_prox_args(const float* Omega, const float* G, int64_t p, double tau, double lambda,
+                    const float* Omega_out, const double* red) {
     TRY(check_dims(1, p));
     TRY(check_ptr(Omega, "Omega"));
     TRY(check_ptr(G, "G"));
@@ -473,9 +478,13 @@ int accord_prox(const float* Omega, const float* G, int64_t p, double tau, doubl
     if (!(tau > 0.0) || !isfinite(tau)) return fail(ACCORD_ERR_INVALID_ARG, "tau must be finite and > 0");
     if (!(lambda >= 0.0) || !isfinite(lambda))
         return fail(ACCORD_ERR_INVALID_ARG, "lambda must be finite and >= 0");
-    const Plan P = make_plan(1, p, 1, PREC_FP32);
-    TRY(check_ws(ws, ws_bytes, P.end_prox));
-    hipStream_t st = (hipStream_t)stream;
+    return ACCORD_OK;
+}
+
+// the prox pass and the fixed-order combine of its FP64 partial sums (one row of
+// kPartCols per workgroup) into red
+int enqueue_prox(const float* Omega, const float* G, int64_t p, double tau, double lambda,
+                 float* Omega_out, double* red, double* part, hipStream_t st) {
     ProxArgs a = {};
     a.om = Omega;
     a.g = G;
@@ -486,12 +495,26 @@ int accord_prox(const float* Omega, const float* G, int64_t p, double tau, doubl
     a.p = p;
     a.tau = tau;
     a.lambda = lambda;
-    a.part = at<double>(ws, P.off_prox_part);
+    a.part = part;
     const int nb = prox_blocks(a.total);
     launch_prox(a, nb, st);
     launch_combine_prox(a.part, nb, red, st);
     HIP_TRY(hipGetLastError());
     return ACCORD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int accord_prox(const float* Omega, const float* G, int64_t p, double tau, double lambda,
+                float* Omega_out, double* red, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    TRY(check_prox_args(Omega, G, p, tau, lambda, Omega_out, red));
+    const Plan P = make_plan(1, p, 1, PREC_FP32);
+    TRY(check_ws(ws, ws_bytes, P.end_prox));
+    return enqueue_prox(Omega, G, p, tau, lambda, Omega_out, red,
+                        at<double>(ws, P.off_prox_part), (hipStream_t)stream);
 }
 
 // shared by accord_grad and accord_objective: X -> padded copies, Omega -> Om0,
@@ -1489,6 +1512,61 @@ int accord_fbs_adjoint_step(const float* X, int64_t n, int64_t p, const float* O
     enqueue_trial(x, PREC_FP32, st);
     HIP_TRY(hipGetLastError());
     return ACCORD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free prox: the FP64 partial sums of accord_prox go to a file-scope
+// device array instead of the caller's workspace.  Each GPU holds its own copy of
+// the array; its address on a device comes from hipGetSymbolAddress (the array's
+// name in host code is only a host-side stand-in) and is looked up once per device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kScratchRows = kMaxProxBlocks;             // prox workgroups of one call, at most
+constexpr int kScratchDoubles = kScratchRows * kPartCols;  // 256 KiB
+constexpr int kMaxScratchDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxScratchDevices];  // device address of `scratch` on each GPU
+
+int scratch_on_current_device(double** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(ACCORD_ERR_UNSUPPORTED, "device index %d beyond the %d devices supported",
+                    dev, kMaxScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(ACCORD_ERR_HIP, "no device address for the prox scratch array");
+        g_scratch_dev[dev] = (double*)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return ACCORD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int accord_prox_noalloc(const float* Omega, const float* G, int64_t p, double tau,
+                        double lambda, float* Omega_out, double* red, void* stream) {
+    g_last_error.clear();
+    TRY(check_prox_args(Omega, G, p, tau, lambda, Omega_out, red));
+    const int nb = prox_blocks(p * p);
+    if (nb > kScratchRows)
+        return fail(ACCORD_ERR_INVALID_ARG, "p=%lld needs %d partial rows; the scratch array "
+                    "holds %d", (long long)p, nb, kScratchRows);
+    double* part = nullptr;
+    TRY(scratch_on_current_device(&part));
+    return enqueue_prox(Omega, G, p, tau, lambda, Omega_out, red, part, (hipStream_t)stream);
 }
 
 }  // extern "C"
