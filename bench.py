@@ -260,6 +260,8 @@ def run_form(form, X, w, iters, ws, om, steps, warmup, check, warm_tau=False, ca
            "ms_per_step": elapsed / steps * 1e3,
            "steps": steps, "warmup": warmup, "iters_per_step": iters,
            "trials_per_iter": sum(s["trials"] for s in stats) / max(1, sum(s["iters"] for s in stats)),
+           "probe_rejects_per_iter": sum(s["probe_rejects"] for s in stats) /
+                                     max(1, sum(s["iters"] for s in stats)),
            "lipschitz": stats[-1]["lipschitz"], "lz_steps": stats[0]["lz_steps"] if not carry else None,
            "kernels": kernel_report(stats, form, w.n, w.p, traffic_workload)}
     if carry:

@@ -140,6 +140,15 @@ typedef struct {
                            after every k-th accepted iteration W is recomputed as X Omega
                            in FP32 (one extra product), which bounds the drift of the carried
                            W (in the BF16X1 / FP8 forms the carried W sums rounded steps). */
+    int32_t probe;      /* accord_fit / accord_refit, BF16X1 / BF16X3 / FP8 forms with at least
+                           4 tiles of 256 samples (n > 768) and no split-K: 1 (the default of
+                           accord_default_params) = run each trial first on the first 256
+                           samples; ||X Delta||^2 over them is a lower bound of the whole
+                           sum, so when it alone fails Alg. 1's test the trial is rejected
+                           without the rest of the product (the same decision, since every
+                           term is a square); otherwise the product is completed and tested
+                           as usual.  0 = always the whole product.  Same iterates either
+                           way, up to FP64 rounding of the sums at a tie. */
 } accord_params;
 
 /* Results of accord_fit (host memory, filled on return). */
@@ -167,10 +176,11 @@ typedef struct {
     double log_det_d;       /* sum_j log Omega_jj at the result (log det of the diagonal) */
     double l1;              /* ||Omega||_1 at the result (all entries) */
     int32_t lz_steps;       /* Lanczos steps of the device estimate of L (0 if L was given) */
+    int32_t probe_rejects;  /* trials rejected from their first 256 samples (params.probe) */
 } accord_stats;
 
 /* Fills `prm` with defaults: lambda 0.1, tau0 1, beta 0.5, lipschitz 0 (estimate),
- * tol 0, max_iter 100, FP32, power_iters 256, timing 0, warm_tau 0,
+ * tol 0, max_iter 100, FP32, power_iters 256, timing 0, warm_tau 0, probe 1,
  * graph 0, refresh_every 0. */
 void accord_default_params(accord_params* prm);
 

@@ -38,7 +38,7 @@ class accord_params(ctypes.Structure):
                 ("precision", ctypes.c_int32),
                 ("power_iters", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("warm_tau", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("refresh_every", ctypes.c_int32)]
+                ("refresh_every", ctypes.c_int32), ("probe", ctypes.c_int32)]
 
 
 class accord_stats(ctypes.Structure):
@@ -51,7 +51,8 @@ class accord_stats(ctypes.Structure):
                 ("trial_gemm_ms", ctypes.c_double), ("trial_gemm_launches", ctypes.c_int32),
                 ("prox_ms", ctypes.c_double), ("prox_launches", ctypes.c_int32),
                 ("total_ms", ctypes.c_double), ("log_det_d", ctypes.c_double),
-                ("l1", ctypes.c_double), ("lz_steps", ctypes.c_int32)]
+                ("l1", ctypes.c_double), ("lz_steps", ctypes.c_int32),
+                ("probe_rejects", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -249,15 +250,18 @@ def accord_fit(X: torch.Tensor, lam: float, max_iter: int, *, omega0: torch.Tens
                tau0: float = 1.0, beta: float = 0.5, lipschitz: float = 0.0, tol: float = 0.0,
                power_iters: int = 0, precision: str = "fp32",
                trace: bool = False, timing: int = 0, warm_tau: bool = False,
-               refresh_every: int = 0, ws=None, omega_out=None):
+               refresh_every: int = 0, probe: bool = True, ws=None, omega_out=None):
     """ACCORD-FBS (Alg. 1).  Returns (Omega [p, p] paper form, stats dict, trace or None).
-    omega0 defaults to the identity.  warm_tau selects the warm-started step variant."""
+    omega0 defaults to the identity.  warm_tau selects the warm-started step variant;
+    probe=False always runs the whole trial product (no rejection from the first 256
+    samples)."""
     n, p = X.shape
     dev = X.device
     prm = default_params(lam=lam, max_iter=max_iter, tau0=tau0, beta=beta, lipschitz=lipschitz,
                          tol=tol, power_iters=power_iters,
                          precision=precision, timing=int(timing),
-                         warm_tau=1 if warm_tau else 0, refresh_every=refresh_every)
+                         warm_tau=1 if warm_tau else 0, refresh_every=refresh_every,
+                         probe=1 if probe else 0)
     if omega_out is None:
         omega_out = torch.empty((p, p), dtype=torch.float32, device=dev)
     if omega0 is None:

@@ -81,6 +81,8 @@ struct Plan {
     int fused;      // bf16 and FP8 forms: the fused trial kernel's 256 x 128 geometry
     int fused32;    // FP32 form: prox fused into the 128 x 128 FP32 trial tile (else a
                     // separate prox pass writes Delta for the plain FP32 GEMM)
+    int probe;      // fused forms with >= 4 M tiles and no split-K: a trial can be
+                    // rejected from its first M tile (params.probe)
     int prox_rows;  // FP64 prox partial rows left per trial
     int nprox;
     size_t off_ls, off_prox_part, off_norm_part, off_lz,
@@ -138,6 +140,10 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     // n = 500 (4 row tiles: 300 us against 287 + 77 us at p = 5000), slower at n = 1000
     // (8 row tiles: 218 ms against 152 + 33 ms at p = 1e5).  So it runs up to 4 row tiles.
     P.fused32 = !P.fused && P.t32.tilesM <= 4;
+    // A probe (M tile 0, a quarter of the samples or less) rejects a trial whose test
+    // fails by more than the inverse of its share of the rows; with fewer M tiles the
+    // probe is a large share of the product and cannot reject the near misses.
+    P.probe = P.fused && P.tp.splits == 1 && P.tp.tilesM >= 4;
     P.prox_rows = P.fused ? P.tp.tilesN * P.tp.splits
                           : (P.fused32 ? P.t32.tilesN * P.t32.splits : P.nprox);
     const bool bf = is_bf16(prec);
@@ -349,6 +355,8 @@ int check_params(const accord_params* prm) {
     if (prm->graph != 0 && prm->graph != 1)
         return fail(ACCORD_ERR_INVALID_ARG, "graph must be 0 or 1");
     if (prm->refresh_every < 0) return fail(ACCORD_ERR_INVALID_ARG, "refresh_every must be >= 0");
+    if (prm->probe != 0 && prm->probe != 1)
+        return fail(ACCORD_ERR_INVALID_ARG, "probe must be 0 or 1");
     return ACCORD_OK;
 }
 
@@ -434,6 +442,7 @@ void accord_default_params(accord_params* prm) {
     prm->precision = ACCORD_FP32;
     prm->power_iters = kLzDefaultSteps;
     prm->timing = 0;
+    prm->probe = 1;
 }
 
 size_t accord_workspace_bytes(int64_t n, int64_t p, const accord_params* prm) {
@@ -718,7 +727,26 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
             }
             Launch lt = {nullptr, nullptr, t, k};
             if (tim) { lt.a = pool.get(); lt.b = pool.get(); HIP_TRY(hipEventRecord(lt.a, st)); }
-            if (fused)
+            if (fused && P.probe && prm->probe) {
+                // probe: M tile 0 with the prox sums, no Omega+ store; then the test of
+                // its lower bound; then (unless rejected) the other M tiles, the first of
+                // which stores Omega+
+                GemmArgs tpb = ta;
+                tpb.m_first = 0;
+                tpb.m_count = 1;
+                tpb.store_m = -1;
+                tpb.sums_m = 0;
+                launch_trial_fused(tpb, a, prec, st);
+                launch_probe_decide(ls, prox_part, P.prox_rows, norm_part, P.tp.tilesN,
+                                    P.tp.tilesM, mbox_dev, st);
+                GemmArgs tcp = ta;
+                tcp.m_first = 1;
+                tcp.m_count = P.tp.tilesM - 1;
+                tcp.store_m = 1;
+                tcp.sums_m = -1;
+                tcp.pred = 3;
+                launch_trial_fused(tcp, a, prec, st);
+            } else if (fused)
                 launch_trial_fused(ta, a, prec, st);
             else if (P.fused32)
                 launch_trial_fused32(ta, a, st);
@@ -798,6 +826,7 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
         stats->log_det_d = host.logd_cur;
         stats->l1 = host.l1_cur;
         stats->lz_steps = host.lz_steps;
+        stats->probe_rejects = host.probe_rejects;
         if (timing) {
             std::vector<int32_t> tl((size_t)(host.iter > 0 ? host.iter : 1), 0);
             if (host.iter > 0)

@@ -57,6 +57,8 @@ struct LsState {
     int32_t fixed_step; // beta == 1: the single trial is accepted
     int32_t warm_tau;   // 1: an iteration starts from min(tau0, tau_acc / beta), not tau0
     int32_t lz_steps;   // Lanczos steps of the device estimate of L (0: L was given)
+    int32_t probe_rej;  // the trial in flight was rejected by its probe (row tile 0)
+    int32_t probe_rejects;  // trials rejected by their probe, over the fit
 };
 
 // Pinned host mailbox: after every executed acceptance test the device posts the
@@ -121,11 +123,16 @@ struct GemmArgs {
     float* P;           // EPI_PARTIAL: split partial tiles
     double* norm_part;  // EPI_TRIAL: per tile {||V||^2, ||C||^2}
     LsState* ls;        // predication state (null = always run)
-    int pred;           // 1: skip if converged; 2: skip if done or converged
+    int pred;           // 1: skip if converged; 2: skip if done or converged; 3: also
+                        // skip if the trial's probe rejected it
     int begin_iter;     // reset the line-search state of a new iteration
     int Mvalid, Nvalid; // extent counted in the norms
     const uint8_t* cmask; // EPI_GRAD, optional: C entries whose byte (same layout as C)
                           // is 0 are stored as 0 (the refit's support)
+    // fused trial kernels: the launch covers the M tiles m_first .. m_first + m_count - 1
+    // (m_count 0: all tilesM); the tile with tile_m == store_m writes Omega+ and the one
+    // with tile_m == sums_m writes the prox sums (-1: none).  trial_args sets 0, 0, 0, 0.
+    int m_first, m_count, store_m, sums_m;
 };
 
 struct ProxArgs {
@@ -188,6 +195,9 @@ void launch_prox(ProxArgs a, int nblocks, hipStream_t st);
 void launch_finalize(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
                      int ntiles, double* trace, int32_t* trials_log, Mailbox* mbox,
                      hipStream_t st);
+void launch_probe_decide(LsState* ls, const double* prox_part, int nprox,
+                         const double* norm_part, int tilesN, int tilesM, Mailbox* mbox,
+                         hipStream_t st);
 void launch_fit_init(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
                      int ntiles, double* trace, hipStream_t st);
 void launch_combine_prox(const double* prox_part, int nprox, double* red, hipStream_t st);

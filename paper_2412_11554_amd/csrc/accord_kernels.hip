@@ -293,11 +293,13 @@ __device__ inline bool gemm_skip(const GemmArgs& g) {
     if (g.ls) {
         if (g.pred >= 1 && g.ls->converged) return true;
         if (g.pred >= 2 && g.ls->done) return true;
+        if (g.pred >= 3 && g.ls->probe_rej) return true;
     }
     if (g.begin_iter && blockIdx.x == 0 && threadIdx.x == 0) {
         // a new iteration starts from tau0 (Alg. 1); nothing else reads these now
         g.ls->done = 0;
         g.ls->trials = 0;
+        g.ls->probe_rej = 0;
         g.ls->tau = start_tau(*g.ls);
     }
     return false;
@@ -1392,14 +1394,17 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
     const double tau = px.ls->tau, lam = px.ls->lambda;
     const float tau_f = (float)tau, thr_f = (float)(tau * lam);
 
-    // tile order: tile_m fastest, then tile_n, then split (XCD-contiguous ranges)
+    // tile order: tile_m fastest, then tile_n, then split (XCD-contiguous ranges), over
+    // the launch's M tiles m_first .. m_first + m_count - 1
     const int nblk = gridDim.x, bid = blockIdx.x;
     const int xcd = bid & 7, local = bid >> 3, q8 = nblk >> 3, r8 = nblk & 7;
     const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + local;
-    const int tile_m = logical % g.tilesM;
-    const int tile_n = (logical / g.tilesM) % g.tilesN;
-    const int split = logical / (g.tilesM * g.tilesN);
-    const bool owner = tile_m == 0;
+    const int mcnt = g.m_count > 0 ? g.m_count : g.tilesM;
+    const int tile_m = g.m_first + logical % mcnt;
+    const int tile_n = (logical / mcnt) % g.tilesN;
+    const int split = logical / (mcnt * g.tilesN);
+    const bool owner = tile_m == g.store_m;         // stores Omega+
+    const bool sums_owner = tile_m == g.sums_m;     // writes the prox sums
     const int m0 = tile_m * kFBM, n0 = tile_n * kFBN;
     const int ksteps = g.K / BK;
     const int s_begin = (int)((int64_t)ksteps * split / g.splits);
@@ -1550,7 +1555,7 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
 
     const int tile = tile_m + tile_n * g.tilesM;
     double* red = (double*)&sA[0][0][0];  // LDS is free after the K loop
-    if (owner) {
+    if (sums_owner) {
         double v[6] = {pacc.d2, pacc.dg, pacc.l1, pacc.logd, pacc.nnz, pacc.fro};
         block_sum_in<6, kWThreads / 64>(v, red);
         if (tid == 0) {
@@ -1675,7 +1680,8 @@ void launch_trial_fused(const GemmArgs& a, const ProxArgs& px, int prec, hipStre
         launch_trial_fused8(a, px, st);
         return;
     }
-    const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
+    const int mcnt = a.m_count > 0 ? a.m_count : a.tilesM;
+    const unsigned blocks = (unsigned)((int64_t)mcnt * a.tilesN * a.splits);
     if (a.splits > 1) {
         if (prec == PREC_BF16X3)
             k_trial_fused<3, EPI_PARTIAL><<<blocks, kWThreads, 0, st>>>(a, px);
@@ -1997,8 +2003,10 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_fp8w(GemmArgs g) {
             *(uint2*)&sB8[(buf)][col_ * kLDK8 + br] = make_uint2(w0_, w1_);               \
             if ((tid & 3) == 0) sBs8[(buf)][col_ * 2 + ((tid >> 2) & 1)] = (uint8_t)sb_;  \
             if (owner && jvalid[q]) {                                                     \
-                st_stream(nw_[0], (f4*)(pn[q] + k0_));                                    \
-                st_stream(nw_[1], (f4*)(pn[q] + k0_ + 4));                                \
+                if (store_owner) {                                                        \
+                    st_stream(nw_[0], (f4*)(pn[q] + k0_));                                \
+                    st_stream(nw_[1], (f4*)(pn[q] + k0_ + 4));                            \
+                }                                                                         \
                 float sd2_ = 0.f, sdg_ = 0.f, sl1_ = 0.f, sfr_ = 0.f;                     \
                 int nz_ = 0;                                                              \
                 _Pragma("unroll") for (int h = 0; h < 2; ++h) {                           \
@@ -2036,10 +2044,13 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused8(GemmArgs g, ProxA
     const int nblk = gridDim.x, bid = blockIdx.x;
     const int xcd = bid & 7, local = bid >> 3, q8 = nblk >> 3, r8 = nblk & 7;
     const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + local;
-    const int tile_m = logical % g.tilesM;
-    const int tile_n = (logical / g.tilesM) % g.tilesN;
-    const int split = logical / (g.tilesM * g.tilesN);
-    const bool owner = tile_m == 0;
+    const int mcnt = g.m_count > 0 ? g.m_count : g.tilesM;
+    const int tile_m = g.m_first + logical % mcnt;
+    const int tile_n = (logical / mcnt) % g.tilesN;
+    const int split = logical / (mcnt * g.tilesN);
+    const bool store_owner = tile_m == g.store_m;   // stores Omega+
+    const bool sums_owner = tile_m == g.sums_m;     // writes the prox sums
+    const bool owner = store_owner || sums_owner;   // computes them
     const int m0 = tile_m * kFBM, n0 = tile_n * kFBN;
     const int ksteps = g.K / 64;
     const int s_begin = (int)((int64_t)ksteps * split / g.splits);
@@ -2150,7 +2161,7 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused8(GemmArgs g, ProxA
 
     const int tile = tile_m + tile_n * g.tilesM;
     double* red = (double*)&sA8[0][0];  // LDS is free after the K loop
-    if (owner) {
+    if (sums_owner) {
         double v[6] = {pacc.d2, pacc.dg, pacc.l1, pacc.logd, pacc.nnz, pacc.fro};
         block_sum_in<6, kWThreads / 64>(v, red);
         if (tid == 0) {
@@ -2199,7 +2210,8 @@ void launch_grad_fp8(const GemmArgs& a, hipStream_t st) {
 }
 
 void launch_trial_fused8(const GemmArgs& a, const ProxArgs& px, hipStream_t st) {
-    const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
+    const int mcnt = a.m_count > 0 ? a.m_count : a.tilesM;
+    const unsigned blocks = (unsigned)((int64_t)mcnt * a.tilesN * a.splits);
     if (a.splits > 1) {
         k_trial_fused8<EPI_PARTIAL><<<blocks, kWThreads, 0, st>>>(a, px);
         launch_splitk_reduce_f(a, st);
@@ -2252,6 +2264,13 @@ __device__ __forceinline__ void finalize_run(LsState* ls, const double* prox_par
                                              const double* norm_part, int ntiles, double* trace,
                                              int32_t* trials_log, Mailbox* mbox) {
     if (ls->done || ls->converged) return;
+    // a trial its probe has rejected is complete: clear the flag for the next trial
+    const int probe_rej = ls->probe_rej;
+    __syncthreads();
+    if (probe_rej) {
+        if (threadIdx.x == 0) ls->probe_rej = 0;
+        return;
+    }
     double pv[6];
     sum_partials<6>(prox_part, nprox, kPartCols, pv);
     double nv[2];
@@ -2320,6 +2339,48 @@ void launch_finalize(LsState* ls, const double* prox_part, int nprox, const doub
                      hipStream_t st) {
     k_finalize<<<1, kThreads, 0, st>>>(ls, prox_part, nprox, norm_part, ntiles, trace,
                                        trials_log, mbox);
+}
+
+// Probe of a trial: the fused trial kernel ran on M tile 0 only (the first kFBM samples),
+// whose workgroups also wrote the prox sums over every column.  ||X Delta||^2 summed over
+// the probe's rows is a lower bound of the sum over all samples (every term is a square),
+// so when it alone exceeds n ||Delta||^2 / tau the trial fails Alg. 1's test exactly as
+// the full product would.  The trial is then rejected here (counted, tau <- beta tau,
+// posted to the mailbox) and flagged, so that the launch over the remaining M tiles and
+// the acceptance test of this trial do nothing.  A trial at the floor tau <= 1/L, a fixed
+// step and non-finite sums always go on to the full test.  Norm rows of M tile 0 are
+// rows tile_n * tilesM (no split-K).
+__global__ void __launch_bounds__(kThreads) k_probe_decide(LsState* ls, const double* prox_part,
+                                                           int nprox, const double* norm_part,
+                                                           int tilesN, int tilesM, Mailbox* mbox) {
+    if (ls->done || ls->converged) return;
+    double pv[6];
+    sum_partials<6>(prox_part, nprox, kPartCols, pv);
+    double nv[1] = {0.0};
+    for (int r = threadIdx.x; r < tilesN; r += kThreads)
+        nv[0] += norm_part[(int64_t)r * tilesM * kNormCols];
+    block_sum<1>(nv);
+    if (threadIdx.x != 0) return;
+    const double d2 = pv[P_D2], v2 = nv[0], tau = ls->tau;
+    const bool reject = isfinite(d2) && isfinite(v2) && !(tau <= ls->inv_L) &&
+                        !ls->fixed_step && v2 * ls->inv_n > d2 / tau;
+    if (reject) {
+        ls->trials += 1;
+        ls->total_trials += 1;
+        ls->tau = tau * ls->beta;
+        ls->probe_rej = 1;
+        ls->probe_rejects += 1;
+        post_mailbox(mbox, ls);
+    } else {
+        ls->probe_rej = 0;
+    }
+}
+
+void launch_probe_decide(LsState* ls, const double* prox_part, int nprox,
+                         const double* norm_part, int tilesN, int tilesM, Mailbox* mbox,
+                         hipStream_t st) {
+    k_probe_decide<<<1, kThreads, 0, st>>>(ls, prox_part, nprox, norm_part, tilesN, tilesM,
+                                           mbox);
 }
 
 // Starting point: objective pieces of Omega^(0) (reduce-only prox sums of Omega^(0)

@@ -64,6 +64,7 @@ def test_default_params(L):
     assert prm.lipschitz == 0.0 and prm.max_iter == 100
     assert prm.warm_tau == 0 and prm.graph == 0 and prm.refresh_every == 0
     assert prm.power_iters == 256  # cap on the Lanczos steps of the L estimate
+    assert prm.probe == 1
 
 
 def test_status_strings(L):
@@ -95,18 +96,18 @@ FAKE = 1 << 20  # a 16-byte aligned non-null address; validation fails before an
     (dict(max_iter=-1), 1), (dict(precision=7), 5), (dict(tol=-1e-6), 1),
     (dict(lipschitz=-2.0), 1), (dict(lam=float("nan")), 1),
     (dict(p=(1 << 20) + 1), 1), (dict(n=(1 << 20) + 1), 1),
-    (dict(timing=-1), 1), (dict(power_iters=-1), 1),
+    (dict(timing=-1), 1), (dict(power_iters=-1), 1), (dict(probe=2), 1),
 ])
 def test_fit_validation(L, kw, status):
     args = dict(X=FAKE, n=10, p=12, Omega=FAKE, ws=FAKE, ws_bytes=1 << 40, lam=0.1, tau0=1.0,
                 beta=0.5, max_iter=3, precision=0, tol=0.0, lipschitz=0.0,
-                timing=0, power_iters=0)
+                timing=0, power_iters=0, probe=1)
     args.update(kw)
     prm = accord.default_params(lam=args["lam"], tau0=args["tau0"], beta=args["beta"],
                                 max_iter=args["max_iter"], precision=args["precision"],
                                 tol=args["tol"],
                                 lipschitz=args["lipschitz"], timing=args["timing"],
-                                power_iters=args["power_iters"])
+                                power_iters=args["power_iters"], probe=args["probe"])
     st = accord.accord_stats()
     r = L.accord_fit(args["X"], args["n"], args["p"], args["Omega"], ctypes.byref(prm),
                      ctypes.byref(st), None, args["ws"], args["ws_bytes"], None)

@@ -91,6 +91,31 @@ def test_c2_bf16x3_deterministic(c2):
     assert h1 == h2 and sa["f"] == sb["f"]
 
 
+def test_c2_probe_is_the_full_trial(c2):
+    """Three BF16x3 iterations with trials probed on the first 256 samples equal those that
+    always run the whole product, bit for bit (checked by column-chunk sums of the FP32
+    bit patterns and on sampled columns), with the same trial counts."""
+    import torch
+    from paper_2412_11554_amd import accord
+    w = c2["w"]
+
+    def bit_sums(om):
+        return [int(om[r:r + 5000].view(torch.int32).to(torch.int64).sum())
+                for r in range(0, om.shape[0], 5000)]
+
+    cols = np.array([0, 777, 50000, 99999])
+    runs = []
+    for probe in (True, False):
+        print(f"[c2] bf16x3 3 iterations, probe {probe}", flush=True)
+        _, st, tr = accord.accord_fit(c2["X"], w.lam, 3, precision="bf16x3", trace=True,
+                                      ws=c2["ws"], omega_out=c2["om"], probe=probe)
+        runs.append((st, tr.clone(), c2["om"][cols, :].clone(), bit_sums(c2["om"])))
+    (sa, ta, ca, ha), (sb, tb, cb, hb) = runs
+    print(f"[c2] trials {sa['trials']} (probe) vs {sb['trials']}", flush=True)
+    assert sa["trials"] == sb["trials"] and torch.equal(ta, tb)
+    assert torch.equal(ca, cb) and ha == hb
+
+
 def _check_sampled(c2, form, om, st, tr):
     import oracle
     from oracle import mx_oracle

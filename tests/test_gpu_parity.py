@@ -420,6 +420,37 @@ def test_fit_deterministic_benchmark_shape(gpu_lib, dev, form):
     assert sa["f"] == sb["f"] and sa["trials"] == sb["trials"]
 
 
+@pytest.mark.parametrize("form", ["bf16x3", "bf16x1", "fp8"])
+def test_fit_probe_is_the_full_trial(gpu_lib, dev, form):
+    """n = 800, p = 8192: 4 M tiles of 256 samples and no split-K, so every trial first runs
+    on M tile 0 and is rejected there when that lower bound of ||X Delta||^2 already fails
+    the test.  The prox of every tile is the same FP32 arithmetic and the acceptance sums
+    are unchanged, so the fit equals the one that always runs the whole product bit for
+    bit, with the same trial counts; BF16x3 also against the oracle's replay."""
+    import torch
+    w = datagen.small_random_problem(800, 8192, seed=31, lam=0.05)
+    X = _t(w.X, dev)
+    print(f"[probe] {form} n=800 p=8192 12 iterations, probe on and off", flush=True)
+    a, sa, ta = gpu_lib.accord_fit(X, 0.05, 12, precision=form, trace=True, probe=True)
+    a = a.clone()
+    b, sb, tb = gpu_lib.accord_fit(X, 0.05, 12, precision=form, trace=True, probe=False)
+    torch.cuda.synchronize()
+    assert sa["trials"] == sb["trials"] and sa["trials"] > sa["iters"]
+    assert sb["probe_rejects"] == 0 and sa["probe_rejects"] <= sa["trials"] - sa["iters"]
+    print(f"[probe] {sa['probe_rejects']} of {sa['trials'] - sa['iters']} rejected trials "
+          f"settled by the probe", flush=True)
+    assert torch.equal(ta, tb) and torch.equal(a, b)
+    if form == "bf16x3":
+        taus = ta.cpu().numpy()[1:, 3]
+        cols = np.array([0, 1, 4095, 8190, 8191])
+        ref = oracle.fit_fbs(w.X.astype(np.float64), 0.05, 12, L=sa["lipschitz"],
+                             tau_replay=taus, columns=cols)
+        got = a.cpu().numpy()[cols, :].astype(np.float64).T
+        rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
+        print(f"[probe] bf16x3 vs oracle replay: {rel:.2e}, {sa['trials']} trials", flush=True)
+        assert rel <= 1e-4, rel
+
+
 def test_fit_errors(gpu_lib, dev):
     import torch
     w = datagen.small_random_problem(20, 30, seed=5)
