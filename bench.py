@@ -131,6 +131,36 @@ def _traffic_table(workload):
     return tab["bytes_per_launch"] if tab.get("kernel_sha256_16") == digest else {}
 
 
+def _trial_plan(form, n, p):
+    """The library's launch plan of one trial (from n and p, as the library derives it):
+    the kernel, the split-K count (2 .. 8 when the tiles do not fill the CUs) and whether
+    trials are probed on the first 256 samples (fused forms, >= 4 tiles of 256 samples,
+    no split-K).  Names as rocprofv3 reports them; EPI 1 = trial epilogue, 2 = split-K
+    partials (then a reduce kernel).  Used only to pick the profiled traffic rows."""
+    n_pad, p_pad = -(-n // 64) * 64, -(-p // 64) * 64
+    fused = form != "fp32"
+    bm, bn, slots = (256, 128, 256) if fused else (128, 128, 512)
+    tm, tn = -(-n_pad // bm), -(-p // bn)
+    tiles, ks = tm * tn, p_pad // 64
+    best, cost = 1, float(-(-tiles // slots))
+    for sp in range(2, 9):
+        if ks // sp < 2:
+            break
+        c = -(-(tiles * sp) // slots) / sp
+        if c < cost * 0.9:
+            best, cost = sp, c
+    probe = fused and best == 1 and tm >= 4
+    if form == "fp32":
+        kern = "k_gemm_f32" if tm > 4 else "k_trial_fused32"
+        name = f"void {kern}<{1 if best == 1 else 2}>"
+    else:
+        kern = "k_trial_fused8" if form == "fp8" else f"k_trial_fused<{PASSES[form]},"
+        epi = 1 if best == 1 else 2
+        name = f"void {kern}<{epi}>" if form == "fp8" else f"void {kern} {epi}>"
+    return {"name": name, "splits": best, "probe": probe, "tilesM": tm, "tilesN": tn,
+            "grid": tiles * best, "probe_grid": tn, "rest_grid": (tm - 1) * tn}
+
+
 def kernel_report(stats, form, n, p, traffic_workload):
     """Per kernel group: mean duration from the library's HIP events, the achieved
     algorithmic rate and the roofline it is held to.
@@ -138,8 +168,13 @@ def kernel_report(stats, form, n, p, traffic_workload):
     gradient  G = X^T W / n: 2 n p^2 flops, MFMA-bound.
     trial     the fused prox + trial GEMM (+ its split-K reduce), which streams Omega, G
               in and Omega+ out (12 p^2 algorithmic bytes against HBM) and executes
-              2 n p^2 flops per MFMA pass; the bound is the larger of the two lower
-              bounds (MFMA for fp32 at these sizes, HBM for the bf16 and fp8 forms).
+              2 n p^2 flops per MFMA pass.  With probed trials (n > 768 in the fused
+              forms) a trial first runs on the first 256 samples (reads Omega, G: 8 p^2
+              bytes; 2 * 256 p^2 flops per pass) and only the fraction r of trials its
+              probe does not reject runs on the other samples and stores Omega+ (4 p^2
+              bytes, 2 (n - 256) p^2 flops): per executed trial 8 p^2 + (1 - r) 4 p^2
+              bytes and 2 (256 + (1 - r)(n - 256)) p^2 flops per pass.  The bound is the
+              larger of the two lower bounds.
     prox      separate prox launches (the FP32 form with more than 4 row tiles of 128
               samples, whose trial is then the plain FP32 GEMM): 16 p^2 bytes (read Omega,
               G; write Omega+, Delta)."""
@@ -153,6 +188,11 @@ def kernel_report(stats, form, n, p, traffic_workload):
         cnt = sum(s[key + "_launches"] for s in stats)
         return (ms, cnt, ms / cnt) if cnt else (0.0, 0, None)
 
+    def measured(name, grid=None):
+        if grid is not None and f"{name}@{grid}" in traffic:
+            return traffic[f"{name}@{grid}"]
+        return traffic.get(name)
+
     ms, cnt, avg = group("grad_gemm")
     if avg:
         a = flops / (avg * 1e-3) / 1e12
@@ -162,22 +202,41 @@ def kernel_report(stats, form, n, p, traffic_workload):
                             "avg_ms": avg, "total_ms": ms, "bound": "mfma", "achieved": a,
                             "peak": peak, "unit": "TFLOP/s", "frac": a / peak,
                             "executed_tflops": a * PASSES[form],
-                            "executed_frac": a * PASSES[form] / peak}
+                            "executed_frac": a * PASSES[form] / peak,
+                            "traffic": measured(f"void {name}")}
     ms, cnt, avg = group("trial_gemm")
     if avg:
-        a = flops / (avg * 1e-3) / 1e12
+        plan = _trial_plan(form, n, p)
         sep = group("prox")[1] > 0  # FP32 with a separate prox pass: plain trial GEMM
-        names = ((["k_gemm_f32<2>" if sep else "k_trial_fused32<2>", "k_splitk_reduce"])
-                 if form == "fp32" else
-                 ["k_trial_fused8<2>", "k_splitk_reduce_f"] if form == "fp8" else
-                 [f"k_trial_fused<{PASSES[form]}, 2>", "k_splitk_reduce_f"])
-        alg = 12.0 * p * p
+        trials = sum(s["trials"] for s in stats)
+        rej = sum(s.get("probe_rejects", 0) for s in stats) / max(1, trials)
+        if plan["probe"]:
+            n0 = min(256, n)
+            alg = 8.0 * p * p + (1.0 - rej) * 4.0 * p * p
+            fl = 2.0 * (n0 + (1.0 - rej) * (n - n0)) * p * p
+            names = [plan["name"] + " (probe)", "k_probe_decide", plan["name"] + " (rest)"]
+            tp, tr = measured(plan["name"], plan["probe_grid"]), measured(plan["name"],
+                                                                          plan["rest_grid"])
+            traf = tp + (1.0 - rej) * tr if (tp is not None and tr is not None) else None
+        else:
+            alg, fl = 12.0 * p * p, flops
+            S = plan["splits"]
+            if form == "fp32":  # the fused FP32 trial streams its partials, the plain one not
+                reduce_ = (f"k_splitk_reduce<{S}, "
+                           f"{'true' if 'fused32' in plan['name'] else 'false'}>")
+            else:
+                reduce_ = f"k_splitk_reduce_f<{S}>"
+            names = [plan["name"]] + ([reduce_] if S > 1 else [])
+            got = [measured(k if k.startswith("void") else f"void {k}") for k in names]
+            traf = sum(got) if all(g is not None for g in got) else None
+        a = fl / (avg * 1e-3) / 1e12
         gbs = alg / (avg * 1e-3) / 1e9
         t_hbm = alg / (PEAK_HBM_GBS * 1e9)
-        t_mfma = flops * PASSES[form] / (peak * 1e12)
+        t_mfma = fl * PASSES[form] / (peak * 1e12)
         d = {"what": "W+ = W + X Delta (+ norms)" if sep else
                      "fused prox (eq. 3.5) + W+ = W + X Delta (+ norms)",
-             "algorithmic_bytes": alg,
+             "algorithmic_bytes": alg, "useful_flops": fl,
+             "probe_reject_fraction": rej if plan["probe"] else None,
              "mfma": {"achieved": a * PASSES[form], "peak": peak, "unit": "TFLOP/s",
                       "frac": a * PASSES[form] / peak, "useful_tflops": a}}
         if t_hbm >= t_mfma:
@@ -186,7 +245,8 @@ def kernel_report(stats, form, n, p, traffic_workload):
         else:
             d.update({"bound": "mfma", "achieved": a * PASSES[form], "peak": peak,
                       "unit": "TFLOP/s", "frac": a * PASSES[form] / peak})
-        d.update({"kernels": names, "launches": cnt, "avg_ms": avg, "total_ms": ms})
+        d.update({"kernels": names, "launches": cnt, "avg_ms": avg, "total_ms": ms,
+                  "traffic": traf})
         out["trial_gemm"] = d
     ms, cnt, avg = group("prox")
     if avg:
@@ -195,17 +255,8 @@ def kernel_report(stats, form, n, p, traffic_workload):
         out["prox"] = {"what": "fused prox + reductions", "kernels": ["k_prox<0>"],
                        "launches": cnt, "avg_ms": avg, "total_ms": ms, "bound": "hbm",
                        "algorithmic_bytes": alg, "achieved": a, "peak": PEAK_HBM_GBS,
-                       "unit": "GB/s", "frac": a / PEAK_HBM_GBS}
-    def measured(k):
-        # exact name, else the one instantiation of a kernel templated on the split count
-        if f"void {k}" in traffic or k in traffic:
-            return traffic.get(f"void {k}", traffic.get(k))
-        inst = [v for name, v in traffic.items() if name.startswith(f"void {k}<")]
-        return inst[0] if len(inst) == 1 else None
-
-    for d in out.values():
-        got = [measured(k) for k in d["kernels"]]
-        d["traffic"] = sum(got) if got and all(g is not None for g in got) else None
+                       "unit": "GB/s", "frac": a / PEAK_HBM_GBS,
+                       "traffic": measured("void k_prox<0>")}
     return out
 
 
