@@ -149,6 +149,12 @@ typedef struct {
                            term is a square); otherwise the product is completed and tested
                            as usual.  0 = always the whole product.  Same iterates either
                            way, up to FP64 rounding of the sums at a tie. */
+    int32_t support_skip; /* accord_refit, BF16X1 / BF16X3 / FP8 forms: 1 (the default of
+                           accord_default_params) = the trial products walk only the K steps
+                           of each 128-column block that hold support entries, and the
+                           gradient skips its 256 x 256 tiles without any (everything off
+                           the support stays exactly zero, so the results are the same bits);
+                           0 = every block.  Ignored by accord_fit. */
 } accord_params;
 
 /* Results of accord_fit (host memory, filled on return). */
@@ -180,7 +186,7 @@ typedef struct {
 } accord_stats;
 
 /* Fills `prm` with defaults: lambda 0.1, tau0 1, beta 0.5, lipschitz 0 (estimate),
- * tol 0, max_iter 100, FP32, power_iters 256, timing 0, warm_tau 0, probe 1,
+ * tol 0, max_iter 100, FP32, power_iters 256, timing 0, warm_tau 0, probe 1, support_skip 1,
  * graph 0, refresh_every 0. */
 void accord_default_params(accord_params* prm);
 

@@ -38,7 +38,8 @@ class accord_params(ctypes.Structure):
                 ("precision", ctypes.c_int32),
                 ("power_iters", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("warm_tau", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("refresh_every", ctypes.c_int32), ("probe", ctypes.c_int32)]
+                ("refresh_every", ctypes.c_int32), ("probe", ctypes.c_int32),
+                ("support_skip", ctypes.c_int32)]
 
 
 class accord_stats(ctypes.Structure):
@@ -418,15 +419,17 @@ def accord_refit(X: torch.Tensor, omega_hat: torch.Tensor, lam: float, phi: floa
                  *, omega0: torch.Tensor | None = None, tau0: float = 1.0, beta: float = 0.5,
                  lipschitz: float = 0.0, tol: float = 0.0, power_iters: int = 0,
                  precision: str = "fp32", trace: bool = False, timing: int = 0, ws=None,
-                 omega_out=None):
+                 omega_out=None, support_skip: bool = True, probe: bool = True):
     """Refit on the support of omega_hat with penalty phi * lam there (eq. 3.8), in any
     precision form.  Returns (Omega [p, p] paper form, stats dict, trace or None); the
-    start defaults to omega_hat."""
+    start defaults to omega_hat.  support_skip=False makes the fused forms walk every
+    block (same results)."""
     n, p = X.shape
     dev = X.device
     prm = default_params(lam=lam, max_iter=max_iter, tau0=tau0, beta=beta, lipschitz=lipschitz,
                          tol=tol, power_iters=power_iters, timing=int(timing),
-                         precision=precision)
+                         precision=precision, support_skip=1 if support_skip else 0,
+                         probe=1 if probe else 0)
     if omega_out is None:
         omega_out = torch.empty((p, p), dtype=torch.float32, device=dev)
     omega_out.copy_(omega_hat if omega0 is None else omega0)

@@ -90,6 +90,11 @@ struct Plan {
         off_wt1, off_wsplit[4], off_w8, off_w8s, off_split,
         off_om0, end_grad, off_g, off_d, off_om1, end_fit;
     size_t off_mask, end_refit;  // refit: support bytes in the padded layout of Omega
+    // refit, fused forms: which blocks hold support entries (32-row K steps of each
+    // 128-column block), the K-step lists of the trial kernels (CSR) and the occupied
+    // 256 x 256 tiles of the gradient
+    size_t off_occ, off_kptr, off_kidx, off_gocc;
+    int ks32, tilesMg, tilesNg;
     size_t end_prox;
 };
 
@@ -188,6 +193,13 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     P.off_om1 = bump(cur, onc * sizeof(float));
     P.end_fit = cur;
     P.off_mask = bump(cur, on);
+    P.ks32 = (int)(P.p_pad / 32);
+    P.tilesMg = (int)cdiv(P.p_pad, kWBM);
+    P.tilesNg = (int)cdiv(p, kWBN);
+    P.off_occ = bump(cur, (size_t)P.tp.tilesN * P.ks32);
+    P.off_kptr = bump(cur, (size_t)(P.tp.tilesN + 1) * sizeof(int32_t));
+    P.off_kidx = bump(cur, (size_t)P.tp.tilesN * P.ks32 * sizeof(int32_t));
+    P.off_gocc = bump(cur, (size_t)P.tilesMg * P.tilesNg);
     P.end_refit = cur;
     return P;
 }
@@ -357,6 +369,8 @@ int check_params(const accord_params* prm) {
     if (prm->refresh_every < 0) return fail(ACCORD_ERR_INVALID_ARG, "refresh_every must be >= 0");
     if (prm->probe != 0 && prm->probe != 1)
         return fail(ACCORD_ERR_INVALID_ARG, "probe must be 0 or 1");
+    if (prm->support_skip != 0 && prm->support_skip != 1)
+        return fail(ACCORD_ERR_INVALID_ARG, "support_skip must be 0 or 1");
     return ACCORD_OK;
 }
 
@@ -443,6 +457,7 @@ void accord_default_params(accord_params* prm) {
     prm->power_iters = kLzDefaultSteps;
     prm->timing = 0;
     prm->probe = 1;
+    prm->support_skip = 1;
 }
 
 size_t accord_workspace_bytes(int64_t n, int64_t p, const accord_params* prm) {
@@ -589,6 +604,49 @@ int accord_objective(const float* X, int64_t n, int64_t p, const float* Omega, d
     return ACCORD_OK;
 }
 
+// Refit in a fused form: find the blocks that can hold support entries (on the device),
+// then build on the host the K-step list of every 128-column block at the trial kernel's
+// step length (units32 32-row units per step) and the occupied 256 x 256 tiles of the
+// gradient, and upload them.  Synchronous (set-up of a synchronous call).
+static int plan_support_skip(const Plan& P, void* ws, const uint8_t* mask, int units32,
+                             hipStream_t st) {
+    const int tn = P.tp.tilesN, ks32 = P.ks32;
+    uint8_t* occ = at<uint8_t>(ws, P.off_occ);
+    launch_support_occupancy(mask, P.p, P.p_pad, tn, ks32, occ, st);
+    std::vector<uint8_t> h((size_t)tn * ks32);
+    HIP_TRY(hipMemcpyAsync(h.data(), occ, h.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int ks = ks32 / units32;
+    std::vector<int32_t> ptr((size_t)tn + 1, 0), idx;
+    idx.reserve((size_t)tn * 8);
+    for (int c = 0; c < tn; ++c) {
+        for (int s = 0; s < ks; ++s) {
+            bool any = false;
+            for (int u = 0; u < units32; ++u) any = any || h[(size_t)c * ks32 + s * units32 + u];
+            if (any) idx.push_back(s);
+        }
+        ptr[c + 1] = (int32_t)idx.size();
+    }
+    std::vector<uint8_t> gocc((size_t)P.tilesMg * P.tilesNg, 0);
+    for (int tm = 0; tm < P.tilesMg; ++tm)
+        for (int tg = 0; tg < P.tilesNg; ++tg) {
+            bool any = false;
+            for (int c = 2 * tg; c < 2 * tg + 2 && c < tn; ++c)
+                for (int s = 8 * tm; s < 8 * tm + 8 && s < ks32; ++s)
+                    any = any || h[(size_t)c * ks32 + s];
+            gocc[tm + (size_t)tg * P.tilesMg] = any ? 1 : 0;
+        }
+    HIP_TRY(hipMemcpyAsync(at<int32_t>(ws, P.off_kptr), ptr.data(), ptr.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st));
+    if (!idx.empty())
+        HIP_TRY(hipMemcpyAsync(at<int32_t>(ws, P.off_kidx), idx.data(),
+                               idx.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(at<uint8_t>(ws, P.off_gocc), gocc.data(), gocc.size(),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return ACCORD_OK;
+}
+
 // Alg. 1; with support_src set, the refit of eq. 3.8: penalty phi * lambda on the
 // support of support_src (its nonzero entries and the diagonal), infinite off it.
 static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const accord_params* prm,
@@ -642,6 +700,19 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
     launch_copy_cols(Omega, p, om[0], P.p_pad, p, P.p_pad, ls, st);
     uint8_t* mask = support_src ? at<uint8_t>(ws, P.off_mask) : nullptr;
     if (mask) launch_support_mask(support_src, p, P.p_pad, mask, om[0], st);
+    // refit in a fused form: walk only the blocks that can hold support entries
+    const int32_t* kptr = nullptr;
+    const int32_t* kidx = nullptr;
+    const uint8_t* gocc = nullptr;
+    if (mask && P.fused && prm->support_skip) {
+        TRY(plan_support_skip(P, ws, mask, f8 ? 2 : 1, st));
+        kptr = at<int32_t>(ws, P.off_kptr);
+        kidx = at<int32_t>(ws, P.off_kidx);
+        gocc = at<uint8_t>(ws, P.off_gocc);
+        // skipped blocks are never written: the second iterate buffer and G start at zero
+        HIP_TRY(hipMemsetAsync(om[1], 0, (size_t)(P.p_cols * P.p_pad) * sizeof(float), st));
+        HIP_TRY(hipMemsetAsync(G, 0, (size_t)(P.p_cols * P.p_pad) * sizeof(float), st));
+    }
     if (P.p_cols > p) {  // zero padding columns (the fused kernels keep them zero)
         const size_t pad = (size_t)((P.p_cols - p) * P.p_pad) * sizeof(float);
         for (float* b : {om[0], om[1], G}) HIP_TRY(hipMemsetAsync(b + p * P.p_pad, 0, pad, st));
@@ -699,6 +770,7 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
         const bool tim = timing && t % tstride == 0;
         GemmArgs ga = grad_args(P, ws, prec, wt[cur], cur, G, P.p_pad, (int)P.p_pad, ls);
         ga.cmask = mask;  // refit: G = 0 off the support, so the prox keeps those entries 0
+        ga.tile_occ = gocc;
         Launch lg = {nullptr, nullptr, t, 0};
         if (tim) { lg.a = pool.get(); lg.b = pool.get(); HIP_TRY(hipEventRecord(lg.a, st)); }
         if (f8)  // MX copy of the current W (blocks along the samples) for the gradient
@@ -719,6 +791,8 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
             a.part = prox_part;
             GemmArgs ta = trial_args(P, ws, prec, D, nullptr, nullptr, wt[cur], wt[nxt],
                                      bf ? nxt : -1, ls, 2);
+            ta.kstep_ptr = kptr;
+            ta.kstep_idx = kidx;
             if (D) {  // FP32 form with many row tiles: prox pass, then the plain product
                 Launch lp = {nullptr, nullptr, t, k};
                 if (tim) { lp.a = pool.get(); lp.b = pool.get(); HIP_TRY(hipEventRecord(lp.a, st)); }

@@ -133,6 +133,14 @@ struct GemmArgs {
     // (m_count 0: all tilesM); the tile with tile_m == store_m writes Omega+ and the one
     // with tile_m == sums_m writes the prox sums (-1: none).  trial_args sets 0, 0, 0, 0.
     int m_first, m_count, store_m, sums_m;
+    // fused trial kernels, optional: the K steps (of the kernel's step length) each column
+    // block walks, as CSR lists (kstep_ptr[tilesN + 1] positions into kstep_idx); steps
+    // left out must hold Delta = 0 (a refit's blocks off the support).  Null: every step.
+    const int32_t* kstep_ptr;
+    const int32_t* kstep_idx;
+    // gradient kernels of the bf16 and FP8 forms, optional: one byte per tile (tile_m +
+    // tile_n * tilesM), 0 = the tile of C is zero and is neither computed nor stored
+    const uint8_t* tile_occ;
 };
 
 struct ProxArgs {
@@ -227,6 +235,8 @@ void launch_lipschitz(const float* Xp, int64_t p_pad, const float* Xt, int64_t n
 // steps around the solver: support mask of a refit, reparametrisation
 void launch_support_mask(const float* om_hat, int64_t p, int64_t p_pad, uint8_t* mask,
                          float* om0, hipStream_t st);
+void launch_support_occupancy(const uint8_t* mask, int64_t p, int64_t p_pad, int tilesN,
+                              int ksteps, uint8_t* occ, hipStream_t st);
 void launch_reparam(const float* om, int64_t p, float* theta, float* rho, hipStream_t st);
 
 // differentiation form

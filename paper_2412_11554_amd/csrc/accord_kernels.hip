@@ -278,6 +278,17 @@ __device__ inline void decode_tile(const GemmArgs& g, int& tile_m, int& tile_n, 
     }
 }
 
+// First position p in [lo, hi) of the ascending list a with a[p] >= v (hi if none).
+// Uniform across the workgroup.
+__device__ inline int first_at_least(const int32_t* a, int lo, int hi, int v) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // First trial step of an iteration: tau0 (Alg. 1), or with the warm-start variant
 // min(tau0, tau_{t-1} / beta) once an iteration has been accepted.
 __device__ inline double start_tau(const LsState& s) {
@@ -643,6 +654,7 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16w(GemmArgs g) {
 
     int tile_m, tile_n, split;
     decode_tile(g, tile_m, tile_n, split);
+    if (g.tile_occ && !g.tile_occ[tile_m + tile_n * g.tilesM]) return;  // a zero tile of C
     const int m0 = tile_m * kWBM, n0 = tile_n * kWBN;
     const int ksteps = g.K / BK;
     const int s_begin = (int)((int64_t)ksteps * split / g.splits);
@@ -1406,9 +1418,24 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
     const bool owner = tile_m == g.store_m;         // stores Omega+
     const bool sums_owner = tile_m == g.sums_m;     // writes the prox sums
     const int m0 = tile_m * kFBM, n0 = tile_n * kFBN;
-    const int ksteps = g.K / BK;
-    const int s_begin = (int)((int64_t)ksteps * split / g.splits);
-    const int s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
+    // The split's share of the column block's K steps, as positions in a step sequence:
+    // every step (kstep_idx null), or the column block's list of steps that can hold a
+    // nonzero Delta (a refit's support)
+    // (the split keeps its K range either way, so the FP32 partial sums group the same
+    // products as when every step is walked)
+    const int32_t* kidx = g.kstep_idx;
+    int s_begin, s_end;
+    {
+        const int ksteps = g.K / BK;
+        s_begin = (int)((int64_t)ksteps * split / g.splits);
+        s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
+        if (kidx) {
+            const int c0 = g.kstep_ptr[tile_n], c1 = g.kstep_ptr[tile_n + 1];
+            s_begin = first_at_least(kidx, c0, c1, s_begin);
+            s_end = first_at_least(kidx, c0, c1, s_end);
+        }
+    }
+#define KS(pos) (kidx ? kidx[(pos)] : (pos))
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // A loader: 256 rows x 64 bytes per half, 2 row passes of 128 rows
@@ -1513,37 +1540,37 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
         // Loads past the range re-read the last step (unconditional prefetch, see
         // k_gemm_bf16w).  The producer always runs (no branch between it and the
         // MFMAs); past the range it fills the idle stage and neither counts nor stores.
-        FUSED_LOAD_A(va0, s_begin);
-        FUSED_LOAD_OG(vo0, vg0, s_begin);
-        FUSED_LOAD_A(va1, s_begin + 1 < last ? s_begin + 1 : last);
-        FUSED_LOAD_OG(vo1, vg1, s_begin + 1 < last ? s_begin + 1 : last);
+        FUSED_LOAD_A(va0, KS(s_begin));
+        FUSED_LOAD_OG(vo0, vg0, KS(s_begin));
+        FUSED_LOAD_A(va1, KS(s_begin + 1 < last ? s_begin + 1 : last));
+        FUSED_LOAD_OG(vo1, vg1, KS(s_begin + 1 < last ? s_begin + 1 : last));
         FUSED_PRODUCE(0, s_begin, vo0, vg0, va0, true);
-        FUSED_DIAG(0, s_begin, vo0, vg0, true);
-        FUSED_STORE(s_begin, true);
+        FUSED_DIAG(0, KS(s_begin), vo0, vg0, true);
+        FUSED_STORE(KS(s_begin), true);
         __syncthreads();
         int cur = 0;
         for (int s = s_begin; s < s_end; s += 2) {
             // step s is in LDS[cur]; set 1 holds step s + 1
             const int s1 = s + 1 < last ? s + 1 : last;
             const bool live1 = s + 1 < s_end;
-            FUSED_LOAD_A(va0, s + 2 < last ? s + 2 : last);
-            FUSED_LOAD_OG(vo0, vg0, s + 2 < last ? s + 2 : last);
+            FUSED_LOAD_A(va0, KS(s + 2 < last ? s + 2 : last));
+            FUSED_LOAD_OG(vo0, vg0, KS(s + 2 < last ? s + 2 : last));
             FUSED_MMA(cur);
             FUSED_PRODUCE(cur ^ 1, s1, vo1, vg1, va1, live1);
-            FUSED_DIAG(cur ^ 1, s1, vo1, vg1, live1);
-            FUSED_STORE(s1, live1);
+            FUSED_DIAG(cur ^ 1, KS(s1), vo1, vg1, live1);
+            FUSED_STORE(KS(s1), live1);
             __syncthreads();
             cur ^= 1;
             if (!live1) break;
             // step s + 1 is in LDS[cur]; set 0 holds step s + 2
             const int s2 = s + 2 < last ? s + 2 : last;
             const bool live2 = s + 2 < s_end;
-            FUSED_LOAD_A(va1, s + 3 < last ? s + 3 : last);
-            FUSED_LOAD_OG(vo1, vg1, s + 3 < last ? s + 3 : last);
+            FUSED_LOAD_A(va1, KS(s + 3 < last ? s + 3 : last));
+            FUSED_LOAD_OG(vo1, vg1, KS(s + 3 < last ? s + 3 : last));
             FUSED_MMA(cur);
             FUSED_PRODUCE(cur ^ 1, s2, vo0, vg0, va0, live2);
-            FUSED_DIAG(cur ^ 1, s2, vo0, vg0, live2);
-            FUSED_STORE(s2, live2);
+            FUSED_DIAG(cur ^ 1, KS(s2), vo0, vg0, live2);
+            FUSED_STORE(KS(s2), live2);
             __syncthreads();
             cur ^= 1;
         }
@@ -1551,6 +1578,7 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
 #undef FUSED_LOAD_A
 #undef FUSED_LOAD_OG
 #undef FUSED_MMA
+#undef KS
     __syncthreads();
 
     const int tile = tile_m + tile_n * g.tilesM;
@@ -1851,6 +1879,7 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_fp8w(GemmArgs g) {
 
     int tile_m, tile_n, split;
     decode_tile(g, tile_m, tile_n, split);
+    if (g.tile_occ && !g.tile_occ[tile_m + tile_n * g.tilesM]) return;  // a zero tile of C
     const int m0 = tile_m * kWBM, n0 = tile_n * kWBN;
     const int ksteps = g.K / 64;
     const int s_begin = (int)((int64_t)ksteps * split / g.splits);
@@ -2052,9 +2081,19 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused8(GemmArgs g, ProxA
     const bool sums_owner = tile_m == g.sums_m;     // writes the prox sums
     const bool owner = store_owner || sums_owner;   // computes them
     const int m0 = tile_m * kFBM, n0 = tile_n * kFBN;
-    const int ksteps = g.K / 64;
-    const int s_begin = (int)((int64_t)ksteps * split / g.splits);
-    const int s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
+    // positions over the column block's K steps of 64 (all, or its list: see k_trial_fused)
+    const int32_t* kidx = g.kstep_idx;
+    int s_begin, s_end;
+    {
+        const int ksteps = g.K / 64;
+        s_begin = (int)((int64_t)ksteps * split / g.splits);
+        s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
+        if (kidx) {
+            const int c0 = g.kstep_ptr[tile_n], c1 = g.kstep_ptr[tile_n + 1];
+            s_begin = first_at_least(kidx, c0, c1, s_begin);
+            s_end = first_at_least(kidx, c0, c1, s_end);
+        }
+    }
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // A loader: row tid / 2 of the tile, 32 bytes; scale bytes by threads 0..255
@@ -2099,10 +2138,11 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused8(GemmArgs g, ProxA
 
     if (s_begin < s_end) {
         {
-            const int64_t ko = (int64_t)s_begin * 64;
+            const int64_t sk = kidx ? kidx[s_begin] : s_begin;
+            const int64_t ko = sk * 64;
             va[0] = *(const u4*)(pa + ko);
             va[1] = *(const u4*)(pa + ko + 16);
-            vsa = *(const uint16_t*)(psa + 2 * (int64_t)s_begin);
+            vsa = *(const uint16_t*)(psa + 2 * sk);
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -2111,17 +2151,17 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused8(GemmArgs g, ProxA
                     vg[q][h] = *(const f4*)(pg[q] + ko + 4 * h);
                 }
         }
-        FUSED_PRODUCE8(0, s_begin);
+        FUSED_PRODUCE8(0, kidx ? kidx[s_begin] : s_begin);
         __syncthreads();
         int cur = 0;
         for (int s = s_begin; s < s_end; ++s) {
             const bool more = s + 1 < s_end;
+            const int64_t sn = kidx ? kidx[more ? s + 1 : s] : (more ? s + 1 : s);
             {   // unconditional prefetch (see k_gemm_bf16w)
-                const int sn = more ? s + 1 : s;
-                const int64_t ko = (int64_t)sn * 64;
+                const int64_t ko = sn * 64;
                 va[0] = *(const u4*)(pa + ko);
                 va[1] = *(const u4*)(pa + ko + 16);
-                vsa = *(const uint16_t*)(psa + 2 * (int64_t)sn);
+                vsa = *(const uint16_t*)(psa + 2 * sn);
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -2152,7 +2192,7 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused8(GemmArgs g, ProxA
                     acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
                         af[i], bf[j], acc[i][j], 0, 0, 0, sa[i], 0, sbv[j]);
             __builtin_amdgcn_sched_barrier(0);
-            if (more) FUSED_PRODUCE8(cur ^ 1, s + 1);
+            if (more) FUSED_PRODUCE8(cur ^ 1, sn);
             __syncthreads();
             cur ^= 1;
         }
@@ -2942,6 +2982,38 @@ void launch_support_mask(const float* om_hat, int64_t p, int64_t p_pad, uint8_t*
     int64_t b = cdiv(p * p_pad / 4, kThreads);
     if (b > 16384) b = 16384;
     k_support_mask<<<(unsigned)b, kThreads, 0, st>>>(om_hat, p, p_pad, mask, om0);
+}
+
+// Blocks of a refit that can hold a nonzero entry: occ[tn * ksteps + s] = 1 if the support
+// mask has a nonzero byte in rows 32 s .. 32 s + 31 of the columns 128 tn .. 128 tn + 127
+// (those below p).  Everywhere else the iterate, its gradient and every trial step are
+// zero in every iteration (the start is projected onto the support, and the gradient is
+// stored as zero off it).  One thread per (tn, s), 32 bytes per column.
+__global__ void __launch_bounds__(kThreads) k_support_occupancy(const uint8_t* __restrict__ mask,
+                                                                int64_t p, int64_t p_pad,
+                                                                int tilesN, int ksteps,
+                                                                uint8_t* __restrict__ occ) {
+    const int64_t total = (int64_t)tilesN * ksteps;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kThreads) {
+        const int64_t tn = e / ksteps, s = e - tn * ksteps;
+        const int64_t c0 = tn * kFBN;
+        const int64_t c1 = c0 + kFBN < p ? c0 + kFBN : p;
+        unsigned int any = 0;
+        for (int64_t c = c0; c < c1; ++c) {
+            const u4* q = (const u4*)(mask + c * p_pad + 32 * s);
+            const u4 a = q[0], b = q[1];
+            any |= a[0] | a[1] | a[2] | a[3] | b[0] | b[1] | b[2] | b[3];
+        }
+        occ[e] = any ? 1 : 0;
+    }
+}
+
+void launch_support_occupancy(const uint8_t* mask, int64_t p, int64_t p_pad, int tilesN,
+                              int ksteps, uint8_t* occ, hipStream_t st) {
+    int64_t b = cdiv((int64_t)tilesN * ksteps, kThreads);
+    if (b > 16384) b = 16384;
+    k_support_occupancy<<<(unsigned)b, kThreads, 0, st>>>(mask, p, p_pad, tilesN, ksteps, occ);
 }
 
 // ---------------------------------------------------------------------------

@@ -132,6 +132,38 @@ def test_refit_full_size_sampled(gpu_lib, prec):
     assert rel <= 1e-4
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x1", "fp8"])
+def test_refit_support_skip_is_exact(gpu_lib, prec):
+    """The fused forms' refit walks only the blocks that hold support entries (K steps of
+    the trial products, 256 x 256 tiles of the gradient); everything it skips is exactly
+    zero, so the results equal those of a refit that walks every block, bit for bit: on
+    the benchmark's refit (n = 500, p = 5000, the true graph's support) and on a ragged
+    shape with a sparse random support (p = 300: a partial column block and K step)."""
+    import torch
+    d = datagen.refit_workload()
+    cases = [(d["x"], d["omega_hat"], d["lam"], d["phi"], 25)]
+    w = datagen.small_random_problem(200, 300, seed=77)
+    rng = np.random.default_rng(77)
+    hat = np.where(rng.random((300, 300)) < 0.02, rng.uniform(0.01, 0.05, (300, 300)), 0.0)
+    np.fill_diagonal(hat, 1.0)
+    cases.append((w.X, hat.astype(np.float32), 0.1, 0.5, 25))
+    for x32, om_hat, lam, phi, iters in cases:
+        print(f"[skip] {prec} n={x32.shape[0]} p={x32.shape[1]} {iters} iterations, skip on/off",
+              flush=True)
+        runs = []
+        for skip in (True, False):
+            om, st, tr = gpu_lib.accord_refit(_dev(x32), _dev(om_hat.T), lam, phi, iters,
+                                              precision=prec, trace=True, support_skip=skip)
+            torch.cuda.synchronize()
+            runs.append((om.clone(), tr.clone(), st))
+        (a, ta, sa), (b, tb, sb) = runs
+        assert sa["trials"] == sb["trials"] and torch.equal(ta, tb)
+        assert torch.equal(a, b)
+        # off the support the result is exactly zero
+        off = (om_hat.T == 0) & ~np.eye(om_hat.shape[0], dtype=bool)
+        assert not a.cpu().numpy()[off].any()
+
+
 def test_refit_errors(gpu_lib):
     from paper_2412_11554_amd import accord
     w = datagen.small_random_problem(30, 40, seed=1)
