@@ -450,23 +450,27 @@ def run_batch(args):
                      device="cuda:0")
     om = torch.empty((nprob, p, p), dtype=torch.float32, device="cuda:0")
     torch.cuda.synchronize()
+    # the tile orders of the batched kernels, chosen by the library's autotuner (untimed)
+    code, table = accord.accord_tune_batch(X, w.n, w.lams, max_iter=iters, ws=ws)
+    log(f"[batch] autotuned order code {code}: gradient {code & 0xff}, trial {code >> 8}")
     # a non-default stream, so that the sweeps can be captured into HIP graphs
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
-            accord.accord_fit_batch(X, w.n, w.lams, iters, ws=ws, omega_out=om, graph=True)
+            accord.accord_fit_batch(X, w.n, w.lams, iters, ws=ws, omega_out=om, graph=True,
+                                    batch_order=code)
         torch.cuda.synchronize()
         log("[batch] warmup done")
         t0 = time.perf_counter()
         for i in range(args.steps):
             _, stats, tr = accord.accord_fit_batch(X, w.n, w.lams, iters, ws=ws, omega_out=om,
-                                                   trials=True, graph=True)
+                                                   trials=True, graph=True, batch_order=code)
             log(f"[batch] step {i + 1}/{args.steps}")
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         # the same fit with every launch enqueued by the host (no graphs), for comparison
         t1 = time.perf_counter()
-        accord.accord_fit_batch(X, w.n, w.lams, iters, ws=ws, omega_out=om)
+        accord.accord_fit_batch(X, w.n, w.lams, iters, ws=ws, omega_out=om, batch_order=code)
         torch.cuda.synchronize()
         eager_s = time.perf_counter() - t1
         log(f"[batch] eager step {eager_s:.2f} s")
@@ -488,6 +492,10 @@ def run_batch(args):
                    "p": p, "nsub": nsub, "nlam": nlam, "iters": iters},
         "trials_per_iter": float(trials[:, :iters].mean()),
         "launch": "two captured HIP graphs (one sweep of each parity) replayed per sweep",
+        "autotune": {"order_code": code, "grad_order": code & 0xff, "trial_order": code >> 8,
+                     "ms_per_launch": table,
+                     "orders": "code 1 + c: bands of 2^(c % 5) M tiles, plain block order "
+                               "(c < 5) or XCD-contiguous (c >= 5); default = code 4"},
         "eager_ms_per_step": eager_s * 1e3,
         "roofline": {"bound": "mfma", "kernel": "whole fit (batched FP32 gradient and fused prox + trial GEMMs, tests)",
                      "achieved": tflops, "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",

@@ -155,6 +155,10 @@ typedef struct {
                            gradient skips its 256 x 256 tiles without any (everything off
                            the support stays exactly zero, so the results are the same bits);
                            0 = every block.  Ignored by accord_fit. */
+    int32_t batch_order; /* accord_fit_batch: tile order of the batched gradient (bits 0-7)
+                           and trial kernel (bits 8-15), each 0 (default) or a code 1..10
+                           from accord_tune_batch.  The order decides only which workgroup
+                           computes which tile, so every code gives the same bits. */
 } accord_params;
 
 /* Results of accord_fit (host memory, filled on return). */
@@ -289,6 +293,19 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
                      const accord_params* prm, const double* lipschitz,
                      accord_batch_stats* stats, int32_t* trials, void* ws, size_t ws_bytes,
                      void* stream);
+
+/* Autotuner of the batched form's launches (for callers that repeat fits of one shape,
+ * e.g. a lambda path over bootstrap subsamples).  Runs the set-up of accord_fit_batch
+ * (same arguments, max_iter ignored), then times the batched gradient and trial kernels
+ * in each of 10 tile orders (bands of 1, 2, 4, 8 or 16 M tiles; plain block order or an
+ * XCD-contiguous one) and writes the fastest as a params.batch_order code to *order
+ * (host).  table (host float[20], or NULL) receives the mean ms per launch of each order,
+ * gradient first.  The tile order never changes a result.  Omega is left as given;
+ * workspace as accord_fit_batch; synchronous. */
+int accord_tune_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
+                      const double* lambda, int64_t nlam, float* Omega,
+                      const accord_params* prm, const double* lipschitz, void* ws,
+                      size_t ws_bytes, void* stream, int32_t* order, float* table);
 
 /* ---- Differentiation form: gradients of a held-out loss through K unrolled
  * iterations with the step sizes held fixed (recorded from a backtracking fit and

@@ -39,7 +39,7 @@ class accord_params(ctypes.Structure):
                 ("power_iters", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("warm_tau", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("refresh_every", ctypes.c_int32), ("probe", ctypes.c_int32),
-                ("support_skip", ctypes.c_int32)]
+                ("support_skip", ctypes.c_int32), ("batch_order", ctypes.c_int32)]
 
 
 class accord_stats(ctypes.Structure):
@@ -113,6 +113,11 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(accord_params), _pd,
                                        ctypes.POINTER(accord_batch_stats), _vp, _vp, _sz, _vp]
         L.accord_fit_batch.restype = ctypes.c_int
+        L.accord_tune_batch.argtypes = [_vp, _pi64, _i64, _i64, _pd, _i64, _vp,
+                                        ctypes.POINTER(accord_params), _pd, _vp, _sz, _vp,
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_float)]
+        L.accord_tune_batch.restype = ctypes.c_int
         L.accord_adjoint_workspace_bytes.argtypes = [_i64, _i64]
         L.accord_adjoint_workspace_bytes.restype = _sz
         L.accord_fbs_replay.argtypes = [_vp, _i64, _i64, _vp, _pd, _i64, _d, _vp, _vp, _sz, _vp]
@@ -291,11 +296,13 @@ def accord_batch_workspace_bytes(n, p: int, nlam: int, params: accord_params | N
 def accord_fit_batch(X: torch.Tensor, n, lambdas, max_iter: int, *,
                      omega0: torch.Tensor | None = None, tau0: float = 1.0, beta: float = 0.5,
                      tol: float = 0.0, power_iters: int = 0, lipschitz=None, trials: bool = False,
-                     warm_tau: bool = False, graph: bool = False, ws=None, omega_out=None):
+                     warm_tau: bool = False, graph: bool = False, batch_order: int = 0, ws=None,
+                     omega_out=None):
     """Batched ACCORD-FBS: X is the row-wise stack of the data sets (sum(n) x p),
     n their row counts, lambdas the penalties.  Problem k = b * len(lambdas) + l.
     Returns (Omega [nprob, p, p] paper form, list of stats dicts, trials
-    [nprob, max_iter] int32 device tensor or None).  omega0 defaults to identities."""
+    [nprob, max_iter] int32 device tensor or None).  omega0 defaults to identities.
+    batch_order: a tile order code from accord_tune_batch (0 = default)."""
     n = [int(v) for v in n]
     nsub, p = len(n), X.shape[1]
     if X.shape[0] != sum(n):
@@ -306,7 +313,7 @@ def accord_fit_batch(X: torch.Tensor, n, lambdas, max_iter: int, *,
     dev = X.device
     prm = default_params(max_iter=max_iter, tau0=tau0, beta=beta, tol=tol,
                          power_iters=power_iters, warm_tau=1 if warm_tau else 0,
-                         graph=1 if graph else 0)
+                         graph=1 if graph else 0, batch_order=batch_order)
     if omega_out is None:
         omega_out = torch.empty((nprob, p, p), dtype=torch.float32, device=dev)
     if omega0 is None:
@@ -328,6 +335,36 @@ def accord_fit_batch(X: torch.Tensor, n, lambdas, max_iter: int, *,
                                   tr.data_ptr() if tr is not None else None,
                                   ws.data_ptr(), ws.numel(), _stream(dev)))
     return omega_out, [s.as_dict() for s in st], tr
+
+
+BATCH_ORDERS = 10  # tile orders per kernel that accord_tune_batch times
+
+
+def accord_tune_batch(X: torch.Tensor, n, lambdas, *, max_iter: int = 1, tau0: float = 1.0,
+                      beta: float = 0.5, power_iters: int = 0, lipschitz=None, ws=None):
+    """Times the batched kernels in every tile order on this problem set (after the fit's
+    set-up) and returns (batch_order code, {"grad": [ms per order], "trial": [...]})."""
+    n = [int(v) for v in n]
+    nsub, p = len(n), X.shape[1]
+    lam = [float(v) for v in lambdas]
+    nlam = len(lam)
+    dev = X.device
+    prm = default_params(max_iter=max_iter, tau0=tau0, beta=beta, power_iters=power_iters)
+    om = torch.zeros((nsub * nlam, p, p), dtype=torch.float32, device=dev)
+    om.diagonal(dim1=1, dim2=2).fill_(1.0)
+    need = accord_batch_workspace_bytes(n, p, nlam, prm)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    na = (ctypes.c_int64 * nsub)(*n)
+    la = (ctypes.c_double * nlam)(*lam)
+    lp = (ctypes.c_double * nsub)(*[float(v) for v in lipschitz]) if lipschitz is not None else None
+    order = ctypes.c_int32(0)
+    table = (ctypes.c_float * (2 * BATCH_ORDERS))()
+    _check(lib().accord_tune_batch(_dev(X, "X"), na, nsub, p, la, nlam, _dev(om, "Omega"),
+                                   ctypes.byref(prm), lp, ws.data_ptr(), ws.numel(), _stream(dev),
+                                   ctypes.byref(order), table))
+    t = list(table)
+    return int(order.value), {"grad": t[:BATCH_ORDERS], "trial": t[BATCH_ORDERS:]}
 
 
 def accord_adjoint_workspace_bytes(n: int, p: int) -> int:

@@ -371,6 +371,7 @@ int check_params(const accord_params* prm) {
         return fail(ACCORD_ERR_INVALID_ARG, "probe must be 0 or 1");
     if (prm->support_skip != 0 && prm->support_skip != 1)
         return fail(ACCORD_ERR_INVALID_ARG, "support_skip must be 0 or 1");
+    if (prm->batch_order < 0) return fail(ACCORD_ERR_INVALID_ARG, "batch_order must be >= 0");
     return ACCORD_OK;
 }
 
@@ -1125,11 +1126,16 @@ size_t accord_batch_workspace_bytes(const int64_t* n, int64_t nsub, int64_t p, i
     return B.end;
 }
 
-int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
-                     const double* lambda, int64_t nlam, float* Omega, const accord_params* prm,
-                     const double* lipschitz, accord_batch_stats* stats, int32_t* trials,
-                     void* ws, size_t ws_bytes, void* stream) {
-    g_last_error.clear();
+}  // extern "C"
+
+// The batched fit; with tune_order set, the set-up is followed by timing every tile order
+// of the gradient and of the trial kernel (tune_table: mean ms per launch), and the
+// fastest of each is written to tune_order (and used by the sweeps, if any).
+static int fit_batch_impl(const float* X, const int64_t* n, int64_t nsub, int64_t p,
+                          const double* lambda, int64_t nlam, float* Omega,
+                          const accord_params* prm, const double* lipschitz,
+                          accord_batch_stats* stats, int32_t* trials, void* ws, size_t ws_bytes,
+                          void* stream, int32_t* tune_order, float* tune_table) {
     TRY(check_batch_dims(n, nsub, p, nlam));
     TRY(check_ptr(X, "X"));
     TRY(check_ptr(Omega, "Omega"));
@@ -1146,6 +1152,11 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
                 return fail(ACCORD_ERR_INVALID_ARG, "lipschitz[%lld] must be finite and > 0",
                             (long long)b);
     if (trials && !aligned(trials, 4)) return fail(ACCORD_ERR_INVALID_ARG, "trials must be 4-byte aligned");
+    const int order_grad = prm->batch_order & 0xff, order_trial = (prm->batch_order >> 8) & 0xff;
+    if (prm->batch_order < 0 || (prm->batch_order >> 16) != 0 || order_grad > kBatchOrders ||
+        order_trial > kBatchOrders)
+        return fail(ACCORD_ERR_INVALID_ARG, "batch_order %d is not a tile order code",
+                    prm->batch_order);
     BatchPlan B;
     TRY(make_batch_plan(n, nsub, p, nlam, prm->max_iter, B));
     TRY(check_ws(ws, ws_bytes, B.end));
@@ -1198,10 +1209,12 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
             t.pred = par == 2 ? 0 : 2;
             t.Mvalid = (int)B.n[b];
             t.Nvalid = t.N;  // padding columns of Delta and Omega are zero
-            if (par == 2)
+            if (par == 2) {
                 a_w0[b] = t;
-            else
+            } else {
+                t.order = order_trial;
                 a_trial[par * nsub + b] = t;
+            }
         }
         for (int par = 0; par < 2; ++par) {
             // the prox of the fused trial: the group's Omega, G and Omega+ (its problems'
@@ -1236,6 +1249,7 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
             g.ls = ls + k0;
             g.pred = 1;
             g.begin_iter = 1;
+            g.order = order_grad;
             a_grad[par * nsub + b] = g;
         }
         for (int64_t l = 0; l < nlam; ++l) {
@@ -1323,6 +1337,54 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
         ntr = std::max(ntr, max_trials(prm->tau0, prm->beta, host[k].inv_L));
     }
 
+    if (tune_order) {
+        // Time every tile order of the gradient, then of the trial kernel (three launches
+        // each, the first to warm up).  Nothing here disturbs the fit: the gradient resets
+        // each problem's line search to the start of an iteration, as the first sweep's
+        // does; the trial launches (without an acceptance test) only write buffers the
+        // first sweep overwrites.
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        int best[2] = {0, 0};
+        int err = ACCORD_OK;
+        for (int kind = 0; kind < 2 && err == ACCORD_OK; ++kind) {
+            std::vector<GemmArgs>& args = kind == 0 ? a_grad : a_trial;
+            GemmArgs* dev = kind == 0 ? d_grad : d_trial;
+            float best_ms = 0.f;
+            for (int code = 1; code <= kBatchOrders && err == ACCORD_OK; ++code) {
+                for (GemmArgs& g : args) g.order = code;
+                HIP_TRY(hipMemcpyAsync(dev, args.data(), args.size() * sizeof(GemmArgs),
+                                       hipMemcpyHostToDevice, st));
+                for (int rep = 0; rep < 3; ++rep) {
+                    if (rep == 1) HIP_TRY(hipEventRecord(e0, st));
+                    if (kind == 0)
+                        launch_gemm_f32_batch(d_grad, (int)nsub, B.tiles_grad, B.tpp, EPI_GRAD, st);
+                    else
+                        launch_trial_fused32_batch(d_trial, d_px, (int)nsub, B.max_tiles_trial,
+                                                   B.tpp, B.part_rows, st);
+                }
+                HIP_TRY(hipEventRecord(e1, st));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                ms *= 0.5f;
+                if (tune_table) tune_table[kind * kBatchOrders + code - 1] = ms;
+                if (best[kind] == 0 || ms < best_ms) {
+                    best[kind] = code;
+                    best_ms = ms;
+                }
+            }
+            for (GemmArgs& g : args) g.order = best[kind];
+            HIP_TRY(hipMemcpyAsync(dev, args.data(), args.size() * sizeof(GemmArgs),
+                                   hipMemcpyHostToDevice, st));
+        }
+        HIP_TRY(hipStreamSynchronize(st));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *tune_order = best[0] | (best[1] << 8);
+    }
+
     // ---- Alg. 1 for every problem, one iteration per sweep.  Each sweep enqueues the
     // gradient and ntr trials (enough for the problem whose floor is lowest); a
     // problem that accepted, or stopped, skips the rest of the sweep.
@@ -1337,7 +1399,8 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
             launch_finalize_batch(d_fin, (int)np, st);
         }
     };
-    if (prm->graph && st != nullptr && prm->max_iter > 0) {
+    const int nsweeps = tune_order ? 0 : prm->max_iter;  // tuning: no sweeps
+    if (prm->graph && st != nullptr && nsweeps > 0) {
         struct Graphs {
             hipGraph_t g[2] = {nullptr, nullptr};
             hipGraphExec_t e[2] = {nullptr, nullptr};
@@ -1348,7 +1411,7 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
                 }
             }
         } G;
-        const int nsweep = prm->max_iter < 2 ? prm->max_iter : 2;
+        const int nsweep = nsweeps < 2 ? nsweeps : 2;
         for (int par = 0; par < nsweep; ++par) {
             HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             enqueue_sweep(par);
@@ -1358,10 +1421,10 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
             if (end != hipSuccess) return fail(ACCORD_ERR_HIP, "sweep capture: %s", hipGetErrorString(end));
             HIP_TRY(hipGraphInstantiate(&G.e[par], G.g[par], nullptr, nullptr, 0));
         }
-        for (int t = 0; t < prm->max_iter; ++t) HIP_TRY(hipGraphLaunch(G.e[t & 1], st));
+        for (int t = 0; t < nsweeps; ++t) HIP_TRY(hipGraphLaunch(G.e[t & 1], st));
         HIP_TRY(hipStreamSynchronize(st));  // before the graphs are destroyed
     } else {
-        for (int t = 0; t < prm->max_iter; ++t) {
+        for (int t = 0; t < nsweeps; ++t) {
             enqueue_sweep(t & 1);
             HIP_TRY(hipGetLastError());
         }
@@ -1371,7 +1434,7 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
     for (int64_t k = 0; k < np; ++k)
         launch_copy_cols(om[host[k].iter & 1] + k * mat, B.p_pad, Omega + k * p * p, p, p, p,
                          nullptr, st);
-    if (trials && prm->max_iter > 0)
+    if (trials && nsweeps > 0)
         HIP_TRY(hipMemcpyAsync(trials, trials_log, (size_t)np * prm->max_iter * sizeof(int32_t),
                                hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipGetLastError());
@@ -1401,6 +1464,34 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
             status = fail(ACCORD_ERR_DOMAIN, "non-positive diagonal in an iterate of problem %lld", (long long)k);
     }
     return status;
+}
+
+extern "C" {
+
+int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
+                     const double* lambda, int64_t nlam, float* Omega, const accord_params* prm,
+                     const double* lipschitz, accord_batch_stats* stats, int32_t* trials,
+                     void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return fit_batch_impl(X, n, nsub, p, lambda, nlam, Omega, prm, lipschitz, stats, trials, ws,
+                          ws_bytes, stream, nullptr, nullptr);
+}
+
+int accord_tune_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
+                      const double* lambda, int64_t nlam, float* Omega, const accord_params* prm,
+                      const double* lipschitz, void* ws, size_t ws_bytes, void* stream,
+                      int32_t* order, float* table) {
+    g_last_error.clear();
+    if (!order) return fail(ACCORD_ERR_INVALID_ARG, "order is null");
+    if (!prm) return fail(ACCORD_ERR_INVALID_ARG, "params is null");
+    accord_params q = *prm;
+    // the set-up of a fit (which must leave the problems running: max_iter >= 1), then the
+    // timing instead of the sweeps
+    q.max_iter = q.max_iter > 0 ? q.max_iter : 1;
+    q.tol = 0.0;
+    q.batch_order = 0;
+    return fit_batch_impl(X, n, nsub, p, lambda, nlam, Omega, &q, lipschitz, nullptr, nullptr,
+                          ws, ws_bytes, stream, order, table);
 }
 
 }  // extern "C"

@@ -141,6 +141,7 @@ struct GemmArgs {
     // gradient kernels of the bf16 and FP8 forms, optional: one byte per tile (tile_m +
     // tile_n * tilesM), 0 = the tile of C is zero and is neither computed nor stored
     const uint8_t* tile_occ;
+    int order;          // batched kernels: tile order code (batch_tile), 0 = default
 };
 
 struct ProxArgs {
@@ -214,6 +215,7 @@ void launch_combine_objective(const double* prox_part, int nprox, const double* 
 void launch_transpose_w(const float* Wt, int64_t ldt, int64_t n, int64_t p, float* W,
                         hipStream_t st);
 // Lanczos estimate of L (buffers carved by lz_buf from lz_buf_bytes bytes)
+constexpr int kBatchOrders = 10;   // tile orders accord_tune_batch tries per kernel
 constexpr int kLzMaxSteps = 256;   // cap on the Lanczos steps
 constexpr int kLzDefaultSteps = 256;
 constexpr int kLzCheck = 8;         // steps between checks of the Ritz residual bound

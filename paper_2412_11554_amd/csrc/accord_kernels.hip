@@ -2787,27 +2787,47 @@ void launch_lipschitz(const float* Xp, int64_t p_pad, const float* Xt, int64_t n
 // ---------------------------------------------------------------------------
 namespace accord {
 
+// Tile order of the batched kernels: which tile of group blockIdx.y workgroup blockIdx.x
+// computes.  Every order is a permutation of the tiles, and a tile's arithmetic and the
+// rows its partial sums go to do not depend on which workgroup computes it, so the order
+// changes the run time only, never a result.  code 0: the default (plain block order,
+// bands of 8 M tiles walking across N); code 1 + c, c < kBatchOrders: bands of
+// GM = 2^(c % 5) M tiles, in plain block order (c < 5) or with every XCD given a
+// contiguous range of the tiles (c >= 5; blocks are dispatched round-robin over the 8
+// XCDs).  Returns false for the workgroups beyond the group's tiles.
+__device__ inline bool batch_tile(int code, int tilesM, int tilesN, int& tile_m, int& tile_n) {
+    const int tiles = tilesM * tilesN;
+    const int c = code > 0 ? code - 1 : 3;
+    const int GM = 1 << (c % 5);
+    int logical = blockIdx.x;
+    if (c >= 5) {
+        const int nblk = gridDim.x, bid = blockIdx.x;
+        const int xcd = bid & 7, local = bid >> 3, q8 = nblk >> 3, r8 = nblk & 7;
+        logical = xcd * q8 + (xcd < r8 ? xcd : r8) + local;
+    }
+    if (logical >= tiles) return false;
+    const int per_group = GM * tilesN;
+    const int group = logical / per_group;
+    const int first_m = group * GM;
+    const int gsize = (tilesM - first_m) < GM ? (tilesM - first_m) : GM;
+    const int in_group = logical - group * per_group;
+    tile_m = first_m + in_group % gsize;
+    tile_n = in_group / gsize;
+    return true;
+}
+
 template <int EPI>
 __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32_batch(const GemmArgs* __restrict__ batch,
                                                                int tpp) {
     const GemmArgs g = batch[blockIdx.y];
-    const int tiles = g.tilesM * g.tilesN;
-    // Plain block order: consecutive tiles land on different XCDs (blocks are
-    // dispatched round-robin over the 8 XCDs), so the tiles of every problem spread
-    // over all of them.  Problems finish their line searches at different trials; an
-    // XCD-contiguous order would leave the XCDs of finished problems idle while the
-    // others carry the problems still searching.  The operand shared by a group's
-    // tiles (its X) is a few MB and stays in every XCD's L2.
-    const int logical = blockIdx.x;
-    if (logical >= tiles) return;
-    constexpr int GM = 8;
-    const int per_group = GM * g.tilesN;
-    const int group = logical / per_group;
-    const int first_m = group * GM;
-    const int gsize = (g.tilesM - first_m) < GM ? (g.tilesM - first_m) : GM;
-    const int in_group = logical - group * per_group;
-    const int tile_m = first_m + in_group % gsize;
-    const int tile_n = in_group / gsize;
+    // Default order (code 0): plain block order, so consecutive tiles land on different
+    // XCDs and the tiles of every problem spread over all of them.  Problems finish
+    // their line searches at different trials; an XCD-contiguous order can leave the
+    // XCDs of finished problems idle while the others carry the problems still
+    // searching.  The operand shared by a group's tiles (its X) is a few MB and stays
+    // in every XCD's L2.  Other orders: batch_tile (chosen by accord_tune_batch).
+    int tile_m, tile_n;
+    if (!batch_tile(g.order, g.tilesM, g.tilesN, tile_m, tile_n)) return;
     const int prob = tile_n / tpp;
     LsState* ls = g.ls + prob;
     if (g.pred >= 1 && ls->converged) return;
@@ -2833,17 +2853,8 @@ __global__ void __launch_bounds__(kThreads, 2) k_trial_fused32_batch(
     const GemmArgs* __restrict__ gb, const ProxArgs* __restrict__ pb, int tpp, int nprox_rows) {
     const GemmArgs g = gb[blockIdx.y];
     const ProxArgs px = pb[blockIdx.y];
-    const int tiles = g.tilesM * g.tilesN;
-    const int logical = blockIdx.x;
-    if (logical >= tiles) return;
-    constexpr int GM = 8;
-    const int per_group = GM * g.tilesN;
-    const int group = logical / per_group;
-    const int first_m = group * GM;
-    const int gsize = (g.tilesM - first_m) < GM ? (g.tilesM - first_m) : GM;
-    const int in_group = logical - group * per_group;
-    const int tile_m = first_m + in_group % gsize;
-    const int tile_n = in_group / gsize;
+    int tile_m, tile_n;
+    if (!batch_tile(g.order, g.tilesM, g.tilesN, tile_m, tile_n)) return;
     const int prob = tile_n / tpp;
     const LsState* ls = px.ls + prob;
     if (g.pred >= 1 && ls->converged) return;

@@ -171,6 +171,13 @@ def test_fit_batch_validation(L):
     assert call(ws_bytes=16) == 4
     assert call(pr=accord.default_params(max_iter=3, precision=2)) == 5
     assert call(pr=accord.default_params(beta=0.0)) == 1
+    assert call(pr=accord.default_params(max_iter=3, batch_order=11)) == 1      # code > 10
+    assert call(pr=accord.default_params(max_iter=3, batch_order=1 << 16)) == 1
+    order = ctypes.c_int32()
+    assert L.accord_tune_batch(None, n, 2, 7, lam, 2, FAKE, ctypes.byref(prm), None, FAKE,
+                               1 << 40, None, ctypes.byref(order), None) == 1
+    assert L.accord_tune_batch(FAKE, n, 2, 7, lam, 2, FAKE, ctypes.byref(prm), None, FAKE,
+                               1 << 40, None, None, None) == 1
     assert L.accord_last_error()
 
 
@@ -275,7 +282,8 @@ def test_reparam_validation(L):
 
 
 @pytest.mark.parametrize("field,value", [("warm_tau", 2), ("warm_tau", -1), ("graph", 3),
-                                         ("refresh_every", -1)])
+                                         ("refresh_every", -1), ("batch_order", -1),
+                                         ("support_skip", 2)])
 def test_variant_params_validation(L, field, value):
     prm = accord.default_params(lam=0.1, max_iter=3)
     setattr(prm, field, value)

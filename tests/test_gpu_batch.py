@@ -131,6 +131,49 @@ def test_batch_full_size_deterministic(gpu_lib):
     assert [d["f"] for d in sa] == [d["f"] for d in sb]
 
 
+def test_batch_tile_orders_are_bit_identical(gpu_lib):
+    """Every tile order of the batched kernels (params.batch_order, codes 1..10 for the
+    gradient and the trial kernel) gives the default order's bits: the order decides only
+    which workgroup computes which tile."""
+    import torch
+    w = datagen.batch_workload(p=300, nsub=3, nlam=4, n_base=120, lo=40, hi=120, prob=0.02,
+                               iters=20, key=35)
+    X = torch.from_numpy(w.stacked()).cuda()
+    ref, st_ref, tr_ref = gpu_lib.accord_fit_batch(X, w.n, w.lams, w.iters, trials=True)
+    ref, tr_ref = ref.clone(), tr_ref.clone()
+    for c in range(1, gpu_lib.BATCH_ORDERS + 1):
+        code = c | ((gpu_lib.BATCH_ORDERS + 1 - c) << 8)
+        om, st, tr = gpu_lib.accord_fit_batch(X, w.n, w.lams, w.iters, trials=True,
+                                              batch_order=code)
+        torch.cuda.synchronize()
+        assert torch.equal(om, ref) and torch.equal(tr, tr_ref), code
+        assert [d["f"] for d in st] == [d["f"] for d in st_ref]
+
+
+def test_batch_autotune_full_size(gpu_lib):
+    """The autotuner on the benchmark's 16 x 32 problems at p = 2000: a valid order code
+    from timings of all 20 candidates, and a fit in that order equal to the default."""
+    import torch
+    w = datagen.workload("batch")
+    X = torch.from_numpy(w.stacked()).cuda()
+    print(f"[tune] batch {len(w.xs)} x {len(w.lams)} problems, p={w.p}", flush=True)
+    code, table = gpu_lib.accord_tune_batch(X, w.n, w.lams)
+    g, t = code & 0xff, code >> 8
+    print(f"[tune] order code {code}: gradient {g} ({min(table['grad']):.2f} ms), trial {t} "
+          f"({min(table['trial']):.2f} ms); default {table['grad'][3]:.2f} / "
+          f"{table['trial'][3]:.2f} ms", flush=True)
+    assert 1 <= g <= gpu_lib.BATCH_ORDERS and 1 <= t <= gpu_lib.BATCH_ORDERS
+    # every candidate did the work: a gradient over 512 problems at p = 2000 is about
+    # 1e12 flops, a trial (all problems searching) as much
+    assert all(v > 1.0 for v in table["grad"] + table["trial"]), table
+    assert table["grad"][g - 1] == min(table["grad"]) and table["trial"][t - 1] == min(table["trial"])
+    a, sa, ta = gpu_lib.accord_fit_batch(X, w.n, w.lams, 8, trials=True)
+    a, ta = a.clone(), ta.clone()
+    b, sb, tb = gpu_lib.accord_fit_batch(X, w.n, w.lams, 8, trials=True, batch_order=code)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(ta, tb)
+
+
 def test_batch_errors(gpu_lib):
     import torch
     from paper_2412_11554_amd import accord
