@@ -133,23 +133,34 @@ def _traffic_table(workload):
 
 def _trial_plan(form, n, p):
     """The library's launch plan of one trial (from n and p, as the library derives it):
-    the kernel, the split-K count (2 .. 8 when the tiles do not fill the CUs) and whether
-    trials are probed on the first 256 samples (fused forms, >= 4 tiles of 256 samples,
-    no split-K).  Names as rocprofv3 reports them; EPI 1 = trial epilogue, 2 = split-K
-    partials (then a reduce kernel).  Used only to pick the profiled traffic rows."""
+    the kernel, the split-K count and whether trials are probed on the first 256 samples
+    (fused forms with >= 4 tiles of 256 samples; their split count minimises the rounds of
+    the probe and completion launches, otherwise 2 .. 8 when the tiles do not fill the
+    CUs).  Names as rocprofv3 reports them; EPI 1 = trial epilogue, 2 = split-K partials
+    (then a reduce kernel).  Used only to pick the profiled traffic rows."""
     n_pad, p_pad = -(-n // 64) * 64, -(-p // 64) * 64
     fused = form != "fp32"
     bm, bn, slots = (256, 128, 256) if fused else (128, 128, 512)
     tm, tn = -(-n_pad // bm), -(-p // bn)
     tiles, ks = tm * tn, p_pad // 64
-    best, cost = 1, float(-(-tiles // slots))
-    for sp in range(2, 9):
-        if ks // sp < 2:
-            break
-        c = -(-(tiles * sp) // slots) / sp
-        if c < cost * 0.9:
-            best, cost = sp, c
-    probe = fused and best == 1 and tm >= 4
+    probe = fused and tm >= 4
+    if probe:
+        best, cost = 1, 0.0
+        for sp in range(1, 5 if tn < slots else 2):
+            if sp > 1 and ks // sp < 2:
+                break
+            rounds = 2 * -(-(tn * sp) // slots) + -(-((tm - 1) * tn * sp) // slots)
+            c = rounds / sp * (1.0 + 0.03 * (sp - 1))
+            if sp == 1 or c < 0.99 * cost:
+                best, cost = sp, c
+    else:
+        best, cost = 1, float(-(-tiles // slots))
+        for sp in range(2, 9):
+            if ks // sp < 2:
+                break
+            c = -(-(tiles * sp) // slots) / sp
+            if c < cost * 0.9:
+                best, cost = sp, c
     if form == "fp32":
         kern = "k_gemm_f32" if tm > 4 else "k_trial_fused32"
         name = f"void {kern}<{1 if best == 1 else 2}>"
@@ -158,7 +169,9 @@ def _trial_plan(form, n, p):
         epi = 1 if best == 1 else 2
         name = f"void {kern}<{epi}>" if form == "fp8" else f"void {kern} {epi}>"
     return {"name": name, "splits": best, "probe": probe, "tilesM": tm, "tilesN": tn,
-            "grid": tiles * best, "probe_grid": tn, "rest_grid": (tm - 1) * tn}
+            "grid": tiles * best, "probe_grid": tn * best, "rest_grid": (tm - 1) * tn * best,
+            "reduce": f"void k_splitk_reduce_f<{best}>" if fused and best > 1 else None,
+            "probe_reduce_grid": tn * 2, "rest_reduce_grid": (tm - 1) * tn * 2}
 
 
 def kernel_report(stats, form, n, p, traffic_workload):
@@ -214,9 +227,15 @@ def kernel_report(stats, form, n, p, traffic_workload):
             n0 = min(256, n)
             alg = 8.0 * p * p + (1.0 - rej) * 4.0 * p * p
             fl = 2.0 * (n0 + (1.0 - rej) * (n - n0)) * p * p
-            names = [plan["name"] + " (probe)", "k_probe_decide", plan["name"] + " (rest)"]
+            red = plan["reduce"]
+            names = [plan["name"] + " (probe)"] + ([red[5:] + " (probe)"] if red else []) + \
+                ["k_probe_decide", plan["name"] + " (rest)"] + ([red[5:] + " (rest)"] if red else [])
             tp, tr = measured(plan["name"], plan["probe_grid"]), measured(plan["name"],
                                                                           plan["rest_grid"])
+            if red and tp is not None and tr is not None:
+                rp, rr = measured(red, plan["probe_reduce_grid"]), measured(red,
+                                                                           plan["rest_reduce_grid"])
+                tp, tr = (tp + rp, tr + rr) if (rp is not None and rr is not None) else (None, None)
             traf = tp + (1.0 - rej) * tr if (tp is not None and tr is not None) else None
         else:
             alg, fl = 12.0 * p * p, flops

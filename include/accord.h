@@ -141,7 +141,7 @@ typedef struct {
                            in FP32 (one extra product), which bounds the drift of the carried
                            W (in the BF16X1 / FP8 forms the carried W sums rounded steps). */
     int32_t probe;      /* accord_fit / accord_refit, BF16X1 / BF16X3 / FP8 forms with at least
-                           4 tiles of 256 samples (n > 768) and no split-K: 1 (the default of
+                           4 tiles of 256 samples (n > 768): 1 (the default of
                            accord_default_params) = run each trial first on the first 256
                            samples; ||X Delta||^2 over them is a lower bound of the whole
                            sum, so when it alone fails Alg. 1's test the trial is rejected

@@ -119,6 +119,36 @@ int choose_splits(int tiles, int ksteps64, int slots) {
     return best;
 }
 
+// Split count of the fused trial product when its trials are probed (>= 4 M tiles): a
+// trial is one launch over M tile 0 (tilesN workgroups per split), then, for about every
+// other trial, one over the other M tiles.  When the probe launch alone fills the CUs
+// (tilesN >= slots) the product is not split: measured at n = 1000, p = 1e5 (782 column
+// blocks), two splits moved the BF16x3 probe from 24.9 to 24.2 ms and left the rest at
+// 60.1 ms, while the BF16x1 launches took 15% longer (a split's K steps ran slower).
+// Otherwise, with every workgroup of a launch doing the same work, a launch takes
+// ceil(workgroups / slots) rounds of 1 / S of the unsplit time, and weighting the probe
+// launch twice (it runs for every trial) S minimises
+//   (2 ceil(tilesN S / slots) + ceil((tilesM - 1) tilesN S / slots)) / S  (1 + 0.03 (S - 1)),
+// the last factor a charge for the split-K reduce and the shorter K loops; S = 1 .. 4,
+// at least 2 K steps of 64 per split, a larger S only for a 1% lower cost (n = 800,
+// p = 8192: 64 column blocks, S = 4).
+int choose_probe_splits(int tilesM, int tilesN, int ksteps64, int slots) {
+    if (tilesN >= slots) return 1;
+    int best = 1;
+    double best_cost = 0.0;
+    for (int s = 1; s <= 4; ++s) {
+        if (s > 1 && ksteps64 / s < 2) break;
+        const double rounds = 2.0 * (double)cdiv((int64_t)tilesN * s, slots) +
+                              (double)cdiv((int64_t)(tilesM - 1) * tilesN * s, slots);
+        const double cost = rounds / s * (1.0 + 0.03 * (s - 1));
+        if (s == 1 || cost < 0.99 * best_cost) {  // near ties keep the smaller S
+            best = s;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
 Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     Plan P = {};
     P.n = n;
@@ -135,7 +165,10 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     } else {
         P.tp.tilesM = (int)cdiv(P.n_pad, kFBM);
         P.tp.tilesN = (int)cdiv(p, kFBN);
-        P.tp.splits = choose_splits(P.tp.tiles(), (int)(P.p_pad / kPad), kWSlots);
+        P.tp.splits = P.tp.tilesM >= 4
+                          ? choose_probe_splits(P.tp.tilesM, P.tp.tilesN, (int)(P.p_pad / kPad),
+                                                kWSlots)
+                          : choose_splits(P.tp.tiles(), (int)(P.p_pad / kPad), kWSlots);
     }
     P.nprox = prox_blocks(p * P.p_pad);
     // every form's fit runs the prox inside its trial kernel: one row of prox sums per
@@ -148,7 +181,7 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     // A probe (M tile 0, a quarter of the samples or less) rejects a trial whose test
     // fails by more than the inverse of its share of the rows; with fewer M tiles the
     // probe is a large share of the product and cannot reject the near misses.
-    P.probe = P.fused && P.tp.splits == 1 && P.tp.tilesM >= 4;
+    P.probe = P.fused && P.tp.tilesM >= 4;
     P.prox_rows = P.fused ? P.tp.tilesN * P.tp.splits
                           : (P.fused32 ? P.t32.tilesN * P.t32.splits : P.nprox);
     const bool bf = is_bf16(prec);
@@ -813,7 +846,8 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
                 tpb.sums_m = 0;
                 launch_trial_fused(tpb, a, prec, st);
                 launch_probe_decide(ls, prox_part, P.prox_rows, norm_part, P.tp.tilesN,
-                                    P.tp.tilesM, mbox_dev, st);
+                                    P.tp.tilesM, P.tp.splits > 1 ? kFReduceParts : 1, mbox_dev,
+                                    st);
                 GemmArgs tcp = ta;
                 tcp.m_first = 1;
                 tcp.m_count = P.tp.tilesM - 1;

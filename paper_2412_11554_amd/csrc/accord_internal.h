@@ -205,8 +205,8 @@ void launch_finalize(LsState* ls, const double* prox_part, int nprox, const doub
                      int ntiles, double* trace, int32_t* trials_log, Mailbox* mbox,
                      hipStream_t st);
 void launch_probe_decide(LsState* ls, const double* prox_part, int nprox,
-                         const double* norm_part, int tilesN, int tilesM, Mailbox* mbox,
-                         hipStream_t st);
+                         const double* norm_part, int tilesN, int tilesM, int nparts,
+                         Mailbox* mbox, hipStream_t st);
 void launch_fit_init(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
                      int ntiles, double* trace, hipStream_t st);
 void launch_combine_prox(const double* prox_part, int nprox, double* red, hipStream_t st);

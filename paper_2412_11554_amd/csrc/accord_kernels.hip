@@ -1629,7 +1629,9 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
 // Split-K reduction for the fused tiles; kFReduceParts (2) workgroups per tile, part
 // p owning the rows 64 c + 32 p .. + 31 (c = 0..3) of the tile, norm row =
 // part * tiles + tile.  S > 0: the split count at compile time, so that a thread's
-// loads of one split are issued together (S = 0 takes it from g.splits).
+// loads of one split are issued together (S = 0 takes it from g.splits).  Like the
+// trial launch it follows, it covers the M tiles m_first .. m_first + m_count - 1 (all
+// with m_count 0), and pred 3 skips it after a probe rejected the trial.
 // The partial fragments are summed in the GEMM's thread -> fragment map (coalesced
 // reads, each sum over s = 0, 1, ... in order), then turned through LDS so that the
 // epilogue (store_frag) walks W column by column: 8 lanes cover 32 consecutive samples
@@ -1640,12 +1642,16 @@ __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_f(GemmArgs g) {
     if (g.ls) {
         if (g.pred >= 1 && g.ls->converged) return;
         if (g.pred >= 2 && g.ls->done) return;
+        if (g.pred >= 3 && g.ls->probe_rej) return;
     }
     constexpr int LDR = 132;  // LDS floats per column (128 rows + 4: 16 lanes hit 64 banks)
     __shared__ __attribute__((aligned(16))) float sT[kFBN * LDR];
     const int tiles = g.tilesM * g.tilesN;
-    const int tile = blockIdx.x % tiles, part = blockIdx.x / tiles;
-    const int tile_m = tile % g.tilesM, tile_n = tile / g.tilesM;
+    const int mcnt = g.m_count > 0 ? g.m_count : g.tilesM;
+    const int in_launch = mcnt * g.tilesN;
+    const int local = blockIdx.x % in_launch, part = blockIdx.x / in_launch;
+    const int tile_m = g.m_first + local % mcnt, tile_n = local / mcnt;
+    const int tile = tile_m + tile_n * g.tilesM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int PER = 16 / kFReduceParts;
     f4 v[PER];
@@ -1694,7 +1700,8 @@ __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_f(GemmArgs g) {
 }
 
 void launch_splitk_reduce_f(const GemmArgs& a, hipStream_t st) {
-    const unsigned blocks = (unsigned)(a.tilesM * a.tilesN * kFReduceParts);
+    const int mcnt = a.m_count > 0 ? a.m_count : a.tilesM;
+    const unsigned blocks = (unsigned)(mcnt * a.tilesN * kFReduceParts);
     switch (a.splits) {
         case 2: k_splitk_reduce_f<2><<<blocks, kWThreads, 0, st>>>(a); break;
         case 3: k_splitk_reduce_f<3><<<blocks, kWThreads, 0, st>>>(a); break;
@@ -2390,15 +2397,19 @@ void launch_finalize(LsState* ls, const double* prox_part, int nprox, const doub
 // the acceptance test of this trial do nothing.  A trial at the floor tau <= 1/L, a fixed
 // step and non-finite sums always go on to the full test.  Norm rows of M tile 0 are
 // rows tile_n * tilesM (no split-K).
+// nparts: norm rows per tile (kFReduceParts after a split-K reduce: row part * tiles +
+// tile; 1 otherwise).
 __global__ void __launch_bounds__(kThreads) k_probe_decide(LsState* ls, const double* prox_part,
                                                            int nprox, const double* norm_part,
-                                                           int tilesN, int tilesM, Mailbox* mbox) {
+                                                           int tilesN, int tilesM, int nparts,
+                                                           Mailbox* mbox) {
     if (ls->done || ls->converged) return;
     double pv[6];
     sum_partials<6>(prox_part, nprox, kPartCols, pv);
     double nv[1] = {0.0};
-    for (int r = threadIdx.x; r < tilesN; r += kThreads)
-        nv[0] += norm_part[(int64_t)r * tilesM * kNormCols];
+    const int64_t tiles = (int64_t)tilesM * tilesN;
+    for (int r = threadIdx.x; r < tilesN * nparts; r += kThreads)
+        nv[0] += norm_part[((r / tilesN) * tiles + (int64_t)(r % tilesN) * tilesM) * kNormCols];
     block_sum<1>(nv);
     if (threadIdx.x != 0) return;
     const double d2 = pv[P_D2], v2 = nv[0], tau = ls->tau;
@@ -2417,10 +2428,10 @@ __global__ void __launch_bounds__(kThreads) k_probe_decide(LsState* ls, const do
 }
 
 void launch_probe_decide(LsState* ls, const double* prox_part, int nprox,
-                         const double* norm_part, int tilesN, int tilesM, Mailbox* mbox,
-                         hipStream_t st) {
+                         const double* norm_part, int tilesN, int tilesM, int nparts,
+                         Mailbox* mbox, hipStream_t st) {
     k_probe_decide<<<1, kThreads, 0, st>>>(ls, prox_part, nprox, norm_part, tilesN, tilesM,
-                                           mbox);
+                                           nparts, mbox);
 }
 
 // Starting point: objective pieces of Omega^(0) (reduce-only prox sums of Omega^(0)

@@ -422,9 +422,10 @@ def test_fit_deterministic_benchmark_shape(gpu_lib, dev, form):
 
 @pytest.mark.parametrize("form", ["bf16x3", "bf16x1", "fp8"])
 def test_fit_probe_is_the_full_trial(gpu_lib, dev, form):
-    """n = 800, p = 8192: 4 M tiles of 256 samples and no split-K, so every trial first runs
-    on M tile 0 and is rejected there when that lower bound of ||X Delta||^2 already fails
-    the test.  The prox of every tile is the same FP32 arithmetic and the acceptance sums
+    """n = 800, p = 8192: 4 M tiles of 256 samples, and 64 column blocks, too few to fill
+    the CUs, so the product is split 4 ways along K (a split-K reduce per launch); every
+    trial first runs on M tile 0 and is rejected there when that lower bound of
+    ||X Delta||^2 already fails the test.  The prox of every tile is the same FP32 arithmetic and the acceptance sums
     are unchanged, so the fit equals the one that always runs the whole product bit for
     bit, with the same trial counts; BF16x3 also against the oracle's replay."""
     import torch
