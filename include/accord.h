@@ -149,12 +149,13 @@ typedef struct {
                            term is a square); otherwise the product is completed and tested
                            as usual.  0 = always the whole product.  Same iterates either
                            way, up to FP64 rounding of the sums at a tie. */
-    int32_t support_skip; /* accord_refit, BF16X1 / BF16X3 / FP8 forms: 1 (the default of
-                           accord_default_params) = the trial products walk only the K steps
-                           of each 128-column block that hold support entries, and the
-                           gradient skips its 256 x 256 tiles without any (everything off
-                           the support stays exactly zero, so the results are the same bits);
-                           0 = every block.  Ignored by accord_fit. */
+    int32_t support_skip; /* accord_refit: 1 (the default of accord_default_params) = the
+                           trial products walk only the 32-row K steps of each 128-column
+                           block that hold support entries, and the gradient skips its tiles
+                           (256 x 256 in the BF16 / FP8 forms, 128 x 128 in FP32) without any
+                           (everything off the support stays exactly zero, so the results are
+                           the same bits); 0 = every block.  The FP32 form with n > 512 (a
+                           separate prox pass) walks every block.  Ignored by accord_fit. */
     int32_t batch_order; /* accord_fit_batch: tile order of the batched gradient (bits 0-7)
                            and trial kernel (bits 8-15), each 0 (default) or a code 1..10
                            from accord_tune_batch.  The order decides only which workgroup

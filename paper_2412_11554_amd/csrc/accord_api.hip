@@ -94,7 +94,7 @@ struct Plan {
     // 128-column block), the K-step lists of the trial kernels (CSR) and the occupied
     // 256 x 256 tiles of the gradient
     size_t off_occ, off_kptr, off_kidx, off_gocc;
-    int ks32, tilesMg, tilesNg;
+    int ks32, gbm, gbn, tilesMg, tilesNg;
     size_t end_prox;
 };
 
@@ -227,8 +227,10 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     P.end_fit = cur;
     P.off_mask = bump(cur, on);
     P.ks32 = (int)(P.p_pad / 32);
-    P.tilesMg = (int)cdiv(P.p_pad, kWBM);
-    P.tilesNg = (int)cdiv(p, kWBN);
+    P.gbm = prec == PREC_FP32 ? kBM : kWBM;  // gradient tile (G rows x columns)
+    P.gbn = prec == PREC_FP32 ? kBN : kWBN;
+    P.tilesMg = (int)cdiv(P.p_pad, P.gbm);
+    P.tilesNg = (int)cdiv(p, P.gbn);
     P.off_occ = bump(cur, (size_t)P.tp.tilesN * P.ks32);
     P.off_kptr = bump(cur, (size_t)(P.tp.tilesN + 1) * sizeof(int32_t));
     P.off_kidx = bump(cur, (size_t)P.tp.tilesN * P.ks32 * sizeof(int32_t));
@@ -661,12 +663,14 @@ static int plan_support_skip(const Plan& P, void* ws, const uint8_t* mask, int u
         }
         ptr[c + 1] = (int32_t)idx.size();
     }
+    // a gradient tile covers gbm / 32 steps of 32 rows and gbn / 128 column blocks
+    const int spt = P.gbm / 32, cpt = P.gbn / 128;
     std::vector<uint8_t> gocc((size_t)P.tilesMg * P.tilesNg, 0);
     for (int tm = 0; tm < P.tilesMg; ++tm)
         for (int tg = 0; tg < P.tilesNg; ++tg) {
             bool any = false;
-            for (int c = 2 * tg; c < 2 * tg + 2 && c < tn; ++c)
-                for (int s = 8 * tm; s < 8 * tm + 8 && s < ks32; ++s)
+            for (int c = cpt * tg; c < cpt * tg + cpt && c < tn; ++c)
+                for (int s = spt * tm; s < spt * tm + spt && s < ks32; ++s)
                     any = any || h[(size_t)c * ks32 + s];
             gocc[tm + (size_t)tg * P.tilesMg] = any ? 1 : 0;
         }
@@ -734,11 +738,12 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
     launch_copy_cols(Omega, p, om[0], P.p_pad, p, P.p_pad, ls, st);
     uint8_t* mask = support_src ? at<uint8_t>(ws, P.off_mask) : nullptr;
     if (mask) launch_support_mask(support_src, p, P.p_pad, mask, om[0], st);
-    // refit in a fused form: walk only the blocks that can hold support entries
+    // refit: walk only the blocks that can hold support entries
     const int32_t* kptr = nullptr;
     const int32_t* kidx = nullptr;
     const uint8_t* gocc = nullptr;
-    if (mask && P.fused && prm->support_skip) {
+    // (the FP32 form with a separate prox pass, n > 512, walks every block)
+    if (mask && (P.fused || P.fused32) && prm->support_skip) {
         TRY(plan_support_skip(P, ws, mask, f8 ? 2 : 1, st));
         kptr = at<int32_t>(ws, P.off_kptr);
         kidx = at<int32_t>(ws, P.off_kidx);

@@ -582,6 +582,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32(GemmArgs g) {
     if (gemm_skip(g)) return;
     int tile_m, tile_n, split;
     decode_tile(g, tile_m, tile_n, split);
+    if (g.tile_occ && !g.tile_occ[tile_m + tile_n * g.tilesM]) return;  // a zero tile of C
     gemm_f32_tile<EPI>(g, tile_m, tile_n, split,
                        g.norm_part + (int64_t)(tile_m + tile_n * g.tilesM) * kNormCols);
 }
@@ -1095,9 +1096,23 @@ __device__ __forceinline__ void trial_fused32_tile(const GemmArgs& g, const Prox
     const bool owner = tile_m == 0;
     const float tau_f = (float)tau, thr_f = (float)(tau * lam);
     const int m0 = tile_m * kBM, n0 = tile_n * kBN;
-    const int ksteps = g.K / kBK32;
-    const int s_begin = (int)((int64_t)ksteps * split / g.splits);
-    const int s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
+    // the split's share of the column block's K steps, as positions in a step sequence:
+    // every step (kstep_idx null), or the column block's list of steps that can hold a
+    // nonzero Delta (a refit's support); the split keeps its K range either way, so the
+    // partial sums group the same products as when every step is walked
+    const int32_t* kidx = g.kstep_idx;
+    int s_begin, s_end;
+    {
+        const int ksteps = g.K / kBK32;
+        s_begin = (int)((int64_t)ksteps * split / g.splits);
+        s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
+        if (kidx) {
+            const int c0 = g.kstep_ptr[tile_n], c1 = g.kstep_ptr[tile_n + 1];
+            s_begin = first_at_least(kidx, c0, c1, s_begin);
+            s_end = first_at_least(kidx, c0, c1, s_end);
+        }
+    }
+#define KS32(pos) (kidx ? kidx[(pos)] : (pos))
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lrow = tid >> 3, lcol = (tid & 7) * 4;
@@ -1210,13 +1225,13 @@ __device__ __forceinline__ void trial_fused32_tile(const GemmArgs& g, const Prox
     } while (0)
 
     if (s_begin < s_end) {
-        F32_LOAD(s_begin);
-        F32_PRODUCE(0, s_begin);
+        F32_LOAD(KS32(s_begin));
+        F32_PRODUCE(0, KS32(s_begin));
         __syncthreads();
         int cur = 0;
         for (int s = s_begin; s < s_end; ++s) {
             const bool more = s + 1 < s_end;
-            if (more) F32_LOAD(s + 1);
+            if (more) F32_LOAD(KS32(s + 1));
             __builtin_amdgcn_sched_barrier(0);
             const float* a_base = &sA[cur][(wm + r16) * kLDK32 + g4];
             const float* b_base = &sB[cur][(wn + r16) * kLDK32 + g4];
@@ -1237,13 +1252,14 @@ __device__ __forceinline__ void trial_fused32_tile(const GemmArgs& g, const Prox
                                                                              acc[i][j], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
-            if (more) F32_PRODUCE(cur ^ 1, s + 1);
+            if (more) F32_PRODUCE(cur ^ 1, KS32(s + 1));
             __syncthreads();
             cur ^= 1;
         }
     }
 #undef F32_LOAD
 #undef F32_PRODUCE
+#undef KS32
     __syncthreads();
     double* red = (double*)&sA[0][0];  // LDS is free after the K loop
     if (owner) {

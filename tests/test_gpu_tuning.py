@@ -132,13 +132,14 @@ def test_refit_full_size_sampled(gpu_lib, prec):
     assert rel <= 1e-4
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "bf16x1", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x1", "fp8", "fp32"])
 def test_refit_support_skip_is_exact(gpu_lib, prec):
-    """The fused forms' refit walks only the blocks that hold support entries (K steps of
-    the trial products, 256 x 256 tiles of the gradient); everything it skips is exactly
-    zero, so the results equal those of a refit that walks every block, bit for bit: on
-    the benchmark's refit (n = 500, p = 5000, the true graph's support) and on a ragged
-    shape with a sparse random support (p = 300: a partial column block and K step)."""
+    """The refit walks only the blocks that hold support entries (K steps of the trial
+    products, gradient tiles of 256 x 256, or 128 x 128 in FP32); everything it skips is
+    exactly zero, so the results equal those of a refit that walks every block, bit for
+    bit: on the benchmark's refit (n = 500, p = 5000, the true graph's support) and on a
+    ragged shape with a sparse random support (p = 300: a partial column block and K
+    step)."""
     import torch
     d = datagen.refit_workload()
     cases = [(d["x"], d["omega_hat"], d["lam"], d["phi"], 25)]
