@@ -493,6 +493,12 @@ def run_batch(args):
         torch.cuda.synchronize()
         eager_s = time.perf_counter() - t1
         log(f"[batch] eager step {eager_s:.2f} s")
+        # and with the library's default launches (code 0), to measure what tuning bought
+        t2 = time.perf_counter()
+        accord.accord_fit_batch(X, w.n, w.lams, iters, ws=ws, omega_out=om, graph=True)
+        torch.cuda.synchronize()
+        default_s = time.perf_counter() - t2
+        log(f"[batch] default-launch step {default_s:.2f} s")
     trials = tr.cpu().numpy()
     ns = np.repeat(np.array(w.n, dtype=np.float64), nlam)
     products = iters + trials[:, :iters].sum(axis=1)     # gradients + executed trials
@@ -513,9 +519,12 @@ def run_batch(args):
         "launch": "two captured HIP graphs (one sweep of each parity) replayed per sweep",
         "autotune": {"order_code": code, "grad_order": code & 0xff, "trial_order": code >> 8,
                      "ms_per_launch": table,
-                     "orders": "code 1 + c: bands of 2^(c % 5) M tiles, plain block order "
-                               "(c < 5) or XCD-contiguous (c >= 5); default = code 4"},
+                     "orders": "code 1 + c and 11 + c: bands of 2^(c % 5) M tiles, plain "
+                               "block order (c < 5) or XCD-contiguous (c >= 5), at two "
+                               "(codes 1..10) or one (11..20) workgroups per CU; "
+                               "default = code 4"},
         "eager_ms_per_step": eager_s * 1e3,
+        "default_launch_ms_per_step": default_s * 1e3,
         "roofline": {"bound": "mfma", "kernel": "whole fit (batched FP32 gradient and fused prox + trial GEMMs, tests)",
                      "achieved": tflops, "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
                      "frac": tflops / PEAK_TFLOPS["fp32"], "traffic": None},

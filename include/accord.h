@@ -156,10 +156,12 @@ typedef struct {
                            (everything off the support stays exactly zero, so the results are
                            the same bits); 0 = every block.  The FP32 form with n > 512 (a
                            separate prox pass) walks every block.  Ignored by accord_fit. */
-    int32_t batch_order; /* accord_fit_batch: tile order of the batched gradient (bits 0-7)
-                           and trial kernel (bits 8-15), each 0 (default) or a code 1..10
-                           from accord_tune_batch.  The order decides only which workgroup
-                           computes which tile, so every code gives the same bits. */
+    int32_t batch_order; /* accord_fit_batch: launch code of the batched gradient (bits 0-7)
+                           and trial kernel (bits 8-15), each 0 (default) or a code 1..20
+                           from accord_tune_batch: codes 1..10 are tile orders at two
+                           workgroups per CU, 11..20 the same orders at one.  Both decide
+                           only which workgroup computes which tile and how many share a
+                           CU, so every code gives the same bits. */
 } accord_params;
 
 /* Results of accord_fit (host memory, filled on return). */
@@ -298,11 +300,12 @@ int accord_fit_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
 /* Autotuner of the batched form's launches (for callers that repeat fits of one shape,
  * e.g. a lambda path over bootstrap subsamples).  Runs the set-up of accord_fit_batch
  * (same arguments, max_iter ignored), then times the batched gradient and trial kernels
- * in each of 10 tile orders (bands of 1, 2, 4, 8 or 16 M tiles; plain block order or an
- * XCD-contiguous one) and writes the fastest as a params.batch_order code to *order
- * (host).  table (host float[20], or NULL) receives the mean ms per launch of each order,
- * gradient first.  The tile order never changes a result.  Omega is left as given;
- * workspace as accord_fit_batch; synchronous. */
+ * under each of 20 launch codes (10 tile orders: bands of 1, 2, 4, 8 or 16 M tiles in
+ * plain block order or an XCD-contiguous one; each with the kernel compiled for two or
+ * for one workgroup per CU) and writes the fastest as a params.batch_order code to
+ * *order (host).  table (host float[40], or NULL) receives the mean ms per launch of each
+ * code, gradient first.  No code changes a result.  Omega is left as given; workspace as
+ * accord_fit_batch; synchronous. */
 int accord_tune_batch(const float* X, const int64_t* n, int64_t nsub, int64_t p,
                       const double* lambda, int64_t nlam, float* Omega,
                       const accord_params* prm, const double* lipschitz, void* ws,

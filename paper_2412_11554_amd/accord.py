@@ -337,13 +337,15 @@ def accord_fit_batch(X: torch.Tensor, n, lambdas, max_iter: int, *,
     return omega_out, [s.as_dict() for s in st], tr
 
 
-BATCH_ORDERS = 10  # tile orders per kernel that accord_tune_batch times
+BATCH_ORDERS = 20  # launch codes per kernel that accord_tune_batch times (10 tile orders
+                   # at two workgroups per CU, then at one)
 
 
 def accord_tune_batch(X: torch.Tensor, n, lambdas, *, max_iter: int = 1, tau0: float = 1.0,
                       beta: float = 0.5, power_iters: int = 0, lipschitz=None, ws=None):
-    """Times the batched kernels in every tile order on this problem set (after the fit's
-    set-up) and returns (batch_order code, {"grad": [ms per order], "trial": [...]})."""
+    """Times the batched kernels under every launch code (tile order x workgroups per CU)
+    on this problem set (after the fit's set-up) and returns (batch_order code,
+    {"grad": [ms per code], "trial": [...]})."""
     n = [int(v) for v in n]
     nsub, p = len(n), X.shape[1]
     lam = [float(v) for v in lambdas]

@@ -1167,9 +1167,9 @@ size_t accord_batch_workspace_bytes(const int64_t* n, int64_t nsub, int64_t p, i
 
 }  // extern "C"
 
-// The batched fit; with tune_order set, the set-up is followed by timing every tile order
-// of the gradient and of the trial kernel (tune_table: mean ms per launch), and the
-// fastest of each is written to tune_order (and used by the sweeps, if any).
+// The batched fit; with tune_order set, the set-up is followed by timing every order code
+// (tile order x workgroups per CU) of the gradient and of the trial kernel (tune_table:
+// mean ms per launch), and the fastest of each is written to tune_order.
 static int fit_batch_impl(const float* X, const int64_t* n, int64_t nsub, int64_t p,
                           const double* lambda, int64_t nlam, float* Omega,
                           const accord_params* prm, const double* lipschitz,
@@ -1192,8 +1192,9 @@ static int fit_batch_impl(const float* X, const int64_t* n, int64_t nsub, int64_
                             (long long)b);
     if (trials && !aligned(trials, 4)) return fail(ACCORD_ERR_INVALID_ARG, "trials must be 4-byte aligned");
     const int order_grad = prm->batch_order & 0xff, order_trial = (prm->batch_order >> 8) & 0xff;
-    if (prm->batch_order < 0 || (prm->batch_order >> 16) != 0 || order_grad > kBatchOrders ||
-        order_trial > kBatchOrders)
+    int code_grad = order_grad, code_trial = order_trial;  // launch codes (tuning may change)
+    if (prm->batch_order < 0 || (prm->batch_order >> 16) != 0 || order_grad > kBatchCodes ||
+        order_trial > kBatchCodes)
         return fail(ACCORD_ERR_INVALID_ARG, "batch_order %d is not a tile order code",
                     prm->batch_order);
     BatchPlan B;
@@ -1355,7 +1356,7 @@ static int fit_batch_impl(const float* X, const int64_t* n, int64_t nsub, int64_
     if (!lipschitz) launch_share_L_batch(ls, (int)np, (int)nlam, st);
     for (int64_t k = 0; k < np; ++k)
         launch_copy_cols(Omega + k * p * p, p, om[0] + k * mat, B.p_pad, p, B.p_pad, ls + k, st);
-    launch_gemm_f32_batch(d_w0, (int)nsub, B.max_tiles_trial, B.tpp, EPI_TRIAL, st);
+    launch_gemm_f32_batch(d_w0, (int)nsub, B.max_tiles_trial, B.tpp, EPI_TRIAL, 0, st);
     launch_prox_batch(d_prox_init, (int)np, B.nprox, st);
     launch_fit_init_batch(d_fin_init, (int)np, st);
     HIP_TRY(hipGetLastError());
@@ -1377,8 +1378,8 @@ static int fit_batch_impl(const float* X, const int64_t* n, int64_t nsub, int64_
     }
 
     if (tune_order) {
-        // Time every tile order of the gradient, then of the trial kernel (three launches
-        // each, the first to warm up).  Nothing here disturbs the fit: the gradient resets
+        // Time every order code (tile order x workgroups per CU) of the gradient, then of
+        // the trial kernel (three launches each, the first to warm up).  Nothing here disturbs the fit: the gradient resets
         // each problem's line search to the start of an iteration, as the first sweep's
         // does; the trial launches (without an acceptance test) only write buffers the
         // first sweep overwrites.
@@ -1391,24 +1392,25 @@ static int fit_batch_impl(const float* X, const int64_t* n, int64_t nsub, int64_
             std::vector<GemmArgs>& args = kind == 0 ? a_grad : a_trial;
             GemmArgs* dev = kind == 0 ? d_grad : d_trial;
             float best_ms = 0.f;
-            for (int code = 1; code <= kBatchOrders && err == ACCORD_OK; ++code) {
+            for (int code = 1; code <= kBatchCodes && err == ACCORD_OK; ++code) {
                 for (GemmArgs& g : args) g.order = code;
                 HIP_TRY(hipMemcpyAsync(dev, args.data(), args.size() * sizeof(GemmArgs),
                                        hipMemcpyHostToDevice, st));
                 for (int rep = 0; rep < 3; ++rep) {
                     if (rep == 1) HIP_TRY(hipEventRecord(e0, st));
                     if (kind == 0)
-                        launch_gemm_f32_batch(d_grad, (int)nsub, B.tiles_grad, B.tpp, EPI_GRAD, st);
+                        launch_gemm_f32_batch(d_grad, (int)nsub, B.tiles_grad, B.tpp, EPI_GRAD,
+                                              code, st);
                     else
                         launch_trial_fused32_batch(d_trial, d_px, (int)nsub, B.max_tiles_trial,
-                                                   B.tpp, B.part_rows, st);
+                                                   B.tpp, B.part_rows, code, st);
                 }
                 HIP_TRY(hipEventRecord(e1, st));
                 HIP_TRY(hipEventSynchronize(e1));
                 float ms = 0.f;
                 HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
                 ms *= 0.5f;
-                if (tune_table) tune_table[kind * kBatchOrders + code - 1] = ms;
+                if (tune_table) tune_table[kind * kBatchCodes + code - 1] = ms;
                 if (best[kind] == 0 || ms < best_ms) {
                     best[kind] = code;
                     best_ms = ms;
@@ -1422,6 +1424,8 @@ static int fit_batch_impl(const float* X, const int64_t* n, int64_t nsub, int64_
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         *tune_order = best[0] | (best[1] << 8);
+        code_grad = best[0];
+        code_trial = best[1];
     }
 
     // ---- Alg. 1 for every problem, one iteration per sweep.  Each sweep enqueues the
@@ -1431,10 +1435,11 @@ static int fit_batch_impl(const float* X, const int64_t* n, int64_t nsub, int64_
     // sweep depends on the host, so with prm->graph the two sweeps are captured once and
     // replayed.
     auto enqueue_sweep = [&](int par) {
-        launch_gemm_f32_batch(d_grad + par * nsub, (int)nsub, B.tiles_grad, B.tpp, EPI_GRAD, st);
+        launch_gemm_f32_batch(d_grad + par * nsub, (int)nsub, B.tiles_grad, B.tpp, EPI_GRAD,
+                              code_grad, st);
         for (int k = 0; k < ntr; ++k) {
             launch_trial_fused32_batch(d_trial + par * nsub, d_px + par * nsub, (int)nsub,
-                                       B.max_tiles_trial, B.tpp, B.part_rows, st);
+                                       B.max_tiles_trial, B.tpp, B.part_rows, code_trial, st);
             launch_finalize_batch(d_fin, (int)np, st);
         }
     };

@@ -216,6 +216,10 @@ void launch_transpose_w(const float* Wt, int64_t ldt, int64_t n, int64_t p, floa
                         hipStream_t st);
 // Lanczos estimate of L (buffers carved by lz_buf from lz_buf_bytes bytes)
 constexpr int kBatchOrders = 10;   // tile orders accord_tune_batch tries per kernel
+constexpr int kBatchCodes = 2 * kBatchOrders;  // codes per kernel: each order at 2 and at 1
+                                               // workgroups per CU
+// workgroups per CU a batched kernel is compiled for under an order code
+inline int batch_occupancy(int code) { return code > kBatchOrders ? 1 : 2; }
 constexpr int kLzMaxSteps = 256;   // cap on the Lanczos steps
 constexpr int kLzDefaultSteps = 256;
 constexpr int kLzCheck = 8;         // steps between checks of the Ritz residual bound
@@ -252,11 +256,14 @@ void launch_sub_inv_diag(float* obar, int64_t ld_obar, const float* om, int64_t 
                          hipStream_t st);
 
 // batched form (argument blocks in device memory)
+// code: the params.batch_order code of the launch (0 = default), which also picks the
+// workgroups per CU the kernel is compiled for (batch_occupancy)
 void launch_gemm_f32_batch(const GemmArgs* batch, int ngroups, int max_tiles, int tpp, int epi,
-                           hipStream_t st);
+                           int code, hipStream_t st);
 void launch_prox_batch(const ProxArgs* batch, int nprob, int nblocks, hipStream_t st);
 void launch_trial_fused32_batch(const GemmArgs* gb, const ProxArgs* pb, int ngroups,
-                                int max_tiles, int tpp, int nprox_rows, hipStream_t st);
+                                int max_tiles, int tpp, int nprox_rows, int code,
+                                hipStream_t st);
 void launch_finalize_batch(const FinArgs* batch, int nprob, hipStream_t st);
 void launch_fit_init_batch(const FinArgs* batch, int nprob, hipStream_t st);
 void launch_init_state_batch(LsState* ls, int nprob, int nlam, const double* lam,

@@ -2818,13 +2818,14 @@ namespace accord {
 // computes.  Every order is a permutation of the tiles, and a tile's arithmetic and the
 // rows its partial sums go to do not depend on which workgroup computes it, so the order
 // changes the run time only, never a result.  code 0: the default (plain block order,
-// bands of 8 M tiles walking across N); code 1 + c, c < kBatchOrders: bands of
+// bands of 8 M tiles walking across N); code 1 + c and 1 + kBatchOrders + c (the same
+// order at one workgroup per CU, batch_occupancy), c < kBatchOrders: bands of
 // GM = 2^(c % 5) M tiles, in plain block order (c < 5) or with every XCD given a
 // contiguous range of the tiles (c >= 5; blocks are dispatched round-robin over the 8
 // XCDs).  Returns false for the workgroups beyond the group's tiles.
 __device__ inline bool batch_tile(int code, int tilesM, int tilesN, int& tile_m, int& tile_n) {
     const int tiles = tilesM * tilesN;
-    const int c = code > 0 ? code - 1 : 3;
+    const int c = code > 0 ? (code - 1) % kBatchOrders : 3;
     const int GM = 1 << (c % 5);
     int logical = blockIdx.x;
     if (c >= 5) {
@@ -2843,9 +2844,12 @@ __device__ inline bool batch_tile(int code, int tilesM, int tilesN, int& tile_m,
     return true;
 }
 
-template <int EPI>
-__global__ void __launch_bounds__(kThreads, 2) k_gemm_f32_batch(const GemmArgs* __restrict__ batch,
-                                                               int tpp) {
+// OCC: workgroups per CU the code is compiled for (2: at most 128 registers per lane;
+// 1: up to 512, which the compiler spends on accumulators in AGPRs and deeper operand
+// staging).  The arithmetic of a tile is the same instruction sequence either way.
+template <int EPI, int OCC>
+__global__ void __launch_bounds__(kThreads, OCC) k_gemm_f32_batch(const GemmArgs* __restrict__ batch,
+                                                                 int tpp) {
     const GemmArgs g = batch[blockIdx.y];
     // Default order (code 0): plain block order, so consecutive tiles land on different
     // XCDs and the tiles of every problem spread over all of them.  Problems finish
@@ -2876,7 +2880,8 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_f32_batch(const GemmArgs* 
 // order as k_gemm_f32_batch.  Each tile reads its problem's state (skipped once that
 // problem accepted or stopped), step and penalty, and leaves its prox sums in row
 // tile_n - prob * tpp of the problem's block of nprox_rows rows.
-__global__ void __launch_bounds__(kThreads, 2) k_trial_fused32_batch(
+template <int OCC>
+__global__ void __launch_bounds__(kThreads, OCC) k_trial_fused32_batch(
     const GemmArgs* __restrict__ gb, const ProxArgs* __restrict__ pb, int tpp, int nprox_rows) {
     const GemmArgs g = gb[blockIdx.y];
     const ProxArgs px = pb[blockIdx.y];
@@ -2945,18 +2950,26 @@ __global__ void k_share_L_batch(LsState* ls, int nprob, int nlam) {
 }
 
 void launch_gemm_f32_batch(const GemmArgs* batch, int ngroups, int max_tiles, int tpp, int epi,
-                           hipStream_t st) {
+                           int code, hipStream_t st) {
     dim3 grid((unsigned)max_tiles, (unsigned)ngroups);
-    if (epi == EPI_GRAD)
-        k_gemm_f32_batch<EPI_GRAD><<<grid, kThreads, 0, st>>>(batch, tpp);
-    else
-        k_gemm_f32_batch<EPI_TRIAL><<<grid, kThreads, 0, st>>>(batch, tpp);
+    const bool one = batch_occupancy(code) == 1;
+    if (epi == EPI_GRAD) {
+        if (one) k_gemm_f32_batch<EPI_GRAD, 1><<<grid, kThreads, 0, st>>>(batch, tpp);
+        else k_gemm_f32_batch<EPI_GRAD, 2><<<grid, kThreads, 0, st>>>(batch, tpp);
+    } else {
+        if (one) k_gemm_f32_batch<EPI_TRIAL, 1><<<grid, kThreads, 0, st>>>(batch, tpp);
+        else k_gemm_f32_batch<EPI_TRIAL, 2><<<grid, kThreads, 0, st>>>(batch, tpp);
+    }
 }
 
 void launch_trial_fused32_batch(const GemmArgs* gb, const ProxArgs* pb, int ngroups,
-                                int max_tiles, int tpp, int nprox_rows, hipStream_t st) {
+                                int max_tiles, int tpp, int nprox_rows, int code,
+                                hipStream_t st) {
     dim3 grid((unsigned)max_tiles, (unsigned)ngroups);
-    k_trial_fused32_batch<<<grid, kThreads, 0, st>>>(gb, pb, tpp, nprox_rows);
+    if (batch_occupancy(code) == 1)
+        k_trial_fused32_batch<1><<<grid, kThreads, 0, st>>>(gb, pb, tpp, nprox_rows);
+    else
+        k_trial_fused32_batch<2><<<grid, kThreads, 0, st>>>(gb, pb, tpp, nprox_rows);
 }
 
 void launch_prox_batch(const ProxArgs* batch, int nprob, int nblocks, hipStream_t st) {

@@ -171,7 +171,7 @@ def test_fit_batch_validation(L):
     assert call(ws_bytes=16) == 4
     assert call(pr=accord.default_params(max_iter=3, precision=2)) == 5
     assert call(pr=accord.default_params(beta=0.0)) == 1
-    assert call(pr=accord.default_params(max_iter=3, batch_order=11)) == 1      # code > 10
+    assert call(pr=accord.default_params(max_iter=3, batch_order=21)) == 1      # code > 20
     assert call(pr=accord.default_params(max_iter=3, batch_order=1 << 16)) == 1
     order = ctypes.c_int32()
     assert L.accord_tune_batch(None, n, 2, 7, lam, 2, FAKE, ctypes.byref(prm), None, FAKE,

@@ -132,9 +132,10 @@ def test_batch_full_size_deterministic(gpu_lib):
 
 
 def test_batch_tile_orders_are_bit_identical(gpu_lib):
-    """Every tile order of the batched kernels (params.batch_order, codes 1..10 for the
-    gradient and the trial kernel) gives the default order's bits: the order decides only
-    which workgroup computes which tile."""
+    """Every launch code of the batched kernels (params.batch_order, codes 1..20 for the
+    gradient and the trial kernel: 10 tile orders at two and at one workgroups per CU)
+    gives the default's bits: a code decides only which workgroup computes which tile and
+    the register budget the kernel is compiled for."""
     import torch
     w = datagen.batch_workload(p=300, nsub=3, nlam=4, n_base=120, lo=40, hi=120, prob=0.02,
                                iters=20, key=35)
@@ -152,7 +153,7 @@ def test_batch_tile_orders_are_bit_identical(gpu_lib):
 
 def test_batch_autotune_full_size(gpu_lib):
     """The autotuner on the benchmark's 16 x 32 problems at p = 2000: a valid order code
-    from timings of all 20 candidates, and a fit in that order equal to the default."""
+    from timings of all 40 candidates, and a fit in that order equal to the default."""
     import torch
     w = datagen.workload("batch")
     X = torch.from_numpy(w.stacked()).cuda()
