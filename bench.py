@@ -171,7 +171,8 @@ def _trial_plan(form, n, p):
     return {"name": name, "splits": best, "probe": probe, "tilesM": tm, "tilesN": tn,
             "grid": tiles * best, "probe_grid": tn * best, "rest_grid": (tm - 1) * tn * best,
             "reduce": f"void k_splitk_reduce_f<{best}>" if fused and best > 1 else None,
-            "probe_reduce_grid": tn * 2, "rest_reduce_grid": (tm - 1) * tn * 2}
+            "probe_reduce_grid": tn * 2, "rest_reduce_grid": (tm - 1) * tn * 2,
+            "full_reduce_grid": tm * tn * 2}
 
 
 def kernel_report(stats, form, n, p, traffic_workload):
@@ -223,20 +224,29 @@ def kernel_report(stats, form, n, p, traffic_workload):
         sep = group("prox")[1] > 0  # FP32 with a separate prox pass: plain trial GEMM
         trials = sum(s["trials"] for s in stats)
         rej = sum(s.get("probe_rejects", 0) for s in stats) / max(1, trials)
+        unp = sum(s.get("unprobed_trials", 0) for s in stats) / max(1, trials)
         if plan["probe"]:
             n0 = min(256, n)
             alg = 8.0 * p * p + (1.0 - rej) * 4.0 * p * p
             fl = 2.0 * (n0 + (1.0 - rej) * (n - n0)) * p * p
             red = plan["reduce"]
             names = [plan["name"] + " (probe)"] + ([red[5:] + " (probe)"] if red else []) + \
-                ["k_probe_decide", plan["name"] + " (rest)"] + ([red[5:] + " (rest)"] if red else [])
-            tp, tr = measured(plan["name"], plan["probe_grid"]), measured(plan["name"],
-                                                                          plan["rest_grid"])
-            if red and tp is not None and tr is not None:
-                rp, rr = measured(red, plan["probe_reduce_grid"]), measured(red,
-                                                                           plan["rest_reduce_grid"])
-                tp, tr = (tp + rp, tr + rr) if (rp is not None and rr is not None) else (None, None)
-            traf = tp + (1.0 - rej) * tr if (tp is not None and tr is not None) else None
+                ["k_probe_decide", plan["name"] + " (rest)"] + \
+                ([red[5:] + " (rest)"] if red else []) + [plan["name"] + " (unprobed)"] + \
+                ([red[5:] + " (unprobed)"] if red else [])
+            tp, tr, tf = (measured(plan["name"], plan[k])
+                          for k in ("probe_grid", "rest_grid", "grid"))
+            if red and None not in (tp, tr, tf):
+                rp, rr, rf = (measured(red, plan[k]) for k in
+                              ("probe_reduce_grid", "rest_reduce_grid", "full_reduce_grid"))
+                tp, tr, tf = ((tp + rp, tr + rr, tf + rf) if None not in (rp, rr, rf)
+                              else (None, None, None))
+            # probed trials pay the probe, the probed ones it did not reject the rest, and
+            # the trials run unprobed (after a full-test rejection) the whole product
+            if None in (tp, tr) or (unp > 0 and tf is None):
+                traf = None
+            else:
+                traf = (1.0 - unp) * tp + (1.0 - rej - unp) * tr + (unp * tf if unp > 0 else 0.0)
         else:
             alg, fl = 12.0 * p * p, flops
             S = plan["splits"]
@@ -256,6 +266,7 @@ def kernel_report(stats, form, n, p, traffic_workload):
                      "fused prox (eq. 3.5) + W+ = W + X Delta (+ norms)",
              "algorithmic_bytes": alg, "useful_flops": fl,
              "probe_reject_fraction": rej if plan["probe"] else None,
+             "unprobed_fraction": unp if plan["probe"] else None,
              "mfma": {"achieved": a * PASSES[form], "peak": peak, "unit": "TFLOP/s",
                       "frac": a * PASSES[form] / peak, "useful_tflops": a}}
         if t_hbm >= t_mfma:
@@ -332,6 +343,8 @@ def run_form(form, X, w, iters, ws, om, steps, warmup, check, warm_tau=False, ca
            "trials_per_iter": sum(s["trials"] for s in stats) / max(1, sum(s["iters"] for s in stats)),
            "probe_rejects_per_iter": sum(s["probe_rejects"] for s in stats) /
                                      max(1, sum(s["iters"] for s in stats)),
+           "unprobed_trials_per_iter": sum(s["unprobed_trials"] for s in stats) /
+                                       max(1, sum(s["iters"] for s in stats)),
            "lipschitz": stats[-1]["lipschitz"], "lz_steps": stats[0]["lz_steps"] if not carry else None,
            "kernels": kernel_report(stats, form, w.n, w.p, traffic_workload)}
     if carry:

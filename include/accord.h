@@ -147,8 +147,11 @@ typedef struct {
                            sum, so when it alone fails Alg. 1's test the trial is rejected
                            without the rest of the product (the same decision, since every
                            term is a square); otherwise the product is completed and tested
-                           as usual.  0 = always the whole product.  Same iterates either
-                           way, up to FP64 rounding of the sums at a tie. */
+                           as usual.  Once a trial of an iteration has failed the full test,
+                           the iteration's later trials (whose test ratio is about half and
+                           below what the probe can reject) run without a probe.  0 = always
+                           the whole product.  Same iterates either way, up to FP64 rounding
+                           of the sums at a tie. */
     int32_t support_skip; /* accord_refit: 1 (the default of accord_default_params) = the
                            trial products walk only the 32-row K steps of each 128-column
                            block that hold support entries, and the gradient skips its tiles
@@ -190,6 +193,9 @@ typedef struct {
     double l1;              /* ||Omega||_1 at the result (all entries) */
     int32_t lz_steps;       /* Lanczos steps of the device estimate of L (0 if L was given) */
     int32_t probe_rejects;  /* trials rejected from their first 256 samples (params.probe) */
+    int32_t unprobed_trials;/* trials of a probed fit run without a probe: once a trial of
+                               an iteration fails the full test, the later ones (at half
+                               the step and less) run as one launch over all samples */
 } accord_stats;
 
 /* Fills `prm` with defaults: lambda 0.1, tau0 1, beta 0.5, lipschitz 0 (estimate),

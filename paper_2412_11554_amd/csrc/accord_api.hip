@@ -817,6 +817,7 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
                             at<uint8_t>(ws, P.off_w8s), ls, st);
         launch_gemm(ga, EPI_GRAD, prec, st);
         if (tim) { HIP_TRY(hipEventRecord(lg.b, st)); ev_grad.push_back(lg); }
+        const bool probing = fused && P.probe && prm->probe;
         auto enqueue_trial_k = [&](int k) -> int {
             ProxArgs a = {};
             a.om = om[cur];
@@ -840,15 +841,18 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
             }
             Launch lt = {nullptr, nullptr, t, k};
             if (tim) { lt.a = pool.get(); lt.b = pool.get(); HIP_TRY(hipEventRecord(lt.a, st)); }
-            if (fused && P.probe && prm->probe) {
+            if (probing) {
                 // probe: M tile 0 with the prox sums, no Omega+ store; then the test of
                 // its lower bound; then (unless rejected) the other M tiles, the first of
-                // which stores Omega+
+                // which stores Omega+.  Once a trial of the iteration has failed the full
+                // test, these three are skipped and the last launch runs the whole
+                // product instead (see finalize_run).
                 GemmArgs tpb = ta;
                 tpb.m_first = 0;
                 tpb.m_count = 1;
                 tpb.store_m = -1;
                 tpb.sums_m = 0;
+                tpb.probe_mode = 1;
                 launch_trial_fused(tpb, a, prec, st);
                 launch_probe_decide(ls, prox_part, P.prox_rows, norm_part, P.tp.tilesN,
                                     P.tp.tilesM, P.tp.splits > 1 ? kFReduceParts : 1, mbox_dev,
@@ -859,7 +863,11 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
                 tcp.store_m = 1;
                 tcp.sums_m = -1;
                 tcp.pred = 3;
+                tcp.probe_mode = 1;
                 launch_trial_fused(tcp, a, prec, st);
+                GemmArgs tfl = ta;
+                tfl.probe_mode = 2;
+                launch_trial_fused(tfl, a, prec, st);
             } else if (fused)
                 launch_trial_fused(ta, a, prec, st);
             else if (P.fused32)
@@ -868,7 +876,7 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
                 enqueue_trial(ta, prec, st);
             if (tim) { HIP_TRY(hipEventRecord(lt.b, st)); ev_trial.push_back(lt); }
             launch_finalize(ls, prox_part, P.prox_rows, norm_part, ttiles, trace, trials_log,
-                            mbox_dev, st);
+                            mbox_dev, probing ? 1 : 0, st);
             HIP_TRY(hipGetLastError());
             return ACCORD_OK;
         };
@@ -941,6 +949,7 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
         stats->l1 = host.l1_cur;
         stats->lz_steps = host.lz_steps;
         stats->probe_rejects = host.probe_rejects;
+        stats->unprobed_trials = host.unprobed;
         if (timing) {
             std::vector<int32_t> tl((size_t)(host.iter > 0 ? host.iter : 1), 0);
             if (host.iter > 0)

@@ -59,6 +59,9 @@ struct LsState {
     int32_t lz_steps;   // Lanczos steps of the device estimate of L (0: L was given)
     int32_t probe_rej;  // the trial in flight was rejected by its probe (row tile 0)
     int32_t probe_rejects;  // trials rejected by their probe, over the fit
+    int32_t probe_off;  // this iteration's later trials run unprobed (set when a trial
+                        // fails the full test of a probing fit)
+    int32_t unprobed;   // trials of a probing fit that ran unprobed, over the fit
 };
 
 // Pinned host mailbox: after every executed acceptance test the device posts the
@@ -138,10 +141,12 @@ struct GemmArgs {
     // left out must hold Delta = 0 (a refit's blocks off the support).  Null: every step.
     const int32_t* kstep_ptr;
     const int32_t* kstep_idx;
-    // gradient kernels of the bf16 and FP8 forms, optional: one byte per tile (tile_m +
-    // tile_n * tilesM), 0 = the tile of C is zero and is neither computed nor stored
+    // gradient kernels, optional: one byte per tile (tile_m + tile_n * tilesM), 0 = the
+    // tile of C is zero and is neither computed nor stored
     const uint8_t* tile_occ;
     int order;          // batched kernels: tile order code (batch_tile), 0 = default
+    int probe_mode;     // trials of a probing fit: 0 always run; 1 only while the
+                        // iteration probes (probe_off == 0); 2 only once it stopped
 };
 
 struct ProxArgs {
@@ -201,9 +206,11 @@ void launch_trial_fused(const GemmArgs& a, const ProxArgs& px, int prec, hipStre
 void launch_trial_fused32(const GemmArgs& a, const ProxArgs& px, hipStream_t st);
 int prox_blocks(int64_t total);
 void launch_prox(ProxArgs a, int nblocks, hipStream_t st);
+// probing: the fit probes its trials; a trial failing the full test then turns the
+// probes off for the rest of its iteration (LsState::probe_off)
 void launch_finalize(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
                      int ntiles, double* trace, int32_t* trials_log, Mailbox* mbox,
-                     hipStream_t st);
+                     int probing, hipStream_t st);
 void launch_probe_decide(LsState* ls, const double* prox_part, int nprox,
                          const double* norm_part, int tilesN, int tilesM, int nparts,
                          Mailbox* mbox, hipStream_t st);

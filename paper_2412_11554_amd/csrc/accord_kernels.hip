@@ -305,12 +305,15 @@ __device__ inline bool gemm_skip(const GemmArgs& g) {
         if (g.pred >= 1 && g.ls->converged) return true;
         if (g.pred >= 2 && g.ls->done) return true;
         if (g.pred >= 3 && g.ls->probe_rej) return true;
+        if (g.probe_mode == 1 && g.ls->probe_off) return true;
+        if (g.probe_mode == 2 && !g.ls->probe_off) return true;
     }
     if (g.begin_iter && blockIdx.x == 0 && threadIdx.x == 0) {
         // a new iteration starts from tau0 (Alg. 1); nothing else reads these now
         g.ls->done = 0;
         g.ls->trials = 0;
         g.ls->probe_rej = 0;
+        g.ls->probe_off = 0;
         g.ls->tau = start_tau(*g.ls);
     }
     return false;
@@ -1659,6 +1662,8 @@ __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_f(GemmArgs g) {
         if (g.pred >= 1 && g.ls->converged) return;
         if (g.pred >= 2 && g.ls->done) return;
         if (g.pred >= 3 && g.ls->probe_rej) return;
+        if (g.probe_mode == 1 && g.ls->probe_off) return;
+        if (g.probe_mode == 2 && !g.ls->probe_off) return;
     }
     constexpr int LDR = 132;  // LDS floats per column (128 rows + 4: 16 lanes hit 64 banks)
     __shared__ __attribute__((aligned(16))) float sT[kFBN * LDR];
@@ -2323,9 +2328,15 @@ __device__ inline void post_mailbox(Mailbox* mb, const LsState* ls) {
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// probing: the fit probes its trials (see launch_finalize).  Once a trial that was not
+// rejected by its probe fails the full test, its ratio ||X Delta||^2 tau / (n ||Delta||^2)
+// was below the inverse of the probe's share of the samples, and the next trial's, at
+// half the step, is about half of it: its probe could reject it only if the ratio did not
+// fall, so the rest of the iteration runs each trial as one launch over all samples (the
+// same tiles and sums, so the same bits, without the probe's extra launch).
 __device__ __forceinline__ void finalize_run(LsState* ls, const double* prox_part, int nprox,
                                              const double* norm_part, int ntiles, double* trace,
-                                             int32_t* trials_log, Mailbox* mbox) {
+                                             int32_t* trials_log, Mailbox* mbox, int probing) {
     if (ls->done || ls->converged) return;
     // a trial its probe has rejected is complete: clear the flag for the next trial
     const int probe_rej = ls->probe_rej;
@@ -2348,6 +2359,7 @@ __device__ __forceinline__ void finalize_run(LsState* ls, const double* prox_par
                         isfinite(logd) && isfinite(fro);
     ls->trials += 1;
     ls->total_trials += 1;
+    if (probing && ls->probe_off) ls->unprobed += 1;
     if (!finite) {
         ls->bad |= 2;
         ls->converged = 1;  // stop: every later launch is skipped
@@ -2386,6 +2398,7 @@ __device__ __forceinline__ void finalize_run(LsState* ls, const double* prox_par
         if (ls->iter >= ls->max_iter) ls->converged = 1;
     } else {
         ls->tau = tau * ls->beta;
+        if (probing) ls->probe_off = 1;
     }
     post_mailbox(mbox, ls);
 }
@@ -2393,15 +2406,16 @@ __device__ __forceinline__ void finalize_run(LsState* ls, const double* prox_par
 __global__ void __launch_bounds__(kThreads) k_finalize(LsState* ls, const double* prox_part,
                                                        int nprox, const double* norm_part,
                                                        int ntiles, double* trace,
-                                                       int32_t* trials_log, Mailbox* mbox) {
-    finalize_run(ls, prox_part, nprox, norm_part, ntiles, trace, trials_log, mbox);
+                                                       int32_t* trials_log, Mailbox* mbox,
+                                                       int probing) {
+    finalize_run(ls, prox_part, nprox, norm_part, ntiles, trace, trials_log, mbox, probing);
 }
 
 void launch_finalize(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
                      int ntiles, double* trace, int32_t* trials_log, Mailbox* mbox,
-                     hipStream_t st) {
+                     int probing, hipStream_t st) {
     k_finalize<<<1, kThreads, 0, st>>>(ls, prox_part, nprox, norm_part, ntiles, trace,
-                                       trials_log, mbox);
+                                       trials_log, mbox, probing);
 }
 
 // Probe of a trial: the fused trial kernel ran on M tile 0 only (the first kFBM samples),
@@ -2419,7 +2433,7 @@ __global__ void __launch_bounds__(kThreads) k_probe_decide(LsState* ls, const do
                                                            int nprox, const double* norm_part,
                                                            int tilesN, int tilesM, int nparts,
                                                            Mailbox* mbox) {
-    if (ls->done || ls->converged) return;
+    if (ls->done || ls->converged || ls->probe_off) return;  // (no probe ran)
     double pv[6];
     sum_partials<6>(prox_part, nprox, kPartCols, pv);
     double nv[1] = {0.0};
@@ -2908,7 +2922,7 @@ __global__ void __launch_bounds__(kThreads) k_prox_batch(const ProxArgs* __restr
 __global__ void __launch_bounds__(kThreads) k_finalize_batch(const FinArgs* __restrict__ batch) {
     const FinArgs f = batch[blockIdx.x];
     finalize_run(f.ls, f.prox_part, f.nprox, f.norm_part, f.ntiles, nullptr, f.trials_log,
-                 nullptr);
+                 nullptr, 0);
 }
 
 __global__ void __launch_bounds__(kThreads) k_fit_init_batch(const FinArgs* __restrict__ batch) {

@@ -92,7 +92,8 @@ def test_c2_bf16x3_deterministic(c2):
 
 
 def test_c2_probe_is_the_full_trial(c2):
-    """Three BF16x3 iterations with trials probed on the first 256 samples equal those that
+    """Three BF16x3 iterations with trials probed on the first 256 samples (and, after a
+    trial of an iteration fails the full test, the later ones unprobed) equal those that
     always run the whole product, bit for bit (checked by column-chunk sums of the FP32
     bit patterns and on sampled columns), with the same trial counts."""
     import torch
@@ -111,7 +112,9 @@ def test_c2_probe_is_the_full_trial(c2):
                                       ws=c2["ws"], omega_out=c2["om"], probe=probe)
         runs.append((st, tr.clone(), c2["om"][cols, :].clone(), bit_sums(c2["om"])))
     (sa, ta, ca, ha), (sb, tb, cb, hb) = runs
-    print(f"[c2] trials {sa['trials']} (probe) vs {sb['trials']}", flush=True)
+    print(f"[c2] trials {sa['trials']} (probe: {sa['probe_rejects']} rejected by the probe, "
+          f"{sa['unprobed_trials']} unprobed) vs {sb['trials']}", flush=True)
+    assert sb["probe_rejects"] == 0 and sb["unprobed_trials"] == 0
     assert sa["trials"] == sb["trials"] and torch.equal(ta, tb)
     assert torch.equal(ca, cb) and ha == hb
 

@@ -425,7 +425,8 @@ def test_fit_probe_is_the_full_trial(gpu_lib, dev, form):
     """n = 800, p = 8192: 4 M tiles of 256 samples, and 64 column blocks, too few to fill
     the CUs, so the product is split 4 ways along K (a split-K reduce per launch); every
     trial first runs on M tile 0 and is rejected there when that lower bound of
-    ||X Delta||^2 already fails the test.  The prox of every tile is the same FP32 arithmetic and the acceptance sums
+    ||X Delta||^2 already fails the test; after a trial fails the full test, the rest of
+    its iteration runs unprobed.  The prox of every tile is the same FP32 arithmetic and the acceptance sums
     are unchanged, so the fit equals the one that always runs the whole product bit for
     bit, with the same trial counts; BF16x3 also against the oracle's replay."""
     import torch
@@ -437,9 +438,11 @@ def test_fit_probe_is_the_full_trial(gpu_lib, dev, form):
     b, sb, tb = gpu_lib.accord_fit(X, 0.05, 12, precision=form, trace=True, probe=False)
     torch.cuda.synchronize()
     assert sa["trials"] == sb["trials"] and sa["trials"] > sa["iters"]
-    assert sb["probe_rejects"] == 0 and sa["probe_rejects"] <= sa["trials"] - sa["iters"]
+    assert sb["probe_rejects"] == 0 and sb["unprobed_trials"] == 0
+    assert sa["probe_rejects"] + sa["unprobed_trials"] <= sa["trials"]
+    assert sa["probe_rejects"] <= sa["trials"] - sa["iters"]
     print(f"[probe] {sa['probe_rejects']} of {sa['trials'] - sa['iters']} rejected trials "
-          f"settled by the probe", flush=True)
+          f"settled by the probe, {sa['unprobed_trials']} trials unprobed", flush=True)
     assert torch.equal(ta, tb) and torch.equal(a, b)
     if form == "bf16x3":
         taus = ta.cpu().numpy()[1:, 3]
