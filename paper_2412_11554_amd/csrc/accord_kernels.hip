@@ -4,15 +4,21 @@
 //                  128x128 tiles, XCD-aware tile order
 //   k_gemm_bf16w   256x256 bf16 GEMM (v_mfma_f32_32x32x16_bf16) on bf16 (hi) or
 //                  hi+lo split operands, 1 or 3 passes: the bf16 forms' gradient
-//   k_trial_fused  bf16 forms: prox (eq. 3.5) fused into the trial product
+//   k_gemm_fp8w    the same tile on MX-FP8 operands: the FP8 form's gradient
+//   k_trial_fused  bf16 forms: prox (eq. 3.5) fused into the trial product (k_trial_fused8:
+//                  FP8, k_trial_fused32: FP32), over an M range so that a trial can be
+//                  probed on its first 256 samples (k_probe_decide)
 //   FP32 uses of k_gemm_f32:
 //                    gradient  G  = X^T W / n              (Remark 3.1, two-step product)
 //                    trial     W+ = W + X Delta, ||X Delta||^2, ||W+||^2 (Alg. 1 test)
 //   k_splitk_reduce fixed-order sum of split-K partial tiles + trial epilogue
+//                  (k_splitk_reduce_f for the fused tiles)
 //   k_prox         fused closed-form prox (eq. 3.5) + FP64 line-search partial sums
 //   k_finalize     FP64 acceptance test of Alg. 1, step update, iteration record
 //   k_lz_*         Lanczos estimate of L = sigma_max(X^T X / n) (Sec. 3.2)
 //   copies / transposes into the padded operand layouts
+//   *_batch        the batched form (many problems per launch, tile orders batch_tile)
+//   k_support_*, k_reparam, k_prox_adjoint ...  steps after the fit, differentiation form
 //
 // All cross-workgroup reductions are two-stage (per-workgroup partials, then one
 // workgroup summing them in a fixed order), so results are bit-reproducible.
@@ -2426,9 +2432,8 @@ void launch_finalize(LsState* ls, const double* prox_part, int nprox, const doub
 // posted to the mailbox) and flagged, so that the launch over the remaining M tiles and
 // the acceptance test of this trial do nothing.  A trial at the floor tau <= 1/L, a fixed
 // step and non-finite sums always go on to the full test.  Norm rows of M tile 0 are
-// rows tile_n * tilesM (no split-K).
-// nparts: norm rows per tile (kFReduceParts after a split-K reduce: row part * tiles +
-// tile; 1 otherwise).
+// rows part * tiles + tile_n * tilesM, part < nparts (kFReduceParts after a split-K
+// reduce, else 1).  Nothing runs once the iteration has stopped probing.
 __global__ void __launch_bounds__(kThreads) k_probe_decide(LsState* ls, const double* prox_part,
                                                            int nprox, const double* norm_part,
                                                            int tilesN, int tilesM, int nparts,
