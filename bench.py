@@ -161,13 +161,15 @@ def _trial_plan(form, n, p):
             c = -(-(tiles * sp) // slots) / sp
             if c < cost * 0.9:
                 best, cost = sp, c
+    # the fused trial kernels have a compile-time variant that walks K-step lists (the
+    # refit's support); a fit runs the other ("false")
     if form == "fp32":
-        kern = "k_gemm_f32" if tm > 4 else "k_trial_fused32"
-        name = f"void {kern}<{1 if best == 1 else 2}>"
-    else:
-        kern = "k_trial_fused8" if form == "fp8" else f"k_trial_fused<{PASSES[form]},"
         epi = 1 if best == 1 else 2
-        name = f"void {kern}<{epi}>" if form == "fp8" else f"void {kern} {epi}>"
+        name = f"void k_gemm_f32<{epi}>" if tm > 4 else f"void k_trial_fused32<{epi}, false>"
+    else:
+        epi = 1 if best == 1 else 2
+        name = (f"void k_trial_fused8<{epi}, false>" if form == "fp8"
+                else f"void k_trial_fused<{PASSES[form]}, {epi}, false>")
     return {"name": name, "splits": best, "probe": probe, "tilesM": tm, "tilesN": tn,
             "grid": tiles * best, "probe_grid": tn * best, "rest_grid": (tm - 1) * tn * best,
             "reduce": f"void k_splitk_reduce_f<{best}>" if fused and best > 1 else None,

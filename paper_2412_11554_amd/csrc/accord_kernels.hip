@@ -1095,7 +1095,12 @@ __global__ void __launch_bounds__(kThreads) k_prox(ProxArgs a) {
 // problem's columns are padded to a multiple of 128 with zero columns, which produce
 // Delta = 0 and W+ = W there.  Only columns of the problem store Omega+ and count.
 // ---------------------------------------------------------------------------
-template <int EPI>
+// LIST: the K steps come from g.kstep_ptr / kstep_idx (a refit's support).  A compile-time
+// choice: with a runtime test on the list pointer the compiler loads list entries inside
+// the K loop, and since vector loads retire in order, their waits drain the operand
+// prefetch (measured at n = 1000, p = 1e5: the plain fit's BF16x1 trial launches 20-27 %
+// slower, BF16x3 7-8 %).
+template <int EPI, bool LIST = false>
 __device__ __forceinline__ void trial_fused32_tile(const GemmArgs& g, const ProxArgs& px,
                                                    int tile_m, int tile_n, int split, int jbase,
                                                    int ncols, double tau, double lam,
@@ -1109,7 +1114,7 @@ __device__ __forceinline__ void trial_fused32_tile(const GemmArgs& g, const Prox
     // every step (kstep_idx null), or the column block's list of steps that can hold a
     // nonzero Delta (a refit's support); the split keeps its K range either way, so the
     // partial sums group the same products as when every step is walked
-    const int32_t* kidx = g.kstep_idx;
+    const int32_t* kidx = LIST ? g.kstep_idx : nullptr;
     int s_begin, s_end;
     {
         const int ksteps = g.K / kBK32;
@@ -1287,12 +1292,12 @@ __device__ __forceinline__ void trial_fused32_tile(const GemmArgs& g, const Prox
     gemm_epilogue<EPI, true>(g, acc, tile_m, tile_n, split, red, nrm);
 }
 
-template <int EPI>
+template <int EPI, bool LIST>
 __global__ void __launch_bounds__(kThreads, 2) k_trial_fused32(GemmArgs g, ProxArgs px) {
     if (gemm_skip(g)) return;
     int tile_m, tile_n, split;
     decode_tile(g, tile_m, tile_n, split);
-    trial_fused32_tile<EPI>(g, px, tile_m, tile_n, split, 0, (int)px.p, px.ls->tau,
+    trial_fused32_tile<EPI, LIST>(g, px, tile_m, tile_n, split, 0, (int)px.p, px.ls->tau,
                             px.ls->lambda,
                             px.part + ((int64_t)tile_n * g.splits + split) * kPartCols,
                             g.norm_part + (int64_t)(tile_m + tile_n * g.tilesM) * kNormCols);
@@ -1300,11 +1305,14 @@ __global__ void __launch_bounds__(kThreads, 2) k_trial_fused32(GemmArgs g, ProxA
 
 void launch_trial_fused32(const GemmArgs& a, const ProxArgs& px, hipStream_t st) {
     const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
+    const bool list = a.kstep_idx != nullptr;
     if (a.splits > 1) {
-        k_trial_fused32<EPI_PARTIAL><<<blocks, kThreads, 0, st>>>(a, px);
+        if (list) k_trial_fused32<EPI_PARTIAL, true><<<blocks, kThreads, 0, st>>>(a, px);
+        else k_trial_fused32<EPI_PARTIAL, false><<<blocks, kThreads, 0, st>>>(a, px);
         launch_splitk_reduce_t<true>(a, st);
     } else {
-        k_trial_fused32<EPI_TRIAL><<<blocks, kThreads, 0, st>>>(a, px);
+        if (list) k_trial_fused32<EPI_TRIAL, true><<<blocks, kThreads, 0, st>>>(a, px);
+        else k_trial_fused32<EPI_TRIAL, false><<<blocks, kThreads, 0, st>>>(a, px);
     }
 }
 
@@ -1418,7 +1426,8 @@ void launch_trial_fused32(const GemmArgs& a, const ProxArgs& px, hipStream_t st)
 // v_mfma_f32_32x32x16_bf16; tile_m is the fastest tile index, so the M tiles of a
 // column block run together on one XCD and share Omega / G through its L2.
 // ---------------------------------------------------------------------------
-template <int PASSES, int EPI>
+// LIST: K steps from a list, as in trial_fused32_tile.
+template <int PASSES, int EPI, bool LIST>
 __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxArgs px) {
     if (gemm_skip(g)) return;
     constexpr int BK = 32;
@@ -1448,7 +1457,7 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
     // nonzero Delta (a refit's support)
     // (the split keeps its K range either way, so the FP32 partial sums group the same
     // products as when every step is walked)
-    const int32_t* kidx = g.kstep_idx;
+    const int32_t* kidx = LIST ? g.kstep_idx : nullptr;
     int s_begin, s_end;
     {
         const int ksteps = g.K / BK;
@@ -1744,17 +1753,19 @@ void launch_trial_fused(const GemmArgs& a, const ProxArgs& px, int prec, hipStre
     }
     const int mcnt = a.m_count > 0 ? a.m_count : a.tilesM;
     const unsigned blocks = (unsigned)((int64_t)mcnt * a.tilesN * a.splits);
+    const bool list = a.kstep_idx != nullptr;
+    const bool x3 = prec == PREC_BF16X3;
     if (a.splits > 1) {
-        if (prec == PREC_BF16X3)
-            k_trial_fused<3, EPI_PARTIAL><<<blocks, kWThreads, 0, st>>>(a, px);
-        else
-            k_trial_fused<1, EPI_PARTIAL><<<blocks, kWThreads, 0, st>>>(a, px);
+        if (list && x3) k_trial_fused<3, EPI_PARTIAL, true><<<blocks, kWThreads, 0, st>>>(a, px);
+        else if (list) k_trial_fused<1, EPI_PARTIAL, true><<<blocks, kWThreads, 0, st>>>(a, px);
+        else if (x3) k_trial_fused<3, EPI_PARTIAL, false><<<blocks, kWThreads, 0, st>>>(a, px);
+        else k_trial_fused<1, EPI_PARTIAL, false><<<blocks, kWThreads, 0, st>>>(a, px);
         launch_splitk_reduce_f(a, st);
     } else {
-        if (prec == PREC_BF16X3)
-            k_trial_fused<3, EPI_TRIAL><<<blocks, kWThreads, 0, st>>>(a, px);
-        else
-            k_trial_fused<1, EPI_TRIAL><<<blocks, kWThreads, 0, st>>>(a, px);
+        if (list && x3) k_trial_fused<3, EPI_TRIAL, true><<<blocks, kWThreads, 0, st>>>(a, px);
+        else if (list) k_trial_fused<1, EPI_TRIAL, true><<<blocks, kWThreads, 0, st>>>(a, px);
+        else if (x3) k_trial_fused<3, EPI_TRIAL, false><<<blocks, kWThreads, 0, st>>>(a, px);
+        else k_trial_fused<1, EPI_TRIAL, false><<<blocks, kWThreads, 0, st>>>(a, px);
     }
 }
 
@@ -2093,7 +2104,8 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_fp8w(GemmArgs g) {
         }                                                                                 \
     } while (0)
 
-template <int EPI>
+// LIST: K steps from a list, as in trial_fused32_tile.
+template <int EPI, bool LIST>
 __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused8(GemmArgs g, ProxArgs px) {
     if (gemm_skip(g)) return;
     __shared__ __attribute__((aligned(16))) uint8_t sA8[2][kFBM * kLDK8];
@@ -2116,7 +2128,7 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused8(GemmArgs g, ProxA
     const bool owner = store_owner || sums_owner;   // computes them
     const int m0 = tile_m * kFBM, n0 = tile_n * kFBN;
     // positions over the column block's K steps of 64 (all, or its list: see k_trial_fused)
-    const int32_t* kidx = g.kstep_idx;
+    const int32_t* kidx = LIST ? g.kstep_idx : nullptr;
     int s_begin, s_end;
     {
         const int ksteps = g.K / 64;
@@ -2286,11 +2298,14 @@ void launch_grad_fp8(const GemmArgs& a, hipStream_t st) {
 void launch_trial_fused8(const GemmArgs& a, const ProxArgs& px, hipStream_t st) {
     const int mcnt = a.m_count > 0 ? a.m_count : a.tilesM;
     const unsigned blocks = (unsigned)((int64_t)mcnt * a.tilesN * a.splits);
+    const bool list = a.kstep_idx != nullptr;
     if (a.splits > 1) {
-        k_trial_fused8<EPI_PARTIAL><<<blocks, kWThreads, 0, st>>>(a, px);
+        if (list) k_trial_fused8<EPI_PARTIAL, true><<<blocks, kWThreads, 0, st>>>(a, px);
+        else k_trial_fused8<EPI_PARTIAL, false><<<blocks, kWThreads, 0, st>>>(a, px);
         launch_splitk_reduce_f(a, st);
     } else {
-        k_trial_fused8<EPI_TRIAL><<<blocks, kWThreads, 0, st>>>(a, px);
+        if (list) k_trial_fused8<EPI_TRIAL, true><<<blocks, kWThreads, 0, st>>>(a, px);
+        else k_trial_fused8<EPI_TRIAL, false><<<blocks, kWThreads, 0, st>>>(a, px);
     }
 }
 
