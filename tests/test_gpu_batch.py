@@ -91,16 +91,18 @@ def test_batch_stop_rule_per_problem(gpu_lib):
 
 def test_batch_full_size_sampled(gpu_lib):
     """16 bootstrap subsamples (n in 100..400) x 32 penalties in [0.02, 0.5] at
-    p = 2000, 300 iterations, L by the Lanczos estimate: sampled problems and columns
-    against the oracle replaying their steps."""
+    p = 2000, 300 iterations, L by the Lanczos estimate: 34 problems (every subsample at
+    the smallest and the largest penalty, and two more) on 24 columns each against the
+    oracle replaying their steps."""
     w = datagen.workload("batch")
     print(f"batch: {len(w.xs)} x {len(w.lams)} problems, p={w.p}, {w.iters} iterations",
           flush=True)
     om, stats, tr = _run(gpu_lib, w, w.iters)
     assert all(s["iters"] == w.iters for s in stats)
-    cols = np.array([0, 1, 999, 1998, 1999])
+    cols = np.r_[np.arange(0, 2000, 100), [1, 999, 1998, 1999]]
     nlam = len(w.lams)
-    for k in (0, nlam - 1, 5 * nlam + 13, 15 * nlam + 31, 9 * nlam + 2):
+    probs = [b * nlam for b in range(len(w.xs))] + [b * nlam + nlam - 1 for b in range(len(w.xs))]
+    for k in probs + [5 * nlam + 13, 9 * nlam + 2]:
         b = k // nlam
         L = oracle.lipschitz(w.xs[b].astype(np.float64))
         assert L * (1 - 1e-3) <= stats[k]["lipschitz"] <= L * (1 + 1e-9)
