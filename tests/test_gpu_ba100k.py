@@ -24,7 +24,7 @@ TOL_MX = 1e-4
 
 
 @pytest.fixture(scope="module")
-def c2(gpu_lib, ba100k):
+def big(gpu_lib, ba100k):
     import torch
 
     from paper_2412_11554_amd import accord
@@ -46,35 +46,35 @@ def c2(gpu_lib, ba100k):
 
 
 @pytest.mark.parametrize("form", ["bf16x3", "fp32", "bf16x1"])
-def test_c2_sampled_columns(c2, form):
+def test_ba100k_sampled_columns(big, form):
     from paper_2412_11554_amd import accord
 
-    w = c2["w"]
+    w = big["w"]
     T = ITERS[form]
-    print(f"[c2] {form}: accord_fit n={w.n} p={w.p} iters={T}", flush=True)
-    om, st, tr = accord.accord_fit(c2["X"], w.lam, T, precision=form, trace=True,
-                                   ws=c2["ws"], omega_out=c2["om"])
-    _check_sampled(c2, form, om, st, tr)
+    print(f"[big] {form}: accord_fit n={w.n} p={w.p} iters={T}", flush=True)
+    om, st, tr = accord.accord_fit(big["X"], w.lam, T, precision=form, trace=True,
+                                   ws=big["ws"], omega_out=big["om"])
+    _check_sampled(big, form, om, st, tr)
 
 
-def test_c2_fp8_fixed_step(c2):
+def test_ba100k_fp8_fixed_step(big):
     """FP8: one fixed step (beta = 1, tau = 1/64) from the identity."""
     from paper_2412_11554_amd import accord
-    w = c2["w"]
-    print(f"[c2] fp8: accord_fit n={w.n} p={w.p} one fixed step", flush=True)
-    om, st, tr = accord.accord_fit(c2["X"], w.lam, 1, precision="fp8", trace=True,
-                                   tau0=1.0 / 64, beta=1.0, ws=c2["ws"], omega_out=c2["om"])
-    _check_sampled(c2, "fp8", om, st, tr)
+    w = big["w"]
+    print(f"[big] fp8: accord_fit n={w.n} p={w.p} one fixed step", flush=True)
+    om, st, tr = accord.accord_fit(big["X"], w.lam, 1, precision="fp8", trace=True,
+                                   tau0=1.0 / 64, beta=1.0, ws=big["ws"], omega_out=big["om"])
+    _check_sampled(big, "fp8", om, st, tr)
 
 
-def test_c2_bf16x3_deterministic(c2):
+def test_ba100k_bf16x3_deterministic(big):
     """Two 2-iteration BF16x3 fits at n = 1000, p = 1e5 give the same bits."""
     import torch
     from paper_2412_11554_amd import accord
-    w = c2["w"]
-    print(f"[c2] bf16x3 twice, 2 iterations, n={w.n} p={w.p}", flush=True)
-    _, sa, ta = accord.accord_fit(c2["X"], w.lam, 2, precision="bf16x3", trace=True,
-                                  ws=c2["ws"], omega_out=c2["om"])
+    w = big["w"]
+    print(f"[big] bf16x3 twice, 2 iterations, n={w.n} p={w.p}", flush=True)
+    _, sa, ta = accord.accord_fit(big["X"], w.lam, 2, precision="bf16x3", trace=True,
+                                  ws=big["ws"], omega_out=big["om"])
     def bit_sums(om):
         # int64 sums of the FP32 bit patterns, 5000 columns at a time (any changed bit
         # changes its chunk's sum unless differences cancel exactly)
@@ -82,23 +82,23 @@ def test_c2_bf16x3_deterministic(c2):
                 for r in range(0, om.shape[0], 5000)]
 
     cols = np.array([0, 777, 50000, 99999])
-    first = c2["om"][cols, :].clone()
-    h1 = bit_sums(c2["om"])
-    _, sb, tb = accord.accord_fit(c2["X"], w.lam, 2, precision="bf16x3", trace=True,
-                                  ws=c2["ws"], omega_out=c2["om"])
-    h2 = bit_sums(c2["om"])
-    assert torch.equal(first, c2["om"][cols, :]) and torch.equal(ta, tb)
+    first = big["om"][cols, :].clone()
+    h1 = bit_sums(big["om"])
+    _, sb, tb = accord.accord_fit(big["X"], w.lam, 2, precision="bf16x3", trace=True,
+                                  ws=big["ws"], omega_out=big["om"])
+    h2 = bit_sums(big["om"])
+    assert torch.equal(first, big["om"][cols, :]) and torch.equal(ta, tb)
     assert h1 == h2 and sa["f"] == sb["f"]
 
 
-def test_c2_probe_is_the_full_trial(c2):
+def test_ba100k_probe_is_the_full_trial(big):
     """Three BF16x3 iterations with trials probed on the first 256 samples (and, after a
     trial of an iteration fails the full test, the later ones unprobed) equal those that
     always run the whole product, bit for bit (checked by column-chunk sums of the FP32
     bit patterns and on sampled columns), with the same trial counts."""
     import torch
     from paper_2412_11554_amd import accord
-    w = c2["w"]
+    w = big["w"]
 
     def bit_sums(om):
         return [int(om[r:r + 5000].view(torch.int32).to(torch.int64).sum())
@@ -107,22 +107,22 @@ def test_c2_probe_is_the_full_trial(c2):
     cols = np.array([0, 777, 50000, 99999])
     runs = []
     for probe in (True, False):
-        print(f"[c2] bf16x3 3 iterations, probe {probe}", flush=True)
-        _, st, tr = accord.accord_fit(c2["X"], w.lam, 3, precision="bf16x3", trace=True,
-                                      ws=c2["ws"], omega_out=c2["om"], probe=probe)
-        runs.append((st, tr.clone(), c2["om"][cols, :].clone(), bit_sums(c2["om"])))
+        print(f"[big] bf16x3 3 iterations, probe {probe}", flush=True)
+        _, st, tr = accord.accord_fit(big["X"], w.lam, 3, precision="bf16x3", trace=True,
+                                      ws=big["ws"], omega_out=big["om"], probe=probe)
+        runs.append((st, tr.clone(), big["om"][cols, :].clone(), bit_sums(big["om"])))
     (sa, ta, ca, ha), (sb, tb, cb, hb) = runs
-    print(f"[c2] trials {sa['trials']} (probe: {sa['probe_rejects']} rejected by the probe, "
+    print(f"[big] trials {sa['trials']} (probe: {sa['probe_rejects']} rejected by the probe, "
           f"{sa['unprobed_trials']} unprobed) vs {sb['trials']}", flush=True)
     assert sb["probe_rejects"] == 0 and sb["unprobed_trials"] == 0
     assert sa["trials"] == sb["trials"] and torch.equal(ta, tb)
     assert torch.equal(ca, cb) and ha == hb
 
 
-def _check_sampled(c2, form, om, st, tr):
+def _check_sampled(big, form, om, st, tr):
     import oracle
     from oracle import mx_oracle
-    w = c2["w"]
+    w = big["w"]
     T = ITERS[form]
     assert st["iters"] == T
     trace = tr.cpu().numpy()
@@ -132,24 +132,24 @@ def _check_sampled(c2, form, om, st, tr):
     assert np.allclose(k, np.round(k)) and np.all(taus <= 1.0)
     # device Lanczos estimate: top Ritz value plus its residual bound, so never below
     # sigma_max beyond rounding, and within 1e-10 once the bound is met
-    assert st["lipschitz"] >= c2["L"] * (1 - 1e-13)
-    assert abs(st["lipschitz"] - c2["L"]) <= 1e-10 * c2["L"]
+    assert st["lipschitz"] >= big["L"] * (1 - 1e-13)
+    assert abs(st["lipschitz"] - big["L"]) <= 1e-10 * big["L"]
     f = trace[:, 0]
     assert np.all(np.isfinite(f))
     if form == "fp8":
         # (the FP8 form carries W + X q(Delta), not X Omega+, so its traced g is not
         # that of the iterate and need not decrease)
         assert np.all(taus == 1.0 / 64)
-        ref = mx_oracle.fit_fbs_mx(c2["x64"], w.lam, taus, columns=COLS)
+        ref = mx_oracle.fit_fbs_mx(big["x64"], w.lam, taus, columns=COLS)
     else:
         # the objective does not increase (sufficient decrease of the accepted steps),
         # up to the FP32 rounding of sums over 1e10 entries
         assert np.all(np.diff(f) <= 1e-5 * np.abs(f[:-1])), f
-        ref = oracle.fit_fbs(c2["x64"], w.lam, T, L=st["lipschitz"], tau_replay=taus,
+        ref = oracle.fit_fbs(big["x64"], w.lam, T, L=st["lipschitz"], tau_replay=taus,
                              columns=COLS)
     got = om[COLS, :].cpu().numpy().astype(np.float64).T
     err = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
-    print(f"[c2] {form}: rel err {err:.3e}, trials {st['trials']}, "
-          f"floor accepts {st['floor_accepts']}, L {st['lipschitz']:.6f} vs {c2['L']:.6f}",
+    print(f"[big] {form}: rel err {err:.3e}, trials {st['trials']}, "
+          f"floor accepts {st['floor_accepts']}, L {st['lipschitz']:.6f} vs {big['L']:.6f}",
           flush=True)
     assert err <= (TOL_MX if form == "fp8" else TOL[form]), err

@@ -56,7 +56,7 @@ def _replay(name, x64, lam, L, taus, cols):
 
     def progress(t):
         if t % 25 == 0:
-            print(f"[c2 300] {name}: oracle replay at iteration {t}/{len(taus)}", flush=True)
+            print(f"[big 300] {name}: oracle replay at iteration {t}/{len(taus)}", flush=True)
     return oracle.fit_fbs(x64, lam, len(taus), L=L, tau_replay=taus, columns=cols,
                           record=False, progress=progress).omega
 
@@ -95,10 +95,10 @@ def runs(gpu_lib, ba100k):
                 fs.append(trace[:st["iters"] + 1, 0])
                 stats.append(st)
                 L = st["lipschitz"]
-                print(f"[c2 300] {name}: {form} iterations {c + 1}..{c + m} done "
+                print(f"[big 300] {name}: {form} iterations {c + 1}..{c + m} done "
                       f"({st['trials']} trials), n={w.n} p={w.p}", flush=True)
         got = om[cols, :].cpu().numpy().astype(np.float64).T
-        print(f"[c2 300] {name}: done on the GPU, {sum(s['trials'] for s in stats)} trials; "
+        print(f"[big 300] {name}: done on the GPU, {sum(s['trials'] for s in stats)} trials; "
               f"replaying {len(taus)} steps on {len(cols)} columns on the host", flush=True)
         out[name] = {"got": got, "taus": np.asarray(taus), "f": fs, "stats": stats,
                      "ref": pool.submit(_replay, name, x64, w.lam, L, taus, cols)}
@@ -109,7 +109,7 @@ def runs(gpu_lib, ba100k):
 
 
 @pytest.mark.parametrize("name", list(RUNS))
-def test_c2_300_iterations(runs, ba100k, name):
+def test_ba100k_300_iterations(runs, ba100k, name):
     w = ba100k["w"]
     phases, cols, bar, flip_bar, flip_count_bar = RUNS[name]
     r = runs[name]
@@ -136,7 +136,7 @@ def test_c2_300_iterations(runs, ba100k, name):
     flips = off & ((got != 0) != (ref != 0))
     scale = np.abs(ref[off]).max()
     worst = float(np.maximum(np.abs(got), np.abs(ref))[flips].max()) if flips.any() else 0.0
-    print(f"[c2 300] {name}: rel err {err:.3e} on {len(cols)} columns after {len(taus)} "
+    print(f"[big 300] {name}: rel err {err:.3e} on {len(cols)} columns after {len(taus)} "
           f"iterations; off-diagonal nonzeros {int(nz_ref.sum())}, zero-state flips "
           f"{int(flips.sum())} (largest {worst:.2e}, scale {scale:.2e}); trials/iter "
           f"{sum(s['trials'] for s in r['stats']) / len(taus):.2f}", flush=True)
