@@ -213,7 +213,7 @@ def kernel_report(stats, form, n, p, traffic_workload):
     if avg:
         a = flops / (avg * 1e-3) / 1e12
         name = {"fp32": "k_gemm_f32<0>", "fp8": "k_gemm_fp8w<0>"}.get(
-            form, f"k_gemm_bf16w<{PASSES[form]}, 0>")
+            form, f"k_gemm_bf16pp<{PASSES[form]}>")
         out["grad_gemm"] = {"what": "G = X^T W / n", "kernels": [name], "launches": cnt,
                             "avg_ms": avg, "total_ms": ms, "bound": "mfma", "achieved": a,
                             "peak": peak, "unit": "TFLOP/s", "frac": a / peak,

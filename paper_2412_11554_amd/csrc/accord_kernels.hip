@@ -2,8 +2,9 @@
 //
 //   k_gemm_f32     FP32 MFMA (v_mfma_f32_16x16x4f32) GEMM, LDS double-buffered
 //                  128x128 tiles, XCD-aware tile order
-//   k_gemm_bf16w   256x256 bf16 GEMM (v_mfma_f32_32x32x16_bf16) on bf16 (hi) or
-//                  hi+lo split operands, 1 or 3 passes: the bf16 forms' gradient
+//   k_gemm_bf16pp  256x256 bf16 GEMM (v_mfma_f32_32x32x16_bf16) on bf16 (hi) or
+//                  hi+lo split operands, 1 or 3 passes, ping-pong schedule: the bf16
+//                  forms' gradient
 //   k_gemm_fp8w    the same tile on MX-FP8 operands: the FP8 form's gradient
 //   k_trial_fused  bf16 forms: prox (eq. 3.5) fused into the trial product (k_trial_fused8:
 //                  FP8, k_trial_fused32: FP32), over an M range so that a trial can be
@@ -543,7 +544,11 @@ __device__ __forceinline__ void gemm_f32_tile(const GemmArgs& g, int tile_m, int
         __syncthreads();
         int cur = 0;
         for (int s = s_begin; s < s_end; ++s) {
-            {   // unconditional prefetch (see k_gemm_bf16w)
+            {   // Unconditional prefetch (the last step re-reads its own rows into the idle
+                // buffer): a conditional load would be merged at a branch join, which forces
+                // a wait on it before the MFMAs below.  The scheduling barriers keep the
+                // loads ahead of the MFMAs and their LDS stores after them, so the load
+                // latency hides behind the whole MFMA block.
                 const int64_t ko = (int64_t)(s + 1 < s_end ? s + 1 : s) * kBK32;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -650,15 +655,29 @@ __device__ __forceinline__ void grad_epilogue_cols(const GemmArgs& g, const f16v
     }
 }
 
-template <int PASSES, int EPI>
-__global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16w(GemmArgs g) {
+// Gradient of the bf16 forms (G = X^T W / n on bf16 hi or hi + lo operands, 1 or 3
+// passes), with a ping-pong schedule.  Wave w computes rows (w / 4) 128 .. + 127 and
+// columns (w % 4) 64 .. + 63 of the 256 x 256 tile; the two halves of the workgroup
+// (waves 0-3: rows 0..127, waves 4-7: rows 128..255; one wave of each on every SIMD)
+// take turns.  Each K step has two phases separated by barriers: in the first, waves 0-3
+// run the step's MFMAs from LDS while waves 4-7 store the B operand of the next step
+// (loaded a step earlier) into the other stage and issue the loads of the step after; in
+// the second the roles swap (waves 4-7 multiply, waves 0-3 stage A).  So on every SIMD
+// one wave multiplies while the other moves data.  Every element is summed over K in a
+// fixed order (16-deep slices in K order; per slice hi*hi, hi*lo, lo*hi).  Measured at
+// n = 1000, p = 1e5 against the same tile with all eight waves staging and multiplying in
+// step (one barrier per K step; the same bits on every fit tried): BF16x3 60.6 against
+// 66.4 ms, BF16x1 27.4 against 28.6 ms.
+template <int PASSES>
+__global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16pp(GemmArgs g) {
     if (gemm_skip(g)) return;
     constexpr int BK = PASSES == 1 ? 64 : 32;
     constexpr int LDK = BK + 8;
     constexpr int H = PASSES == 1 ? 1 : 2;
     constexpr int CPR = BK / 8;
-    constexpr int ROWS = kWThreads / CPR;
-    constexpr int RPT = kWBM / ROWS;
+    constexpr int GT = kWThreads / 2;          // threads per half
+    constexpr int ROWS = GT / CPR;             // rows one pass of a half's threads covers
+    constexpr int RPT = kWBM / ROWS;           // passes per operand half
     __shared__ __attribute__((aligned(16))) uint16_t sA[2][H][kWBM * LDK];
     __shared__ __attribute__((aligned(16))) uint16_t sB[2][H][kWBN * LDK];
 
@@ -667,28 +686,45 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16w(GemmArgs g) {
     if (g.tile_occ && !g.tile_occ[tile_m + tile_n * g.tilesM]) return;  // a zero tile of C
     const int m0 = tile_m * kWBM, n0 = tile_n * kWBN;
     const int ksteps = g.K / BK;
-    const int s_begin = (int)((int64_t)ksteps * split / g.splits);
-    const int s_end = (int)((int64_t)ksteps * (split + 1) / g.splits);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lrow = tid / CPR, lcol = (tid % CPR) * 8;
-    // operand half h, row pass i -> flat index h * RPT + i
-    const uint16_t* pa[H * RPT];
-    const uint16_t* pb[H * RPT];
+    const int half = wave >> 2;                // 0: multiplies first, stages A; 1: stages B
+    const int gt = tid & (GT - 1);
+    const int lrow = gt / CPR, lcol = (gt % CPR) * 8;
+    // this half's operand (A for half 0, B for half 1): tile base and 32-bit byte offsets
+    // per row pass (rows past M / N re-read the last row; 2 x 256 rows x ld < 2^31 bytes)
+    const int64_t ld = half == 0 ? g.lda : g.ldb;
+    const int lim = half == 0 ? g.M - m0 : g.N - n0;
+    const char* const oph = (const char*)((half == 0 ? g.Ah + (int64_t)m0 * g.lda
+                                                     : g.Bh + (int64_t)n0 * g.ldb));
+    const char* const opl = H == 2 ? (const char*)((half == 0 ? g.Al + (int64_t)m0 * g.lda
+                                                              : g.Bl + (int64_t)n0 * g.ldb))
+                                   : oph;
+    uint32_t off[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-        int ra = m0 + lrow + ROWS * i;
-        ra = ra < g.M ? ra : g.M - 1;
-        int rb = n0 + lrow + ROWS * i;
-        rb = rb < g.N ? rb : g.N - 1;
-        pa[i] = g.Ah + (int64_t)ra * g.lda + lcol;
-        pb[i] = g.Bh + (int64_t)rb * g.ldb + lcol;
-        if (H == 2) {
-            pa[(H - 1) * RPT + i] = g.Al + (int64_t)ra * g.lda + lcol;
-            pb[(H - 1) * RPT + i] = g.Bl + (int64_t)rb * g.ldb + lcol;
-        }
+        int r = lrow + ROWS * i;
+        r = r < lim ? r : lim - 1;
+        off[i] = (uint32_t)(((int64_t)r * ld + lcol) * 2);
     }
-    u4 va[H * RPT], vb[H * RPT];
+    u4 v[H][RPT];
+    auto load_step = [&](int s) {
+        const int64_t kb = (int64_t)(s < ksteps ? s : ksteps - 1) * BK * 2;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            v[0][i] = *(const u4*)(oph + kb + off[i]);
+            if (H == 2) v[H - 1][i] = *(const u4*)(opl + kb + off[i]);
+        }
+    };
+    auto store_stage = [&](int st) {
+        uint16_t* base = half == 0 ? &sA[st][0][0] : &sB[st][0][0];
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                *(u4*)&base[h * (kWBM * LDK) + (lrow + ROWS * i) * LDK + lcol] = v[h][i];
+    };
+
     f16v acc[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -696,131 +732,79 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16w(GemmArgs g) {
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
     const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
     const int r32 = lane & 31, k8 = (lane >> 5) * 8;
-
-
-    if (s_begin < s_end) {
-        {
-            const int64_t ko = (int64_t)s_begin * BK;
+    auto mfma_step = [&](int cur) {
 #pragma unroll
-        for (int q = 0; q < H * RPT; ++q) {
-            va[q] = *(const u4*)(pa[q] + ko);
-            vb[q] = *(const u4*)(pb[q] + ko);
-        }
-        }
+        for (int kk = 0; kk < BK; kk += 16) {
+            bf8 ah[4], bh[2];
 #pragma unroll
-        for (int q = 0; q < H * RPT; ++q) {
-            const int off = (lrow + ROWS * (q % RPT)) * LDK + lcol;
-            *(u4*)&sA[0][q / RPT][off] = va[q];
-            *(u4*)&sB[0][q / RPT][off] = vb[q];
-        }
-        __syncthreads();
-        int cur = 0;
-        for (int s = s_begin; s < s_end; ++s) {
-            // Unconditional prefetch (the last step re-reads its own rows into the idle
-            // buffer): a conditional load would be merged at a branch join, which forces
-            // a wait on it before the MFMAs below.  The scheduling barriers keep the
-            // loads ahead of the MFMAs and their LDS stores after them, so the load
-            // latency hides behind the whole MFMA block.
-            {
-                const int64_t ko = (int64_t)(s + 1 < s_end ? s + 1 : s) * BK;
-#pragma unroll
-            for (int q = 0; q < H * RPT; ++q) {
-                va[q] = *(const u4*)(pa[q] + ko);
-                vb[q] = *(const u4*)(pb[q] + ko);
-            }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 16) {
-                bf8 ah[4], bh[2];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    ah[i] = *(const bf8*)&sA[cur][0][(wm + 32 * i + r32) * LDK + kk + k8];
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    bh[j] = *(const bf8*)&sB[cur][0][(wn + 32 * j + r32) * LDK + kk + k8];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j],
-                                                                            acc[i][j], 0, 0, 0);
-                if (PASSES == 3) {
-                    bf8 al[4], bl[2];
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        bl[j] = *(const bf8*)&sB[cur][H - 1][(wn + 32 * j + r32) * LDK + kk + k8];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int j = 0; j < 2; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                ah[i], bl[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        al[i] = *(const bf8*)&sA[cur][H - 1][(wm + 32 * i + r32) * LDK + kk + k8];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int j = 0; j < 2; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                al[i], bh[j], acc[i][j], 0, 0, 0);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int q = 0; q < H * RPT; ++q) {
-                const int off = (lrow + ROWS * (q % RPT)) * LDK + lcol;
-                *(u4*)&sA[cur ^ 1][q / RPT][off] = va[q];
-                *(u4*)&sB[cur ^ 1][q / RPT][off] = vb[q];
-            }
-            __syncthreads();
-            cur ^= 1;
-        }
-    }
-    __syncthreads();
-
-    const int tile = tile_m + tile_n * g.tilesM;
-    if (EPI == EPI_PARTIAL) {
-        f4* P = (f4*)(g.P + ((int64_t)split * g.tilesM * g.tilesN + tile) * (kWBM * kWBN));
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i)
+                ah[i] = *(const bf8*)&sA[cur][0][(wm + 32 * i + r32) * LDK + kk + k8];
 #pragma unroll
             for (int j = 0; j < 2; ++j)
+                bh[j] = *(const bf8*)&sB[cur][0][(wn + 32 * j + r32) * LDK + kk + k8];
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    P[((i * 2 + j) * 4 + q) * kWThreads + tid] =
-                        f4{acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2],
-                           acc[i][j][4 * q + 3]};
-        return;
-    }
-    double nv[2] = {0.0, 0.0};
-    if (EPI == EPI_GRAD) {
-        static_assert(sizeof(sA) >= kEpiFloats * sizeof(float), "epilogue regions live in sA");
-        grad_epilogue_cols<EPI>(g, acc, (float*)&sA[0][0][0], m0 + wm, n0 + wn, nv);
-        return;
-    }
-    const int mw = m0 + wm + 4 * (lane >> 5), nw = n0 + wn + (lane & 31);
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j],
+                                                                        0, 0, 0);
+            if (PASSES == 3) {
+                bf8 al[4], bl[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < 2; ++j)
+                    bl[j] = *(const bf8*)&sB[cur][H - 1][(wn + 32 * j + r32) * LDK + kk + k8];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                store_frag<EPI>(g,
-                                f4{acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2],
-                                   acc[i][j][4 * q + 3]},
-                                mw + 32 * i + 8 * q, nw + 32 * j, nv);
-    if (EPI == EPI_TRIAL) {
-        block_sum_in<2, kWThreads / 64>(nv, (double*)&sA[0][0][0]);
-        if (tid == 0) {
-            g.norm_part[(int64_t)tile * kNormCols + 0] = nv[0];
-            g.norm_part[(int64_t)tile * kNormCols + 1] = nv[1];
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j],
+                                                                            acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    al[i] = *(const bf8*)&sA[cur][H - 1][(wm + 32 * i + r32) * LDK + kk + k8];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j],
+                                                                            acc[i][j], 0, 0, 0);
+            }
         }
+    };
+
+    // prologue: stage 0 from both halves, then each half's loads of step 1
+    load_step(0);
+    store_stage(0);
+    load_step(1);
+    __syncthreads();
+    int cur = 0;
+    for (int s = 0; s < ksteps; ++s) {
+        // phase 1: half 0 multiplies stage cur; half 1 stages B of step s + 1 into the
+        // other stage (steps past the end re-store the last step: in bounds, unused) and
+        // loads B of step s + 2
+        if (half == 0) {
+            mfma_step(cur);
+        } else {
+            store_stage(cur ^ 1);
+            load_step(s + 2);
+        }
+        __syncthreads();
+        // phase 2: the roles swap
+        if (half == 1) {
+            mfma_step(cur);
+        } else {
+            store_stage(cur ^ 1);
+            load_step(s + 2);
+        }
+        __syncthreads();
+        cur ^= 1;
     }
+
+    double nv[2] = {0.0, 0.0};
+    static_assert(sizeof(sA) >= kEpiFloats * sizeof(float), "epilogue regions live in sA");
+    grad_epilogue_cols<EPI_GRAD>(g, acc, (float*)&sA[0][0][0], m0 + wm, n0 + wn, nv);
 }
 
 // Fixed-order sum of the split-K partial tiles, then the trial epilogue.  One
@@ -891,9 +875,9 @@ void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st) {
     if (prec != PREC_FP32) {
         // bf16 forms: gradient only (their trial products run in k_trial_fused)
         if (prec == PREC_BF16X3)
-            k_gemm_bf16w<3, EPI_GRAD><<<blocks, kWThreads, 0, st>>>(a);
+            k_gemm_bf16pp<3><<<blocks, kWThreads, 0, st>>>(a);
         else
-            k_gemm_bf16w<1, EPI_GRAD><<<blocks, kWThreads, 0, st>>>(a);
+            k_gemm_bf16pp<1><<<blocks, kWThreads, 0, st>>>(a);
         return;
     }
     if (epi == EPI_GRAD)
@@ -1572,7 +1556,7 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
     if (s_begin < s_end) {
         const int last = s_end - 1;
         // Loads past the range re-read the last step (unconditional prefetch, see
-        // k_gemm_bf16w).  The producer always runs (no branch between it and the
+        // gemm_f32_tile).  The producer always runs (no branch between it and the
         // MFMAs); past the range it fills the idle stage and neither counts nor stores.
         FUSED_LOAD_A(va0, KS(s_begin));
         FUSED_LOAD_OG(vo0, vg0, KS(s_begin));
@@ -1979,7 +1963,7 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_fp8w(GemmArgs g) {
         __syncthreads();
         int cur = 0;
         for (int s = s_begin; s < s_end; ++s) {
-            {   // unconditional prefetch (see k_gemm_bf16w)
+            {   // unconditional prefetch (see gemm_f32_tile)
                 const int sn = s + 1 < s_end ? s + 1 : s;
                 const int64_t ko = (int64_t)sn * 64;
                 va[0] = *(const u4*)(pa + ko);
@@ -2203,7 +2187,7 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused8(GemmArgs g, ProxA
         for (int s = s_begin; s < s_end; ++s) {
             const bool more = s + 1 < s_end;
             const int64_t sn = kidx ? kidx[more ? s + 1 : s] : (more ? s + 1 : s);
-            {   // unconditional prefetch (see k_gemm_bf16w)
+            {   // unconditional prefetch (see gemm_f32_tile)
                 const int64_t ko = sn * 64;
                 va[0] = *(const u4*)(pa + ko);
                 va[1] = *(const u4*)(pa + ko + 16);
