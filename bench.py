@@ -131,13 +131,16 @@ def _traffic_table(workload):
     return tab["bytes_per_launch"] if tab.get("kernel_sha256_16") == digest else {}
 
 
-def _trial_plan(form, n, p):
-    """The library's launch plan of one trial (from n and p, as the library derives it):
-    the kernel, the split-K count and whether trials are probed on the first 256 samples
-    (fused forms with >= 4 tiles of 256 samples; their split count minimises the rounds of
-    the probe and completion launches, otherwise 2 .. 8 when the tiles do not fill the
-    CUs).  Names as rocprofv3 reports them; EPI 1 = trial epilogue, 2 = split-K partials
-    (then a reduce kernel).  Used only to pick the profiled traffic rows."""
+def _trial_plan(form, n, p, tail_blocks=0, tail_splits=0):
+    """The library's launch plan of one trial (from n and p, as the library derives it,
+    and the split-K tail the fit reports): the kernels and grids of each launch, the
+    split-K count and whether trials are probed on the first 256 samples (fused forms
+    with >= 4 tiles of 256 samples; their split count minimises the rounds of the probe
+    and completion launches, otherwise 2 .. 8 when the tiles do not fill the CUs; with
+    one split, the column blocks past the last whole round of workgroups may run as a
+    separate launch split along K, then reduced).  Names as rocprofv3 reports them; EPI
+    1 = trial epilogue, 2 = split-K partials (then a reduce kernel).  Used only to pick
+    the profiled traffic rows."""
     n_pad, p_pad = -(-n // 64) * 64, -(-p // 64) * 64
     fused = form != "fp32"
     bm, bn, slots = (256, 128, 256) if fused else (128, 128, 512)
@@ -161,20 +164,32 @@ def _trial_plan(form, n, p):
             c = -(-(tiles * sp) // slots) / sp
             if c < cost * 0.9:
                 best, cost = sp, c
+
     # the fused trial kernels have a compile-time variant that walks K-step lists (the
     # refit's support); a fit runs the other ("false")
-    if form == "fp32":
-        epi = 1 if best == 1 else 2
-        name = f"void k_gemm_f32<{epi}>" if tm > 4 else f"void k_trial_fused32<{epi}, false>"
-    else:
-        epi = 1 if best == 1 else 2
-        name = (f"void k_trial_fused8<{epi}, false>" if form == "fp8"
+    def kname(epi):
+        if form == "fp32":
+            return f"void k_gemm_f32<{epi}>" if tm > 4 else f"void k_trial_fused32<{epi}, false>"
+        return (f"void k_trial_fused8<{epi}, false>" if form == "fp8"
                 else f"void k_trial_fused<{PASSES[form]}, {epi}, false>")
-    return {"name": name, "splits": best, "probe": probe, "tilesM": tm, "tilesN": tn,
-            "grid": tiles * best, "probe_grid": tn * best, "rest_grid": (tm - 1) * tn * best,
-            "reduce": f"void k_splitk_reduce_f<{best}>" if fused and best > 1 else None,
-            "probe_reduce_grid": tn * 2, "rest_reduce_grid": (tm - 1) * tn * 2,
-            "full_reduce_grid": tm * tn * 2}
+
+    def reduce(sp):
+        if form == "fp32":  # the fused FP32 trial streams its partials, the plain one not
+            return f"void k_splitk_reduce<{sp}, {'true' if tm <= 4 else 'false'}>"
+        return f"void k_splitk_reduce_f<{sp if sp in (2, 3, 4) else 0}>"
+
+    def launches(m):  # (kernel, grid) of the launches over m M tiles
+        if best > 1:
+            return [(kname(2), m * tn * best), (reduce(best), m * tn * 2)]
+        if fused and tail_splits > 1 and 0 < tail_blocks < tn:
+            return [(kname(1), m * (tn - tail_blocks)),
+                    (kname(2), m * tail_blocks * tail_splits), (reduce(tail_splits), m * tail_blocks * 2)]
+        return [(kname(1), m * tn)]
+
+    return {"splits": best, "probe": probe, "tilesM": tm, "tilesN": tn,
+            "tail_blocks": tail_blocks if best == 1 else 0,
+            "probe_launches": launches(1), "rest_launches": launches(tm - 1),
+            "whole_launches": launches(tm)}
 
 
 def kernel_report(stats, form, n, p, traffic_workload):
@@ -222,27 +237,27 @@ def kernel_report(stats, form, n, p, traffic_workload):
                             "traffic": measured(f"void {name}")}
     ms, cnt, avg = group("trial_gemm")
     if avg:
-        plan = _trial_plan(form, n, p)
+        plan = _trial_plan(form, n, p, stats[0].get("tail_blocks", 0),
+                           stats[0].get("tail_splits", 0))
         sep = group("prox")[1] > 0  # FP32 with a separate prox pass: plain trial GEMM
         trials = sum(s["trials"] for s in stats)
         rej = sum(s.get("probe_rejects", 0) for s in stats) / max(1, trials)
         unp = sum(s.get("unprobed_trials", 0) for s in stats) / max(1, trials)
+
+        def traffic_of(kind):  # measured bytes of one launch group, or None
+            got = [measured(k, g) for k, g in plan[kind + "_launches"]]
+            return sum(got) if got and None not in got else None
+
+        def labels(kind, tag):
+            return [f"{k[5:]}@{g}" + (f" ({tag})" if tag else "") for k, g in plan[kind + "_launches"]]
+
         if plan["probe"]:
             n0 = min(256, n)
             alg = 8.0 * p * p + (1.0 - rej) * 4.0 * p * p
             fl = 2.0 * (n0 + (1.0 - rej) * (n - n0)) * p * p
-            red = plan["reduce"]
-            names = [plan["name"] + " (probe)"] + ([red[5:] + " (probe)"] if red else []) + \
-                ["k_probe_decide", plan["name"] + " (rest)"] + \
-                ([red[5:] + " (rest)"] if red else []) + [plan["name"] + " (unprobed)"] + \
-                ([red[5:] + " (unprobed)"] if red else [])
-            tp, tr, tf = (measured(plan["name"], plan[k])
-                          for k in ("probe_grid", "rest_grid", "grid"))
-            if red and None not in (tp, tr, tf):
-                rp, rr, rf = (measured(red, plan[k]) for k in
-                              ("probe_reduce_grid", "rest_reduce_grid", "full_reduce_grid"))
-                tp, tr, tf = ((tp + rp, tr + rr, tf + rf) if None not in (rp, rr, rf)
-                              else (None, None, None))
+            names = labels("probe", "probe") + ["k_probe_decide"] + labels("rest", "rest") + \
+                labels("whole", "unprobed")
+            tp, tr, tf = traffic_of("probe"), traffic_of("rest"), traffic_of("whole")
             # probed trials pay the probe, the probed ones it did not reject the rest, and
             # the trials run unprobed (after a full-test rejection) the whole product
             if None in (tp, tr) or (unp > 0 and tf is None):
@@ -251,15 +266,8 @@ def kernel_report(stats, form, n, p, traffic_workload):
                 traf = (1.0 - unp) * tp + (1.0 - rej - unp) * tr + (unp * tf if unp > 0 else 0.0)
         else:
             alg, fl = 12.0 * p * p, flops
-            S = plan["splits"]
-            if form == "fp32":  # the fused FP32 trial streams its partials, the plain one not
-                reduce_ = (f"k_splitk_reduce<{S}, "
-                           f"{'true' if 'fused32' in plan['name'] else 'false'}>")
-            else:
-                reduce_ = f"k_splitk_reduce_f<{S}>"
-            names = [plan["name"]] + ([reduce_] if S > 1 else [])
-            got = [measured(k if k.startswith("void") else f"void {k}") for k in names]
-            traf = sum(got) if all(g is not None for g in got) else None
+            names = labels("whole", "")
+            traf = traffic_of("whole")
         a = fl / (avg * 1e-3) / 1e12
         gbs = alg / (avg * 1e-3) / 1e9
         t_hbm = alg / (PEAK_HBM_GBS * 1e9)

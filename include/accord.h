@@ -196,6 +196,10 @@ typedef struct {
     int32_t unprobed_trials;/* trials of a probed fit run without a probe: once a trial of
                                an iteration fails the full test, the later ones (at half
                                the step and less) run as one launch over all samples */
+    int32_t tail_blocks;    /* fused trial product: 128-column blocks run as a separate
+                               launch split along the contraction (the blocks past the
+                               last whole round of workgroups; 0: none) */
+    int32_t tail_splits;    /* its split count (0: none) */
 } accord_stats;
 
 /* Fills `prm` with defaults: lambda 0.1, tau0 1, beta 0.5, lipschitz 0 (estimate),

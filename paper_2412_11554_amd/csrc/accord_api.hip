@@ -59,6 +59,7 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // tile grid of one GEMM launch
 struct Geo {
     int tilesM, tilesN, splits;
+    int tail_n0, tail_splits;  // fused trial product: split-K tail (choose_tail_splits)
     int tiles() const { return tilesM * tilesN; }
 };
 
@@ -67,7 +68,8 @@ struct Geo {
 bool is_bf16(int prec) { return prec == PREC_BF16X1 || prec == PREC_BF16X3; }
 
 int norm_rows(const Geo& g, int prec) {
-    return (g.splits > 1 && prec != PREC_FP32) ? g.tiles() * kFReduceParts : g.tiles();
+    return ((g.splits > 1 || g.tail_splits > 1) && prec != PREC_FP32) ? g.tiles() * kFReduceParts
+                                                                       : g.tiles();
 }
 
 struct Plan {
@@ -149,6 +151,41 @@ int choose_probe_splits(int tilesM, int tilesN, int ksteps64, int slots) {
     return best;
 }
 
+// Split-K tail of the fused trial product.  Its workgroups all run the same K loop, one
+// per CU, so a launch takes whole rounds of slots workgroups: with tilesN = F + T column
+// blocks (F a multiple of slots, 0 < T < slots) the last T blocks add a round in which
+// most CUs idle.  Measured at n = 1000, p = 1e5 (782 blocks) in BF16x3: over 768 blocks
+// instead of 782 the probe took 19.1 instead of 25.2 ms, the rest of a trial 57.5
+// instead of 60.6 ms and the whole product 68.9 instead of 75.2 ms.  So the last T blocks
+// run as a launch of their own, split S ways along K and reduced, in every launch of the
+// product (probe, rest, whole; the same S, so a column block sums its products in the
+// same order whichever launch covers it).  S in {2, 4, 8, 16} minimises the tail's
+// rounds, ceil(m T S / slots) / S (1 + 0.03 (S - 1)), summed over the launches that
+// cover m = 1 (weighted 2: the probe runs for every probed trial), tilesM - 1 and tilesM
+// M tiles (the whole product only, without probes), with at least 8 K steps of 64 per
+// split; 0 (no tail launch) unless that beats the unsplit tail by 10%.
+int choose_tail_splits(int tilesM, int tilesN, int ksteps64, int slots, bool probe) {
+    const int T = tilesN % slots;
+    if (tilesN < slots || T == 0) return 0;
+    auto cost = [&](int S) {
+        auto part = [&](int m) {
+            return (double)cdiv((int64_t)m * T * S, slots) / S * (1.0 + 0.03 * (S - 1));
+        };
+        return probe ? 2.0 * part(1) + part(tilesM - 1) + part(tilesM) : part(tilesM);
+    };
+    int best = 0;
+    double best_cost = 0.9 * cost(1);
+    for (int S = 2; S <= 16; S *= 2) {
+        if (ksteps64 / S < 8) break;
+        const double c = cost(S);
+        if (c < best_cost) {
+            best = S;
+            best_cost = c;
+        }
+    }
+    return best;
+}
+
 Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     Plan P = {};
     P.n = n;
@@ -169,6 +206,11 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
                           ? choose_probe_splits(P.tp.tilesM, P.tp.tilesN, (int)(P.p_pad / kPad),
                                                 kWSlots)
                           : choose_splits(P.tp.tiles(), (int)(P.p_pad / kPad), kWSlots);
+        if (P.tp.splits == 1) {
+            P.tp.tail_splits = choose_tail_splits(P.tp.tilesM, P.tp.tilesN, (int)(P.p_pad / kPad),
+                                                  kWSlots, P.tp.tilesM >= 4);
+            P.tp.tail_n0 = P.tp.tail_splits > 1 ? P.tp.tilesN - P.tp.tilesN % kWSlots : 0;
+        }
     }
     P.nprox = prox_blocks(p * P.p_pad);
     // every form's fit runs the prox inside its trial kernel: one row of prox sums per
@@ -182,7 +224,7 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     // fails by more than the inverse of its share of the rows; with fewer M tiles the
     // probe is a large share of the product and cannot reject the near misses.
     P.probe = P.fused && P.tp.tilesM >= 4;
-    P.prox_rows = P.fused ? P.tp.tilesN * P.tp.splits
+    P.prox_rows = P.fused ? P.tp.tilesN * (P.tp.tail_splits > 1 ? P.tp.tail_splits : P.tp.splits)
                           : (P.fused32 ? P.t32.tilesN * P.t32.splits : P.nprox);
     const bool bf = is_bf16(prec);
     const bool f8 = prec == PREC_FP8;
@@ -191,6 +233,8 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
         std::max((size_t)(P.t32.splits > 1 ? P.t32.splits : 0) * P.t32.tiles() * kBM * kBN,
                  (size_t)(P.tp.splits > 1 ? P.tp.splits : 0) * P.tp.tiles() * kFBM * kFBN *
                      (P.fused ? 1 : 0));
+    const size_t tail_floats = (size_t)(P.tp.tail_splits > 1 ? P.tp.tail_splits : 0) *
+                               P.tp.tilesM * (P.tp.tilesN - P.tp.tail_n0) * kFBM * kFBN;
     const size_t xn = (size_t)(P.n_pad * P.p_pad);   // padded X elements
     const size_t wn = (size_t)(p * P.n_pad);         // W^T elements
     const size_t on = (size_t)(p * P.p_pad);         // p x p_pad elements
@@ -218,7 +262,7 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     for (int k = 0; k < 4; ++k) P.off_wsplit[k] = bump(cur, bf ? wn * sizeof(uint16_t) : 0);
     P.off_w8 = bump(cur, f8 ? wn : 0);
     P.off_w8s = bump(cur, f8 ? wn / 32 : 0);
-    P.off_split = bump(cur, split_floats * sizeof(float));
+    P.off_split = bump(cur, std::max(split_floats, tail_floats) * sizeof(float));
     P.off_om0 = bump(cur, onc * sizeof(float));
     P.end_grad = cur;
     P.off_g = bump(cur, onc * sizeof(float));
@@ -281,7 +325,9 @@ GemmArgs trial_args(const Plan& P, void* ws, int prec, const float* B32, const u
     a.vec_store = 1;
     a.alpha = 1.f;
     a.Wprev = Wprev;
-    a.P = geo.splits > 1 ? at<float>(ws, P.off_split) : nullptr;
+    a.tail_n0 = geo.tail_n0;
+    a.tail_splits = geo.tail_splits;
+    a.P = (geo.splits > 1 || geo.tail_splits > 1) ? at<float>(ws, P.off_split) : nullptr;
     a.norm_part = at<double>(ws, P.off_norm_part);
     a.ls = ls;
     a.pred = pred;
@@ -855,7 +901,9 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
                 tpb.probe_mode = 1;
                 launch_trial_fused(tpb, a, prec, st);
                 launch_probe_decide(ls, prox_part, P.prox_rows, norm_part, P.tp.tilesN,
-                                    P.tp.tilesM, P.tp.splits > 1 ? kFReduceParts : 1, mbox_dev,
+                                    P.tp.tilesM,
+                                    (P.tp.splits > 1 || P.tp.tail_splits > 1) ? kFReduceParts : 1,
+                                    mbox_dev,
                                     st);
                 GemmArgs tcp = ta;
                 tcp.m_first = 1;
@@ -950,6 +998,8 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
         stats->lz_steps = host.lz_steps;
         stats->probe_rejects = host.probe_rejects;
         stats->unprobed_trials = host.unprobed;
+        stats->tail_blocks = fused && P.tp.tail_splits > 1 ? P.tp.tilesN - P.tp.tail_n0 : 0;
+        stats->tail_splits = fused ? P.tp.tail_splits : 0;
         if (timing) {
             std::vector<int32_t> tl((size_t)(host.iter > 0 ? host.iter : 1), 0);
             if (host.iter > 0)

@@ -147,6 +147,18 @@ struct GemmArgs {
     int order;          // batched kernels: tile order code (batch_tile), 0 = default
     int probe_mode;     // trials of a probing fit: 0 always run; 1 only while the
                         // iteration probes (probe_off == 0); 2 only once it stopped
+    // fused trial kernels: the launch covers the column blocks n_first .. n_first +
+    // n_count - 1 (n_count 0: all tilesN) and numbers its split-K partial tiles within
+    // that range; the prox sums of (column block, split) go to row tile_n * part_stride +
+    // split (part_stride 0: splits), and a split-0 workgroup zeroes the rows of its
+    // column block that the launch's splits do not reach; zero_part1: the trial epilogue
+    // also writes a zero norm row at tiles + tile (the row a second reduce part fills
+    // for the split tiles of the same product)
+    int n_first, n_count, part_stride, zero_part1;
+    // fused trial product as launch_trial_fused splits it: the column blocks from
+    // tail_n0 on run as a separate launch split tail_splits ways along K, then reduced
+    // (tail_splits 0: one launch over every column block)
+    int tail_n0, tail_splits;
 };
 
 struct ProxArgs {

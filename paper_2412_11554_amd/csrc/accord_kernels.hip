@@ -1300,6 +1300,33 @@ void launch_trial_fused32(const GemmArgs& a, const ProxArgs& px, hipStream_t st)
     }
 }
 
+// Prox sums of a fused trial workgroup: row tile_n * stride + split (stride =
+// part_stride, or the launch's split count), and, from split 0, zero rows for the splits
+// of the column block that this launch does not run (a column block's rows are summed
+// whole, whichever launch covered it).
+__device__ inline void fused_sums_out(const GemmArgs& g, const ProxArgs& px, int tile_n,
+                                      int split, const double (&v)[6]) {
+    const int stride = g.part_stride > 0 ? g.part_stride : g.splits;
+    double* out = px.part + ((int64_t)tile_n * stride + split) * kPartCols;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) out[k] = v[k];
+    out[6] = 0.0;
+    out[7] = 0.0;
+    if (split == 0)
+        for (int s = g.splits; s < stride; ++s)
+#pragma unroll
+            for (int k = 0; k < kPartCols; ++k)
+                px.part[((int64_t)tile_n * stride + s) * kPartCols + k] = 0.0;
+}
+
+// Split-K partial tile of (tile_m, tile_n, split), numbered within the launch's column
+// blocks n_first .. n_first + ncnt - 1 (split-major, then the tile in column-major tile
+// order); k_splitk_reduce_f reads the same numbering.
+__device__ inline int64_t fused_partial_tile(const GemmArgs& g, int ncnt, int tile_m,
+                                             int tile_n, int split) {
+    return ((int64_t)split * ncnt + (tile_n - g.n_first)) * g.tilesM + tile_m;
+}
+
 // B-operand producer of k_trial_fused for stage `buf` holding K step `step`, written
 // without branches so that it shares one basic block with the MFMAs of the previous
 // stage and the scheduler can interleave the two: prox of the 2 x 4 staged Omega / G
@@ -1425,14 +1452,16 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
     const float tau_f = (float)tau, thr_f = (float)(tau * lam);
 
     // tile order: tile_m fastest, then tile_n, then split (XCD-contiguous ranges), over
-    // the launch's M tiles m_first .. m_first + m_count - 1
+    // the launch's M tiles m_first .. m_first + m_count - 1 and column blocks n_first ..
+    // n_first + n_count - 1
     const int nblk = gridDim.x, bid = blockIdx.x;
     const int xcd = bid & 7, local = bid >> 3, q8 = nblk >> 3, r8 = nblk & 7;
     const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + local;
     const int mcnt = g.m_count > 0 ? g.m_count : g.tilesM;
+    const int ncnt = g.n_count > 0 ? g.n_count : g.tilesN;
     const int tile_m = g.m_first + logical % mcnt;
-    const int tile_n = (logical / mcnt) % g.tilesN;
-    const int split = logical / (mcnt * g.tilesN);
+    const int tile_n = g.n_first + (logical / mcnt) % ncnt;
+    const int split = logical / (mcnt * ncnt);
     const bool owner = tile_m == g.store_m;         // stores Omega+
     const bool sums_owner = tile_m == g.sums_m;     // writes the prox sums
     const int m0 = tile_m * kFBM, n0 = tile_n * kFBN;
@@ -1604,16 +1633,10 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
     if (sums_owner) {
         double v[6] = {pacc.d2, pacc.dg, pacc.l1, pacc.logd, pacc.nnz, pacc.fro};
         block_sum_in<6, kWThreads / 64>(v, red);
-        if (tid == 0) {
-            double* out = px.part + ((int64_t)tile_n * g.splits + split) * kPartCols;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) out[k] = v[k];
-            out[6] = 0.0;
-            out[7] = 0.0;
-        }
+        if (tid == 0) fused_sums_out(g, px, tile_n, split, v);
     }
     if (EPI == EPI_PARTIAL) {
-        f4* P = (f4*)(g.P + ((int64_t)split * g.tilesM * g.tilesN + tile) * (kFBM * kFBN));
+        f4* P = (f4*)(g.P + fused_partial_tile(g, ncnt, tile_m, tile_n, split) * (kFBM * kFBN));
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -1641,6 +1664,11 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
     if (tid == 0) {
         g.norm_part[(int64_t)tile * kNormCols + 0] = nv[0];
         g.norm_part[(int64_t)tile * kNormCols + 1] = nv[1];
+        if (g.zero_part1) {
+            const int64_t row = (int64_t)g.tilesM * g.tilesN + tile;
+            g.norm_part[row * kNormCols + 0] = 0.0;
+            g.norm_part[row * kNormCols + 1] = 0.0;
+        }
     }
 }
 
@@ -1648,8 +1676,9 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused(GemmArgs g, ProxAr
 // p owning the rows 64 c + 32 p .. + 31 (c = 0..3) of the tile, norm row =
 // part * tiles + tile.  S > 0: the split count at compile time, so that a thread's
 // loads of one split are issued together (S = 0 takes it from g.splits).  Like the
-// trial launch it follows, it covers the M tiles m_first .. m_first + m_count - 1 (all
-// with m_count 0), and pred 3 skips it after a probe rejected the trial.
+// trial launch it follows, it covers the M tiles m_first .. m_first + m_count - 1 and the
+// column blocks n_first .. n_first + n_count - 1 (all with a count of 0), and pred 3
+// skips it after a probe rejected the trial.
 // The partial fragments are summed in the GEMM's thread -> fragment map (coalesced
 // reads, each sum over s = 0, 1, ... in order), then turned through LDS so that the
 // epilogue (store_frag) walks W column by column: 8 lanes cover 32 consecutive samples
@@ -1668,10 +1697,14 @@ __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_f(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) float sT[kFBN * LDR];
     const int tiles = g.tilesM * g.tilesN;
     const int mcnt = g.m_count > 0 ? g.m_count : g.tilesM;
-    const int in_launch = mcnt * g.tilesN;
+    const int ncnt = g.n_count > 0 ? g.n_count : g.tilesN;
+    const int in_launch = mcnt * ncnt;
     const int local = blockIdx.x % in_launch, part = blockIdx.x / in_launch;
-    const int tile_m = g.m_first + local % mcnt, tile_n = local / mcnt;
+    const int tile_m = g.m_first + local % mcnt, tile_n = g.n_first + local / mcnt;
     const int tile = tile_m + tile_n * g.tilesM;
+    // partial tiles of split s: s * in_split + ptile (fused_partial_tile's numbering)
+    const int64_t in_split = (int64_t)g.tilesM * ncnt;
+    const int64_t ptile = (int64_t)(tile_n - g.n_first) * g.tilesM + tile_m;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int PER = 16 / kFReduceParts;
     f4 v[PER];
@@ -1680,13 +1713,13 @@ __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_f(GemmArgs g) {
     if (S > 0) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kFBM * kFBN));
+            const f4* P = (const f4*)(g.P + (s * in_split + ptile) * (kFBM * kFBN));
 #pragma unroll
             for (int u = 0; u < PER; ++u) v[u] += ld_stream(&P[(part * PER + u) * kWThreads + tid]);
         }
     } else {
         for (int s = 0; s < g.splits; ++s) {
-            const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kFBM * kFBN));
+            const f4* P = (const f4*)(g.P + (s * in_split + ptile) * (kFBM * kFBN));
 #pragma unroll
             for (int u = 0; u < PER; ++u) v[u] += ld_stream(&P[(part * PER + u) * kWThreads + tid]);
         }
@@ -1721,7 +1754,8 @@ __global__ void __launch_bounds__(kWThreads) k_splitk_reduce_f(GemmArgs g) {
 
 void launch_splitk_reduce_f(const GemmArgs& a, hipStream_t st) {
     const int mcnt = a.m_count > 0 ? a.m_count : a.tilesM;
-    const unsigned blocks = (unsigned)(mcnt * a.tilesN * kFReduceParts);
+    const int ncnt = a.n_count > 0 ? a.n_count : a.tilesN;
+    const unsigned blocks = (unsigned)(mcnt * ncnt * kFReduceParts);
     switch (a.splits) {
         case 2: k_splitk_reduce_f<2><<<blocks, kWThreads, 0, st>>>(a); break;
         case 3: k_splitk_reduce_f<3><<<blocks, kWThreads, 0, st>>>(a); break;
@@ -1731,12 +1765,31 @@ void launch_splitk_reduce_f(const GemmArgs& a, hipStream_t st) {
 }
 
 void launch_trial_fused(const GemmArgs& a, const ProxArgs& px, int prec, hipStream_t st) {
+    if (a.splits == 1 && a.tail_splits > 1 && a.tail_n0 > 0 && a.tail_n0 < a.tilesN) {
+        // the column blocks before tail_n0 unsplit, then the tail split along K (and its
+        // reduce); each column block keeps its split count in every launch of the product
+        GemmArgs f = a, t = a;
+        f.tail_splits = t.tail_splits = 0;
+        f.n_first = 0;
+        f.n_count = a.tail_n0;
+        f.part_stride = a.tail_splits;
+        f.zero_part1 = 1;
+        t.n_first = a.tail_n0;
+        t.n_count = a.tilesN - a.tail_n0;
+        t.splits = a.tail_splits;
+        t.part_stride = a.tail_splits;
+        t.zero_part1 = 0;
+        launch_trial_fused(f, px, prec, st);
+        launch_trial_fused(t, px, prec, st);
+        return;
+    }
     if (prec == PREC_FP8) {
         launch_trial_fused8(a, px, st);
         return;
     }
     const int mcnt = a.m_count > 0 ? a.m_count : a.tilesM;
-    const unsigned blocks = (unsigned)((int64_t)mcnt * a.tilesN * a.splits);
+    const int ncnt = a.n_count > 0 ? a.n_count : a.tilesN;
+    const unsigned blocks = (unsigned)((int64_t)mcnt * ncnt * a.splits);
     const bool list = a.kstep_idx != nullptr;
     const bool x3 = prec == PREC_BF16X3;
     if (a.splits > 1) {
@@ -2104,9 +2157,10 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused8(GemmArgs g, ProxA
     const int xcd = bid & 7, local = bid >> 3, q8 = nblk >> 3, r8 = nblk & 7;
     const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + local;
     const int mcnt = g.m_count > 0 ? g.m_count : g.tilesM;
+    const int ncnt = g.n_count > 0 ? g.n_count : g.tilesN;
     const int tile_m = g.m_first + logical % mcnt;
-    const int tile_n = (logical / mcnt) % g.tilesN;
-    const int split = logical / (mcnt * g.tilesN);
+    const int tile_n = g.n_first + (logical / mcnt) % ncnt;
+    const int split = logical / (mcnt * ncnt);
     const bool store_owner = tile_m == g.store_m;   // stores Omega+
     const bool sums_owner = tile_m == g.sums_m;     // writes the prox sums
     const bool owner = store_owner || sums_owner;   // computes them
@@ -2234,16 +2288,10 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused8(GemmArgs g, ProxA
     if (sums_owner) {
         double v[6] = {pacc.d2, pacc.dg, pacc.l1, pacc.logd, pacc.nnz, pacc.fro};
         block_sum_in<6, kWThreads / 64>(v, red);
-        if (tid == 0) {
-            double* out = px.part + ((int64_t)tile_n * g.splits + split) * kPartCols;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) out[k] = v[k];
-            out[6] = 0.0;
-            out[7] = 0.0;
-        }
+        if (tid == 0) fused_sums_out(g, px, tile_n, split, v);
     }
     if (EPI == EPI_PARTIAL) {
-        f4* P = (f4*)(g.P + ((int64_t)split * g.tilesM * g.tilesN + tile) * (kFBM * kFBN));
+        f4* P = (f4*)(g.P + fused_partial_tile(g, ncnt, tile_m, tile_n, split) * (kFBM * kFBN));
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -2271,6 +2319,11 @@ __global__ void __launch_bounds__(kWThreads, 1) k_trial_fused8(GemmArgs g, ProxA
     if (tid == 0) {
         g.norm_part[(int64_t)tile * kNormCols + 0] = nv[0];
         g.norm_part[(int64_t)tile * kNormCols + 1] = nv[1];
+        if (g.zero_part1) {
+            const int64_t row = (int64_t)g.tilesM * g.tilesN + tile;
+            g.norm_part[row * kNormCols + 0] = 0.0;
+            g.norm_part[row * kNormCols + 1] = 0.0;
+        }
     }
 }
 
@@ -2281,7 +2334,8 @@ void launch_grad_fp8(const GemmArgs& a, hipStream_t st) {
 
 void launch_trial_fused8(const GemmArgs& a, const ProxArgs& px, hipStream_t st) {
     const int mcnt = a.m_count > 0 ? a.m_count : a.tilesM;
-    const unsigned blocks = (unsigned)((int64_t)mcnt * a.tilesN * a.splits);
+    const int ncnt = a.n_count > 0 ? a.n_count : a.tilesN;
+    const unsigned blocks = (unsigned)((int64_t)mcnt * ncnt * a.splits);
     const bool list = a.kstep_idx != nullptr;
     if (a.splits > 1) {
         if (list) k_trial_fused8<EPI_PARTIAL, true><<<blocks, kWThreads, 0, st>>>(a, px);

@@ -496,6 +496,57 @@ def test_fit_probe_is_the_full_trial(gpu_lib, dev, form):
         assert rel <= 1e-4, rel
 
 
+@pytest.mark.parametrize("form", ["bf16x3", "bf16x1", "fp8"])
+def test_fit_split_k_tail(gpu_lib, dev, form):
+    """n = 800, p = 33000: 258 column blocks of 128, one more than a whole round of
+    workgroups (256) and 2 over, so the last 2 blocks run as a launch of their own split
+    16 ways along K with a reduce, in the probe, in the rest and in the unprobed launches
+    alike.  Probed and unprobed fits give the same bits; BF16x3 against the oracle's replay
+    on columns of both parts (the last two in the tail)."""
+    import torch
+    w = datagen.small_random_problem(800, 33000, seed=37, lam=0.05)
+    X = _t(w.X, dev)
+    print(f"[tail] {form} n=800 p=33000 6 iterations, probe on and off", flush=True)
+    a, sa, ta = gpu_lib.accord_fit(X, 0.05, 6, precision=form, trace=True, probe=True)
+    a = a.clone()
+    assert sa["tail_blocks"] == 2 and sa["tail_splits"] == 16, (sa["tail_blocks"], sa["tail_splits"])
+    b, sb, tb = gpu_lib.accord_fit(X, 0.05, 6, precision=form, trace=True, probe=False)
+    torch.cuda.synchronize()
+    assert sa["trials"] == sb["trials"] and sa["trials"] > sa["iters"]
+    print(f"[tail] {sa['trials']} trials, {sa['probe_rejects']} probe rejections, "
+          f"{sa['unprobed_trials']} unprobed", flush=True)
+    assert torch.equal(ta, tb) and torch.equal(a, b)
+    if form == "bf16x3":
+        taus = ta.cpu().numpy()[1:, 3]
+        cols = np.array([0, 1, 20000, 32767, 32768, 32999])
+        ref = oracle.fit_fbs(w.X.astype(np.float64), 0.05, 6, L=sa["lipschitz"],
+                             tau_replay=taus, columns=cols)
+        got = a.cpu().numpy()[cols, :].astype(np.float64).T
+        rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
+        print(f"[tail] bf16x3 vs oracle replay: {rel:.2e}", flush=True)
+        assert rel <= 1e-4, rel
+    # The last trace row's objective pieces come from the FP64 sums of every column block
+    # (16 partial rows per tail block, zero rows for the others) and of the reduce parts;
+    # against plain FP64 PyTorch on the returned iterate (too large for the oracle here):
+    # h and the nonzero count from the same FP32 entries (the kernels add |entries| in
+    # FP32 over 8 at a time before the FP64 sum, so lambda ||Omega||_1 is good to
+    # 8 u32 of itself), g from the carried W (the form's rounding).
+    om = a.double()  # row j = column j of Omega
+    g_ref = float((X.double() @ om.T).square().sum()) / (2 * 800)
+    dg = torch.diagonal(om)
+    l1_ref = float(om.abs().sum())
+    logd_ref = float(torch.log(dg).sum())
+    h_ref = -logd_ref + 0.05 * l1_ref
+    nnz_ref = int((om != 0).sum() - (dg != 0).sum())
+    last = tb.cpu().numpy()[sa["iters"]]
+    print(f"[tail] g {last[1]:.9e} / {g_ref:.9e}, h {last[2]:.12e} / {h_ref:.12e}, "
+          f"nnz {int(last[7])} / {nnz_ref}", flush=True)
+    assert int(last[7]) == nnz_ref
+    assert abs(last[2] - h_ref) <= 8 * U32 * 0.05 * l1_ref + 1e-12 * abs(logd_ref)
+    assert abs(last[1] - g_ref) <= {"bf16x3": 1e-5, "bf16x1": 5e-3, "fp8": 3e-2}[form] * g_ref
+    del om
+
+
 def test_fit_errors(gpu_lib, dev):
     import torch
     w = datagen.small_random_problem(20, 30, seed=5)
