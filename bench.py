@@ -187,6 +187,7 @@ def _trial_plan(form, n, p, tail_blocks=0, tail_splits=0):
         return [(kname(1), m * tn)]
 
     return {"splits": best, "probe": probe, "tilesM": tm, "tilesN": tn,
+            "staged": probe and tn * best >= slots,
             "tail_blocks": tail_blocks if best == 1 else 0,
             "probe_launches": launches(1), "rest_launches": launches(tm - 1),
             "whole_launches": launches(tm)}
@@ -251,7 +252,22 @@ def kernel_report(stats, form, n, p, traffic_workload):
         def labels(kind, tag):
             return [f"{k[5:]}@{g}" + (f" ({tag})" if tag else "") for k, g in plan[kind + "_launches"]]
 
-        if plan["probe"]:
+        if plan["probe"] and plan["staged"]:
+            # trials tested after each M tile of 256 samples: the rejected ones ran
+            # probe_mtiles M tiles in all, the others every M tile (one launch each, or
+            # one launch over all of them when run unprobed)
+            tm = plan["tilesM"]
+            mt = sum(s.get("probe_mtiles", 0) for s in stats) / max(1, trials)
+            alg = 8.0 * p * p + (1.0 - rej) * 4.0 * p * p
+            fl = 2.0 * (256.0 * mt + (1.0 - rej) * n) * p * p
+            names = labels("probe", "M tile") + ["k_probe_decide"] + labels("whole", "unprobed")
+            tp, tf = traffic_of("probe"), traffic_of("whole")
+            staged = mt + (1.0 - rej - unp) * tm  # one-M-tile launches per trial
+            if tp is None or (unp > 0 and tf is None):
+                traf = None
+            else:
+                traf = staged * tp + (unp * tf if unp > 0 else 0.0)
+        elif plan["probe"]:
             n0 = min(256, n)
             alg = 8.0 * p * p + (1.0 - rej) * 4.0 * p * p
             fl = 2.0 * (n0 + (1.0 - rej) * (n - n0)) * p * p
@@ -355,6 +371,8 @@ def run_form(form, X, w, iters, ws, om, steps, warmup, check, warm_tau=False, ca
                                      max(1, sum(s["iters"] for s in stats)),
            "unprobed_trials_per_iter": sum(s["unprobed_trials"] for s in stats) /
                                        max(1, sum(s["iters"] for s in stats)),
+           "rejected_trial_mtiles": sum(s["probe_mtiles"] for s in stats) /
+                                    max(1, sum(s["probe_rejects"] for s in stats)),
            "lipschitz": stats[-1]["lipschitz"], "lz_steps": stats[0]["lz_steps"] if not carry else None,
            "kernels": kernel_report(stats, form, w.n, w.p, traffic_workload)}
     if carry:

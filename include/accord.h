@@ -147,11 +147,14 @@ typedef struct {
                            sum, so when it alone fails Alg. 1's test the trial is rejected
                            without the rest of the product (the same decision, since every
                            term is a square); otherwise the product is completed and tested
-                           as usual.  Once a trial of an iteration has failed the full test,
-                           the iteration's later trials (whose test ratio is about half and
-                           below what the probe can reject) run without a probe.  0 = always
-                           the whole product.  Same iterates either way, up to FP64 rounding
-                           of the sums at a tie. */
+                           as usual.  When one tile of 256 samples fills the GPU (p of about
+                           32768 and more, or a split product) the rest also goes one tile
+                           at a time, with the same partial test after each.  Once a trial
+                           of an iteration has failed the full test, or a partial test
+                           over two thirds of the tiles or more, the iteration's later
+                           trials (whose test ratio is about half and likely to pass) run
+                           without partial tests.  0 = always the whole product.  Same
+                           iterates either way, up to FP64 rounding of the sums at a tie. */
     int32_t support_skip; /* accord_refit: 1 (the default of accord_default_params) = the
                            trial products walk only the 32-row K steps of each 128-column
                            block that hold support entries, and the gradient skips its tiles
@@ -192,10 +195,14 @@ typedef struct {
     double log_det_d;       /* sum_j log Omega_jj at the result (log det of the diagonal) */
     double l1;              /* ||Omega||_1 at the result (all entries) */
     int32_t lz_steps;       /* Lanczos steps of the device estimate of L (0 if L was given) */
-    int32_t probe_rejects;  /* trials rejected from their first 256 samples (params.probe) */
+    int32_t probe_rejects;  /* trials rejected by a partial test over their first tiles of
+                               256 samples (params.probe) */
     int32_t unprobed_trials;/* trials of a probed fit run without a probe: once a trial of
-                               an iteration fails the full test, the later ones (at half
-                               the step and less) run as one launch over all samples */
+                               an iteration fails the full test (or a late partial test), the
+                               later ones (at half the step and less) run as one launch over
+                               all samples */
+    int32_t probe_mtiles;   /* tiles of 256 samples that the trials rejected by a partial
+                               test had multiplied (params.probe) */
     int32_t tail_blocks;    /* fused trial product: 128-column blocks run as a separate
                                launch split along the contraction (the blocks past the
                                last whole round of workgroups; 0: none) */

@@ -54,7 +54,8 @@ class accord_stats(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("log_det_d", ctypes.c_double),
                 ("l1", ctypes.c_double), ("lz_steps", ctypes.c_int32),
                 ("probe_rejects", ctypes.c_int32), ("unprobed_trials", ctypes.c_int32),
-                ("tail_blocks", ctypes.c_int32), ("tail_splits", ctypes.c_int32)]
+                ("probe_mtiles", ctypes.c_int32), ("tail_blocks", ctypes.c_int32),
+                ("tail_splits", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

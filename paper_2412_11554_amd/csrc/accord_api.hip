@@ -83,8 +83,10 @@ struct Plan {
     int fused;      // bf16 and FP8 forms: the fused trial kernel's 256 x 128 geometry
     int fused32;    // FP32 form: prox fused into the 128 x 128 FP32 trial tile (else a
                     // separate prox pass writes Delta for the plain FP32 GEMM)
-    int probe;      // fused forms with >= 4 M tiles and no split-K: a trial can be
-                    // rejected from its first M tile (params.probe)
+    int probe;      // fused forms with >= 4 M tiles: a trial can be rejected from its
+                    // first M tile (params.probe)
+    int staged;     // probing, and one M tile's launch fills the CUs: the other M tiles
+                    // run one launch each, with a partial test after each
     int prox_rows;  // FP64 prox partial rows left per trial
     int nprox;
     size_t off_ls, off_prox_part, off_norm_part, off_lz,
@@ -224,6 +226,12 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     // fails by more than the inverse of its share of the rows; with fewer M tiles the
     // probe is a large share of the product and cannot reject the near misses.
     P.probe = P.fused && P.tp.tilesM >= 4;
+    // Staged partial tests: after M tile 0 the trial goes on one M tile at a time, with the
+    // test of the lower bound after each, while one M tile's launch fills the CUs (at
+    // n = 1000, p = 1e5 a launch over one M tile took 19.3 ms and one over three 58.2 ms:
+    // the same time per M tile).  A trial whose ratio lies between 2 and 4 is then rejected
+    // after two M tiles instead of after the whole product.
+    P.staged = P.probe && ((int64_t)P.tp.tilesN * P.tp.splits >= kWSlots);
     P.prox_rows = P.fused ? P.tp.tilesN * (P.tp.tail_splits > 1 ? P.tp.tail_splits : P.tp.splits)
                           : (P.fused32 ? P.t32.tilesN * P.t32.splits : P.nprox);
     const bool bf = is_bf16(prec);
@@ -889,10 +897,14 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
             if (tim) { lt.a = pool.get(); lt.b = pool.get(); HIP_TRY(hipEventRecord(lt.a, st)); }
             if (probing) {
                 // probe: M tile 0 with the prox sums, no Omega+ store; then the test of
-                // its lower bound; then (unless rejected) the other M tiles, the first of
-                // which stores Omega+.  Once a trial of the iteration has failed the full
-                // test, these three are skipped and the last launch runs the whole
-                // product instead (see finalize_run).
+                // its lower bound; then (unless rejected) the other M tiles: staged, one
+                // launch each with the test of the lower bound after each but the last
+                // (whose launch stores Omega+), else one launch whose first M tile stores
+                // Omega+.  Once the iteration has stopped probing (see k_probe_decide and
+                // finalize_run) these are skipped and the last launch runs the whole
+                // product instead; a trial rejected by a partial test skips that too.
+                const int nparts = (P.tp.splits > 1 || P.tp.tail_splits > 1) ? kFReduceParts : 1;
+                const int tm = P.tp.tilesM;
                 GemmArgs tpb = ta;
                 tpb.m_first = 0;
                 tpb.m_count = 1;
@@ -900,20 +912,34 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
                 tpb.sums_m = 0;
                 tpb.probe_mode = 1;
                 launch_trial_fused(tpb, a, prec, st);
-                launch_probe_decide(ls, prox_part, P.prox_rows, norm_part, P.tp.tilesN,
-                                    P.tp.tilesM,
-                                    (P.tp.splits > 1 || P.tp.tail_splits > 1) ? kFReduceParts : 1,
-                                    mbox_dev,
-                                    st);
-                GemmArgs tcp = ta;
-                tcp.m_first = 1;
-                tcp.m_count = P.tp.tilesM - 1;
-                tcp.store_m = 1;
-                tcp.sums_m = -1;
-                tcp.pred = 3;
-                tcp.probe_mode = 1;
-                launch_trial_fused(tcp, a, prec, st);
+                launch_probe_decide(ls, prox_part, P.prox_rows, norm_part, P.tp.tilesN, tm,
+                                    nparts, 1, mbox_dev, st);
+                if (P.staged) {
+                    for (int m = 1; m < tm; ++m) {
+                        GemmArgs ts = ta;
+                        ts.m_first = m;
+                        ts.m_count = 1;
+                        ts.store_m = tm - 1;
+                        ts.sums_m = -1;
+                        ts.pred = 3;
+                        ts.probe_mode = 1;
+                        launch_trial_fused(ts, a, prec, st);
+                        if (m + 1 < tm)
+                            launch_probe_decide(ls, prox_part, P.prox_rows, norm_part,
+                                                P.tp.tilesN, tm, nparts, m + 1, mbox_dev, st);
+                    }
+                } else {
+                    GemmArgs tcp = ta;
+                    tcp.m_first = 1;
+                    tcp.m_count = tm - 1;
+                    tcp.store_m = 1;
+                    tcp.sums_m = -1;
+                    tcp.pred = 3;
+                    tcp.probe_mode = 1;
+                    launch_trial_fused(tcp, a, prec, st);
+                }
                 GemmArgs tfl = ta;
+                tfl.pred = 3;
                 tfl.probe_mode = 2;
                 launch_trial_fused(tfl, a, prec, st);
             } else if (fused)
@@ -998,6 +1024,7 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
         stats->lz_steps = host.lz_steps;
         stats->probe_rejects = host.probe_rejects;
         stats->unprobed_trials = host.unprobed;
+        stats->probe_mtiles = host.probe_mtiles;
         stats->tail_blocks = fused && P.tp.tail_splits > 1 ? P.tp.tilesN - P.tp.tail_n0 : 0;
         stats->tail_splits = fused ? P.tp.tail_splits : 0;
         if (timing) {

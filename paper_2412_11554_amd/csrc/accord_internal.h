@@ -57,11 +57,13 @@ struct LsState {
     int32_t fixed_step; // beta == 1: the single trial is accepted
     int32_t warm_tau;   // 1: an iteration starts from min(tau0, tau_acc / beta), not tau0
     int32_t lz_steps;   // Lanczos steps of the device estimate of L (0: L was given)
-    int32_t probe_rej;  // the trial in flight was rejected by its probe (row tile 0)
-    int32_t probe_rejects;  // trials rejected by their probe, over the fit
+    int32_t probe_rej;  // the trial in flight was rejected by a partial test (its first
+                        // M tiles)
+    int32_t probe_rejects;  // trials rejected by a partial test, over the fit
     int32_t probe_off;  // this iteration's later trials run unprobed (set when a trial
-                        // fails the full test of a probing fit)
+                        // fails the full test of a probing fit, or a partial test late)
     int32_t unprobed;   // trials of a probing fit that ran unprobed, over the fit
+    int32_t probe_mtiles;   // M tiles the trials rejected by partial tests had run
 };
 
 // Pinned host mailbox: after every executed acceptance test the device posts the
@@ -223,8 +225,9 @@ void launch_prox(ProxArgs a, int nblocks, hipStream_t st);
 void launch_finalize(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
                      int ntiles, double* trace, int32_t* trials_log, Mailbox* mbox,
                      int probing, hipStream_t st);
+// partial test of a probed trial after its first mt M tiles (1 <= mt < tilesM)
 void launch_probe_decide(LsState* ls, const double* prox_part, int nprox,
-                         const double* norm_part, int tilesN, int tilesM, int nparts,
+                         const double* norm_part, int tilesN, int tilesM, int nparts, int mt,
                          Mailbox* mbox, hipStream_t st);
 void launch_fit_init(LsState* ls, const double* prox_part, int nprox, const double* norm_part,
                      int ntiles, double* trace, hipStream_t st);

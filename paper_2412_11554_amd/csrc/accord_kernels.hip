@@ -8,7 +8,7 @@
 //   k_gemm_fp8w    the same tile on MX-FP8 operands: the FP8 form's gradient
 //   k_trial_fused  bf16 forms: prox (eq. 3.5) fused into the trial product (k_trial_fused8:
 //                  FP8, k_trial_fused32: FP32), over an M range so that a trial can be
-//                  probed on its first 256 samples (k_probe_decide)
+//                  tested on its first M tiles of 256 samples (k_probe_decide)
 //   FP32 uses of k_gemm_f32:
 //                    gradient  G  = X^T W / n              (Remark 3.1, two-step product)
 //                    trial     W+ = W + X Delta, ||X Delta||^2, ||W+||^2 (Alg. 1 test)
@@ -2387,12 +2387,12 @@ __device__ inline void post_mailbox(Mailbox* mb, const LsState* ls) {
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// probing: the fit probes its trials (see launch_finalize).  Once a trial that was not
-// rejected by its probe fails the full test, its ratio ||X Delta||^2 tau / (n ||Delta||^2)
-// was below the inverse of the probe's share of the samples, and the next trial's, at
-// half the step, is about half of it: its probe could reject it only if the ratio did not
-// fall, so the rest of the iteration runs each trial as one launch over all samples (the
-// same tiles and sums, so the same bits, without the probe's extra launch).
+// probing: the fit probes its trials (see k_probe_decide).  Once a trial that no partial
+// test rejected fails the full test, its ratio ||X Delta||^2 tau / (n ||Delta||^2) was
+// below the inverse of the last partial test's share of the samples, and the next
+// trial's, at half the step, is about half of it: a partial test could reject it only if
+// the ratio did not fall, so the rest of the iteration runs each trial as one launch over
+// all samples (the same tiles and sums, so the same bits, without the extra launches).
 __device__ __forceinline__ void finalize_run(LsState* ls, const double* prox_part, int nprox,
                                              const double* norm_part, int ntiles, double* trace,
                                              int32_t* trials_log, Mailbox* mbox, int probing) {
@@ -2477,27 +2477,35 @@ void launch_finalize(LsState* ls, const double* prox_part, int nprox, const doub
                                        trials_log, mbox, probing);
 }
 
-// Probe of a trial: the fused trial kernel ran on M tile 0 only (the first kFBM samples),
-// whose workgroups also wrote the prox sums over every column.  ||X Delta||^2 summed over
-// the probe's rows is a lower bound of the sum over all samples (every term is a square),
-// so when it alone exceeds n ||Delta||^2 / tau the trial fails Alg. 1's test exactly as
-// the full product would.  The trial is then rejected here (counted, tau <- beta tau,
-// posted to the mailbox) and flagged, so that the launch over the remaining M tiles and
+// Partial test of a probed trial after the fused trial kernel ran on its first mt M
+// tiles (samples 0 .. 256 mt - 1; M tile 0 also wrote the prox sums over every column).
+// Every term of ||X Delta||^2 is a square, so the sum over those samples is a lower bound
+// of the whole: when it alone exceeds n ||Delta||^2 / tau, the trial fails Alg. 1's test
+// exactly as the full product would.  It is then rejected here (counted, tau <- beta tau,
+// posted to the mailbox) and flagged, so that the later M tiles, the unprobed launch and
 // the acceptance test of this trial do nothing.  A trial at the floor tau <= 1/L, a fixed
-// step and non-finite sums always go on to the full test.  Norm rows of M tile 0 are
-// rows part * tiles + tile_n * tilesM, part < nparts (kFReduceParts after a split-K
-// reduce, else 1).  Nothing runs once the iteration has stopped probing.
+// step and non-finite sums always go on to the full test.  A trial rejected this late
+// (3 mt >= 2 tilesM: its ratio is only known to exceed tilesM / mt) leaves a next trial,
+// at half the step, that most likely passes, so the iteration's later trials run
+// unprobed, as after a failed full test.  Norm rows: part * tiles + tile_n * tilesM +
+// tile_m, part < nparts (kFReduceParts after a split-K reduce, else 1).  Nothing runs once
+// the iteration has stopped probing.
 __global__ void __launch_bounds__(kThreads) k_probe_decide(LsState* ls, const double* prox_part,
                                                            int nprox, const double* norm_part,
                                                            int tilesN, int tilesM, int nparts,
-                                                           Mailbox* mbox) {
+                                                           int mt, Mailbox* mbox) {
     if (ls->done || ls->converged || ls->probe_off) return;  // (no probe ran)
+    if (mt > 1 && ls->probe_rej) return;                      // rejected at an earlier test
     double pv[6];
     sum_partials<6>(prox_part, nprox, kPartCols, pv);
     double nv[1] = {0.0};
     const int64_t tiles = (int64_t)tilesM * tilesN;
-    for (int r = threadIdx.x; r < tilesN * nparts; r += kThreads)
-        nv[0] += norm_part[((r / tilesN) * tiles + (int64_t)(r % tilesN) * tilesM) * kNormCols];
+    // norm rows of M tiles 0 .. mt - 1 of every column block, for each reduce part
+    const int per = tilesN * mt;
+    for (int r = threadIdx.x; r < per * nparts; r += kThreads) {
+        const int part = r / per, q = r % per;
+        nv[0] += norm_part[(part * tiles + (int64_t)(q / mt) * tilesM + q % mt) * kNormCols];
+    }
     block_sum<1>(nv);
     if (threadIdx.x != 0) return;
     const double d2 = pv[P_D2], v2 = nv[0], tau = ls->tau;
@@ -2509,17 +2517,19 @@ __global__ void __launch_bounds__(kThreads) k_probe_decide(LsState* ls, const do
         ls->tau = tau * ls->beta;
         ls->probe_rej = 1;
         ls->probe_rejects += 1;
+        ls->probe_mtiles += mt;
+        if (3 * mt >= 2 * tilesM) ls->probe_off = 1;
         post_mailbox(mbox, ls);
-    } else {
+    } else if (mt == 1) {
         ls->probe_rej = 0;
     }
 }
 
 void launch_probe_decide(LsState* ls, const double* prox_part, int nprox,
-                         const double* norm_part, int tilesN, int tilesM, int nparts,
+                         const double* norm_part, int tilesN, int tilesM, int nparts, int mt,
                          Mailbox* mbox, hipStream_t st) {
     k_probe_decide<<<1, kThreads, 0, st>>>(ls, prox_part, nprox, norm_part, tilesN, tilesM,
-                                           nparts, mbox);
+                                           nparts, mt, mbox);
 }
 
 // Starting point: objective pieces of Omega^(0) (reduce-only prox sums of Omega^(0)

@@ -92,10 +92,11 @@ def test_ba100k_bf16x3_deterministic(big):
 
 
 def test_ba100k_probe_is_the_full_trial(big):
-    """Three BF16x3 iterations with trials probed on the first 256 samples (and, after a
-    trial of an iteration fails the full test, the later ones unprobed) equal those that
-    always run the whole product, bit for bit (checked by column-chunk sums of the FP32
-    bit patterns and on sampled columns), with the same trial counts."""
+    """Three BF16x3 iterations with trials tested on their first 256 samples and then
+    after each further tile of 256 (and, after a trial of an iteration fails the full
+    test or a late partial test, the later ones unprobed) equal those that always run the
+    whole product, bit for bit (checked by column-chunk sums of the FP32 bit patterns and
+    on sampled columns), with the same trial counts."""
     import torch
     from paper_2412_11554_amd import accord
     w = big["w"]
@@ -112,8 +113,9 @@ def test_ba100k_probe_is_the_full_trial(big):
                                       ws=big["ws"], omega_out=big["om"], probe=probe)
         runs.append((st, tr.clone(), big["om"][cols, :].clone(), bit_sums(big["om"])))
     (sa, ta, ca, ha), (sb, tb, cb, hb) = runs
-    print(f"[big] trials {sa['trials']} (probe: {sa['probe_rejects']} rejected by the probe, "
-          f"{sa['unprobed_trials']} unprobed) vs {sb['trials']}", flush=True)
+    print(f"[big] trials {sa['trials']} (probe: {sa['probe_rejects']} rejected by partial "
+          f"tests after {sa['probe_mtiles']} M tiles, {sa['unprobed_trials']} unprobed) "
+          f"vs {sb['trials']}", flush=True)
     assert sb["probe_rejects"] == 0 and sb["unprobed_trials"] == 0
     assert sa["trials"] == sb["trials"] and torch.equal(ta, tb)
     assert torch.equal(ca, cb) and ha == hb

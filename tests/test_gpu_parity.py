@@ -483,7 +483,9 @@ def test_fit_probe_is_the_full_trial(gpu_lib, dev, form):
     assert sa["probe_rejects"] + sa["unprobed_trials"] <= sa["trials"]
     assert sa["probe_rejects"] <= sa["trials"] - sa["iters"]
     print(f"[probe] {sa['probe_rejects']} of {sa['trials'] - sa['iters']} rejected trials "
-          f"settled by the probe, {sa['unprobed_trials']} trials unprobed", flush=True)
+          f"settled by partial tests (after {sa['probe_mtiles']} M tiles in all), "
+          f"{sa['unprobed_trials']} trials unprobed", flush=True)
+    assert sa["probe_rejects"] <= sa["probe_mtiles"] <= 3 * sa["probe_rejects"]
     assert torch.equal(ta, tb) and torch.equal(a, b)
     if form == "bf16x3":
         taus = ta.cpu().numpy()[1:, 3]
@@ -513,8 +515,10 @@ def test_fit_split_k_tail(gpu_lib, dev, form):
     b, sb, tb = gpu_lib.accord_fit(X, 0.05, 6, precision=form, trace=True, probe=False)
     torch.cuda.synchronize()
     assert sa["trials"] == sb["trials"] and sa["trials"] > sa["iters"]
-    print(f"[tail] {sa['trials']} trials, {sa['probe_rejects']} probe rejections, "
-          f"{sa['unprobed_trials']} unprobed", flush=True)
+    print(f"[tail] {sa['trials']} trials, {sa['probe_rejects']} rejected by partial tests "
+          f"after {sa['probe_mtiles']} M tiles, {sa['unprobed_trials']} unprobed", flush=True)
+    # staged: partial tests after M tiles 1, 2 and 3 of 4
+    assert sa["probe_rejects"] <= sa["probe_mtiles"] <= 3 * sa["probe_rejects"]
     assert torch.equal(ta, tb) and torch.equal(a, b)
     if form == "bf16x3":
         taus = ta.cpu().numpy()[1:, 3]
