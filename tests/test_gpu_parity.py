@@ -498,6 +498,39 @@ def test_fit_probe_is_the_full_trial(gpu_lib, dev, form):
         assert rel <= 1e-4, rel
 
 
+@pytest.mark.parametrize("form", ["bf16x3", "bf16x1"])
+def test_fit_staged_six_m_tiles(gpu_lib, dev, form):
+    """n = 1300, p = 8192: six M tiles of 256 samples (the last holds 20), 64 column blocks
+    split 4 ways, so one M tile's launch fills the CUs and a probed trial goes on one M
+    tile per launch with a partial test after each of the first five; a rejection after
+    four or five M tiles turns the partial tests off for the rest of the iteration.  Same
+    bits and trial counts as the fit that always runs the whole product; BF16x3 also
+    against the oracle's replay."""
+    import torch
+    w = datagen.small_random_problem(1300, 8192, seed=41, lam=0.05)
+    X = _t(w.X, dev)
+    print(f"[staged] {form} n=1300 p=8192 10 iterations, probe on and off", flush=True)
+    a, sa, ta = gpu_lib.accord_fit(X, 0.05, 10, precision=form, trace=True, probe=True)
+    a = a.clone()
+    b, sb, tb = gpu_lib.accord_fit(X, 0.05, 10, precision=form, trace=True, probe=False)
+    torch.cuda.synchronize()
+    print(f"[staged] {sa['trials']} trials, {sa['probe_rejects']} rejected by partial tests "
+          f"after {sa['probe_mtiles']} M tiles, {sa['unprobed_trials']} unprobed", flush=True)
+    assert sa["trials"] == sb["trials"] and sa["trials"] > sa["iters"]
+    assert sa["probe_rejects"] > 0 and sa["probe_mtiles"] > sa["probe_rejects"]
+    assert sa["probe_mtiles"] <= 5 * sa["probe_rejects"]
+    assert torch.equal(ta, tb) and torch.equal(a, b)
+    if form == "bf16x3":
+        taus = ta.cpu().numpy()[1:, 3]
+        cols = np.array([0, 1, 4095, 8191])
+        ref = oracle.fit_fbs(w.X.astype(np.float64), 0.05, 10, L=sa["lipschitz"],
+                             tau_replay=taus, columns=cols)
+        got = a.cpu().numpy()[cols, :].astype(np.float64).T
+        rel = np.linalg.norm(got - ref.omega) / np.linalg.norm(ref.omega)
+        print(f"[staged] bf16x3 vs oracle replay: {rel:.2e}", flush=True)
+        assert rel <= 1e-4, rel
+
+
 @pytest.mark.parametrize("form", ["bf16x3", "bf16x1", "fp8"])
 def test_fit_split_k_tail(gpu_lib, dev, form):
     """n = 800, p = 33000: 258 column blocks of 128, one more than a whole round of
