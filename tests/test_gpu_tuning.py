@@ -165,6 +165,45 @@ def test_refit_support_skip_is_exact(gpu_lib, prec):
         assert not a.cpu().numpy()[off].any()
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x1"])
+def test_refit_staged_tail_support_skip(gpu_lib, prec):
+    """The refit at n = 800, p = 33000 (four M tiles, 258 column blocks): its trial products
+    walk the support's K-step lists in the staged one-M-tile launches with partial tests,
+    the unprobed whole product and the split-K tail of the last two column blocks alike.
+    Support skipping on or off, and partial tests on or off, give the same bits; the
+    result is zero off the support.  The first step is 16, so that the early trials of
+    each iteration fail and the partial tests reject them."""
+    import torch
+    w = datagen.small_random_problem(800, 33000, seed=83, lam=0.05)
+    p = 33000
+    rng = np.random.default_rng(83)
+    # a sparse support: about 10 entries per column (and the diagonal), as a COO list
+    rows = rng.integers(0, p, size=10 * p)
+    cols = np.repeat(np.arange(p), 10)
+    hat = torch.zeros((p, p), dtype=torch.float32, device="cuda")  # [column, row]
+    hat[torch.from_numpy(cols).cuda(), torch.from_numpy(rows).cuda()] = torch.from_numpy(
+        rng.uniform(0.01, 0.05, 10 * p).astype(np.float32)).cuda()
+    hat.diagonal().fill_(1.0)
+    x = _dev(w.X)
+    print(f"[refit tail] {prec} n=800 p=33000 8 iterations: skip and probe on/off", flush=True)
+    runs = []
+    for skip, probe in ((True, True), (False, True), (True, False)):
+        om, st, tr = gpu_lib.accord_refit(x, hat, 0.05, 0.5, 8, precision=prec, trace=True,
+                                          support_skip=skip, probe=probe, tau0=16.0)
+        torch.cuda.synchronize()
+        runs.append((om.clone(), tr.clone(), st))
+        del om
+    (a, ta, sa) = runs[0]
+    print(f"[refit tail] {sa['trials']} trials, {sa['probe_rejects']} rejected by partial tests "
+          f"after {sa['probe_mtiles']} M tiles, tail {sa['tail_blocks']} x {sa['tail_splits']}",
+          flush=True)
+    assert sa["tail_blocks"] == 2 and sa["trials"] > sa["iters"] and sa["probe_rejects"] > 0
+    for b, tb, sb in runs[1:]:
+        assert sa["trials"] == sb["trials"] and torch.equal(ta, tb)
+        assert torch.equal(a, b)
+    assert not bool(((hat == 0) & (a != 0)).any())
+
+
 def test_refit_errors(gpu_lib):
     from paper_2412_11554_amd import accord
     w = datagen.small_random_problem(30, 40, seed=1)
