@@ -181,9 +181,10 @@ def _trial_plan(form, n, p, tail_blocks=0, tail_splits=0):
     def launches(m):  # (kernel, grid) of the launches over m M tiles
         if best > 1:
             return [(kname(2), m * tn * best), (reduce(best), m * tn * 2)]
-        if fused and tail_splits > 1 and 0 < tail_blocks < tn:
+        if tail_splits > 1 and 0 < tail_blocks < tn:
             return [(kname(1), m * (tn - tail_blocks)),
-                    (kname(2), m * tail_blocks * tail_splits), (reduce(tail_splits), m * tail_blocks * 2)]
+                    (kname(2), m * tail_blocks * tail_splits),
+                    (reduce(tail_splits), m * tail_blocks * (2 if fused else 1))]
         return [(kname(1), m * tn)]
 
     return {"splits": best, "probe": probe, "tilesM": tm, "tilesN": tn,

@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <numeric>
 #include <map>
 #include <mutex>
 #include <string>
@@ -153,27 +154,33 @@ int choose_probe_splits(int tilesM, int tilesN, int ksteps64, int slots) {
     return best;
 }
 
-// Split-K tail of the fused trial product.  Its workgroups all run the same K loop, one
-// per CU, so a launch takes whole rounds of slots workgroups: with tilesN = F + T column
-// blocks (F a multiple of slots, 0 < T < slots) the last T blocks add a round in which
-// most CUs idle.  Measured at n = 1000, p = 1e5 (782 blocks) in BF16x3: over 768 blocks
-// instead of 782 the probe took 19.1 instead of 25.2 ms, the rest of a trial 57.5
-// instead of 60.6 ms and the whole product 68.9 instead of 75.2 ms.  So the last T blocks
-// run as a launch of their own, split S ways along K and reduced, in every launch of the
-// product (probe, rest, whole; the same S, so a column block sums its products in the
-// same order whichever launch covers it).  S in {2, 4, 8, 16} minimises the tail's
-// rounds, ceil(m T S / slots) / S (1 + 0.03 (S - 1)), summed over the launches that
-// cover m = 1 (weighted 2: the probe runs for every probed trial), tilesM - 1 and tilesM
-// M tiles (the whole product only, without probes), with at least 8 K steps of 64 per
-// split; 0 (no tail launch) unless that beats the unsplit tail by 10%.
-int choose_tail_splits(int tilesM, int tilesN, int ksteps64, int slots, bool probe) {
-    const int T = tilesN % slots;
-    if (tilesN < slots || T == 0) return 0;
+// Split-K tail of a trial product.  Its workgroups all run the same K loop (one per CU in
+// the fused bf16 / fp8 kernels, two in the FP32 GEMM), so a launch takes whole rounds of
+// slots workgroups.  With tilesN = F + T column blocks, F the largest multiple of `unit`
+// (the blocks for which every launch of the product is a whole number of rounds: slots
+// when trials are probed, since the launches then cover one M tile, else
+// slots / gcd(slots, tilesM)), the last T blocks add a round in which most CUs idle.
+// Measured at n = 1000, p = 1e5 (782 blocks) in BF16x3: over 768 blocks instead of 782
+// the probe took 19.1 instead of 25.2 ms, the rest of a trial 57.5 instead of 60.6 ms
+// and the whole product 68.9 instead of 75.2 ms.  So the last T blocks run as a launch
+// of their own, split S ways along K and reduced, in every launch of the product (the
+// same S, so a column block sums its products in the same order whichever launch covers
+// it).  S in {2, 4, 8, 16} minimises the tail's rounds, ceil(m T S / slots) / S
+// (1 + 0.03 (S - 1)), over the launches that cover m = 1 (three times: the probe and the
+// partial-test stages) and tilesM M tiles when trials are probed, else tilesM, with at
+// least 8 K steps of 64 per split; 0 (no tail launch) unless that beats the unsplit tail
+// by 10%.  *tail_n0 = F.
+int choose_tail_splits(int tilesM, int tilesN, int ksteps64, int slots, bool probe,
+                       int* tail_n0) {
+    *tail_n0 = 0;
+    const int unit = probe ? slots : slots / std::gcd(slots, tilesM);
+    const int F = tilesN / unit * unit, T = tilesN - F;
+    if (F == 0 || T == 0) return 0;
     auto cost = [&](int S) {
         auto part = [&](int m) {
             return (double)cdiv((int64_t)m * T * S, slots) / S * (1.0 + 0.03 * (S - 1));
         };
-        return probe ? 2.0 * part(1) + part(tilesM - 1) + part(tilesM) : part(tilesM);
+        return probe ? 3.0 * part(1) + part(tilesM) : part(tilesM);
     };
     int best = 0;
     double best_cost = 0.9 * cost(1);
@@ -185,6 +192,7 @@ int choose_tail_splits(int tilesM, int tilesN, int ksteps64, int slots, bool pro
             best_cost = c;
         }
     }
+    if (best > 1) *tail_n0 = F;
     return best;
 }
 
@@ -208,11 +216,9 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
                           ? choose_probe_splits(P.tp.tilesM, P.tp.tilesN, (int)(P.p_pad / kPad),
                                                 kWSlots)
                           : choose_splits(P.tp.tiles(), (int)(P.p_pad / kPad), kWSlots);
-        if (P.tp.splits == 1) {
+        if (P.tp.splits == 1)
             P.tp.tail_splits = choose_tail_splits(P.tp.tilesM, P.tp.tilesN, (int)(P.p_pad / kPad),
-                                                  kWSlots, P.tp.tilesM >= 4);
-            P.tp.tail_n0 = P.tp.tail_splits > 1 ? P.tp.tilesN - P.tp.tilesN % kWSlots : 0;
-        }
+                                                  kWSlots, P.tp.tilesM >= 4, &P.tp.tail_n0);
     }
     P.nprox = prox_blocks(p * P.p_pad);
     // every form's fit runs the prox inside its trial kernel: one row of prox sums per
@@ -222,6 +228,10 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
     // n = 500 (4 row tiles: 300 us against 287 + 77 us at p = 5000), slower at n = 1000
     // (8 row tiles: 218 ms against 152 + 33 ms at p = 1e5).  So it runs up to 4 row tiles.
     P.fused32 = !P.fused && P.t32.tilesM <= 4;
+    // the plain FP32 trial GEMM (and the FP32 set-up product W0 = X Omega0 of every form)
+    if (!P.fused32 && P.t32.splits == 1)
+        P.t32.tail_splits = choose_tail_splits(P.t32.tilesM, P.t32.tilesN, (int)(P.p_pad / kPad),
+                                               kSlots, false, &P.t32.tail_n0);
     // A probe (M tile 0, a quarter of the samples or less) rejects a trial whose test
     // fails by more than the inverse of its share of the rows; with fewer M tiles the
     // probe is a large share of the product and cannot reject the near misses.
@@ -241,8 +251,11 @@ Plan make_plan(int64_t n, int64_t p, int32_t max_iter, int prec) {
         std::max((size_t)(P.t32.splits > 1 ? P.t32.splits : 0) * P.t32.tiles() * kBM * kBN,
                  (size_t)(P.tp.splits > 1 ? P.tp.splits : 0) * P.tp.tiles() * kFBM * kFBN *
                      (P.fused ? 1 : 0));
-    const size_t tail_floats = (size_t)(P.tp.tail_splits > 1 ? P.tp.tail_splits : 0) *
-                               P.tp.tilesM * (P.tp.tilesN - P.tp.tail_n0) * kFBM * kFBN;
+    const size_t tail_floats = std::max(
+        (size_t)(P.tp.tail_splits > 1 ? P.tp.tail_splits : 0) * P.tp.tilesM *
+            (P.tp.tilesN - P.tp.tail_n0) * kFBM * kFBN,
+        (size_t)(P.t32.tail_splits > 1 ? P.t32.tail_splits : 0) * P.t32.tilesM *
+            (P.t32.tilesN - P.t32.tail_n0) * kBM * kBN);
     const size_t xn = (size_t)(P.n_pad * P.p_pad);   // padded X elements
     const size_t wn = (size_t)(p * P.n_pad);         // W^T elements
     const size_t on = (size_t)(p * P.p_pad);         // p x p_pad elements
@@ -345,6 +358,19 @@ GemmArgs trial_args(const Plan& P, void* ws, int prec, const float* B32, const u
 }
 
 void enqueue_trial(const GemmArgs& a, int prec, hipStream_t st) {
+    if (a.splits == 1 && a.tail_splits > 1 && a.tail_n0 > 0 && a.tail_n0 < a.tilesN) {
+        // the column blocks before tail_n0 unsplit, then the split-K tail and its reduce
+        // (see choose_tail_splits)
+        GemmArgs f = a, t = a;
+        f.tail_splits = t.tail_splits = 0;
+        f.n_count = a.tail_n0;
+        t.n_first = a.tail_n0;
+        t.n_count = a.tilesN - a.tail_n0;
+        t.splits = a.tail_splits;
+        enqueue_trial(f, prec, st);
+        enqueue_trial(t, prec, st);
+        return;
+    }
     if (a.splits > 1) {
         launch_gemm(a, EPI_PARTIAL, prec, st);
         launch_splitk_reduce(a, st);
@@ -1025,8 +1051,12 @@ static int fit_impl(const float* X, int64_t n, int64_t p, float* Omega, const ac
         stats->probe_rejects = host.probe_rejects;
         stats->unprobed_trials = host.unprobed;
         stats->probe_mtiles = host.probe_mtiles;
-        stats->tail_blocks = fused && P.tp.tail_splits > 1 ? P.tp.tilesN - P.tp.tail_n0 : 0;
-        stats->tail_splits = fused ? P.tp.tail_splits : 0;
+        {
+            const Geo& tg = fused ? P.tp : P.t32;
+            const bool used = fused || !P.fused32;  // the fused FP32 trial runs unsplit
+            stats->tail_blocks = used && tg.tail_splits > 1 ? tg.tilesN - tg.tail_n0 : 0;
+            stats->tail_splits = used ? tg.tail_splits : 0;
+        }
         if (timing) {
             std::vector<int32_t> tl((size_t)(host.iter > 0 ? host.iter : 1), 0);
             if (host.iter > 0)

@@ -265,22 +265,24 @@ __device__ inline void decode_tile(const GemmArgs& g, int& tile_m, int& tile_n, 
     const int nblk = gridDim.x, bid = blockIdx.x;
     const int xcd = bid & 7, local = bid >> 3, q8 = nblk >> 3, r8 = nblk & 7;
     const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + local;
+    // over the launch's N tiles n_first .. n_first + n_count - 1 (all with n_count 0)
+    const int ncnt = g.n_count > 0 ? g.n_count : g.tilesN;
     if (g.splits > 1) {
         // tile_m fastest: the M tiles of one (split, N tile) share the B panel
         tile_m = logical % g.tilesM;
         const int rest = logical / g.tilesM;
-        tile_n = rest % g.tilesN;
-        split = rest / g.tilesN;
+        tile_n = g.n_first + rest % ncnt;
+        split = rest / ncnt;
     } else {
         // grouped order: bands of 8 M tiles walk across N
         constexpr int GM = 8;
-        const int per_group = GM * g.tilesN;
+        const int per_group = GM * ncnt;
         const int group = logical / per_group;
         const int first_m = group * GM;
         const int gsize = (g.tilesM - first_m) < GM ? (g.tilesM - first_m) : GM;
         const int in_group = logical - group * per_group;
         tile_m = first_m + in_group % gsize;
-        tile_n = in_group / gsize;
+        tile_n = g.n_first + in_group / gsize;
         split = 0;
     }
 }
@@ -427,9 +429,11 @@ template <int EPI, bool STREAM = false>
 __device__ inline void gemm_epilogue(const GemmArgs& g, f4 (&acc)[4][4], int tile_m, int tile_n,
                                      int split, double* red_lds, double* nrm) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile = tile_m + tile_n * g.tilesM;
     if (EPI == EPI_PARTIAL) {
-        f4* P = (f4*)(g.P + ((int64_t)split * g.tilesM * g.tilesN + tile) * (kBM * kBN));
+        // numbered within the launch's N tiles (split-major), as k_splitk_reduce reads them
+        const int ncnt = g.n_count > 0 ? g.n_count : g.tilesN;
+        const int64_t ptile = (int64_t)(tile_n - g.n_first) * g.tilesM + tile_m;
+        f4* P = (f4*)(g.P + ((int64_t)split * g.tilesM * ncnt + ptile) * (kBM * kBN));
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -823,10 +827,13 @@ __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
     }
     constexpr int LDR = kBM + 4;  // LDS floats per column (16 lanes of a quad write hit 64 banks)
     __shared__ __attribute__((aligned(16))) float sT[kBN * LDR];
-    const int tile = blockIdx.x;
-    const int tile_m = tile % g.tilesM, tile_n = tile / g.tilesM;
+    // one workgroup per tile of the launch's N tiles n_first .. n_first + n_count - 1
+    const int ncnt = g.n_count > 0 ? g.n_count : g.tilesN;
+    const int ptile = blockIdx.x;
+    const int tile_m = ptile % g.tilesM, tile_n = g.n_first + ptile / g.tilesM;
+    const int tile = tile_m + tile_n * g.tilesM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t tiles = (int64_t)g.tilesM * g.tilesN;
+    const int64_t tiles = (int64_t)g.tilesM * ncnt;  // partial tiles per split
     f4 v[16];
 #pragma unroll
     for (int idx = 0; idx < 16; ++idx) v[idx] = f4{0.f, 0.f, 0.f, 0.f};
@@ -834,7 +841,7 @@ __global__ void __launch_bounds__(kThreads) k_splitk_reduce(GemmArgs g) {
     constexpr int kUnroll = S > 0 ? S : 1;
 #pragma unroll kUnroll
     for (int s = 0; s < nsplit; ++s) {
-        const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + tile) * (kBM * kBN));
+        const f4* P = (const f4*)(g.P + ((int64_t)s * tiles + ptile) * (kBM * kBN));
 #pragma unroll
         for (int idx = 0; idx < 16; ++idx)
             v[idx] += STREAM ? ld_stream(&P[idx * kThreads + tid]) : P[idx * kThreads + tid];
@@ -867,7 +874,8 @@ void launch_grad_fp8(const GemmArgs& a, hipStream_t st);
 void launch_trial_fused8(const GemmArgs& a, const ProxArgs& px, hipStream_t st);
 
 void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st) {
-    const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN * a.splits);
+    const int ncnt = a.n_count > 0 ? a.n_count : a.tilesN;
+    const unsigned blocks = (unsigned)((int64_t)a.tilesM * ncnt * a.splits);
     if (prec == PREC_FP8) {  // FP8 form: gradient only, like the bf16 forms
         launch_grad_fp8(a, st);
         return;
@@ -890,7 +898,8 @@ void launch_gemm(const GemmArgs& a, int epi, int prec, hipStream_t st) {
 
 template <bool STREAM>
 void launch_splitk_reduce_t(const GemmArgs& a, hipStream_t st) {
-    const unsigned blocks = (unsigned)((int64_t)a.tilesM * a.tilesN);
+    const int ncnt = a.n_count > 0 ? a.n_count : a.tilesN;
+    const unsigned blocks = (unsigned)((int64_t)a.tilesM * ncnt);
     switch (a.splits) {
         case 2: k_splitk_reduce<2, STREAM><<<blocks, kThreads, 0, st>>>(a); break;
         case 3: k_splitk_reduce<3, STREAM><<<blocks, kThreads, 0, st>>>(a); break;

@@ -54,6 +54,11 @@ def test_ba100k_sampled_columns(big, form):
     print(f"[big] {form}: accord_fit n={w.n} p={w.p} iters={T}", flush=True)
     om, st, tr = accord.accord_fit(big["X"], w.lam, T, precision=form, trace=True,
                                    ws=big["ws"], omega_out=big["om"])
+    # 782 column blocks: the trial products run the last 14 (the fused forms: past three
+    # whole rounds of 256 workgroups; FP32: past 768 x 8 tiles, 12 rounds of 512) as a
+    # split-K tail launch, and COLS samples columns 99998, 99999 of it
+    assert st["tail_blocks"] == 14 and st["tail_splits"] == (4 if form == "fp32" else 16), (
+        st["tail_blocks"], st["tail_splits"])
     _check_sampled(big, form, om, st, tr)
 
 
