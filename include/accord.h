@@ -203,9 +203,10 @@ typedef struct {
                                all samples */
     int32_t probe_mtiles;   /* tiles of 256 samples that the trials rejected by a partial
                                test had multiplied (params.probe) */
-    int32_t tail_blocks;    /* fused trial product: 128-column blocks run as a separate
-                               launch split along the contraction (the blocks past the
-                               last whole round of workgroups; 0: none) */
+    int32_t tail_blocks;    /* trial product: 128-column blocks run as a separate launch
+                               split along the contraction (the blocks past the last whole
+                               round of workgroups; 0: none, and always 0 for the FP32 form
+                               up to 512 samples, whose fused trial runs unsplit) */
     int32_t tail_splits;    /* its split count (0: none) */
 } accord_stats;
 
