@@ -788,8 +788,13 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16pp(GemmArgs g) {
         // phase 1: half 0 multiplies stage cur; half 1 stages B of step s + 1 into the
         // other stage (steps past the end re-store the last step: in bounds, unused) and
         // loads B of step s + 2
+        // (the multiplying wave runs at raised issue priority, so that on its SIMD its
+        // MFMAs go first and the staging wave fills the gaps: same bits, BF16x3 56.4 ->
+        // 54.6 ms at n = 1000, p = 1e5)
         if (half == 0) {
+            __builtin_amdgcn_s_setprio(1);
             mfma_step(cur);
+            __builtin_amdgcn_s_setprio(0);
         } else {
             store_stage(cur ^ 1);
             load_step(s + 2);
@@ -797,7 +802,9 @@ __global__ void __launch_bounds__(kWThreads, 1) k_gemm_bf16pp(GemmArgs g) {
         __syncthreads();
         // phase 2: the roles swap
         if (half == 1) {
+            __builtin_amdgcn_s_setprio(1);
             mfma_step(cur);
+            __builtin_amdgcn_s_setprio(0);
         } else {
             store_stage(cur ^ 1);
             load_step(s + 2);
